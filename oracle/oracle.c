@@ -1,0 +1,302 @@
+/*
+ * CPU ORACLE -- test infrastructure only.
+ *
+ * Plain, slow, obviously correct reference computations for exact
+ * higher-order U-statistics with edge-factorised kernels.  Only the test
+ * suite, the smoke check and the benchmark's CPU-baseline leg may load this
+ * library.  It shares no code, header or table with the HIP engine.
+ *
+ * What is computed here, and where the paper defines it:
+ *   - oracle_sum_tuples: the U-statistic of Definition 1 (sum over ordered
+ *     tuples of distinct indices) and the V-statistic of Definition 2 (sum
+ *     over all tuples), for a kernel that is a product of one n x n factor
+ *     per edge (Definition "Multiplicative Decomposition", tensorised as in
+ *     Algorithm 1).  A restricted V-statistic (Definition "Restricted
+ *     V-Statistic") is the V-statistic of the edge list relabelled by block,
+ *     which the Python wrapper builds.
+ *   - oracle_sum_tuples_i64: the same sums in exact integer arithmetic.
+ *   - oracle_lowrank_dp: the U-statistic of Definition 1 for factors of low
+ *     rank, T_k = F_k G_k^T, by a subset dynamic programme over the samples.
+ *     It never forms a V-statistic, so it is independent of the paper's
+ *     decomposition and works at any n.
+ *   - oracle_cycle_walks: closed-walk quantities of a 0/1 graph used by the
+ *     textbook 5-cycle trace formula (Harary & Manvel), exact in int64.
+ *
+ * Floating point: every sum is in fp64 with Neumaier compensation; partial
+ * sums over the outermost index are combined in a fixed order, so results
+ * are bitwise reproducible for any thread count.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <omp.h>
+
+#define ORACLE_MAX_M 10
+#define ORACLE_MAX_E 64
+
+typedef struct { double s, c; } ksum;
+
+static inline void ks_add(ksum *a, double x) {
+    /* Neumaier's improved Kahan summation. */
+    double t = a->s + x;
+    if (__builtin_fabs(a->s) >= __builtin_fabs(x)) a->c += (a->s - t) + x;
+    else a->c += (x - t) + a->s;
+    a->s = t;
+}
+static inline double ks_val(const ksum *a) { return a->s + a->c; }
+
+/* Per-depth edge schedule: after index d is chosen, multiply every factor
+ * whose later endpoint is d.  Vertices are visited in the order 0..m-1. */
+typedef struct {
+    int m, ne, distinct;
+    long n;
+    const double *const *T;
+    const int64_t *const *Ti;
+    int cnt[ORACLE_MAX_M];
+    int list[ORACLE_MAX_M][ORACLE_MAX_E];
+    const int *eu, *ev;
+} sched_t;
+
+static int build_sched(sched_t *s, int m, int ne, const int *eu, const int *ev) {
+    if (m < 1 || m > ORACLE_MAX_M || ne < 0 || ne > ORACLE_MAX_E) return -1;
+    s->m = m; s->ne = ne; s->eu = eu; s->ev = ev;
+    memset(s->cnt, 0, sizeof(s->cnt));
+    for (int k = 0; k < ne; ++k) {
+        if (eu[k] < 0 || eu[k] >= m || ev[k] < 0 || ev[k] >= m) return -1;
+        int d = eu[k] > ev[k] ? eu[k] : ev[k];
+        s->list[d][s->cnt[d]++] = k;
+    }
+    return 0;
+}
+
+static void rec_f64(const sched_t *s, int d, long *idx, double prod, ksum *acc) {
+    const long n = s->n;
+    for (long i = 0; i < n; ++i) {
+        if (s->distinct) {
+            int clash = 0;
+            for (int j = 0; j < d; ++j) if (idx[j] == i) { clash = 1; break; }
+            if (clash) continue;
+        }
+        idx[d] = i;
+        double p = prod;
+        for (int t = 0; t < s->cnt[d]; ++t) {
+            int k = s->list[d][t];
+            p *= s->T[k][idx[s->eu[k]] * n + idx[s->ev[k]]];
+        }
+        if (d + 1 == s->m) ks_add(acc, p);
+        else rec_f64(s, d + 1, idx, p, acc);
+    }
+}
+
+/*
+ * Sum over tuples (i_0..i_{m-1}) in [n]^m -- restricted to pairwise distinct
+ * indices when `distinct` is nonzero -- with i_0 in [lo, hi), of
+ *     prod_k T_k[i_{eu[k]}, i_{ev[k]}]
+ * (factors row-major n x n, fp64).  eu[k] == ev[k] is allowed and reads the
+ * diagonal.  Returns 0, or -1 on bad arguments.
+ */
+int oracle_sum_tuples(int m, int ne, const int *eu, const int *ev,
+                      const double *const *T, long n, int distinct,
+                      long lo, long hi, double *out) {
+    sched_t s;
+    if (build_sched(&s, m, ne, eu, ev)) return -1;
+    if (n < 1 || lo < 0 || hi > n || lo > hi || !out) return -1;
+    s.n = n; s.T = T; s.Ti = NULL; s.distinct = distinct;
+    /* Parallel work items are (i_0, i_1) pairs so that even a one-value
+     * range of i_0 keeps every core busy. */
+    long cnt = hi - lo;
+    long inner = (m >= 2) ? n : 1;
+    long items = cnt * inner;
+    ksum *part = (ksum *)calloc(items > 0 ? items : 1, sizeof(ksum));
+    if (!part) return -1;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long t = 0; t < items; ++t) {
+        long idx[ORACLE_MAX_M];
+        idx[0] = lo + t / inner;
+        double p = 1.0;
+        for (int q = 0; q < s.cnt[0]; ++q) {
+            int k = s.list[0][q];
+            p *= T[k][idx[0] * n + idx[0]];
+        }
+        ksum acc = {0.0, 0.0};
+        if (m == 1) {
+            ks_add(&acc, p);
+        } else {
+            idx[1] = t % inner;
+            if (!(distinct && idx[1] == idx[0])) {
+                for (int q = 0; q < s.cnt[1]; ++q) {
+                    int k = s.list[1][q];
+                    p *= T[k][idx[eu[k]] * n + idx[ev[k]]];
+                }
+                if (m == 2) ks_add(&acc, p);
+                else rec_f64(&s, 2, idx, p, &acc);
+            }
+        }
+        part[t] = acc;
+    }
+    ksum tot = {0.0, 0.0};
+    for (long t = 0; t < items; ++t) { ks_add(&tot, part[t].s); ks_add(&tot, part[t].c); }
+    free(part);
+    *out = ks_val(&tot);
+    return 0;
+}
+
+static void rec_i64(const sched_t *s, int d, long *idx, __int128 prod, __int128 *acc) {
+    const long n = s->n;
+    for (long i = 0; i < n; ++i) {
+        if (s->distinct) {
+            int clash = 0;
+            for (int j = 0; j < d; ++j) if (idx[j] == i) { clash = 1; break; }
+            if (clash) continue;
+        }
+        idx[d] = i;
+        __int128 p = prod;
+        for (int t = 0; t < s->cnt[d]; ++t) {
+            int k = s->list[d][t];
+            p *= (__int128)s->Ti[k][idx[s->eu[k]] * n + idx[s->ev[k]]];
+        }
+        if (d + 1 == s->m) *acc += p;
+        else rec_i64(s, d + 1, idx, p, acc);
+    }
+}
+
+/* Exact integer version of oracle_sum_tuples (int64 factors, 128-bit sum).
+ * The result is returned as (hi, lo) with value = hi * 2^64 + (uint64)lo. */
+int oracle_sum_tuples_i64(int m, int ne, const int *eu, const int *ev,
+                          const int64_t *const *T, long n, int distinct,
+                          long lo, long hi, int64_t *out_hi, uint64_t *out_lo) {
+    sched_t s;
+    if (build_sched(&s, m, ne, eu, ev)) return -1;
+    if (n < 1 || lo < 0 || hi > n || lo > hi || !out_hi || !out_lo) return -1;
+    s.n = n; s.T = NULL; s.Ti = T; s.distinct = distinct;
+    long cnt = hi - lo;
+    __int128 *part = (__int128 *)calloc(cnt > 0 ? cnt : 1, sizeof(__int128));
+    if (!part) return -1;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long t = 0; t < cnt; ++t) {
+        long idx[ORACLE_MAX_M];
+        idx[0] = lo + t;
+        __int128 p = 1;
+        for (int q = 0; q < s.cnt[0]; ++q) {
+            int k = s.list[0][q];
+            p *= (__int128)T[k][idx[0] * n + idx[0]];
+        }
+        __int128 acc = 0;
+        if (m == 1) acc = p;
+        else rec_i64(&s, 1, idx, p, &acc);
+        part[t] = acc;
+    }
+    __int128 tot = 0;
+    for (long t = 0; t < cnt; ++t) tot += part[t];
+    free(part);
+    *out_hi = (int64_t)(tot >> 64);
+    *out_lo = (uint64_t)tot;
+    return 0;
+}
+
+/*
+ * U-statistic (ordered distinct tuples) for rank-r factors
+ *     T_k(i, j) = sum_c F_k[i*r + c] * G_k[j*r + c],
+ * F and G given as arrays of ne pointers to n x r row-major fp64 blocks.
+ * Expanding every factor over its rank index c_k turns the kernel into a
+ * product of per-vertex weights phi_u(i); the sum of prod_u phi_u(i_u) over
+ * distinct tuples is then a 0/1-knapsack style dynamic programme over the
+ * samples: D[S] = weight of assigning the vertex set S to distinct samples
+ * seen so far.  Cost r^ne * n * 2^m * m.
+ */
+int oracle_lowrank_dp(int m, int ne, const int *eu, const int *ev, long n, int r,
+                      const double *const *F, const double *const *G, double *out) {
+    if (m < 1 || m > ORACLE_MAX_M || ne < 1 || ne > 24 || r < 1 || n < 1 || !out) return -1;
+    for (int k = 0; k < ne; ++k)
+        if (eu[k] < 0 || eu[k] >= m || ev[k] < 0 || ev[k] >= m) return -1;
+    long ncol = 1;
+    for (int k = 0; k < ne; ++k) { ncol *= r; if (ncol > (1L << 24)) return -1; }
+    const int full = (1 << m) - 1;
+    ksum *part = (ksum *)calloc(ncol, sizeof(ksum));
+    if (!part) return -1;
+#pragma omp parallel
+    {
+        double *D = (double *)malloc(sizeof(double) * (full + 1));
+        double *phi = (double *)malloc(sizeof(double) * m);
+        int col[ORACLE_MAX_E];
+#pragma omp for schedule(dynamic, 1)
+        for (long c = 0; c < ncol; ++c) {
+            long cc = c;
+            for (int k = 0; k < ne; ++k) { col[k] = (int)(cc % r); cc /= r; }
+            for (int S = 0; S <= full; ++S) D[S] = 0.0;
+            D[0] = 1.0;
+            for (long i = 0; i < n; ++i) {
+                for (int u = 0; u < m; ++u) phi[u] = 1.0;
+                for (int k = 0; k < ne; ++k) {
+                    phi[eu[k]] *= F[k][i * r + col[k]];
+                    phi[ev[k]] *= G[k][i * r + col[k]];
+                }
+                /* descending masks: D[S] is read before any update this round */
+                for (int S = full; S >= 0; --S) {
+                    double ds = D[S];
+                    if (ds == 0.0) continue;
+                    for (int u = 0; u < m; ++u)
+                        if (!(S & (1 << u))) D[S | (1 << u)] += ds * phi[u];
+                }
+            }
+            part[c].s = D[full];
+            part[c].c = 0.0;
+        }
+        free(D); free(phi);
+    }
+    ksum tot = {0.0, 0.0};
+    for (long c = 0; c < ncol; ++c) ks_add(&tot, part[c].s);
+    free(part);
+    *out = ks_val(&tot);
+    return 0;
+}
+
+/*
+ * Closed-walk counts of a simple undirected 0/1 graph given in CSR form
+ * (both directions stored, no self-loops):
+ *   out[0] = tr(A^3), out[1] = tr(A^5), out[2] = sum_i deg_i * (A^3)_ii,
+ *   out[3] = tr(A^4), out[4] = sum_i deg_i^2, out[5] = number of directed
+ *   edges (= 2|E|).
+ * A^2 is formed densely by walking paths of length two; tr(A^5) is
+ * sum over directed edges (j,k) of <row_j(A^2), row_k(A^2)>.
+ */
+int oracle_cycle_walks(long n, const int64_t *rowptr, const int32_t *col, int64_t *out) {
+    if (n < 1 || !rowptr || !col || !out) return -1;
+    int32_t *B = (int32_t *)calloc((size_t)n * (size_t)n, sizeof(int32_t));
+    if (!B) return -1;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (long i = 0; i < n; ++i) {
+        int32_t *Bi = B + (size_t)i * n;
+        for (int64_t a = rowptr[i]; a < rowptr[i + 1]; ++a) {
+            long j = col[a];
+            for (int64_t b = rowptr[j]; b < rowptr[j + 1]; ++b) Bi[col[b]] += 1;
+        }
+    }
+    int64_t trA3 = 0, trA5 = 0, degA3 = 0, trA4 = 0, deg2 = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : trA3, trA5, degA3, trA4, deg2)
+    for (long i = 0; i < n; ++i) {
+        const int32_t *Bi = B + (size_t)i * n;
+        int64_t deg = rowptr[i + 1] - rowptr[i];
+        int64_t a3 = 0;
+        for (int64_t a = rowptr[i]; a < rowptr[i + 1]; ++a) {
+            long k = col[a];
+            a3 += Bi[k];
+            const int32_t *Bk = B + (size_t)k * n;
+            int64_t dot = 0;
+            for (long t = 0; t < n; ++t) dot += (int64_t)Bi[t] * Bk[t];
+            trA5 += dot;
+        }
+        int64_t sq = 0;
+        for (long t = 0; t < n; ++t) sq += (int64_t)Bi[t] * Bi[t];
+        trA4 += sq;
+        trA3 += a3;
+        degA3 += deg * a3;
+        deg2 += deg * deg;
+    }
+    free(B);
+    out[0] = trA3; out[1] = trA5; out[2] = degA3; out[3] = trA4; out[4] = deg2;
+    out[5] = rowptr[n];
+    return 0;
+}
+
+int oracle_num_threads(void) { return omp_get_max_threads(); }
