@@ -1,0 +1,223 @@
+/*
+ * ustat.h -- C ABI of libustat, an MI355X (gfx950) engine for exact
+ * higher-order U-statistics whose kernel factorises over the edges of a
+ * small graph.
+ *
+ * Method (Chen, Liu & Zhang, arXiv 2508.12627):
+ *   - U(h, X) is the unnormalised sum of h over ordered m-tuples of distinct
+ *     sample indices (Definition 1).
+ *   - The kernel is multiplicative-decomposable with one bivariate factor per
+ *     edge (u, v) of a graph on m vertices (Definition "Multiplicative
+ *     Decomposition"); factor k is tensorised to the n x n matrix
+ *     T_k(i, j) = h_k(X_i, X_j) (Algorithm 1).
+ *   - Lemma 2 rewrites U as sum over set partitions pi of [m] of
+ *     mu_pi * V_pi, mu_pi = (-1)^(m-|pi|) prod_{C in pi} (|C|-1)!, where V_pi
+ *     is the restricted V-statistic (Definition "Restricted V-Statistic").
+ *   - V_pi is the Einsum of the induced notation A_pi (Algorithm 3, identity
+ *     "restricted identity"), evaluated by eliminating one index at a time
+ *     (Proposition 1 and its proof in Appendix "complexity_einsum").
+ *   - Optional sparsification (Lemma 3): factor diagonals are treated as
+ *     zero and only partitions in Pi_m^A are evaluated (Algorithm 4).
+ *
+ * Conventions for every call:
+ *   - Every function returns a ustat_status; nothing throws or aborts across
+ *     the ABI.  On error no output is written and ustat_last_error() holds a
+ *     thread-local message.
+ *   - The caller owns every input and output buffer.  "device" pointers are
+ *     HIP device memory on the current device; "host" pointers are ordinary
+ *     host memory.
+ *   - Matrices are n x n, row-major, leading dimension n, element (i, j) at
+ *     offset i*n + j.  Factor k belongs to edge k = (u_k, v_k) and is read as
+ *     T_k(i_{u_k}, i_{v_k}).  The same pointer may be passed for several
+ *     edges.
+ *   - Factor element type follows the plan's precision: USTAT_F64 -> double,
+ *     USTAT_F32 and USTAT_BF16X3 -> float, USTAT_I8 -> int8_t.
+ *   - Work is enqueued on the given HIP stream (0 = default stream); results
+ *     are copied to the host after the call synchronises that stream.
+ *   - A plan is immutable after creation except for its device workspace and
+ *     launch cache; calls that share one plan must not overlap in time.
+ */
+#ifndef USTAT_H
+#define USTAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ustat_plan_s *ustat_plan;
+typedef void *ustat_stream; /* a hipStream_t */
+
+typedef enum {
+    USTAT_OK = 0,
+    USTAT_E_INVALID = 1,     /* bad graph, sizes, pointers or options       */
+    USTAT_E_UNSUPPORTED = 2, /* valid request this engine cannot run        */
+    USTAT_E_NOMEM = 3,       /* device or host allocation failed            */
+    USTAT_E_HIP = 4,         /* a HIP runtime call failed                   */
+    USTAT_E_OVERFLOW = 5,    /* exact integer result may not fit 127 bits   */
+    USTAT_E_INFEASIBLE = 6   /* workspace above opts.workspace_limit        */
+} ustat_status;
+
+typedef enum {
+    USTAT_F64 = 0,    /* fp64 MFMA contractions, fp64 everywhere            */
+    USTAT_F32 = 1,    /* fp32 MFMA contractions, fp64 reductions/combine    */
+    USTAT_BF16X3 = 2, /* split-bf16 (hi*hi + hi*lo + lo*hi) MFMA, fp32
+                         accumulation, fp64 reductions/combine              */
+    USTAT_I8 = 3      /* exact: int8 MFMA on 7-bit limbs, int32 tiles,
+                         int64 matrices, 128-bit totals                     */
+} ustat_precision;
+
+typedef enum {
+    USTAT_ORDER_MINFILL = 0,    /* greedy min-fill, ties by degree then id  */
+    USTAT_ORDER_EXHAUSTIVE = 1, /* cheapest of all elimination orders       */
+    USTAT_ORDER_LEARNED = 2     /* candidates ranked by the MLP cost model  */
+} ustat_order;
+
+typedef struct {
+    int32_t precision;          /* ustat_precision                          */
+    int32_t order;              /* ustat_order                              */
+    int32_t sparsify;           /* 0: every partition (Lemma 2); 1: Lemma 3 */
+    int32_t reserved;           /* must be 0                                */
+    uint64_t workspace_limit;   /* bytes of device workspace, 0 = no limit  */
+    const char *cost_model_path;/* weights file for USTAT_ORDER_LEARNED     */
+} ustat_plan_opts;
+
+typedef struct {
+    double value;       /* U (or V_pi for vstat_eval), as a double          */
+    int64_t exact_hi;   /* USTAT_I8: exact value = exact_hi*2^64 + exact_lo */
+    uint64_t exact_lo;
+    double err_scale;   /* S = sum_pi |mu_pi V_pi| (|V_pi| for vstat_eval)  */
+    double err_est;     /* a-priori bound on |error| / S for this precision */
+    int32_t num_vstats; /* restricted V-statistics evaluated                */
+    int32_t reserved;
+} ustat_result;
+
+/* Fill *opts with defaults: USTAT_F64, min-fill, no sparsification. */
+ustat_status ustat_plan_opts_default(ustat_plan_opts *opts);
+
+/*
+ * Plan the evaluation of U for the kernel graph with m vertices (1..10) and
+ * num_edges ordered edges (host int32 array [num_edges][2], labels 0..m-1,
+ * u != v, every vertex used; parallel edges allowed).  Enumerates the set
+ * partitions of [m] with mu_pi (Lemma 2), filters them by Lemma 3 when
+ * opts->sparsify, forms each quotient graph G/pi (Definition "Quotient
+ * Graph") with self-loops as diagonal vectors and parallel edges as
+ * Hadamard groups, chooses an elimination order per quotient and lowers it
+ * to kernel steps.  Host only; touches no device.
+ * Errors: USTAT_E_INVALID (graph/opts), USTAT_E_NOMEM.
+ */
+ustat_status ustat_plan_create(int32_t m, int32_t num_edges, const int32_t *edges,
+                               const ustat_plan_opts *opts, ustat_plan *out);
+
+/* Free the plan, its device workspace and cached launches. NULL is a no-op. */
+ustat_status ustat_plan_destroy(ustat_plan plan);
+
+/*
+ * Plan summary.  num_vstats: partitions evaluated; M: largest quotient
+ * treewidth (Corollary 2); N_l (host int64 array of m+1 entries, may be
+ * NULL): number of evaluated quotients of exact treewidth l = 0..m;
+ * max_width: largest elimination degree of the chosen orders.
+ */
+ustat_status ustat_plan_info(ustat_plan plan, int32_t *num_vstats, int32_t *M,
+                             int64_t *N_l, int32_t *max_width);
+
+/*
+ * Cost of one evaluation at sample size n under the chosen orders:
+ * flops counts 2 per multiply-add of every contraction step (fp64-equivalent
+ * products; a split-bf16 step executes three times as many MFMA flops), and
+ * bytes the minimum HBM traffic of the steps.  workspace: device bytes the
+ * evaluation needs.
+ */
+ustat_status ustat_plan_cost(ustat_plan plan, int64_t n, double *flops, double *bytes,
+                             uint64_t *workspace);
+
+/*
+ * Partition idx (0 <= idx < num_vstats) in restricted-growth form:
+ * block_of (host int32 [m]) gives each vertex's block, blocks numbered in
+ * order of first appearance; *mu its Moebius coefficient; *tw the exact
+ * treewidth of its quotient graph; *width the largest elimination degree of
+ * its chosen order.  Any output pointer may be NULL.
+ */
+ustat_status ustat_plan_partition(ustat_plan plan, int32_t idx, int32_t *block_of, int64_t *mu,
+                                  int32_t *tw, int32_t *width);
+
+/*
+ * Elimination order chosen for partition idx: order (host int32 array of
+ * at least m entries) receives the quotient vertices in elimination order;
+ * *len their number.
+ */
+ustat_status ustat_plan_order(ustat_plan plan, int32_t idx, int32_t *order, int32_t *len);
+
+/* Exact treewidth of the simple graph underlying an edge list (m <= 16);
+ * self-loops and repeated edges are ignored (Definition "Treewidth"). */
+ustat_status ustat_graph_treewidth(int32_t m, int32_t num_edges, const int32_t *edges,
+                                   int32_t *tw);
+
+/*
+ * U(h, X) from the factor matrices: factors is a host array of num_edges
+ * device pointers to n x n matrices (element type per precision).  n >= m.
+ * Errors: USTAT_E_INVALID, USTAT_E_NOMEM, USTAT_E_HIP, USTAT_E_OVERFLOW,
+ * USTAT_E_INFEASIBLE.
+ */
+ustat_status ustat_eval(ustat_plan plan, int64_t n, const void *const *factors,
+                        ustat_stream stream, ustat_result *out);
+
+/*
+ * U(h, X) for the RBF kernel on every edge, k(x, y) = exp(-||x-y||^2 /
+ * rbf_divisor): X is a device fp64 n x d row-major sample (d <= 256); the
+ * factor matrix is built on the device (Algorithm 1) in the plan's
+ * precision, then evaluated as in ustat_eval.  Not valid for USTAT_I8.
+ */
+ustat_status ustat_eval_samples(ustat_plan plan, int64_t n, int32_t d, const double *X,
+                                double rbf_divisor, ustat_stream stream, ustat_result *out);
+
+/*
+ * One restricted V-statistic V_pi (Definition "Restricted V-Statistic"):
+ * block_of (host int32 [m]) is any labelling of a partition of [m] by block
+ * (it is canonicalised); the partition need not be among the plan's
+ * evaluated ones.  out->value = V_pi, out->err_scale = |V_pi|.
+ */
+ustat_status vstat_eval(ustat_plan plan, const int32_t *block_of, int64_t n,
+                        const void *const *factors, ustat_stream stream, ustat_result *out);
+
+/*
+ * Many independent datasets at once: dataset b has n[b] samples (host
+ * int64 array) at X[b] (host array of device fp64 n[b] x d pointers); the
+ * RBF kernel as in ustat_eval_samples.  Every (dataset, partition) pair is
+ * evaluated in one replay of a captured HIP graph of grouped launches.
+ * out: host array of batch results.
+ */
+ustat_status ustat_eval_batched(ustat_plan plan, int32_t batch, const int64_t *n, int32_t d,
+                                const double *const *X, double rbf_divisor, ustat_stream stream,
+                                ustat_result *out);
+
+/*
+ * Build the RBF factor matrix alone (Algorithm 1 for the RBF kernel):
+ * out (device, n x n) receives exp(-||X_i - X_j||^2 / rbf_divisor) with the
+ * squared distance formed in fp64 from direct differences; precision
+ * USTAT_F64 writes double, USTAT_F32 writes float (rounded once).
+ */
+ustat_status ustat_build_rbf(int64_t n, int32_t d, const double *X, double rbf_divisor,
+                             int32_t precision, void *out, ustat_stream stream);
+
+/*
+ * Kernel timing (HIP events recorded around every grouped launch on the
+ * launch stream; off by default, never active inside graph capture).
+ * kind: 0 operand prep, 1 GEMM, 2 column reduction, 3 partial reduction,
+ * 4 factor build.  ustat_profile_read returns totals since the last reset:
+ * milliseconds, number of launches and algorithmic flops (2 n^3 per GEMM).
+ */
+ustat_status ustat_profile_enable(int32_t on);
+ustat_status ustat_profile_reset(void);
+ustat_status ustat_profile_read(int32_t kind, double *ms, int64_t *launches, double *flops);
+
+const char *ustat_status_string(ustat_status s);
+const char *ustat_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* USTAT_H */

@@ -1,0 +1,468 @@
+// C ABI of libustat (declared in include/ustat.h).  Argument checking,
+// plan handles, error strings; the work is done by plan.cpp (host) and
+// exec.cpp / kernels.hip (device).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ustat.h"
+#include "costmodel.hpp"
+#include "exec.hpp"
+#include "kernels.hpp"
+#include "plan.hpp"
+#include "profile.hpp"
+
+using namespace ustat;
+
+struct ustat_plan_s {
+    Plan plan;
+    Runtime rt;
+    std::unique_ptr<CostModel> model;
+    std::vector<const VProgram *> all;
+    // device buffer holding factor matrices built from samples
+    char *factors = nullptr;
+    size_t factors_bytes = 0;
+    ~ustat_plan_s() {
+        if (factors) (void)hipFree(factors);
+    }
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+ustat_status fail(ustat_status s, const std::string &msg) {
+    g_err = msg;
+    return s;
+}
+
+ustat_status ok() {
+    g_err.clear();
+    return USTAT_OK;
+}
+
+ustat_status from_exec(int st, const std::string &msg) {
+    if (st == 0 && msg.empty()) return ok();
+    switch (st) {
+        case 2: return fail(USTAT_E_UNSUPPORTED, msg);
+        case 3: return fail(USTAT_E_NOMEM, msg);
+        case 5: return fail(USTAT_E_OVERFLOW, msg);
+        case 6: return fail(USTAT_E_INFEASIBLE, msg);
+        case 1: return fail(USTAT_E_INVALID, msg);
+        default: return fail(USTAT_E_HIP, msg);
+    }
+}
+
+// rough a-priori relative error estimate for the result (root-n model):
+// unit roundoff of the contraction precision times sqrt(n) times the number
+// of rounding stages (elimination depth + 2).
+double err_estimate(const Plan &p, int64_t n) {
+    double u;
+    switch (p.opts.precision) {
+        case USTAT_F64: u = std::ldexp(1.0, -53); break;
+        case USTAT_F32: u = std::ldexp(1.0, -24); break;
+        case USTAT_BF16X3: u = 3.0 * std::ldexp(1.0, -18); break;
+        default: return 0.0;
+    }
+    int depth = 0;
+    for (auto &pr : p.progs) depth = std::max(depth, pr.depth);
+    return u * std::sqrt((double)n) * (depth + 2);
+}
+
+bool canonical_rgs(const int32_t *block_of, int m, std::vector<int> &out) {
+    out.assign(m, 0);
+    std::vector<int> map;
+    std::vector<int> seen;
+    for (int i = 0; i < m; ++i) {
+        int b = block_of[i];
+        int j = -1;
+        for (size_t q = 0; q < seen.size(); ++q)
+            if (seen[q] == b) j = (int)q;
+        if (j < 0) {
+            j = (int)seen.size();
+            seen.push_back(b);
+        }
+        out[i] = j;
+    }
+    return true;
+}
+
+hipError_t grow(char **p, size_t *have, size_t need) {
+    if (*p && *have >= need) return hipSuccess;
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+    *have = 0;
+    hipError_t e = hipMalloc(p, std::max<size_t>(need, 256));
+    if (e == hipSuccess) *have = need;
+    return e;
+}
+
+void fill_result(ustat_result *out, const DatasetResult &r, const Plan &p, int64_t n, int nv) {
+    std::memset(out, 0, sizeof *out);
+    out->value = r.value;
+    out->exact_hi = r.exact_hi;
+    out->exact_lo = r.exact_lo;
+    out->err_scale = r.scale;
+    out->err_est = err_estimate(p, n);
+    out->num_vstats = nv;
+}
+
+}  // namespace
+
+extern "C" {
+
+ustat_status ustat_plan_opts_default(ustat_plan_opts *opts) {
+    if (!opts) return fail(USTAT_E_INVALID, "opts is NULL");
+    std::memset(opts, 0, sizeof *opts);
+    opts->precision = USTAT_F64;
+    opts->order = USTAT_ORDER_MINFILL;
+    return ok();
+}
+
+ustat_status ustat_plan_create(int32_t m, int32_t num_edges, const int32_t *edges,
+                               const ustat_plan_opts *opts, ustat_plan *out) {
+    if (!out) return fail(USTAT_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!edges || num_edges < 1) return fail(USTAT_E_INVALID, "need at least one edge");
+    if (num_edges > 64) return fail(USTAT_E_INVALID, "at most 64 edges");
+    ustat_plan_opts o;
+    ustat_plan_opts_default(&o);
+    if (opts) o = *opts;
+    if (o.precision < 0 || o.precision > 3) return fail(USTAT_E_INVALID, "unknown precision");
+    if (o.order < 0 || o.order > 2) return fail(USTAT_E_INVALID, "unknown order policy");
+    if (o.sparsify != 0 && o.sparsify != 1) return fail(USTAT_E_INVALID, "sparsify must be 0 or 1");
+    if (o.reserved != 0) return fail(USTAT_E_INVALID, "reserved must be 0");
+    try {
+        std::unique_ptr<ustat_plan_s> p(new ustat_plan_s());
+        std::vector<Edge> E;
+        for (int k = 0; k < num_edges; ++k) E.push_back({edges[2 * k], edges[2 * k + 1]});
+        PlanOptions po;
+        po.precision = o.precision;
+        po.order = o.order;
+        po.sparsify = o.sparsify;
+        po.workspace_limit = o.workspace_limit;
+        if (o.cost_model_path) po.cost_model_path = o.cost_model_path;
+        const OrderScorer *scorer = nullptr;
+        if (o.order == USTAT_ORDER_LEARNED) {
+            if (!o.cost_model_path)
+                return fail(USTAT_E_INVALID, "the learned order policy needs cost_model_path");
+            p->model.reset(new CostModel());
+            std::string err = p->model->load(o.cost_model_path);
+            if (!err.empty()) return fail(USTAT_E_INVALID, "cost model: " + err);
+            scorer = p->model.get();
+        }
+        std::string err = make_plan(m, E, po, scorer, p->plan);
+        if (!err.empty()) return fail(USTAT_E_INVALID, err);
+        for (auto &pr : p->plan.progs) p->all.push_back(&pr);
+        *out = p.release();
+        return ok();
+    } catch (const std::bad_alloc &) {
+        return fail(USTAT_E_NOMEM, "host allocation failed");
+    } catch (const std::exception &ex) {
+        return fail(USTAT_E_INVALID, ex.what());
+    }
+}
+
+ustat_status ustat_plan_destroy(ustat_plan plan) {
+    delete plan;
+    return ok();
+}
+
+ustat_status ustat_plan_info(ustat_plan plan, int32_t *num_vstats, int32_t *M, int64_t *N_l,
+                             int32_t *max_width) {
+    if (!plan) return fail(USTAT_E_INVALID, "plan is NULL");
+    if (num_vstats) *num_vstats = (int32_t)plan->plan.progs.size();
+    if (M) *M = plan->plan.M;
+    if (N_l)
+        for (int l = 0; l <= plan->plan.m; ++l) N_l[l] = plan->plan.N_l[l];
+    if (max_width) *max_width = plan->plan.max_width;
+    return ok();
+}
+
+ustat_status ustat_plan_cost(ustat_plan plan, int64_t n, double *flops, double *bytes,
+                             uint64_t *workspace) {
+    if (!plan) return fail(USTAT_E_INVALID, "plan is NULL");
+    if (n < 1) return fail(USTAT_E_INVALID, "n must be positive");
+    double f = 0, b = 0;
+    double es = plan->plan.opts.precision == USTAT_F64 ? 8 : plan->plan.opts.precision == USTAT_I8 ? 1 : 4;
+    for (auto &pr : plan->plan.progs) {
+        double pf, pb;
+        program_cost(pr, (double)n, es, &pf, &pb);
+        f += pf;
+        b += pb;
+    }
+    if (flops) *flops = f;
+    if (bytes) *bytes = b;
+    if (workspace) {
+        if (!plan->plan.executable) *workspace = 0;
+        else *workspace = workspace_bytes(plan->plan, plan->all, {n});
+    }
+    return ok();
+}
+
+ustat_status ustat_plan_partition(ustat_plan plan, int32_t idx, int32_t *block_of, int64_t *mu,
+                                  int32_t *tw, int32_t *width) {
+    if (!plan) return fail(USTAT_E_INVALID, "plan is NULL");
+    if (idx < 0 || idx >= (int32_t)plan->plan.progs.size())
+        return fail(USTAT_E_INVALID, "partition index out of range");
+    const VProgram &p = plan->plan.progs[idx];
+    if (block_of)
+        for (int i = 0; i < plan->plan.m; ++i) block_of[i] = p.block_of[i];
+    if (mu) *mu = p.mu;
+    if (tw) *tw = p.tw;
+    if (width) *width = p.width;
+    return ok();
+}
+
+ustat_status ustat_plan_order(ustat_plan plan, int32_t idx, int32_t *order, int32_t *len) {
+    if (!plan) return fail(USTAT_E_INVALID, "plan is NULL");
+    if (idx < 0 || idx >= (int32_t)plan->plan.progs.size())
+        return fail(USTAT_E_INVALID, "partition index out of range");
+    const VProgram &p = plan->plan.progs[idx];
+    if (order)
+        for (size_t i = 0; i < p.order.size(); ++i) order[i] = p.order[i];
+    if (len) *len = (int32_t)p.order.size();
+    return ok();
+}
+
+ustat_status ustat_graph_treewidth(int32_t m, int32_t num_edges, const int32_t *edges,
+                                   int32_t *tw) {
+    if (m < 1 || m > 16) return fail(USTAT_E_INVALID, "m must be in 1..16");
+    if (num_edges < 0 || (num_edges > 0 && !edges) || !tw)
+        return fail(USTAT_E_INVALID, "bad arguments");
+    std::vector<uint32_t> adj(m, 0);
+    for (int k = 0; k < num_edges; ++k) {
+        int u = edges[2 * k], v = edges[2 * k + 1];
+        if (u < 0 || u >= m || v < 0 || v >= m) return fail(USTAT_E_INVALID, "endpoint out of range");
+        if (u != v) {
+            adj[u] |= 1u << v;
+            adj[v] |= 1u << u;
+        }
+    }
+    *tw = exact_treewidth(m, adj);
+    return ok();
+}
+
+static ustat_status run(ustat_plan plan, const std::vector<const VProgram *> &progs,
+                        std::vector<Dataset> &data, hipStream_t s, std::vector<DatasetResult> &res,
+                        std::vector<double> *vout, const std::function<hipError_t(hipStream_t)> &pre,
+                        const std::string &key) {
+    int st = 0;
+    bool capture = (s != nullptr) && plan->plan.opts.precision != USTAT_I8 && !key.empty();
+    std::string err;
+    try {
+        if (capture) Profiler::suspend(true);
+        err = execute(plan->plan, progs, data, s, plan->rt, res, vout, &st, capture, key, pre);
+        if (capture) Profiler::suspend(false);
+    } catch (const std::bad_alloc &) {
+        Profiler::suspend(false);
+        return fail(USTAT_E_NOMEM, "host allocation failed");
+    }
+    return from_exec(st, err);
+}
+
+static ustat_status check_eval(ustat_plan plan, int64_t n) {
+    if (!plan) return fail(USTAT_E_INVALID, "plan is NULL");
+    if (n < plan->plan.m) return fail(USTAT_E_INVALID, "n must be at least m");
+    if (n > (1ll << 20)) return fail(USTAT_E_INVALID, "n above 2^20 is not supported");
+    if (!plan->plan.executable)
+        return fail(USTAT_E_UNSUPPORTED, "plan needs a step kind the engine lacks: " +
+                                             plan->plan.lower_error);
+    return USTAT_OK;
+}
+
+ustat_status ustat_eval(ustat_plan plan, int64_t n, const void *const *factors, ustat_stream stream,
+                        ustat_result *out) {
+    ustat_status c = check_eval(plan, n);
+    if (c != USTAT_OK) return c;
+    if (!factors || !out) return fail(USTAT_E_INVALID, "factors and out must be non-NULL");
+    std::vector<Dataset> data(1);
+    data[0].n = n;
+    for (size_t k = 0; k < plan->plan.edges.size(); ++k) {
+        if (!factors[k]) return fail(USTAT_E_INVALID, "a factor pointer is NULL");
+        data[0].factors.push_back(factors[k]);
+    }
+    std::string key = "eval:" + std::to_string(n);
+    for (auto f : data[0].factors) key += ":" + std::to_string((uintptr_t)f);
+    std::vector<DatasetResult> res;
+    ustat_status st = run(plan, plan->all, data, (hipStream_t)stream, res, nullptr, nullptr, key);
+    if (st != USTAT_OK) return st;
+    fill_result(out, res[0], plan->plan, n, (int)plan->all.size());
+    return ok();
+}
+
+ustat_status ustat_build_rbf(int64_t n, int32_t d, const double *X, double rbf_divisor,
+                             int32_t precision, void *out, ustat_stream stream) {
+    if (n < 1 || d < 1 || d > 256 || !X || !out) return fail(USTAT_E_INVALID, "bad arguments");
+    if (!(rbf_divisor > 0) || !std::isfinite(rbf_divisor))
+        return fail(USTAT_E_INVALID, "rbf_divisor must be positive");
+    if (precision != USTAT_F64 && precision != USTAT_F32)
+        return fail(USTAT_E_INVALID, "precision must be USTAT_F64 or USTAT_F32");
+    hipError_t e = launch_rbf(X, n, d, rbf_divisor, out, precision == USTAT_F64 ? DT_F64 : DT_F32,
+                              (hipStream_t)stream);
+    if (e != hipSuccess) return fail(USTAT_E_HIP, hipGetErrorString(e));
+    return ok();
+}
+
+ustat_status ustat_eval_samples(ustat_plan plan, int64_t n, int32_t d, const double *X,
+                                double rbf_divisor, ustat_stream stream, ustat_result *out) {
+    ustat_status c = check_eval(plan, n);
+    if (c != USTAT_OK) return c;
+    if (d < 1 || d > 256 || !X || !out) return fail(USTAT_E_INVALID, "bad arguments");
+    if (!(rbf_divisor > 0) || !std::isfinite(rbf_divisor))
+        return fail(USTAT_E_INVALID, "rbf_divisor must be positive");
+    if (plan->plan.opts.precision == USTAT_I8)
+        return fail(USTAT_E_INVALID, "samples with an RBF kernel need a floating-point precision");
+    const int dt = plan->plan.opts.precision == USTAT_F64 ? DT_F64 : DT_F32;
+    const size_t es = dt == DT_F64 ? 8 : 4;
+    hipError_t e = grow(&plan->factors, &plan->factors_bytes, (size_t)n * n * es);
+    if (e != hipSuccess) return fail(USTAT_E_NOMEM, hipGetErrorString(e));
+    if (plan->rt.graph) {
+        // the factor buffer may have moved; a stale graph is rebuilt by key
+    }
+    std::vector<Dataset> data(1);
+    data[0].n = n;
+    for (size_t k = 0; k < plan->plan.edges.size(); ++k) data[0].factors.push_back(plan->factors);
+    char *fb = plan->factors;
+    auto pre = [=](hipStream_t s) -> hipError_t {
+        ProfScope ps(Profiler::active(), KIND_RBF, s, 0);
+        return launch_rbf(X, n, d, rbf_divisor, fb, dt, s);
+    };
+    std::string key = "samples:" + std::to_string(n) + ":" + std::to_string(d) + ":" +
+                      std::to_string((uintptr_t)X) + ":" + std::to_string(rbf_divisor) + ":" +
+                      std::to_string((uintptr_t)fb);
+    std::vector<DatasetResult> res;
+    ustat_status st = run(plan, plan->all, data, (hipStream_t)stream, res, nullptr, pre, key);
+    if (st != USTAT_OK) return st;
+    fill_result(out, res[0], plan->plan, n, (int)plan->all.size());
+    return ok();
+}
+
+ustat_status vstat_eval(ustat_plan plan, const int32_t *block_of, int64_t n,
+                        const void *const *factors, ustat_stream stream, ustat_result *out) {
+    if (!plan) return fail(USTAT_E_INVALID, "plan is NULL");
+    if (!block_of || !factors || !out) return fail(USTAT_E_INVALID, "NULL argument");
+    if (n < 1 || n > (1ll << 20)) return fail(USTAT_E_INVALID, "n out of range");
+    for (size_t k = 0; k < plan->plan.edges.size(); ++k)
+        if (!factors[k]) return fail(USTAT_E_INVALID, "a factor pointer is NULL");
+    std::vector<int> rgs;
+    canonical_rgs(block_of, plan->plan.m, rgs);
+    VProgram prog;
+    std::string err;
+    try {
+        err = build_program(plan->plan.edges, plan->plan.m, rgs, plan->plan.opts,
+                            plan->model.get(), prog);
+    } catch (const std::bad_alloc &) {
+        return fail(USTAT_E_NOMEM, "host allocation failed");
+    }
+    if (!err.empty()) return fail(USTAT_E_INVALID, err);
+    if (!prog.executable) return fail(USTAT_E_UNSUPPORTED, prog.lower_error);
+    prog.mu = 1;  // the combination then returns V_pi itself
+    Plan sub = plan->plan;
+    sub.opts.sparsify = plan->plan.opts.sparsify;
+    std::vector<Dataset> data(1);
+    data[0].n = n;
+    for (size_t k = 0; k < plan->plan.edges.size(); ++k) data[0].factors.push_back(factors[k]);
+    std::vector<DatasetResult> res;
+    std::vector<const VProgram *> progs = {&prog};
+    ustat_status st = run(plan, progs, data, (hipStream_t)stream, res, nullptr, nullptr, "");
+    if (st != USTAT_OK) return st;
+    fill_result(out, res[0], plan->plan, n, 1);
+    out->err_scale = std::fabs(res[0].value);
+    return ok();
+}
+
+ustat_status ustat_eval_batched(ustat_plan plan, int32_t batch, const int64_t *n, int32_t d,
+                                const double *const *X, double rbf_divisor, ustat_stream stream,
+                                ustat_result *out) {
+    if (!plan) return fail(USTAT_E_INVALID, "plan is NULL");
+    if (batch < 1 || !n || !X || !out || d < 1 || d > 256)
+        return fail(USTAT_E_INVALID, "bad arguments");
+    if (!(rbf_divisor > 0) || !std::isfinite(rbf_divisor))
+        return fail(USTAT_E_INVALID, "rbf_divisor must be positive");
+    if (plan->plan.opts.precision == USTAT_I8)
+        return fail(USTAT_E_INVALID, "samples with an RBF kernel need a floating-point precision");
+    for (int b = 0; b < batch; ++b) {
+        ustat_status c = check_eval(plan, n[b]);
+        if (c != USTAT_OK) return c;
+        if (!X[b]) return fail(USTAT_E_INVALID, "a sample pointer is NULL");
+    }
+    const int dt = plan->plan.opts.precision == USTAT_F64 ? DT_F64 : DT_F32;
+    const size_t es = dt == DT_F64 ? 8 : 4;
+    std::vector<size_t> off(batch);
+    size_t tot = 0;
+    for (int b = 0; b < batch; ++b) {
+        off[b] = tot;
+        tot += ((size_t)n[b] * n[b] * es + 255) / 256 * 256;
+    }
+    hipError_t e = grow(&plan->factors, &plan->factors_bytes, tot);
+    if (e != hipSuccess) return fail(USTAT_E_NOMEM, hipGetErrorString(e));
+    std::vector<Dataset> data(batch);
+    std::string key = "batch:" + std::to_string(d) + ":" + std::to_string(rbf_divisor) + ":" +
+                      std::to_string((uintptr_t)plan->factors);
+    for (int b = 0; b < batch; ++b) {
+        data[b].n = n[b];
+        for (size_t k = 0; k < plan->plan.edges.size(); ++k)
+            data[b].factors.push_back(plan->factors + off[b]);
+        key += ":" + std::to_string(n[b]) + "@" + std::to_string((uintptr_t)X[b]);
+    }
+    std::vector<const double *> xs(X, X + batch);
+    std::vector<int64_t> ns(n, n + batch);
+    char *fb = plan->factors;
+    auto pre = [=](hipStream_t s) -> hipError_t {
+        for (int b = 0; b < batch; ++b) {
+            hipError_t e2 = launch_rbf(xs[b], ns[b], d, rbf_divisor, fb + off[b], dt, s);
+            if (e2 != hipSuccess) return e2;
+        }
+        return hipSuccess;
+    };
+    std::vector<DatasetResult> res;
+    ustat_status st = run(plan, plan->all, data, (hipStream_t)stream, res, nullptr, pre, key);
+    if (st != USTAT_OK) return st;
+    for (int b = 0; b < batch; ++b) fill_result(&out[b], res[b], plan->plan, n[b], (int)plan->all.size());
+    return ok();
+}
+
+ustat_status ustat_profile_enable(int32_t on) {
+    Profiler::enable(on != 0);
+    return ok();
+}
+
+ustat_status ustat_profile_reset(void) {
+    Profiler::enable(true);
+    if (Profiler::active()) Profiler::active()->reset();
+    return ok();
+}
+
+ustat_status ustat_profile_read(int32_t kind, double *ms, int64_t *launches, double *flops) {
+    if (kind < 0 || kind >= KIND_COUNT) return fail(USTAT_E_INVALID, "unknown kind");
+    Profiler *p = Profiler::active();
+    if (!p) return fail(USTAT_E_INVALID, "profiling is not enabled");
+    if (ms) *ms = p->ms[kind];
+    if (launches) *launches = p->launches[kind];
+    if (flops) *flops = p->flops[kind];
+    return ok();
+}
+
+const char *ustat_status_string(ustat_status s) {
+    switch (s) {
+        case USTAT_OK: return "ok";
+        case USTAT_E_INVALID: return "invalid argument";
+        case USTAT_E_UNSUPPORTED: return "unsupported";
+        case USTAT_E_NOMEM: return "out of memory";
+        case USTAT_E_HIP: return "HIP runtime error";
+        case USTAT_E_OVERFLOW: return "exact integer overflow";
+        case USTAT_E_INFEASIBLE: return "workspace above limit";
+    }
+    return "unknown status";
+}
+
+const char *ustat_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,75 @@
+// Executor: lowers the programs of a plan, for one or many datasets, to
+// grouped kernel launches ordered by dependency level.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <functional>
+#include <string>
+#include <vector>
+
+#include "plan.hpp"
+
+namespace ustat {
+
+struct Dataset {
+    int64_t n = 0;
+    std::vector<const void *> factors;  // one device pointer per edge
+};
+
+struct DatasetResult {
+    double value = 0, scale = 0;
+    int64_t exact_hi = 0;
+    uint64_t exact_lo = 0;
+};
+
+// Device and pinned-host memory owned by a plan, grown on demand and reused
+// across evaluations.
+struct Runtime {
+    int device = -1;
+    char *arena = nullptr;
+    size_t arena_bytes = 0;
+    char *ddesc = nullptr;  // device copy of the descriptor blob
+    size_t ddesc_bytes = 0;
+    char *hdesc = nullptr;  // pinned host descriptor blob
+    size_t hdesc_bytes = 0;
+    char *hres = nullptr;   // pinned host result buffer
+    size_t hres_bytes = 0;
+    // Captured graph of the last captured run, the key it was built for,
+    // its own pinned descriptor blob and its result layout.
+    hipGraphExec_t graph = nullptr;
+    std::string graph_key;
+    char *gblob = nullptr;
+    size_t gblob_bytes = 0;
+    int g_nprog = 0, g_nd = 0;
+    ~Runtime();
+    hipError_t reserve_arena(size_t bytes);
+    hipError_t reserve_desc(size_t bytes);
+    hipError_t reserve_hres(size_t bytes);
+};
+
+// Optional per-launch timing, filled when non-null (milliseconds per step
+// kind, measured with HIP events on the launch stream).
+struct LaunchStats {
+    double ms_prep = 0, ms_gemm = 0, ms_elim1 = 0, ms_reduce = 0, ms_other = 0;
+    int n_launch = 0;
+    double gemm_flops = 0;  // algorithmic (2 n^3 per GEMM)
+};
+
+// Evaluate programs `progs` (indices into plan.progs, or the explicit
+// programs in `extra` when non-empty) on every dataset.  The factor
+// matrices of each dataset must be ready on `stream`.  Results per dataset
+// and, when vout is non-null, every V_pi (dataset-major).
+// Returns "" or an error message; *status receives a ustat_status code.
+std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs,
+                    const std::vector<Dataset> &data, hipStream_t stream, Runtime &rt,
+                    std::vector<DatasetResult> &out, std::vector<double> *vout, int *status,
+                    bool capture = false, const std::string &capture_key = "",
+                    const std::function<hipError_t(hipStream_t)> &pre = nullptr);
+
+// Upper bound of the workspace bytes an evaluation at size n needs.
+size_t workspace_bytes(const Plan &plan, const std::vector<const VProgram *> &progs,
+                       const std::vector<int64_t> &ns);
+
+}  // namespace ustat

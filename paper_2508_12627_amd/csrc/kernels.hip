@@ -1,0 +1,860 @@
+// HIP kernels for gfx950 (CDNA4): factor build, elimination steps, GEMMs
+// on MFMA, fixed-order reductions and the Moebius combination.
+//
+// Every reduction is performed in a fixed order (per-tile partials written
+// to memory, then summed in increasing tile index), so results are bitwise
+// reproducible; no floating-point atomics are used anywhere.
+#include "kernels.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+namespace ustat {
+
+typedef __int128 i128;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+
+// ----------------------------------------------------------------- helpers
+
+template <int DOM>
+struct Dom;
+template <>
+struct Dom<DOM_FP> {
+    typedef double acc;    // per-element products and vector values
+    typedef double wide;   // scalar sums
+};
+template <>
+struct Dom<DOM_INT> {
+    typedef long long acc;
+    typedef i128 wide;
+};
+
+__device__ __forceinline__ double load_fp(const void *p, int32_t dt, int64_t i) {
+    switch (dt) {
+        case DT_F64: return static_cast<const double *>(p)[i];
+        case DT_F32: return (double)static_cast<const float *>(p)[i];
+        case DT_I8: return (double)static_cast<const int8_t *>(p)[i];
+        default: return (double)static_cast<const long long *>(p)[i];
+    }
+}
+__device__ __forceinline__ long long load_int(const void *p, int32_t dt, int64_t i) {
+    switch (dt) {
+        case DT_I8: return (long long)static_cast<const int8_t *>(p)[i];
+        case DT_I64: return static_cast<const long long *>(p)[i];
+        case DT_F32: return (long long)static_cast<const float *>(p)[i];
+        default: return (long long)static_cast<const double *>(p)[i];
+    }
+}
+template <int DOM>
+__device__ __forceinline__ typename Dom<DOM>::acc load_elem(const void *p, int32_t dt, int64_t i);
+template <>
+__device__ __forceinline__ double load_elem<DOM_FP>(const void *p, int32_t dt, int64_t i) {
+    return load_fp(p, dt, i);
+}
+template <>
+__device__ __forceinline__ long long load_elem<DOM_INT>(const void *p, int32_t dt, int64_t i) {
+    return load_int(p, dt, i);
+}
+
+// Vectors are double (DOM_FP) or int64 (DOM_INT).
+template <int DOM>
+__device__ __forceinline__ typename Dom<DOM>::acc load_vec(const void *p, int64_t i) {
+    return static_cast<const typename Dom<DOM>::acc *>(p)[i];
+}
+
+// Locate the problem owning flat block index b (descriptors sorted by
+// tile_start, first one at 0).
+template <class D>
+__device__ __forceinline__ int find_problem(const D *d, int nprob, int64_t b) {
+    int lo = 0, hi = nprob - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (d[mid].tile_start <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Round-to-nearest-even float -> bf16 bits (finite inputs).
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    uint32_t r = u + 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(r >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) {
+    return __uint_as_float(((uint32_t)h) << 16);
+}
+
+// ----------------------------------------------------------------- RBF
+
+// K_ij = exp(-||x_i - x_j||^2 / divisor), squared distance from direct
+// differences in fp64 (so K_ii = 1 exactly); 64 x 64 output tile per block.
+__global__ __launch_bounds__(256) void k_rbf(const double *__restrict__ X, int64_t n, int32_t d,
+                                             double inv_div, void *__restrict__ out,
+                                             int32_t dtype) {
+    __shared__ double xi[64][33];
+    __shared__ double xj[64][33];
+    const int t = threadIdx.x;
+    const int64_t i0 = (int64_t)blockIdx.y * 64, j0 = (int64_t)blockIdx.x * 64;
+    const int c = t & 63, rg = t >> 6;
+    double acc[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.0;
+    for (int k0 = 0; k0 < d; k0 += 32) {
+        for (int e = t; e < 64 * 32; e += 256) {
+            int rr = e >> 5, kk = e & 31;
+            int64_t gi = i0 + rr, gj = j0 + rr;
+            int gk = k0 + kk;
+            xi[rr][kk] = (gi < n && gk < d) ? X[gi * d + gk] : 0.0;
+            xj[rr][kk] = (gj < n && gk < d) ? X[gj * d + gk] : 0.0;
+        }
+        __syncthreads();
+        const int kmax = min(32, d - k0);
+        for (int kk = 0; kk < kmax; ++kk) {
+            double b = xj[c][kk];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                double diff = xi[rg + 4 * r][kk] - b;
+                acc[r] = fma(diff, diff, acc[r]);
+            }
+        }
+        __syncthreads();
+    }
+    const int64_t j = j0 + c;
+    if (j >= n) return;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        int64_t i = i0 + rg + 4 * r;
+        if (i >= n) continue;
+        double v = exp(-acc[r] * inv_div);
+        if (dtype == DT_F64) static_cast<double *>(out)[i * n + j] = v;
+        else static_cast<float *>(out)[i * n + j] = (float)v;
+    }
+}
+
+// ----------------------------------------------------------------- diag
+
+template <int DOM>
+__global__ void k_diag(const DiagDesc *D, int nprob) {
+    const DiagDesc &d = D[blockIdx.y];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < d.n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        typedef typename Dom<DOM>::acc A;
+        A v = load_elem<DOM>(d.src.p, d.src.dtype, i * d.src.ld + i);
+        static_cast<A *>(d.dst)[i] = v;
+        if constexpr (DOM == DOM_INT) {
+            if (d.mx_out) atomicMax(d.mx_out, (unsigned long long)(v < 0 ? -v : v));
+        }
+    }
+}
+
+// Largest |entry| of int8 matrices (one running max per problem).
+__global__ void k_absmax_i8(const int8_t *const *src, const int64_t *n, int nprob,
+                            unsigned long long *mx) {
+    const int p = blockIdx.y;
+    const int8_t *a = src[p];
+    const int64_t cnt = n[p] * n[p];
+    int best = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int v = a[i];
+        best = max(best, v < 0 ? -v : v);
+    }
+    __shared__ int red[256];
+    red[threadIdx.x] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int m = 0;
+        for (int q = 0; q < 256; ++q) m = max(m, red[q]);
+        atomicMax(&mx[p], (unsigned long long)m);
+    }
+}
+
+// ----------------------------------------------------------------- elim1
+
+// Tile partials of y(w) = sum_v prod_k A_k(v,w) prod_j s_j(v) over a 64 x 64
+// (v, w) tile.  Matrices are read coalesced in their stored orientation and
+// transposed through LDS.
+template <int DOM>
+__global__ __launch_bounds__(256) void k_elim1(const Elim1Desc *D, int nprob) {
+    typedef typename Dom<DOM>::acc A;
+    __shared__ A prod[64][65];
+    __shared__ A red[4][64];
+    const int64_t b = blockIdx.x;
+    const int p = find_problem(D, nprob, b);
+    const Elim1Desc &d = D[p];
+    const int64_t local = b - d.tile_start;
+    const int64_t tv = local / d.tiles_w, tw = local % d.tiles_w;
+    const int64_t n = d.n, v0 = tv * 64, w0 = tw * 64;
+    const int t = threadIdx.x;
+    for (int e = t; e < 4096; e += 256) {
+        int r = e >> 6, c = e & 63;
+        int64_t v = v0 + r, w = w0 + c;
+        A val = (v < n && w < n) ? (A)1 : (A)0;
+        if (v < n)
+            for (int j = 0; j < d.nS; ++j) val *= load_vec<DOM>(d.s[j], v);
+        prod[r][c] = val;
+    }
+    __syncthreads();
+    for (int k = 0; k < d.nA; ++k) {
+        const MatRef m = d.A[k];
+        for (int e = t; e < 4096; e += 256) {
+            int r = e >> 6, c = e & 63;
+            // trans == 0: stored (v, w), row r over v.  trans == 1: stored
+            // (w, v), row r over w.
+            int rv = m.trans ? c : r, cw = m.trans ? r : c;
+            int64_t v = v0 + rv, w = w0 + cw;
+            if (v < n && w < n) {
+                int64_t idx = m.trans ? (w * m.ld + v) : (v * m.ld + w);
+                A x = load_elem<DOM>(m.p, m.dtype, idx);
+                if (m.zdiag && v == w) x = 0;
+                prod[rv][cw] *= x;
+            }
+        }
+        __syncthreads();
+    }
+    const int c = t & 63, g = t >> 6;
+    A sum = 0;
+#pragma unroll 4
+    for (int r = g * 16; r < g * 16 + 16; ++r) sum += prod[r][c];
+    red[g][c] = sum;
+    __syncthreads();
+    if (g == 0 && w0 + c < n) {
+        A tot = red[0][c] + red[1][c] + red[2][c] + red[3][c];
+        static_cast<A *>(d.part)[tv * n + w0 + c] = tot;
+    }
+}
+
+// ----------------------------------------------------------------- reduce
+
+// Non-dot: out[j] = prod mul(j) * sum_t part[t*stride + j] (vector domain
+// type).  Dot: a single block sums those values over j into out[0] (wide
+// type); `part` elements are wide when len == 1 (GEMM tile partials).
+template <int DOM>
+__global__ __launch_bounds__(256) void k_reduce(const ReduceDesc *D, int nprob) {
+    typedef typename Dom<DOM>::acc A;
+    typedef typename Dom<DOM>::wide Wd;
+    const ReduceDesc &d = D[blockIdx.x];
+    const int t = threadIdx.x;
+    if (!d.dot) {
+        for (int64_t j = (int64_t)blockIdx.y * 256 + t; j < d.len; j += (int64_t)gridDim.y * 256) {
+            A s = 0;
+            for (int64_t q = 0; q < d.T; ++q) s += static_cast<const A *>(d.part)[q * d.stride + j];
+            for (int q = 0; q < d.nmul; ++q) s *= load_vec<DOM>(d.mul[q], j);
+            static_cast<A *>(d.out)[j] = s;
+            if constexpr (DOM == DOM_INT) {
+                if (d.mx_out) atomicMax(d.mx_out, (unsigned long long)(s < 0 ? -s : s));
+            }
+        }
+        return;
+    }
+    if (blockIdx.y != 0) return;
+    __shared__ Wd red[256];
+    Wd acc = 0;
+    if (d.len == 1) {
+        // scalar partials (wide), summed in tile order by thread 0
+        if (t == 0)
+            for (int64_t q = 0; q < d.T; ++q) acc += static_cast<const Wd *>(d.part)[q * d.stride];
+        if (t == 0) static_cast<Wd *>(d.out)[0] = acc;
+        return;
+    }
+    for (int64_t j = t; j < d.len; j += 256) {
+        A s = 0;
+        for (int64_t q = 0; q < d.T; ++q) s += static_cast<const A *>(d.part)[q * d.stride + j];
+        Wd w = (Wd)s;
+        for (int q = 0; q < d.nmul; ++q) w *= (Wd)load_vec<DOM>(d.mul[q], j);
+        acc += w;
+    }
+    red[t] = acc;
+    __syncthreads();
+    if (t == 0) {
+        Wd s = 0;
+        for (int q = 0; q < 256; ++q) s += red[q];
+        static_cast<Wd *>(d.out)[0] = s;
+    }
+}
+
+// ----------------------------------------------------------------- elim0
+
+template <int DOM>
+__global__ __launch_bounds__(256) void k_elim0(const Elim0Desc *D, int nprob) {
+    typedef typename Dom<DOM>::wide Wd;
+    __shared__ Wd red[256];
+    const Elim0Desc &d = D[blockIdx.x];
+    const int t = threadIdx.x;
+    Wd acc = 0;
+    for (int64_t v = t; v < d.n; v += 256) {
+        Wd x = 1;
+        for (int j = 0; j < d.nS; ++j) x *= (Wd)load_vec<DOM>(d.s[j], v);
+        acc += x;
+    }
+    red[t] = acc;
+    __syncthreads();
+    if (t == 0) {
+        Wd s = 0;
+        for (int q = 0; q < 256; ++q) s += red[q];
+        static_cast<Wd *>(d.out)[0] = s;
+    }
+}
+
+// ----------------------------------------------------------------- prep
+
+template <int DOM>
+__global__ __launch_bounds__(256) void k_prep(const PrepDesc *D, int nprob) {
+    typedef typename Dom<DOM>::acc A;
+    __shared__ A prod[64][65];  // [w offset][v offset]
+    const int64_t b = blockIdx.x;
+    const int p = find_problem(D, nprob, b);
+    const PrepDesc &d = D[p];
+    const int64_t local = b - d.tile_start;
+    const int64_t tw = local / d.tiles, tv = local % d.tiles;
+    const int64_t n = d.n, w0 = tw * 64, v0 = tv * 64;
+    const int t = threadIdx.x;
+    int limbs = d.limbs;
+    if (d.format == PF_I8LIMBS) {
+        // Digits needed for |x| <= prod of the operands' maxima: a top digit
+        // in [-128, 127] above balanced digits in [-64, 63].
+        double bound = 1.0;
+        for (int q = 0; q < d.nmx; ++q) bound *= (double)*d.mx[q];
+        int L = 1;
+        double X = bound;
+        while (X > 127.0 && L < d.limbs) {
+            X = floor((X + 64.0) / 128.0);
+            ++L;
+        }
+        limbs = L;
+        if (local == 0 && t == 0) *d.limbs_out = L;
+    }
+    for (int e = t; e < 4096; e += 256) {
+        int r = e >> 6, c = e & 63;
+        int64_t w = w0 + r, v = v0 + c;
+        A val = (v < n && w < n) ? (A)1 : (A)0;
+        if (v < n && w < n)
+            for (int j = 0; j < d.nS; ++j) val *= load_vec<DOM>(d.s[j], v);
+        prod[r][c] = val;
+    }
+    __syncthreads();
+    for (int k = 0; k < d.nA; ++k) {
+        const MatRef m = d.A[k];
+        for (int e = t; e < 4096; e += 256) {
+            int r = e >> 6, c = e & 63;
+            // canonical operand orientation is (v, w).  trans == 0: stored
+            // (v, w), row r over v; trans == 1: stored (w, v), row r over w.
+            int rw = m.trans ? r : c, cv = m.trans ? c : r;
+            int64_t w = w0 + rw, v = v0 + cv;
+            if (v < n && w < n) {
+                int64_t idx = m.trans ? (w * m.ld + v) : (v * m.ld + w);
+                A x = load_elem<DOM>(m.p, m.dtype, idx);
+                if (m.zdiag && v == w) x = 0;
+                prod[rw][cv] *= x;
+            }
+        }
+        __syncthreads();
+    }
+    for (int e = t; e < 4096; e += 256) {
+        int r = e >> 6, c = e & 63;
+        int64_t w = w0 + r, v = v0 + c;
+        if (w >= d.npad || v >= d.npad) continue;
+        int64_t o = w * d.ldo + v;
+        A x = prod[r][c];
+        switch (d.format) {
+            case PF_F64: static_cast<double *>(d.out)[o] = (double)x; break;
+            case PF_F32: static_cast<float *>(d.out)[o] = (float)x; break;
+            case PF_BF16X2: {
+                double xd = (double)x;
+                uint16_t hi = f32_to_bf16_rne((float)xd);
+                uint16_t lo = f32_to_bf16_rne((float)(xd - (double)bf16_to_f32(hi)));
+                static_cast<uint16_t *>(d.out)[o] = hi;
+                static_cast<uint16_t *>(d.out)[o + d.plane] = lo;
+                break;
+            }
+            default: {
+                long long xi = (long long)x;
+                for (int l = 0; l + 1 < limbs; ++l) {
+                    long long md = ((xi % 128) + 128 + 64) % 128 - 64;  // balanced digit
+                    static_cast<int8_t *>(d.out)[o + l * d.plane] = (int8_t)md;
+                    xi = (xi - md) / 128;
+                }
+                static_cast<int8_t *>(d.out)[o + (int64_t)(limbs - 1) * d.plane] = (int8_t)xi;
+                break;
+            }
+        }
+    }
+}
+
+// ----------------------------------------------------------------- GEMM
+//
+// Block tile 128 x 128, four waves in a 2 x 2 arrangement, each wave a
+// 64 x 64 region of 4 x 4 MFMA blocks of 16 x 16.  Operands live in LDS as
+// [row][k] with padding; every 16x16 MFMA family used here (f64 16x16x4,
+// f32 16x16x4, bf16 16x16x32, i8 16x16x64) reads lane l's A fragment from
+// row l%16 and B fragment from column l%16 at k-slot group l/16, and leaves
+// lane l holding rows 4*(l/16)+r, column l%16 of the 16x16 result.
+
+template <int PREC>
+struct GemmCfg;
+template <>
+struct GemmCfg<0> {  // fp64
+    typedef double E;
+    static constexpr int BK = 16, PADK = 2, PLANES = 1;
+};
+template <>
+struct GemmCfg<1> {  // fp32
+    typedef float E;
+    static constexpr int BK = 16, PADK = 4, PLANES = 1;
+};
+template <>
+struct GemmCfg<2> {  // bf16 hi/lo
+    typedef uint16_t E;
+    static constexpr int BK = 32, PADK = 8, PLANES = 2;
+};
+template <>
+struct GemmCfg<3> {  // int8 limb (one plane per pass)
+    typedef int8_t E;
+    static constexpr int BK = 64, PADK = 16, PLANES = 1;
+};
+
+template <int PREC>
+struct AccT {
+    typedef f32x4 T;
+};
+template <>
+struct AccT<0> {
+    typedef f64x4 T;
+};
+template <>
+struct AccT<3> {
+    typedef i32x4 T;
+};
+
+// Load one 128 x BK tile (all planes) of an operand into registers.
+template <int PREC>
+struct TileIO {
+    typedef GemmCfg<PREC> C;
+    static constexpr int ROWB = C::BK * (int)sizeof(typename C::E);  // bytes per row
+    static constexpr int UPR = ROWB / 16;                            // 16B units per row
+    static constexpr int UNITS = 128 * UPR * C::PLANES;
+    static constexpr int PER = UNITS / 256;
+    static constexpr int LROW = (C::BK + C::PADK) * (int)sizeof(typename C::E);
+    static constexpr int PLANEB = 128 * LROW;
+
+    __device__ static void load(uint4 (&r)[PER], const char *base, int64_t ldb, int64_t planeb,
+                                int64_t row0, int64_t k0b) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            int u = threadIdx.x + 256 * i;
+            int pl = u / (128 * UPR);
+            int uu = u % (128 * UPR);
+            int row = uu / UPR, cu = uu % UPR;
+            const char *g = base + pl * planeb + (row0 + row) * ldb + k0b + cu * 16;
+            r[i] = *reinterpret_cast<const uint4 *>(g);
+        }
+    }
+    __device__ static void store(const uint4 (&r)[PER], char *lds) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            int u = threadIdx.x + 256 * i;
+            int pl = u / (128 * UPR);
+            int uu = u % (128 * UPR);
+            int row = uu / UPR, cu = uu % UPR;
+            *reinterpret_cast<uint4 *>(lds + pl * PLANEB + row * LROW + cu * 16) = r[i];
+        }
+    }
+};
+
+template <int PREC>
+__device__ __forceinline__ void mma_tile(typename AccT<PREC>::T (&acc)[4][4], const char *As,
+                                         const char *Bs, int wy, int wx, int lane);
+
+template <>
+__device__ __forceinline__ void mma_tile<0>(f64x4 (&acc)[4][4], const char *As, const char *Bs,
+                                            int wy, int wx, int lane) {
+    typedef TileIO<0> IO;
+    const int lr = lane & 15, lg = lane >> 4;
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 4) {
+        double a[4], b[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            a[i] = *reinterpret_cast<const double *>(As + (wy * 64 + i * 16 + lr) * IO::LROW +
+                                                     (kk + lg) * 8);
+            b[i] = *reinterpret_cast<const double *>(Bs + (wx * 64 + i * 16 + lr) * IO::LROW +
+                                                     (kk + lg) * 8);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+}
+
+template <>
+__device__ __forceinline__ void mma_tile<1>(f32x4 (&acc)[4][4], const char *As, const char *Bs,
+                                            int wy, int wx, int lane) {
+    typedef TileIO<1> IO;
+    const int lr = lane & 15, lg = lane >> 4;
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 4) {
+        float a[4], b[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            a[i] = *reinterpret_cast<const float *>(As + (wy * 64 + i * 16 + lr) * IO::LROW +
+                                                    (kk + lg) * 4);
+            b[i] = *reinterpret_cast<const float *>(Bs + (wx * 64 + i * 16 + lr) * IO::LROW +
+                                                    (kk + lg) * 4);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+}
+
+template <>
+__device__ __forceinline__ void mma_tile<2>(f32x4 (&acc)[4][4], const char *As, const char *Bs,
+                                            int wy, int wx, int lane) {
+    typedef TileIO<2> IO;
+    const int lr = lane & 15, lg = lane >> 4;
+    bf16x8 ah[4], al[4], bh[4], bl[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int ra = (wy * 64 + i * 16 + lr) * IO::LROW + lg * 16;
+        const int rb = (wx * 64 + i * 16 + lr) * IO::LROW + lg * 16;
+        ah[i] = *reinterpret_cast<const bf16x8 *>(As + ra);
+        al[i] = *reinterpret_cast<const bf16x8 *>(As + IO::PLANEB + ra);
+        bh[i] = *reinterpret_cast<const bf16x8 *>(Bs + rb);
+        bl[i] = *reinterpret_cast<const bf16x8 *>(Bs + IO::PLANEB + rb);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+        }
+}
+
+template <>
+__device__ __forceinline__ void mma_tile<3>(i32x4 (&acc)[4][4], const char *As, const char *Bs,
+                                            int wy, int wx, int lane) {
+    typedef TileIO<3> IO;
+    const int lr = lane & 15, lg = lane >> 4;
+    i32x4 a[4], b[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        a[i] = *reinterpret_cast<const i32x4 *>(As + (wy * 64 + i * 16 + lr) * IO::LROW + lg * 16);
+        b[i] = *reinterpret_cast<const i32x4 *>(Bs + (wx * 64 + i * 16 + lr) * IO::LROW + lg * 16);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[i], b[j], acc[i][j], 0, 0, 0);
+}
+
+// K loop of one (A plane set, B plane set) pass with register prefetch and
+// double-buffered LDS.
+template <int PREC>
+__device__ __forceinline__ void gemm_pass(typename AccT<PREC>::T (&acc)[4][4], const char *Ab,
+                                          const char *Bb, int64_t ldb, int64_t planeb,
+                                          int64_t w0, int64_t x0, int64_t npad, char *lds) {
+    typedef TileIO<PREC> IO;
+    constexpr int STAGE = IO::PLANEB * GemmCfg<PREC>::PLANES;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, wy = wv >> 1, wx = wv & 1;
+    constexpr int KB = GemmCfg<PREC>::BK * (int)sizeof(typename GemmCfg<PREC>::E);
+    const int64_t nk = npad / GemmCfg<PREC>::BK;
+    uint4 ra[IO::PER], rb[IO::PER];
+    IO::load(ra, Ab, ldb, planeb, w0, 0);
+    IO::load(rb, Bb, ldb, planeb, x0, 0);
+    IO::store(ra, lds);
+    IO::store(rb, lds + STAGE);
+    __syncthreads();
+    for (int64_t kt = 0; kt < nk; ++kt) {
+        const int cur = (int)(kt & 1);
+        char *As = lds + cur * 2 * STAGE;
+        char *Bs = As + STAGE;
+        if (kt + 1 < nk) {
+            IO::load(ra, Ab, ldb, planeb, w0, (kt + 1) * KB);
+            IO::load(rb, Bb, ldb, planeb, x0, (kt + 1) * KB);
+        }
+        mma_tile<PREC>(acc, As, Bs, wy, wx, lane);
+        if (kt + 1 < nk) {
+            char *An = lds + (1 - cur) * 2 * STAGE;
+            IO::store(ra, An);
+            IO::store(rb, An + STAGE);
+        }
+        __syncthreads();
+    }
+}
+
+template <int PREC>
+__global__ __launch_bounds__(256) void k_gemm(const GemmDesc *D, int nprob) {
+    typedef TileIO<PREC> IO;
+    typedef typename AccT<PREC>::T AT;
+    constexpr int STAGE = IO::PLANEB * GemmCfg<PREC>::PLANES;
+    extern __shared__ __align__(16) char lds[];
+    const int64_t b = blockIdx.x;
+    const int p = find_problem(D, nprob, b);
+    const GemmDesc &d = D[p];
+    const int64_t local = b - d.tile_start;
+    const int64_t tm = local / d.tiles, tn = local % d.tiles;
+    const int64_t w0 = tm * 128, x0 = tn * 128;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, wy = wv >> 1, wx = wv & 1;
+    constexpr int ES = (int)sizeof(typename GemmCfg<PREC>::E);
+    const int64_t ldb = d.ld * ES, planeb = d.plane * ES;
+
+    // Result accumulators: value(i,j,r) for row w0+wy*64+i*16+4*(lane/16)+r,
+    // column x0+wx*64+j*16+lane%16.
+    double resd[4][4][4];
+    long long resi[4][4][4];
+    (void)resd;
+    (void)resi;
+    if constexpr (PREC == 3) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) resi[i][j][r] = 0;
+        const int nla = d.la_p ? *d.la_p : d.la, nlb = d.lb_p ? *d.lb_p : d.lb;
+        for (int la = 0; la < nla; ++la)
+            for (int lb = 0; lb < nlb; ++lb) {
+                AT acc[4][4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) acc[i][j] = AT{0, 0, 0, 0};
+                gemm_pass<PREC>(acc, static_cast<const char *>(d.A) + la * planeb,
+                                static_cast<const char *>(d.B) + lb * planeb, ldb, planeb, w0, x0,
+                                d.npad, lds);
+                const long long wgt = 1ll << (7 * (la + lb));
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) resi[i][j][r] += wgt * (long long)acc[i][j][r];
+            }
+    } else {
+        AT acc[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = AT{0, 0, 0, 0};
+        gemm_pass<PREC>(acc, static_cast<const char *>(d.A), static_cast<const char *>(d.B), ldb,
+                        planeb, w0, x0, d.npad, lds);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) resd[i][j][r] = (double)acc[i][j][r];
+    }
+    (void)STAGE;
+
+    const int64_t n = d.n;
+    if (!d.final_) {
+        if constexpr (PREC == 3) {
+            if (d.mx_out) {
+                unsigned long long mloc = 0;
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            long long v = resi[i][j][r];
+                            unsigned long long a = (unsigned long long)(v < 0 ? -v : v);
+                            mloc = a > mloc ? a : mloc;
+                        }
+                atomicMax(d.mx_out, mloc);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    int64_t w = w0 + wy * 64 + i * 16 + 4 * (lane >> 4) + r;
+                    int64_t x = x0 + wx * 64 + j * 16 + (lane & 15);
+                    if (w < n && x < n) {
+                        int64_t o = w * d.ldc + x;
+                        if constexpr (PREC == 3) static_cast<long long *>(d.C)[o] = resi[i][j][r];
+                        else if (d.dtype_c == DT_F64) static_cast<double *>(d.C)[o] = resd[i][j][r];
+                        else static_cast<float *>(d.C)[o] = (float)resd[i][j][r];
+                    }
+                }
+        return;
+    }
+    // Fused consumer: sum_{w,x} C(w,x) prod Z(w,x) prod aw(w) prod bx(x).
+    typedef typename std::conditional<PREC == 3, i128, double>::type Wd;
+    Wd part = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                int64_t w = w0 + wy * 64 + i * 16 + 4 * (lane >> 4) + r;
+                int64_t x = x0 + wx * 64 + j * 16 + (lane & 15);
+                if (w >= n || x >= n) continue;
+                Wd val;
+                if constexpr (PREC == 3) val = (Wd)resi[i][j][r];
+                else val = resd[i][j][r];
+                for (int k = 0; k < d.nZ; ++k) {
+                    const MatRef &z = d.Z[k];
+                    int64_t idx = z.trans ? (x * z.ld + w) : (w * z.ld + x);
+                    Wd zv;
+                    if constexpr (PREC == 3) zv = (Wd)load_int(z.p, z.dtype, idx);
+                    else zv = load_fp(z.p, z.dtype, idx);
+                    if (z.zdiag && w == x) zv = 0;
+                    val *= zv;
+                }
+                for (int q = 0; q < d.naw; ++q) {
+                    if constexpr (PREC == 3) val *= (Wd) static_cast<const long long *>(d.aw[q])[w];
+                    else val *= static_cast<const double *>(d.aw[q])[w];
+                }
+                for (int q = 0; q < d.nbx; ++q) {
+                    if constexpr (PREC == 3) val *= (Wd) static_cast<const long long *>(d.bx[q])[x];
+                    else val *= static_cast<const double *>(d.bx[q])[x];
+                }
+                part += val;
+            }
+    __syncthreads();  // LDS reuse
+    Wd *red = reinterpret_cast<Wd *>(lds);
+    red[threadIdx.x] = part;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        Wd s = 0;
+        for (int q = 0; q < 256; ++q) s += red[q];
+        static_cast<Wd *>(d.part)[local] = s;
+    }
+}
+
+// ----------------------------------------------------------------- combine
+
+template <int DOM>
+__global__ void k_combine(const CombineDesc *D, int ndata, const int32_t *off, const int32_t *cnt,
+                          const int32_t *idx, const int64_t *mu, const void *scal, void *vout,
+                          void *uout, double *sout) {
+    typedef typename Dom<DOM>::wide Wd;
+    int ds = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ds >= ndata) return;
+    const Wd *sc = static_cast<const Wd *>(scal);
+    Wd U = 0;
+    double S = 0;
+    for (int p = D[ds].p_begin; p < D[ds].p_end; ++p) {
+        Wd V = 1;
+        for (int q = 0; q < cnt[p]; ++q) V *= sc[idx[off[p] + q]];
+        static_cast<Wd *>(vout)[p] = V;
+        Wd t = (Wd)mu[p] * V;
+        U += t;
+        double td = (double)t;
+        S += td < 0 ? -td : td;
+    }
+    static_cast<Wd *>(uout)[ds] = U;
+    sout[ds] = S;
+}
+
+// ----------------------------------------------------------------- launchers
+
+hipError_t launch_rbf(const double *X, int64_t n, int32_t d, double divisor, void *out,
+                      int32_t dtype, hipStream_t s) {
+    dim3 grid((unsigned)((n + 63) / 64), (unsigned)((n + 63) / 64));
+    hipLaunchKernelGGL(k_rbf, grid, dim3(256), 0, s, X, n, d, 1.0 / divisor, out, dtype);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag(const DiagDesc *d, int nprob, int64_t max_n, int domain, hipStream_t s) {
+    dim3 grid((unsigned)std::min<int64_t>(64, (max_n + 255) / 256), (unsigned)nprob);
+    if (domain == DOM_FP) hipLaunchKernelGGL(k_diag<DOM_FP>, grid, dim3(256), 0, s, d, nprob);
+    else hipLaunchKernelGGL(k_diag<DOM_INT>, grid, dim3(256), 0, s, d, nprob);
+    return hipGetLastError();
+}
+
+hipError_t launch_elim1(const Elim1Desc *d, int nprob, int64_t total_tiles, int domain,
+                        hipStream_t s) {
+    dim3 grid((unsigned)total_tiles);
+    if (domain == DOM_FP) hipLaunchKernelGGL(k_elim1<DOM_FP>, grid, dim3(256), 0, s, d, nprob);
+    else hipLaunchKernelGGL(k_elim1<DOM_INT>, grid, dim3(256), 0, s, d, nprob);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(const ReduceDesc *d, int nprob, int64_t max_len, int domain,
+                         hipStream_t s) {
+    dim3 grid((unsigned)nprob, (unsigned)std::max<int64_t>(1, std::min<int64_t>(64, (max_len + 255) / 256)));
+    if (domain == DOM_FP) hipLaunchKernelGGL(k_reduce<DOM_FP>, grid, dim3(256), 0, s, d, nprob);
+    else hipLaunchKernelGGL(k_reduce<DOM_INT>, grid, dim3(256), 0, s, d, nprob);
+    return hipGetLastError();
+}
+
+hipError_t launch_elim0(const Elim0Desc *d, int nprob, int domain, hipStream_t s) {
+    if (domain == DOM_FP) hipLaunchKernelGGL(k_elim0<DOM_FP>, dim3(nprob), dim3(256), 0, s, d, nprob);
+    else hipLaunchKernelGGL(k_elim0<DOM_INT>, dim3(nprob), dim3(256), 0, s, d, nprob);
+    return hipGetLastError();
+}
+
+hipError_t launch_prep(const PrepDesc *d, int nprob, int64_t total_tiles, int domain,
+                       hipStream_t s) {
+    dim3 grid((unsigned)total_tiles);
+    if (domain == DOM_FP) hipLaunchKernelGGL(k_prep<DOM_FP>, grid, dim3(256), 0, s, d, nprob);
+    else hipLaunchKernelGGL(k_prep<DOM_INT>, grid, dim3(256), 0, s, d, nprob);
+    return hipGetLastError();
+}
+
+template <int PREC>
+static hipError_t launch_gemm_t(const GemmDesc *d, int nprob, int64_t total_tiles, hipStream_t s) {
+    constexpr int STAGE = TileIO<PREC>::PLANEB * GemmCfg<PREC>::PLANES;
+    size_t lds = (size_t)4 * STAGE;
+    size_t red = 256 * 16;
+    if (lds < red) lds = red;
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_gemm<PREC>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(k_gemm<PREC>, dim3((unsigned)total_tiles), dim3(256), lds, s, d, nprob);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm(const GemmDesc *d, int nprob, int64_t total_tiles, int precision,
+                       hipStream_t s) {
+    switch (precision) {
+        case 0: return launch_gemm_t<0>(d, nprob, total_tiles, s);
+        case 1: return launch_gemm_t<1>(d, nprob, total_tiles, s);
+        case 2: return launch_gemm_t<2>(d, nprob, total_tiles, s);
+        default: return launch_gemm_t<3>(d, nprob, total_tiles, s);
+    }
+}
+
+hipError_t launch_absmax_i8(const int8_t *const *src, const int64_t *n, int nprob,
+                            unsigned long long *mx, hipStream_t s) {
+    hipLaunchKernelGGL(k_absmax_i8, dim3(64, (unsigned)nprob), dim3(256), 0, s, src, n, nprob, mx);
+    return hipGetLastError();
+}
+
+hipError_t launch_combine(const CombineDesc *d, int ndata, const int32_t *scal_off,
+                          const int32_t *scal_cnt, const int32_t *scal_idx, const int64_t *mu,
+                          const void *scal, void *vout, void *uout, double *sout, int domain,
+                          hipStream_t s) {
+    dim3 grid((unsigned)((ndata + 63) / 64));
+    if (domain == DOM_FP)
+        hipLaunchKernelGGL(k_combine<DOM_FP>, grid, dim3(64), 0, s, d, ndata, scal_off, scal_cnt,
+                           scal_idx, mu, scal, vout, uout, sout);
+    else
+        hipLaunchKernelGGL(k_combine<DOM_INT>, grid, dim3(64), 0, s, d, ndata, scal_off, scal_cnt,
+                           scal_idx, mu, scal, vout, uout, sout);
+    return hipGetLastError();
+}
+
+}  // namespace ustat

@@ -1,0 +1,150 @@
+// Device kernels of the elimination engine and their grouped-launch
+// descriptors.  Every kernel takes an array of descriptors, one per
+// independent problem, so that all steps of one dependency level of every
+// restricted V-statistic (and every dataset of a batch) go out in a single
+// launch per step kind.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace ustat {
+
+enum DType : int32_t { DT_F64 = 0, DT_F32 = 1, DT_I8 = 2, DT_I64 = 3 };
+
+// Accumulation domain of a launch: floating point (double) or exact
+// integers (int64 values, 128-bit scalars).
+enum Domain : int32_t { DOM_FP = 0, DOM_INT = 1 };
+
+constexpr int kMaxMat = 6;  // matrices per Hadamard group
+constexpr int kMaxVec = 6;  // vectors multiplied on one variable
+
+// Matrix operand addressed in its step's canonical orientation (a, b):
+// trans == 0 reads p[a*ld + b], trans == 1 reads p[b*ld + a].  zdiag
+// zeroes entries with a == b (sparsified input factors, Lemma 3).
+struct MatRef {
+    const void *p;
+    int64_t ld;
+    int32_t dtype;
+    int32_t trans;
+    int32_t zdiag;
+    int32_t pad;
+};
+
+// dst[i] = src(i, i), as double (DOM_FP) or int64 (DOM_INT).
+struct DiagDesc {
+    MatRef src;
+    void *dst;
+    int64_t n;
+    unsigned long long *mx_out;  // DOM_INT: running max |dst|, or null
+};
+
+// Tile partials of y(w) = sum_v prod_k A_k(v, w) prod_j s_j(v):
+// part[tv * n + w] holds the sum over the 64 rows of tile tv.
+struct Elim1Desc {
+    int64_t n;
+    int32_t nA, nS;
+    MatRef A[kMaxMat];
+    const void *s[kMaxVec];
+    void *part;
+    int64_t tile_start;  // first block index of this problem in the launch
+    int32_t tiles_v, tiles_w;
+};
+
+// out[j] = (sum_{t < T} part[t * stride + j]) * prod_q mul_q[j], j < len,
+// summed in increasing t (fixed order).  With `dot` set, the len products
+// are summed as well (fixed order) into the single scalar out[0].
+struct ReduceDesc {
+    const void *part;
+    int64_t T, len, stride;
+    void *out;
+    int32_t nmul, dot;
+    const void *mul[kMaxVec];
+    unsigned long long *mx_out;  // DOM_INT vectors: running max |out|, or null
+};
+
+// out = sum_v prod_j s_j(v) (one block per problem).
+struct Elim0Desc {
+    int64_t n;
+    int32_t nS;
+    const void *s[kMaxVec];
+    void *out;
+};
+
+enum PrepFormat : int32_t { PF_F64 = 0, PF_F32 = 1, PF_BF16X2 = 2, PF_I8LIMBS = 3 };
+
+// GEMM operand: out[w * ldo + v] = prod_j s_j(v) prod_k A_k(v, w) for
+// w, v < n and 0 in the padding up to npad.  PF_BF16X2 writes hi at out and
+// lo at out + plane (elements); PF_I8LIMBS writes `limbs` planes of 7-bit
+// digits (balanced for all but the top one).
+struct PrepDesc {
+    int64_t n, npad, ldo, plane;
+    int32_t nA, nS;
+    MatRef A[kMaxMat];
+    const void *s[kMaxVec];
+    void *out;
+    int32_t format, limbs;  // limbs: planes available (PF_I8LIMBS)
+    int64_t tile_start;
+    int32_t tiles;  // per side, over npad
+    int32_t nmx;
+    // PF_I8LIMBS: the digit count is chosen on the device from the product
+    // of the operands' running maxima mx[0..nmx) and written to *limbs_out.
+    const unsigned long long *mx[kMaxMat + kMaxVec];
+    int32_t *limbs_out;
+};
+
+// C(w, x) = sum_v Aop[w][v] * Bop[x][v] over prepared operands (leading
+// dimension ld, zero-padded to npad).  final == 0 stores C (n x n, ldc) as
+// dtype_c; final == 1 writes per-tile partials of
+//   sum_{w,x} C(w,x) prod_k Z_k(w,x) prod aw(w) prod bx(x).
+struct GemmDesc {
+    int64_t n, npad, ld;
+    const void *A;
+    const void *B;
+    int64_t plane;       // elements between limb / lo planes
+    int32_t la, lb;      // limb counts (int8 path)
+    int32_t final_, dtype_c;
+    void *C;
+    int64_t ldc;
+    int32_t nZ, naw, nbx, tiles;  // tiles per side
+    MatRef Z[kMaxMat];
+    const void *aw[kMaxVec];
+    const void *bx[kMaxVec];
+    void *part;
+    int64_t tile_start;
+    const int32_t *la_p, *lb_p;  // int8 path: limb counts written by prep
+    unsigned long long *mx_out;  // int8 path: running max |C|, or null
+};
+
+// V_p = prod of scal[idx[off_p .. off_p + cnt_p)], then per dataset d:
+//   U_d = sum_{p in d} mu_p V_p,  S_d = sum |mu_p V_p|
+// (in order of p).  DOM_FP scalars are doubles; DOM_INT scalars are int128
+// stored as two int64 (lo, hi).
+struct CombineDesc {
+    int32_t p_begin, p_end;  // V-statistics of this dataset
+};
+
+constexpr int kGemmTile = 128;
+constexpr int kTile = 64;
+
+hipError_t launch_rbf(const double *X, int64_t n, int32_t d, double divisor, void *out,
+                      int32_t dtype, hipStream_t s);
+hipError_t launch_diag(const DiagDesc *d, int nprob, int64_t max_n, int domain, hipStream_t s);
+hipError_t launch_elim1(const Elim1Desc *d, int nprob, int64_t total_tiles, int domain,
+                        hipStream_t s);
+hipError_t launch_reduce(const ReduceDesc *d, int nprob, int64_t max_len, int domain,
+                         hipStream_t s);
+hipError_t launch_elim0(const Elim0Desc *d, int nprob, int domain, hipStream_t s);
+hipError_t launch_prep(const PrepDesc *d, int nprob, int64_t total_tiles, int domain,
+                       hipStream_t s);
+hipError_t launch_gemm(const GemmDesc *d, int nprob, int64_t total_tiles, int precision,
+                       hipStream_t s);
+hipError_t launch_absmax_i8(const int8_t *const *src, const int64_t *n, int nprob,
+                            unsigned long long *mx, hipStream_t s);
+hipError_t launch_combine(const CombineDesc *d, int ndata, const int32_t *scal_off,
+                          const int32_t *scal_cnt, const int32_t *scal_idx, const int64_t *mu,
+                          const void *scal, void *vout, void *uout, double *sout, int domain,
+                          hipStream_t s);
+
+}  // namespace ustat

@@ -1,0 +1,426 @@
+// Host-side planner.  Lemma 2 supplies the partitions and their Moebius
+// coefficients, Algorithm 3 the induced notation (here: the quotient
+// multigraph), Lemma 3 the optional sparsification filter, and the proof of
+// Proposition 1 (one index summed out at a time) the lowering of an
+// elimination order to kernel steps.
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <functional>
+#include <limits>
+#include <numeric>
+#include <string>
+
+namespace ustat {
+
+std::vector<std::vector<int>> enumerate_rgs(int m) {
+    std::vector<std::vector<int>> out;
+    std::vector<int> a(m, 0);
+    std::function<void(int, int)> rec = [&](int i, int mx) {
+        if (i == m) {
+            out.push_back(a);
+            return;
+        }
+        for (int b = 0; b <= mx + 1; ++b) {
+            a[i] = b;
+            rec(i + 1, std::max(mx, b));
+        }
+    };
+    if (m >= 1) {
+        a[0] = 0;
+        rec(1, 0);
+    }
+    return out;
+}
+
+int64_t mobius_mu(const std::vector<int> &block_of) {
+    int m = (int)block_of.size();
+    int J = 0;
+    for (int b : block_of) J = std::max(J, b + 1);
+    std::vector<int> size(J, 0);
+    for (int b : block_of) size[b]++;
+    int64_t p = 1;
+    for (int s : size)
+        for (int t = 2; t < s; ++t) p *= t;
+    return ((m - J) % 2) ? -p : p;
+}
+
+bool survives_sparsification(const std::vector<int> &block_of, const std::vector<Edge> &edges) {
+    for (const Edge &e : edges)
+        if (block_of[e.u] == block_of[e.v]) return false;
+    return true;
+}
+
+// Treewidth by the subset recurrence TW(S) = min_{v in S} max(TW(S\v),
+// |Q(S\v, v)|), where Q(S, v) is the set of vertices outside S + v reachable
+// from v through S; TW(V) is the treewidth (eliminating S first costs the
+// largest such |Q|).
+int exact_treewidth(int J, const std::vector<uint32_t> &adj) {
+    if (J <= 1) return 0;
+    const uint32_t full = (J >= 32) ? 0xffffffffu : ((1u << J) - 1);
+    std::vector<int8_t> TW((size_t)full + 1, 0);
+    auto Q = [&](uint32_t S, int v) {
+        uint32_t seen = 1u << v, frontier = 1u << v, out = 0;
+        while (frontier) {
+            int x = __builtin_ctz(frontier);
+            frontier &= frontier - 1;
+            uint32_t nb = adj[x] & ~seen;
+            seen |= nb;
+            out |= nb & ~S;
+            frontier |= nb & S;
+        }
+        return __builtin_popcount(out);
+    };
+    TW[0] = -1;
+    for (uint32_t S = 1; S <= full; ++S) {
+        int best = 127;
+        for (uint32_t rest = S; rest; rest &= rest - 1) {
+            int v = __builtin_ctz(rest);
+            uint32_t Sv = S & ~(1u << v);
+            int val = std::max<int>(TW[Sv], Q(Sv, v));
+            best = std::min(best, val);
+        }
+        TW[S] = (int8_t)best;
+        if (S == full) break;
+    }
+    return std::max<int>(0, TW[full]);
+}
+
+namespace {
+
+struct LiveFactor {
+    int val;
+    int nv;    // 1 (vector) or 2 (matrix)
+    int a, b;  // vars; for matrices (row, col) of the stored value
+};
+
+std::vector<uint32_t> quotient_adjacency(const std::vector<Edge> &edges,
+                                         const std::vector<int> &block_of, int J) {
+    std::vector<uint32_t> adj(J, 0);
+    for (const Edge &e : edges) {
+        int a = block_of[e.u], b = block_of[e.v];
+        if (a != b) {
+            adj[a] |= 1u << b;
+            adj[b] |= 1u << a;
+        }
+    }
+    return adj;
+}
+
+std::vector<int> minfill_order(int J, std::vector<uint32_t> adj) {
+    std::vector<int> order;
+    uint32_t alive = (J >= 32) ? 0xffffffffu : ((1u << J) - 1);
+    while (alive) {
+        int best = -1;
+        long best_key = std::numeric_limits<long>::max();
+        for (uint32_t r = alive; r; r &= r - 1) {
+            int v = __builtin_ctz(r);
+            uint32_t nb = adj[v] & alive;
+            int fill = 0;
+            for (uint32_t p = nb; p; p &= p - 1) {
+                int x = __builtin_ctz(p);
+                fill += __builtin_popcount(nb & ~adj[x] & ~(1u << x));
+            }
+            fill /= 2;
+            long key = ((long)fill << 20) | ((long)__builtin_popcount(nb) << 8) | v;
+            if (key < best_key) {
+                best_key = key;
+                best = v;
+            }
+        }
+        uint32_t nb = adj[best] & alive;
+        for (uint32_t p = nb; p; p &= p - 1) {
+            int x = __builtin_ctz(p);
+            adj[x] |= nb & ~(1u << x);
+        }
+        alive &= ~(1u << best);
+        order.push_back(best);
+    }
+    return order;
+}
+
+}  // namespace
+
+std::string lower_order(const std::vector<Edge> &edges, const std::vector<int> &block_of, int J,
+                        const std::vector<int> &order, VProgram &out) {
+    out.vals.clear();
+    out.steps.clear();
+    out.scalars.clear();
+    out.order = order;
+    out.width = 0;
+    std::vector<LiveFactor> live;
+    for (size_t k = 0; k < edges.size(); ++k) {
+        int a = block_of[edges[k].u], b = block_of[edges[k].v];
+        Value val;
+        val.src = (int)k;
+        if (a == b) {
+            val.kind = ValKind::InputDiag;
+            val.r = a;
+            val.c = -1;
+            live.push_back({(int)out.vals.size(), 1, a, -1});
+        } else {
+            val.kind = ValKind::InputMat;
+            val.r = a;
+            val.c = b;
+            live.push_back({(int)out.vals.size(), 2, a, b});
+        }
+        out.vals.push_back(val);
+    }
+    std::vector<char> gone(J, 0);
+    std::vector<int> val_level;  // level of each value
+    auto level_of = [&](int val) {
+        const Value &v = out.vals[val];
+        if (v.kind == ValKind::InputMat || v.kind == ValKind::InputDiag) return 0;
+        return out.steps[v.src].level;
+    };
+    for (int v : order) {
+        if (v < 0 || v >= J) return "order names a vertex outside the quotient";
+        if (gone[v]) continue;
+        std::vector<LiveFactor> touch, keep;
+        for (const LiveFactor &f : live) {
+            bool hit = (f.a == v) || (f.nv == 2 && f.b == v);
+            (hit ? touch : keep).push_back(f);
+        }
+        live.swap(keep);
+        std::vector<int> nbrs;
+        for (const LiveFactor &f : touch)
+            if (f.nv == 2) {
+                int o = (f.a == v) ? f.b : f.a;
+                if (std::find(nbrs.begin(), nbrs.end(), o) == nbrs.end()) nbrs.push_back(o);
+            }
+        std::sort(nbrs.begin(), nbrs.end());
+        gone[v] = 1;
+        std::vector<int> remaining;
+        for (int q = 0; q < J; ++q)
+            if (!gone[q]) remaining.push_back(q);
+        int deg = (int)nbrs.size();
+        out.width = std::max(out.width, deg);
+        Step st;
+        st.v = v;
+        for (const LiveFactor &f : touch)
+            if (f.nv == 1) st.sv.push_back(f.val);
+        auto take_vecs = [&](int var, std::vector<int> &dst) {
+            std::vector<LiveFactor> k2;
+            for (const LiveFactor &f : live) {
+                if (f.nv == 1 && f.a == var) dst.push_back(f.val);
+                else k2.push_back(f);
+            }
+            live.swap(k2);
+        };
+        Value res;
+        res.src = (int)out.steps.size();
+        res.r = res.c = -1;
+        if (deg == 0) {
+            st.kind = StepKind::Elim0;
+            res.kind = ValKind::Scalar;
+        } else if (deg == 1) {
+            int w = nbrs[0];
+            st.w = w;
+            for (const LiveFactor &f : touch)
+                if (f.nv == 2) st.A.push_back({f.val, f.a != v});
+            if (remaining.size() == 1 && remaining[0] == w) {
+                st.kind = StepKind::Final1;
+                take_vecs(w, st.aw);
+                gone[w] = 1;
+                res.kind = ValKind::Scalar;
+            } else {
+                st.kind = StepKind::Elim1;
+                res.kind = ValKind::Vec;
+                res.r = w;
+            }
+        } else if (deg == 2) {
+            int w = nbrs[0], x = nbrs[1];
+            st.w = w;
+            st.x = x;
+            for (const LiveFactor &f : touch)
+                if (f.nv == 2) {
+                    int o = (f.a == v) ? f.b : f.a;
+                    (o == w ? st.A : st.B).push_back({f.val, f.a != v});
+                }
+            if (remaining.size() == 2 && remaining[0] == w && remaining[1] == x) {
+                st.kind = StepKind::Final2;
+                std::vector<LiveFactor> k2;
+                for (const LiveFactor &f : live) {
+                    if (f.nv == 2) st.Z.push_back({f.val, f.a != w});
+                    else k2.push_back(f);
+                }
+                live.swap(k2);
+                take_vecs(w, st.aw);
+                take_vecs(x, st.bx);
+                gone[w] = gone[x] = 1;
+                res.kind = ValKind::Scalar;
+            } else {
+                st.kind = StepKind::Elim2;
+                res.kind = ValKind::Mat;
+                res.r = w;
+                res.c = x;
+            }
+        } else {
+            return "elimination degree " + std::to_string(deg) + " is not supported";
+        }
+        int lvl = 0;
+        auto bump = [&](int val) { lvl = std::max(lvl, level_of(val)); };
+        for (auto &o : st.A) bump(o.val);
+        for (auto &o : st.B) bump(o.val);
+        for (auto &o : st.Z) bump(o.val);
+        for (int q : st.sv) bump(q);
+        for (int q : st.aw) bump(q);
+        for (int q : st.bx) bump(q);
+        st.level = lvl + 1;
+        st.out = (int)out.vals.size();
+        out.vals.push_back(res);
+        out.steps.push_back(st);
+        if (res.kind == ValKind::Scalar) {
+            out.scalars.push_back(st.out);
+        } else if (res.kind == ValKind::Vec) {
+            live.push_back({st.out, 1, res.r, -1});
+        } else {
+            live.push_back({st.out, 2, res.r, res.c});
+        }
+    }
+    if (!live.empty()) return "elimination order left factors unconsumed";
+    out.depth = 0;
+    for (const Step &s : out.steps) out.depth = std::max(out.depth, s.level);
+    (void)val_level;
+    return "";
+}
+
+void program_cost(const VProgram &p, double n, double elem_bytes, double *flops, double *bytes) {
+    double f = 0, b = 0;
+    for (const Step &s : p.steps) {
+        switch (s.kind) {
+            case StepKind::Elim0:
+                f += 2 * n * std::max<size_t>(1, s.sv.size());
+                b += 8 * n * s.sv.size();
+                break;
+            case StepKind::Elim1:
+            case StepKind::Final1:
+                f += 2 * n * n * s.A.size();
+                b += elem_bytes * n * n * s.A.size();
+                break;
+            case StepKind::Elim2:
+            case StepKind::Final2:
+                f += 2 * n * n * n;
+                b += elem_bytes * n * n * (s.A.size() + s.B.size() + s.Z.size() +
+                                           (s.kind == StepKind::Elim2 ? 1 : 0));
+                break;
+        }
+    }
+    if (flops) *flops = f;
+    if (bytes) *bytes = b;
+}
+
+std::vector<float> program_features(const VProgram &p, double n) {
+    // Counts per step kind, operand counts, transposition counts, depth,
+    // and log-size terms; the learned model maps them to a log-time.
+    float c[5] = {0, 0, 0, 0, 0};
+    float nA = 0, nTransA = 0, nZ = 0, nVec = 0, nPrep = 0;
+    for (const Step &s : p.steps) {
+        c[(int)s.kind] += 1;
+        nA += (float)(s.A.size() + s.B.size());
+        for (auto &o : s.A) nTransA += o.trans ? 0.f : 1.f;
+        for (auto &o : s.B) nTransA += o.trans ? 0.f : 1.f;
+        nZ += (float)s.Z.size();
+        nVec += (float)(s.sv.size() + s.aw.size() + s.bx.size());
+        if (s.kind == StepKind::Elim2 || s.kind == StepKind::Final2) {
+            bool directA = s.A.size() == 1 && s.A[0].trans && s.sv.empty();
+            bool directB = s.B.size() == 1 && s.B[0].trans;
+            nPrep += (directA ? 0.f : 1.f) + (directB ? 0.f : 1.f);
+        }
+    }
+    float ln = (float)std::log(n);
+    std::vector<float> f = {c[0], c[1], c[2], c[3], c[4], nA, nTransA, nZ, nVec, nPrep,
+                            (float)p.depth, (float)p.width, ln, ln * (c[3] + c[4]),
+                            ln * (c[1] + c[2])};
+    return f;
+}
+
+std::string build_program(const std::vector<Edge> &edges, int m, const std::vector<int> &block_of,
+                          const PlanOptions &opts, const OrderScorer *scorer, VProgram &out) {
+    int J = 0;
+    for (int b : block_of) J = std::max(J, b + 1);
+    out.block_of = block_of;
+    out.J = J;
+    out.mu = mobius_mu(block_of);
+    auto adj = quotient_adjacency(edges, block_of, J);
+    out.tw = exact_treewidth(J, adj);
+    (void)m;
+    std::vector<int> mf = minfill_order(J, adj);
+    auto finish = [&](const std::vector<int> &ord) {
+        std::string err = lower_order(edges, block_of, J, ord, out);
+        out.executable = err.empty();
+        out.lower_error = err;
+        if (!err.empty()) {
+            // Keep the order and its width for reporting.
+            out.order = ord;
+        }
+        return std::string();
+    };
+    if (opts.order == 0 || J <= 1) return finish(mf);
+    // Exhaustive or learned: enumerate every order (J <= 8) and keep the best.
+    if (J > 8) return finish(mf);
+    std::vector<int> perm(J);
+    std::iota(perm.begin(), perm.end(), 0);
+    const double nref = 4096.0;
+    double best = std::numeric_limits<double>::infinity();
+    std::vector<int> best_order = mf;
+    VProgram tmp;
+    do {
+        std::string err = lower_order(edges, block_of, J, perm, tmp);
+        if (!err.empty()) continue;
+        double key;
+        if (opts.order == 2 && scorer) {
+            key = scorer->score(program_features(tmp, nref));
+        } else {
+            double f, b;
+            program_cost(tmp, nref, 4.0, &f, &b);
+            // Time proxy: MFMA work plus memory traffic plus a per-level
+            // launch latency, in seconds at nominal rates.
+            key = f / 100e12 + b / 5e12 + tmp.depth * 8e-6;
+        }
+        if (key < best - 1e-15) {
+            best = key;
+            best_order = perm;
+        }
+    } while (std::next_permutation(perm.begin(), perm.end()));
+    return finish(best_order);
+}
+
+std::string make_plan(int m, const std::vector<Edge> &edges, const PlanOptions &opts,
+                      const OrderScorer *scorer, Plan &out) {
+    if (m < 1 || m > kMaxM) return "m must be in 1..10";
+    if (edges.empty()) return "the kernel graph needs at least one edge";
+    std::vector<char> used(m, 0);
+    for (const Edge &e : edges) {
+        if (e.u < 0 || e.u >= m || e.v < 0 || e.v >= m) return "edge endpoint out of range";
+        if (e.u == e.v) return "self-loop edges are not allowed";
+        used[e.u] = used[e.v] = 1;
+    }
+    for (int i = 0; i < m; ++i)
+        if (!used[i]) return "every vertex must appear in some edge";
+    out.m = m;
+    out.edges = edges;
+    out.opts = opts;
+    out.progs.clear();
+    out.N_l.assign(m + 1, 0);
+    out.M = 0;
+    out.max_width = 0;
+    for (const auto &rgs : enumerate_rgs(m)) {
+        if (opts.sparsify && !survives_sparsification(rgs, edges)) continue;
+        VProgram p;
+        std::string err = build_program(edges, m, rgs, opts, scorer, p);
+        if (!err.empty()) return err;
+        out.N_l[p.tw]++;
+        out.M = std::max(out.M, p.tw);
+        if (!p.executable && out.executable) {
+            out.executable = false;
+            out.lower_error = p.lower_error;
+        }
+        out.max_width = std::max(out.max_width, p.width);
+        out.progs.push_back(std::move(p));
+    }
+    return "";
+}
+
+}  // namespace ustat

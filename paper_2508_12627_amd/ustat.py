@@ -1,0 +1,307 @@
+"""Python binding of libustat (C ABI in ``include/ustat.h``).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of ``libustat.so``.  torch provides device memory and streams.  The
+functions carry the C names (``ustat_plan_create``, ``ustat_eval``,
+``vstat_eval``, ...); ``Plan`` is a small convenience wrapper over them.
+
+Importing this module loads the library and raises if it has not been built
+(``python -c "import __graft_entry__ as g; g.build()"``); there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence, Tuple
+
+import torch  # loads the HIP runtime the library shares
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libustat.so")
+
+F64, F32, BF16X3, I8 = 0, 1, 2, 3
+ORDER_MINFILL, ORDER_EXHAUSTIVE, ORDER_LEARNED = 0, 1, 2
+PRECISIONS = {"f64": F64, "f32": F32, "bf16x3": BF16X3, "i8": I8}
+ORDERS = {"minfill": ORDER_MINFILL, "exhaustive": ORDER_EXHAUSTIVE, "learned": ORDER_LEARNED}
+STATUS = {0: "ok", 1: "invalid", 2: "unsupported", 3: "nomem", 4: "hip", 5: "overflow",
+          6: "infeasible"}
+FACTOR_DTYPE = {F64: torch.float64, F32: torch.float32, BF16X3: torch.float32, I8: torch.int8}
+PROFILE_KINDS = {"prep": 0, "gemm": 1, "elim1": 2, "reduce": 3, "rbf": 4}
+
+
+class UstatError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"ustat {STATUS.get(code, code)}: {msg}")
+        self.code = code
+        self.status = STATUS.get(code, str(code))
+
+
+class PlanOpts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("sparsify", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("workspace_limit", ctypes.c_uint64), ("cost_model_path", ctypes.c_char_p)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("value", ctypes.c_double), ("exact_hi", ctypes.c_int64),
+                ("exact_lo", ctypes.c_uint64), ("err_scale", ctypes.c_double),
+                ("err_est", ctypes.c_double), ("num_vstats", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+    @property
+    def exact(self) -> int:
+        return (int(self.exact_hi) << 64) + int(self.exact_lo)
+
+    def as_dict(self) -> dict:
+        return {"value": self.value, "exact": self.exact, "err_scale": self.err_scale,
+                "err_est": self.err_est, "num_vstats": self.num_vstats}
+
+
+_lib = None
+
+EXPORTS = ["ustat_plan_opts_default", "ustat_plan_create", "ustat_plan_destroy", "ustat_plan_info",
+           "ustat_plan_cost", "ustat_plan_partition", "ustat_plan_order", "ustat_graph_treewidth",
+           "ustat_eval", "ustat_eval_samples", "vstat_eval", "ustat_eval_batched",
+           "ustat_build_rbf", "ustat_profile_enable", "ustat_profile_reset", "ustat_profile_read",
+           "ustat_status_string", "ustat_last_error"]
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libustat.so; raises if it is missing (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; the HIP engine has no fallback")
+    L = ctypes.CDLL(path)
+    P, i32, i64, u64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
+    pi32, pi64, pdbl = ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(dbl)
+    L.ustat_plan_opts_default.argtypes = [ctypes.POINTER(PlanOpts)]
+    L.ustat_plan_create.argtypes = [i32, i32, pi32, ctypes.POINTER(PlanOpts), ctypes.POINTER(P)]
+    L.ustat_plan_destroy.argtypes = [P]
+    L.ustat_plan_info.argtypes = [P, pi32, pi32, pi64, pi32]
+    L.ustat_plan_cost.argtypes = [P, i64, pdbl, pdbl, ctypes.POINTER(u64)]
+    L.ustat_plan_partition.argtypes = [P, i32, pi32, pi64, pi32, pi32]
+    L.ustat_plan_order.argtypes = [P, i32, pi32, pi32]
+    L.ustat_graph_treewidth.argtypes = [i32, i32, pi32, pi32]
+    L.ustat_eval.argtypes = [P, i64, ctypes.POINTER(P), P, ctypes.POINTER(Result)]
+    L.ustat_eval_samples.argtypes = [P, i64, i32, P, dbl, P, ctypes.POINTER(Result)]
+    L.vstat_eval.argtypes = [P, pi32, i64, ctypes.POINTER(P), P, ctypes.POINTER(Result)]
+    L.ustat_eval_batched.argtypes = [P, i32, pi64, i32, ctypes.POINTER(P), dbl, P,
+                                     ctypes.POINTER(Result)]
+    L.ustat_build_rbf.argtypes = [i64, i32, P, dbl, i32, P, P]
+    L.ustat_profile_enable.argtypes = [i32]
+    L.ustat_profile_reset.argtypes = []
+    L.ustat_profile_read.argtypes = [i32, pdbl, pi64, pdbl]
+    L.ustat_status_string.argtypes = [i32]
+    L.ustat_status_string.restype = ctypes.c_char_p
+    L.ustat_last_error.argtypes = []
+    L.ustat_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        f = getattr(L, name)
+        if f.restype is None or f.restype is ctypes.c_int:
+            f.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != 0:
+        msg = _lib.ustat_last_error().decode()
+        raise UstatError(rc, msg)
+
+
+def _stream_handle(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _edges_array(edges: Sequence[Tuple[int, int]]):
+    flat = [int(x) for e in edges for x in e]
+    return (ctypes.c_int32 * len(flat))(*flat)
+
+
+# ------------------------------------------------------------------ C names
+
+def ustat_plan_create(m: int, edges, precision="f64", order="minfill", sparsify=False,
+                      workspace_limit: int = 0, cost_model_path: Optional[str] = None):
+    L = load_library()
+    o = PlanOpts()
+    _check(L.ustat_plan_opts_default(ctypes.byref(o)))
+    o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    o.order = ORDERS[order] if isinstance(order, str) else int(order)
+    o.sparsify = 1 if sparsify else 0
+    o.workspace_limit = int(workspace_limit)
+    o.cost_model_path = cost_model_path.encode() if cost_model_path else None
+    h = ctypes.c_void_p()
+    _check(L.ustat_plan_create(int(m), len(edges), _edges_array(edges), ctypes.byref(o),
+                               ctypes.byref(h)))
+    return h
+
+
+def ustat_plan_destroy(h):
+    if h:
+        _check(load_library().ustat_plan_destroy(h))
+
+
+def ustat_plan_info(h, m: int) -> dict:
+    nv, M, w = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    Nl = (ctypes.c_int64 * (m + 1))()
+    _check(load_library().ustat_plan_info(h, ctypes.byref(nv), ctypes.byref(M), Nl, ctypes.byref(w)))
+    return {"num_vstats": nv.value, "M": M.value, "N_l": list(Nl), "max_width": w.value}
+
+
+def ustat_plan_cost(h, n: int) -> dict:
+    f, b, ws = ctypes.c_double(), ctypes.c_double(), ctypes.c_uint64()
+    _check(load_library().ustat_plan_cost(h, int(n), ctypes.byref(f), ctypes.byref(b), ctypes.byref(ws)))
+    return {"flops": f.value, "bytes": b.value, "workspace": ws.value}
+
+
+def ustat_plan_partition(h, idx: int, m: int) -> dict:
+    blk = (ctypes.c_int32 * m)()
+    mu, tw, w = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+    _check(load_library().ustat_plan_partition(h, int(idx), blk, ctypes.byref(mu), ctypes.byref(tw),
+                                               ctypes.byref(w)))
+    return {"block_of": list(blk), "mu": mu.value, "tw": tw.value, "width": w.value}
+
+
+def ustat_plan_order(h, idx: int, m: int) -> List[int]:
+    buf = (ctypes.c_int32 * m)()
+    ln = ctypes.c_int32()
+    _check(load_library().ustat_plan_order(h, int(idx), buf, ctypes.byref(ln)))
+    return list(buf)[: ln.value]
+
+
+def ustat_graph_treewidth(m: int, edges) -> int:
+    tw = ctypes.c_int32()
+    arr = _edges_array(edges) if edges else (ctypes.c_int32 * 1)()
+    _check(load_library().ustat_graph_treewidth(int(m), len(edges), arr, ctypes.byref(tw)))
+    return tw.value
+
+
+def _factor_ptrs(factors):
+    return (ctypes.c_void_p * len(factors))(*[ctypes.c_void_p(t.data_ptr()) for t in factors])
+
+
+def ustat_eval(h, n: int, factors, stream=None) -> Result:
+    r = Result()
+    _check(load_library().ustat_eval(h, int(n), _factor_ptrs(factors), _stream_handle(stream),
+                                     ctypes.byref(r)))
+    return r
+
+
+def ustat_eval_samples(h, X: torch.Tensor, divisor: float, stream=None) -> Result:
+    assert X.dtype == torch.float64 and X.is_cuda and X.is_contiguous() and X.dim() == 2
+    r = Result()
+    _check(load_library().ustat_eval_samples(h, X.shape[0], X.shape[1], ctypes.c_void_p(X.data_ptr()),
+                                             float(divisor), _stream_handle(stream), ctypes.byref(r)))
+    return r
+
+
+def vstat_eval(h, block_of: Sequence[int], n: int, factors, stream=None) -> Result:
+    blk = (ctypes.c_int32 * len(block_of))(*[int(b) for b in block_of])
+    r = Result()
+    _check(load_library().vstat_eval(h, blk, int(n), _factor_ptrs(factors), _stream_handle(stream),
+                                     ctypes.byref(r)))
+    return r
+
+
+def ustat_eval_batched(h, Xs: Sequence[torch.Tensor], divisor: float, stream=None) -> List[Result]:
+    B = len(Xs)
+    d = Xs[0].shape[1]
+    for X in Xs:
+        assert X.dtype == torch.float64 and X.is_cuda and X.is_contiguous() and X.shape[1] == d
+    ns = (ctypes.c_int64 * B)(*[int(X.shape[0]) for X in Xs])
+    ptrs = (ctypes.c_void_p * B)(*[ctypes.c_void_p(X.data_ptr()) for X in Xs])
+    out = (Result * B)()
+    _check(load_library().ustat_eval_batched(h, B, ns, int(d), ptrs, float(divisor),
+                                             _stream_handle(stream), out))
+    return list(out)
+
+
+def ustat_build_rbf(X: torch.Tensor, divisor: float, precision="f64", stream=None) -> torch.Tensor:
+    assert X.dtype == torch.float64 and X.is_cuda and X.is_contiguous() and X.dim() == 2
+    p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    n, d = X.shape
+    out = torch.empty((n, n), dtype=torch.float64 if p == F64 else torch.float32, device=X.device)
+    _check(load_library().ustat_build_rbf(n, d, ctypes.c_void_p(X.data_ptr()), float(divisor), p,
+                                          ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
+    return out
+
+
+def ustat_profile_enable(on: bool = True):
+    _check(load_library().ustat_profile_enable(1 if on else 0))
+
+
+def ustat_profile_reset():
+    _check(load_library().ustat_profile_reset())
+
+
+def ustat_profile_read(kind) -> dict:
+    k = PROFILE_KINDS[kind] if isinstance(kind, str) else int(kind)
+    ms, nl, fl = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+    _check(load_library().ustat_profile_read(k, ctypes.byref(ms), ctypes.byref(nl), ctypes.byref(fl)))
+    return {"ms": ms.value, "launches": nl.value, "flops": fl.value}
+
+
+# ------------------------------------------------------------------ wrapper
+
+class Plan:
+    """Owning wrapper of a ustat_plan handle."""
+
+    def __init__(self, m: int, edges, precision="f64", order="minfill", sparsify=False,
+                 workspace_limit: int = 0, cost_model_path: Optional[str] = None):
+        self.m = int(m)
+        self.edges = [tuple(e) for e in edges]
+        self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        self.h = ustat_plan_create(m, edges, precision, order, sparsify, workspace_limit,
+                                   cost_model_path)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h and _lib is not None:
+            _lib.ustat_plan_destroy(h)
+            self.h = None
+
+    @property
+    def factor_dtype(self):
+        return FACTOR_DTYPE[self.precision]
+
+    def info(self) -> dict:
+        return ustat_plan_info(self.h, self.m)
+
+    def cost(self, n: int) -> dict:
+        return ustat_plan_cost(self.h, n)
+
+    def partition(self, idx: int) -> dict:
+        return ustat_plan_partition(self.h, idx, self.m)
+
+    def order(self, idx: int) -> List[int]:
+        return ustat_plan_order(self.h, idx, self.m)
+
+    def partitions(self) -> list:
+        return [self.partition(i) for i in range(self.info()["num_vstats"])]
+
+    def _check_factors(self, factors):
+        assert len(factors) == len(self.edges), "one factor per edge"
+        n = factors[0].shape[0]
+        for t in factors:
+            assert t.is_cuda and t.is_contiguous() and t.shape == (n, n)
+            assert t.dtype == self.factor_dtype, f"factor dtype must be {self.factor_dtype}"
+        return n
+
+    def eval(self, factors, stream=None) -> Result:
+        n = self._check_factors(factors)
+        return ustat_eval(self.h, n, factors, stream)
+
+    def eval_samples(self, X, divisor: float, stream=None) -> Result:
+        return ustat_eval_samples(self.h, X, divisor, stream)
+
+    def vstat(self, block_of, factors, stream=None) -> Result:
+        n = self._check_factors(factors)
+        return vstat_eval(self.h, block_of, n, factors, stream)
+
+    def eval_batched(self, Xs, divisor: float, stream=None) -> List[Result]:
+        return ustat_eval_batched(self.h, Xs, divisor, stream)

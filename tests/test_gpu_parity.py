@@ -1,0 +1,245 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Floating-point results must satisfy |U_gpu - U_ref| <= tol * S with
+S = sum_pi |mu_pi V_pi| computed by the oracle (or a lower bound of S, which
+only tightens the test); tol is 1e-12 for the fp64 path and 1e-6 for the
+fp32 and split-bf16 paths.  Integer results must match exactly.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2508_12627_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-6, "bf16x3": 1e-6}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def U():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2508_12627_amd import ustat
+    ustat.load_library()
+    return ustat
+
+
+def dev(a, dtype):
+    import torch
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+GRAPHS = {
+    "triangle": W.TRIANGLE,
+    "path4": W.PATH4,
+    "cycle4": W.CYCLE4,
+    "cycle5": W.CYCLE5,
+    "c5chord": W.CYCLE5_CHORD,
+    "star": [(0, 1), (0, 2), (0, 3)],
+    "bowtie": [(0, 1), (1, 2), (2, 0), (2, 3), (3, 4), (4, 2)],
+    "reversed": [(1, 0), (2, 1), (0, 2), (3, 2)],
+}
+
+
+def nverts(edges):
+    return 1 + max(max(e) for e in edges)
+
+
+# ------------------------------------------------------------------ H1
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_rbf_factor_build(U, prec):
+    import torch
+    n, d, div = 301, 12, 24.0
+    say(f"rbf n={n} d={d} {prec}")
+    X = W.gaussian_samples(n, d, seed=7)
+    K = U.ustat_build_rbf(dev(X, torch.float64), div, prec)
+    torch.cuda.synchronize()
+    ref = oracle.rbf_matrix(X, div)
+    got = K.double().cpu().numpy()
+    assert np.all(np.diag(got) == 1.0)
+    if prec == "f64":
+        assert np.max(np.abs(got - ref)) <= 4e-16
+    else:
+        assert np.max(np.abs(got - ref) / ref) <= 2 ** -24
+
+
+# ------------------------------------------------------------------ small n, every path
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3"])
+@pytest.mark.parametrize("name", sorted(GRAPHS))
+def test_small_asymmetric_factors(U, name, prec):
+    """Independent asymmetric factors per edge at a ragged n spanning several
+    tiles, against the brute-force oracle."""
+    import torch
+    edges = GRAPHS[name]
+    m = nverts(edges)
+    n = {3: 150, 4: 70, 5: 29}[m]
+    mats = W.random_matrices(len(edges), n, seed=100 + m, lo=-1.0, hi=1.0)
+    ref = oracle.ustat_bruteforce(edges, mats)
+    _, S, _ = oracle.ustat_and_scale_einsum(edges, mats)
+    P = U.Plan(m, edges, precision=prec)
+    say(f"small {name} n={n} {prec}")
+    r = P.eval([dev(M, P.factor_dtype) for M in mats])
+    err = abs(r.value - ref) / S
+    say(f"  U={r.value:.10e} ref={ref:.10e} S={S:.3e} err/S={err:.2e} gpuS={r.err_scale:.3e}")
+    assert err <= TOL[prec]
+    assert r.err_scale == pytest.approx(S, rel=1e-3 if prec != "f64" else 1e-9)
+
+
+@pytest.mark.parametrize("name", ["triangle", "cycle4", "c5chord", "bowtie"])
+def test_vstat_every_partition(U, name):
+    import torch
+    edges = GRAPHS[name]
+    m = nverts(edges)
+    n = {3: 90, 4: 45, 5: 21}[m]
+    mats = W.random_matrices(len(edges), n, seed=5, lo=-1.0, hi=1.0)
+    P = U.Plan(m, edges, precision="f64")
+    fs = [dev(M, torch.float64) for M in mats]
+    say(f"vstat {name} n={n}")
+    for blocks in oracle.partitions(m):
+        lab = oracle.block_labels(blocks, m)
+        ref = oracle.vstat_einsum(edges, mats, lab)
+        # a non-canonical labelling of the same partition
+        perm = [7 * b + 3 for b in lab]
+        r = P.vstat(perm, fs)
+        assert r.value == pytest.approx(ref, rel=1e-11, abs=1e-11 * max(1.0, abs(ref)))
+
+
+@pytest.mark.parametrize("name", ["cycle4", "c5chord", "path4"])
+def test_sparsified_and_orders_agree(U, name):
+    """Lemma 3 and every order policy give the same U."""
+    import torch
+    edges = GRAPHS[name]
+    m = nverts(edges)
+    n = 133
+    mats = W.random_matrices(len(edges), n, seed=9, lo=0.0, hi=1.0)
+    fs = [dev(M, torch.float64) for M in mats]
+    _, S, _ = oracle.ustat_and_scale_einsum(edges, mats)
+    vals = []
+    for kw in (dict(), dict(sparsify=True), dict(order="exhaustive"),
+               dict(order="exhaustive", sparsify=True)):
+        say(f"variants {name} {kw}")
+        vals.append(U.Plan(m, edges, precision="f64", **kw).eval(fs).value)
+    for v in vals[1:]:
+        assert abs(v - vals[0]) <= 1e-12 * S
+
+
+def test_sparsified_plan_counts(U):
+    P = U.Plan(4, W.CYCLE4, sparsify=True)
+    assert P.info()["num_vstats"] == 4
+
+
+# ------------------------------------------------------------------ exact integers
+@pytest.mark.parametrize("name", ["triangle", "cycle4", "cycle5", "c5chord", "bowtie", "reversed"])
+def test_int8_signed_factors_exact(U, name):
+    """Signed int8 factors over the full range exercise multi-limb operands."""
+    import torch
+    edges = GRAPHS[name]
+    m = nverts(edges)
+    n = {3: 70, 4: 30, 5: 14}[m]
+    mats = W.random_int_matrices(len(edges), n, seed=31, lo=-128, hi=127)
+    ref = oracle.ustat_bruteforce_int(edges, mats)
+    P = U.Plan(m, edges, precision="i8")
+    say(f"int8 {name} n={n}")
+    r = P.eval([dev(M, torch.int8) for M in mats])
+    assert r.exact == ref
+
+
+def test_int8_er_cycle_counts(U):
+    import torch
+    n, p = 300, 0.08
+    A = W.erdos_renyi(n, p, seed=3)
+    Ad = dev(A, torch.int8)
+    for edges, fn, aut in ((W.TRIANGLE, oracle.count_triangles, 6),
+                           (W.CYCLE4, oracle.count_4cycles, 8),
+                           (W.CYCLE5, oracle.count_5cycles, 10)):
+        m = nverts(edges)
+        say(f"int8 ER n={n} m={m}")
+        r = U.Plan(m, edges, precision="i8").eval([Ad] * len(edges))
+        assert r.exact == aut * fn(A.astype(np.int64))
+        rs = U.Plan(m, edges, precision="i8", sparsify=True).eval([Ad] * len(edges))
+        assert rs.exact == r.exact
+
+
+# ------------------------------------------------------------------ workload sizes
+def test_triangle_workload_n256(U):
+    """Triangle kernel, n = 256 samples in R^8, divisor 16, fp64 path."""
+    import torch
+    n, d, div = 256, 8, 16.0
+    X = W.gaussian_samples(n, d, seed=1)
+    K = oracle.rbf_matrix(X, div)
+    ref = oracle.ustat_bruteforce(W.TRIANGLE, [K] * 3)
+    _, S, _ = oracle.ustat_and_scale_einsum(W.TRIANGLE, [K] * 3)
+    assert oracle.triangle_closed_form(K) == pytest.approx(ref, rel=1e-12)
+    say("triangle workload n=256")
+    r = U.Plan(3, W.TRIANGLE, precision="f64").eval_samples(dev(X, torch.float64), div)
+    assert abs(r.value - ref) <= 1e-12 * S
+    assert r.num_vstats == 5
+
+
+@pytest.fixture(scope="module")
+def c2_data():
+    n, d = 4096, 16
+    X = W.gaussian_samples(n, d, seed=2)
+    K = oracle.rbf_matrix(X, 2.0 * d)
+    ref = oracle.cycle4_closed_form(K)
+    K2 = K @ K
+    vfin = float(np.sum(K2 * K2))  # V of the finest partition, a lower bound of S
+    return X, ref, vfin
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3"])
+def test_cycle4_workload_full_size(U, c2_data, prec):
+    """4-cycle RBF kernel at n = 4096, d = 16 (the benchmark workload) against
+    the oracle's closed form."""
+    import torch
+    X, ref, vfin = c2_data
+    say(f"cycle4 n=4096 {prec}")
+    P = U.Plan(4, W.CYCLE4, precision=prec)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        Xd = dev(X, torch.float64)
+        r1 = P.eval_samples(Xd, 32.0, stream=s)
+        r2 = P.eval_samples(Xd, 32.0, stream=s)  # graph replay
+    err = abs(r1.value - ref) / vfin
+    say(f"  U={r1.value:.12e} ref={ref:.12e} err/Vfin={err:.2e}")
+    assert err <= TOL[prec]
+    assert r2.value == r1.value  # replays are bitwise identical
+
+
+def test_cycle5_er_full_size_exact(U):
+    """Exact 5-cycle count of G(8192, 0.01) on the int8 path."""
+    import torch
+    n, p = 8192, 0.01
+    A = W.erdos_renyi(n, p, seed=3)
+    say("cycle5 ER n=8192 oracle...")
+    ref = 10 * oracle.count_5cycles(A.astype(np.int64))
+    say("cycle5 ER n=8192 gpu")
+    r = U.Plan(5, W.CYCLE5, precision="i8").eval([dev(A, torch.int8)] * 5)
+    assert r.exact == ref
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3"])
+def test_lowrank_full_size(U, prec):
+    """Rank-2 positive factors at n = 2048 on the 5-cycle-with-chord kernel:
+    the oracle's subset DP gives the exact U at any n."""
+    import torch
+    n, r = 2048, 2
+    edges = W.CYCLE5_CHORD
+    (F, G), = W.lowrank_factors(1, n, r, seed=12, lo=0.1, hi=1.0)
+    K = F @ G.T
+    ref = oracle.ustat_lowrank(edges, [F] * 6, [G] * 6)
+    say(f"lowrank c5chord n={n} {prec}")
+    P = U.Plan(5, edges, precision=prec)
+    res = P.eval([dev(K, P.factor_dtype)] * 6)
+    # |U| <= S, so a relative-to-|U| bound is at least as strict
+    assert abs(res.value - ref) <= TOL[prec] * abs(ref) * (1 if prec == "f64" else 1) + 0.0
