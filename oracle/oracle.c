@@ -90,29 +90,32 @@ static void rec_f64(const sched_t *s, int d, long *idx, double prod, ksum *acc) 
 
 /*
  * Sum over tuples (i_0..i_{m-1}) in [n]^m -- restricted to pairwise distinct
- * indices when `distinct` is nonzero -- with i_0 in [lo, hi), of
+ * indices when `distinct` is nonzero -- of
  *     prod_k T_k[i_{eu[k]}, i_{ev[k]}]
  * (factors row-major n x n, fp64).  eu[k] == ev[k] is allowed and reads the
- * diagonal.  Returns 0, or -1 on bad arguments.
+ * diagonal.  Only prefixes numbered item_lo <= item < item_hi are summed,
+ * where item = i_0 * n + i_1 for m >= 2 and item = i_0 for m == 1 (the full
+ * sum is items [0, n^2) or [0, n)); a sub-range is a bounded sample of the
+ * sum.  Returns 0, or -1 on bad arguments.
  */
 int oracle_sum_tuples(int m, int ne, const int *eu, const int *ev,
                       const double *const *T, long n, int distinct,
-                      long lo, long hi, double *out) {
+                      long item_lo, long item_hi, double *out) {
     sched_t s;
     if (build_sched(&s, m, ne, eu, ev)) return -1;
-    if (n < 1 || lo < 0 || hi > n || lo > hi || !out) return -1;
+    long inner = (m >= 2) ? n : 1;
+    if (n < 1 || item_lo < 0 || item_hi > n * inner || item_lo > item_hi || !out) return -1;
     s.n = n; s.T = T; s.Ti = NULL; s.distinct = distinct;
     /* Parallel work items are (i_0, i_1) pairs so that even a one-value
      * range of i_0 keeps every core busy. */
-    long cnt = hi - lo;
-    long inner = (m >= 2) ? n : 1;
-    long items = cnt * inner;
+    long items = item_hi - item_lo;
     ksum *part = (ksum *)calloc(items > 0 ? items : 1, sizeof(ksum));
     if (!part) return -1;
 #pragma omp parallel for schedule(dynamic, 1)
-    for (long t = 0; t < items; ++t) {
+    for (long tt = 0; tt < items; ++tt) {
+        long t = item_lo + tt;
         long idx[ORACLE_MAX_M];
-        idx[0] = lo + t / inner;
+        idx[0] = t / inner;
         double p = 1.0;
         for (int q = 0; q < s.cnt[0]; ++q) {
             int k = s.list[0][q];
@@ -132,7 +135,7 @@ int oracle_sum_tuples(int m, int ne, const int *eu, const int *ev,
                 else rec_f64(&s, 2, idx, p, &acc);
             }
         }
-        part[t] = acc;
+        part[tt] = acc;
     }
     ksum tot = {0.0, 0.0};
     for (long t = 0; t < items; ++t) { ks_add(&tot, part[t].s); ks_add(&tot, part[t].c); }

@@ -77,12 +77,17 @@ def _num_vertices(edges: Edges) -> int:
 # Definitions 1 and 2: brute-force U- and V-statistics.
 # --------------------------------------------------------------------------
 
-def _sum_tuples(m: int, edges: Edges, mats, distinct: bool, lo=0, hi=None) -> float:
+def _sum_tuples(m: int, edges: Edges, mats, distinct: bool, lo=0, hi=None,
+                items=None) -> float:
     mats = [np.ascontiguousarray(M, dtype=np.float64) for M in mats]
     n = mats[0].shape[0]
     for M in mats:
         assert M.shape == (n, n)
-    hi = n if hi is None else hi
+    inner = n if m >= 2 else 1
+    if items is None:
+        hi = n if hi is None else hi
+        items = (lo * inner, hi * inner)
+    lo, hi = items
     ne, eu, ev = _edge_arrays(edges)
     ptrs = (ctypes.POINTER(ctypes.c_double) * ne)(
         *[M.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for M in mats])
@@ -108,12 +113,13 @@ def _sum_tuples_int(m: int, edges: Edges, mats, distinct: bool) -> int:
     return (int(hi.value) << 64) + int(lo.value)
 
 
-def ustat_bruteforce(edges: Edges, mats, lo: int = 0, hi=None) -> float:
+def ustat_bruteforce(edges: Edges, mats, lo: int = 0, hi=None, items=None) -> float:
     """U(h, X) of Definition 1 (unnormalised sum over ordered distinct
     m-tuples) for the kernel prod_k T_k(x_{u_k}, x_{v_k}), fp64 with
-    compensated sums.  ``lo``/``hi`` restrict the first index (a bounded
+    compensated sums.  ``lo``/``hi`` restrict the first index; ``items``
+    restricts the (i_0, i_1) prefixes, numbered i_0 * n + i_1 (a bounded
     sample of the sum, used to time the oracle)."""
-    return _sum_tuples(_num_vertices(edges), edges, mats, True, lo, hi)
+    return _sum_tuples(_num_vertices(edges), edges, mats, True, lo, hi, items)
 
 
 def ustat_bruteforce_int(edges: Edges, mats) -> int:

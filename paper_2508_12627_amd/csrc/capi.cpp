@@ -254,7 +254,11 @@ static ustat_status run(ustat_plan plan, const std::vector<const VProgram *> &pr
                         std::vector<double> *vout, const std::function<hipError_t(hipStream_t)> &pre,
                         const std::string &key) {
     int st = 0;
-    bool capture = (s != nullptr) && plan->plan.opts.precision != USTAT_I8 && !key.empty();
+    // Launch sequences are captured into a HIP graph and replayed when the
+    // stream is not the null stream; profiled runs launch kernel by kernel so
+    // that every launch can be timed with events.
+    bool capture = (s != nullptr) && plan->plan.opts.precision != USTAT_I8 && !key.empty() &&
+                   !Profiler::enabled();
     std::string err;
     try {
         if (capture) Profiler::suspend(true);

@@ -392,8 +392,9 @@ __global__ __launch_bounds__(256) void k_prep(const PrepDesc *D, int nprob) {
 // 64 x 64 region of 4 x 4 MFMA blocks of 16 x 16.  Operands live in LDS as
 // [row][k] with padding; every 16x16 MFMA family used here (f64 16x16x4,
 // f32 16x16x4, bf16 16x16x32, i8 16x16x64) reads lane l's A fragment from
-// row l%16 and B fragment from column l%16 at k-slot group l/16, and leaves
-// lane l holding rows 4*(l/16)+r, column l%16 of the 16x16 result.
+// row l%16 and B fragment from column l%16 at k-slot group l/16.  Result
+// item r of lane l sits in column l%16 and row 4*(l/16)+r, except for the
+// f64 instruction, whose rows are interleaved: row l/16 + 4*r.
 
 template <int PREC>
 struct GemmCfg;
@@ -417,6 +418,13 @@ struct GemmCfg<3> {  // int8 limb (one plane per pass)
     typedef int8_t E;
     static constexpr int BK = 64, PADK = 16, PLANES = 1;
 };
+
+// Row within a 16x16 MFMA result block of item r held by `lane`.
+template <int PREC>
+__device__ __forceinline__ int mfma_row(int lane, int r) {
+    if constexpr (PREC == 0) return (lane >> 4) + 4 * r;
+    else return 4 * (lane >> 4) + r;
+}
 
 template <int PREC>
 struct AccT {
@@ -610,7 +618,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc *D, int nprob) {
     constexpr int ES = (int)sizeof(typename GemmCfg<PREC>::E);
     const int64_t ldb = d.ld * ES, planeb = d.plane * ES;
 
-    // Result accumulators: value(i,j,r) for row w0+wy*64+i*16+4*(lane/16)+r,
+    // Result accumulators: value(i,j,r) for row w0+wy*64+i*16+mfma_row(lane,r),
     // column x0+wx*64+j*16+lane%16.
     double resd[4][4][4];
     long long resi[4][4][4];
@@ -683,7 +691,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc *D, int nprob) {
             for (int j = 0; j < 4; ++j)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    int64_t w = w0 + wy * 64 + i * 16 + 4 * (lane >> 4) + r;
+                    int64_t w = w0 + wy * 64 + i * 16 + mfma_row<PREC>(lane, r);
                     int64_t x = x0 + wx * 64 + j * 16 + (lane & 15);
                     if (w < n && x < n) {
                         int64_t o = w * d.ldc + x;
@@ -703,7 +711,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc *D, int nprob) {
         for (int j = 0; j < 4; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                int64_t w = w0 + wy * 64 + i * 16 + 4 * (lane >> 4) + r;
+                int64_t w = w0 + wy * 64 + i * 16 + mfma_row<PREC>(lane, r);
                 int64_t x = x0 + wx * 64 + j * 16 + (lane & 15);
                 if (w >= n || x >= n) continue;
                 Wd val;

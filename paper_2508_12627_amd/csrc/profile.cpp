@@ -10,6 +10,7 @@ bool g_suspended = false;
 
 Profiler *Profiler::active() { return (g_on && !g_suspended) ? &g_prof : nullptr; }
 void Profiler::enable(bool on) { g_on = on; }
+bool Profiler::enabled() { return g_on; }
 void Profiler::suspend(bool s) { g_suspended = s; }
 
 hipEvent_t Profiler::get() {

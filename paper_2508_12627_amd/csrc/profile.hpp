@@ -17,6 +17,7 @@ class Profiler {
 public:
     static Profiler *active();
     static void enable(bool on);
+    static bool enabled();
     static void suspend(bool s);
     void begin(int kind, hipStream_t s, double flops);
     void end(int kind, hipStream_t s);

@@ -74,24 +74,37 @@ def test_rbf_factor_build(U, prec):
 
 
 # ------------------------------------------------------------------ small n, every path
+@pytest.mark.parametrize("sign", ["signed", "nonneg"])
 @pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3"])
 @pytest.mark.parametrize("name", sorted(GRAPHS))
-def test_small_asymmetric_factors(U, name, prec):
+def test_small_asymmetric_factors(U, name, prec, sign):
     """Independent asymmetric factors per edge at a ragged n spanning several
-    tiles, against the brute-force oracle."""
+    tiles, against the brute-force oracle.
+
+    Non-negative factors (like the RBF kernels) are held to tol * S.  With
+    signed factors the V-statistics cancel internally, so the rounding error
+    of a contraction scales with the V-statistics of |T| rather than of T:
+    there the split-bf16 path (per-product error below 3 * 2^-18) is held to
+    2^-14 * S_abs, S_abs = sum |mu_pi| V_pi(|T|); fp64 and fp32 still meet
+    tol * S."""
     import torch
     edges = GRAPHS[name]
     m = nverts(edges)
     n = {3: 150, 4: 70, 5: 29}[m]
-    mats = W.random_matrices(len(edges), n, seed=100 + m, lo=-1.0, hi=1.0)
+    lo = -1.0 if sign == "signed" else 0.0
+    mats = W.random_matrices(len(edges), n, seed=100 + m, lo=lo, hi=1.0)
     ref = oracle.ustat_bruteforce(edges, mats)
     _, S, _ = oracle.ustat_and_scale_einsum(edges, mats)
     P = U.Plan(m, edges, precision=prec)
-    say(f"small {name} n={n} {prec}")
+    say(f"small {name} n={n} {prec} {sign}")
     r = P.eval([dev(M, P.factor_dtype) for M in mats])
     err = abs(r.value - ref) / S
     say(f"  U={r.value:.10e} ref={ref:.10e} S={S:.3e} err/S={err:.2e} gpuS={r.err_scale:.3e}")
-    assert err <= TOL[prec]
+    if prec == "bf16x3" and sign == "signed":
+        _, S_abs, _ = oracle.ustat_and_scale_einsum(edges, [np.abs(M) for M in mats])
+        assert abs(r.value - ref) <= 2.0 ** -14 * S_abs
+    else:
+        assert err <= TOL[prec]
     assert r.err_scale == pytest.approx(S, rel=1e-3 if prec != "f64" else 1e-9)
 
 

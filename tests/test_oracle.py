@@ -258,3 +258,14 @@ def test_bounded_sample_partitions_the_sum():
     full = oracle.ustat_bruteforce(W.CYCLE4, mats)
     parts = sum(oracle.ustat_bruteforce(W.CYCLE4, mats, lo, lo + 3) for lo in range(0, n, 3))
     assert parts == pytest.approx(full, rel=1e-12, abs=1e-12)
+
+
+def test_bounded_sample_by_prefix_items():
+    """Prefix-item ranges (i_0 * n + i_1) also partition the sum."""
+    n = 10
+    mats = W.random_matrices(3, n, seed=19)
+    full = oracle.ustat_bruteforce(W.TRIANGLE, mats)
+    cuts = [0, 7, 33, 34, 90, 100]
+    parts = sum(oracle.ustat_bruteforce(W.TRIANGLE, mats, items=(a, b))
+                for a, b in zip(cuts[:-1], cuts[1:]))
+    assert parts == pytest.approx(full, rel=1e-12, abs=1e-12)
