@@ -17,6 +17,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // ----------------------------------------------------------------- helpers
 
@@ -256,26 +257,25 @@ __global__ __launch_bounds__(256) void k_reduce(const ReduceDesc *D, int nprob) 
     __shared__ Wd red[256];
     Wd acc = 0;
     if (d.len == 1) {
-        // scalar partials (wide), summed in tile order by thread 0
-        if (t == 0)
-            for (int64_t q = 0; q < d.T; ++q) acc += static_cast<const Wd *>(d.part)[q * d.stride];
-        if (t == 0) static_cast<Wd *>(d.out)[0] = acc;
-        return;
-    }
-    for (int64_t j = t; j < d.len; j += 256) {
-        A s = 0;
-        for (int64_t q = 0; q < d.T; ++q) s += static_cast<const A *>(d.part)[q * d.stride + j];
-        Wd w = (Wd)s;
-        for (int q = 0; q < d.nmul; ++q) w *= (Wd)load_vec<DOM>(d.mul[q], j);
-        acc += w;
+        // scalar (wide) partials: thread t sums q = t, t+256, ... in order
+        for (int64_t q = t; q < d.T; q += 256) acc += static_cast<const Wd *>(d.part)[q * d.stride];
+    } else {
+        for (int64_t j = t; j < d.len; j += 256) {
+            A s = 0;
+            for (int64_t q = 0; q < d.T; ++q) s += static_cast<const A *>(d.part)[q * d.stride + j];
+            Wd w = (Wd)s;
+            for (int q = 0; q < d.nmul; ++q) w *= (Wd)load_vec<DOM>(d.mul[q], j);
+            acc += w;
+        }
     }
     red[t] = acc;
     __syncthreads();
-    if (t == 0) {
-        Wd s = 0;
-        for (int q = 0; q < 256; ++q) s += red[q];
-        static_cast<Wd *>(d.out)[0] = s;
+    // fixed-order tree
+    for (int st = 128; st > 0; st >>= 1) {
+        if (t < st) red[t] += red[t + st];
+        __syncthreads();
     }
+    if (t == 0) static_cast<Wd *>(d.out)[0] = red[0];
 }
 
 // ----------------------------------------------------------------- elim0
@@ -294,11 +294,11 @@ __global__ __launch_bounds__(256) void k_elim0(const Elim0Desc *D, int nprob) {
     }
     red[t] = acc;
     __syncthreads();
-    if (t == 0) {
-        Wd s = 0;
-        for (int q = 0; q < 256; ++q) s += red[q];
-        static_cast<Wd *>(d.out)[0] = s;
+    for (int st = 128; st > 0; st >>= 1) {
+        if (t < st) red[t] += red[t + st];
+        __syncthreads();
     }
+    if (t == 0) static_cast<Wd *>(d.out)[0] = red[0];
 }
 
 // ----------------------------------------------------------------- prep
@@ -401,22 +401,22 @@ struct GemmCfg;
 template <>
 struct GemmCfg<0> {  // fp64
     typedef double E;
-    static constexpr int BK = 16, PADK = 2, PLANES = 1;
+    static constexpr int BK = 16, PLANES = 1;
 };
 template <>
 struct GemmCfg<1> {  // fp32
     typedef float E;
-    static constexpr int BK = 16, PADK = 4, PLANES = 1;
+    static constexpr int BK = 16, PLANES = 1;
 };
 template <>
 struct GemmCfg<2> {  // bf16 hi/lo
     typedef uint16_t E;
-    static constexpr int BK = 32, PADK = 8, PLANES = 2;
+    static constexpr int BK = 32, PLANES = 2;
 };
 template <>
 struct GemmCfg<3> {  // int8 limb (one plane per pass)
     typedef int8_t E;
-    static constexpr int BK = 64, PADK = 16, PLANES = 1;
+    static constexpr int BK = 64, PLANES = 1;
 };
 
 // Row within a 16x16 MFMA result block of item r held by `lane`.
@@ -439,7 +439,10 @@ struct AccT<3> {
     typedef i32x4 T;
 };
 
-// Load one 128 x BK tile (all planes) of an operand into registers.
+// Global <-> LDS staging of one 128 x BK tile (all planes) of an operand.
+// fp64 rows are padded to 144 bytes; the 64-byte rows of the other formats
+// are XOR-swizzled in 16-byte chunks so that the 16 rows read by one MFMA
+// fragment load fall in distinct banks.
 template <int PREC>
 struct TileIO {
     typedef GemmCfg<PREC> C;
@@ -447,10 +450,15 @@ struct TileIO {
     static constexpr int UPR = ROWB / 16;                            // 16B units per row
     static constexpr int UNITS = 128 * UPR * C::PLANES;
     static constexpr int PER = UNITS / 256;
-    static constexpr int LROW = (C::BK + C::PADK) * (int)sizeof(typename C::E);
+    static constexpr int LROW = (PREC == 0) ? ROWB + 16 : ROWB;
     static constexpr int PLANEB = 128 * LROW;
+    static constexpr int STAGE = PLANEB * C::PLANES;
 
-    __device__ static void load(uint4 (&r)[PER], const char *base, int64_t ldb, int64_t planeb,
+    __device__ static __forceinline__ int off(int row, int chunk) {
+        if constexpr (PREC == 0) return row * LROW + chunk * 16;
+        else return row * LROW + ((chunk ^ ((row >> 2) & 3)) << 4);
+    }
+    __device__ static void load(u32x4 (&r)[PER], const char *base, int64_t ldb, int64_t planeb,
                                 int64_t row0, int64_t k0b) {
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
@@ -459,17 +467,19 @@ struct TileIO {
             int uu = u % (128 * UPR);
             int row = uu / UPR, cu = uu % UPR;
             const char *g = base + pl * planeb + (row0 + row) * ldb + k0b + cu * 16;
-            r[i] = *reinterpret_cast<const uint4 *>(g);
+            // global address space: these loads only count against vmcnt, so
+            // waiting for LDS fragment reads never waits for the prefetch
+            r[i] = *(const __attribute__((address_space(1))) u32x4 *)(g);
         }
     }
-    __device__ static void store(const uint4 (&r)[PER], char *lds) {
+    __device__ static void store(const u32x4 (&r)[PER], char *lds) {
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
             int u = threadIdx.x + 256 * i;
             int pl = u / (128 * UPR);
             int uu = u % (128 * UPR);
             int row = uu / UPR, cu = uu % UPR;
-            *reinterpret_cast<uint4 *>(lds + pl * PLANEB + row * LROW + cu * 16) = r[i];
+            *reinterpret_cast<u32x4 *>(lds + pl * PLANEB + off(row, cu)) = r[i];
         }
     }
 };
@@ -511,10 +521,10 @@ __device__ __forceinline__ void mma_tile<1>(f32x4 (&acc)[4][4], const char *As, 
         float a[4], b[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            a[i] = *reinterpret_cast<const float *>(As + (wy * 64 + i * 16 + lr) * IO::LROW +
-                                                    (kk + lg) * 4);
-            b[i] = *reinterpret_cast<const float *>(Bs + (wx * 64 + i * 16 + lr) * IO::LROW +
-                                                    (kk + lg) * 4);
+            a[i] = *reinterpret_cast<const float *>(As + IO::off(wy * 64 + i * 16 + lr, kk >> 2) +
+                                                    lg * 4);
+            b[i] = *reinterpret_cast<const float *>(Bs + IO::off(wx * 64 + i * 16 + lr, kk >> 2) +
+                                                    lg * 4);
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i)
@@ -532,13 +542,14 @@ __device__ __forceinline__ void mma_tile<2>(f32x4 (&acc)[4][4], const char *As, 
     bf16x8 ah[4], al[4], bh[4], bl[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        const int ra = (wy * 64 + i * 16 + lr) * IO::LROW + lg * 16;
-        const int rb = (wx * 64 + i * 16 + lr) * IO::LROW + lg * 16;
+        const int ra = IO::off(wy * 64 + i * 16 + lr, lg);
+        const int rb = IO::off(wx * 64 + i * 16 + lr, lg);
         ah[i] = *reinterpret_cast<const bf16x8 *>(As + ra);
         al[i] = *reinterpret_cast<const bf16x8 *>(As + IO::PLANEB + ra);
         bh[i] = *reinterpret_cast<const bf16x8 *>(Bs + rb);
         bl[i] = *reinterpret_cast<const bf16x8 *>(Bs + IO::PLANEB + rb);
     }
+    // small cross terms first, then the leading hi*hi term
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -557,8 +568,8 @@ __device__ __forceinline__ void mma_tile<3>(i32x4 (&acc)[4][4], const char *As, 
     i32x4 a[4], b[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        a[i] = *reinterpret_cast<const i32x4 *>(As + (wy * 64 + i * 16 + lr) * IO::LROW + lg * 16);
-        b[i] = *reinterpret_cast<const i32x4 *>(Bs + (wx * 64 + i * 16 + lr) * IO::LROW + lg * 16);
+        a[i] = *reinterpret_cast<const i32x4 *>(As + IO::off(wy * 64 + i * 16 + lr, lg));
+        b[i] = *reinterpret_cast<const i32x4 *>(Bs + IO::off(wx * 64 + i * 16 + lr, lg));
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -568,17 +579,17 @@ __device__ __forceinline__ void mma_tile<3>(i32x4 (&acc)[4][4], const char *As, 
 }
 
 // K loop of one (A plane set, B plane set) pass with register prefetch and
-// double-buffered LDS.
+// double-buffered LDS (one barrier per K step).
 template <int PREC>
 __device__ __forceinline__ void gemm_pass(typename AccT<PREC>::T (&acc)[4][4], const char *Ab,
                                           const char *Bb, int64_t ldb, int64_t planeb,
                                           int64_t w0, int64_t x0, int64_t npad, char *lds) {
     typedef TileIO<PREC> IO;
-    constexpr int STAGE = IO::PLANEB * GemmCfg<PREC>::PLANES;
+    constexpr int STAGE = IO::STAGE;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, wy = wv >> 1, wx = wv & 1;
     constexpr int KB = GemmCfg<PREC>::BK * (int)sizeof(typename GemmCfg<PREC>::E);
     const int64_t nk = npad / GemmCfg<PREC>::BK;
-    uint4 ra[IO::PER], rb[IO::PER];
+    u32x4 ra[IO::PER], rb[IO::PER];
     IO::load(ra, Ab, ldb, planeb, w0, 0);
     IO::load(rb, Bb, ldb, planeb, x0, 0);
     IO::store(ra, lds);
@@ -588,41 +599,50 @@ __device__ __forceinline__ void gemm_pass(typename AccT<PREC>::T (&acc)[4][4], c
         const int cur = (int)(kt & 1);
         char *As = lds + cur * 2 * STAGE;
         char *Bs = As + STAGE;
-        if (kt + 1 < nk) {
-            IO::load(ra, Ab, ldb, planeb, w0, (kt + 1) * KB);
-            IO::load(rb, Bb, ldb, planeb, x0, (kt + 1) * KB);
-        }
+        // Prefetch the next K tile (the last step re-reads its own tile into
+        // the idle buffer, which keeps the loop free of branches).
+        const int64_t kn = (kt + 1 < nk) ? kt + 1 : kt;
+        IO::load(ra, Ab, ldb, planeb, w0, kn * KB);
+        IO::load(rb, Bb, ldb, planeb, x0, kn * KB);
         mma_tile<PREC>(acc, As, Bs, wy, wx, lane);
-        if (kt + 1 < nk) {
-            char *An = lds + (1 - cur) * 2 * STAGE;
-            IO::store(ra, An);
-            IO::store(rb, An + STAGE);
-        }
+        char *An = lds + (1 - cur) * 2 * STAGE;
+        IO::store(ra, An);
+        IO::store(rb, An + STAGE);
         __syncthreads();
     }
 }
 
+// Flat block index -> logical tile index.  Consecutive workgroups are
+// dispatched round-robin over the 8 XCDs; this gives each XCD a contiguous
+// range of logical tiles so that neighbouring tiles share its L2.
+__device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t G) {
+    const int64_t per = G / 8, rem = G % 8, x = bid % 8, idx = bid / 8;
+    return x * per + (x < rem ? x : rem) + idx;
+}
+
 template <int PREC>
-__global__ __launch_bounds__(256) void k_gemm(const GemmDesc *D, int nprob) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+void k_gemm(const GemmDesc *D, int nprob) {
     typedef TileIO<PREC> IO;
     typedef typename AccT<PREC>::T AT;
-    constexpr int STAGE = IO::PLANEB * GemmCfg<PREC>::PLANES;
     extern __shared__ __align__(16) char lds[];
-    const int64_t b = blockIdx.x;
+    const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
     const int p = find_problem(D, nprob, b);
     const GemmDesc &d = D[p];
     const int64_t local = b - d.tile_start;
-    const int64_t tm = local / d.tiles, tn = local % d.tiles;
+    // grouped tile order: 8 tile-rows per group, column-major inside it
+    const int64_t T = d.tiles, GM = 8;
+    const int64_t first = (local / (GM * T)) * GM;
+    const int64_t gsz = (T - first) < GM ? (T - first) : GM;
+    const int64_t lg = local - first * T;
+    const int64_t tm = first + lg % gsz, tn = lg / gsz;
     const int64_t w0 = tm * 128, x0 = tn * 128;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, wy = wv >> 1, wx = wv & 1;
     constexpr int ES = (int)sizeof(typename GemmCfg<PREC>::E);
     const int64_t ldb = d.ld * ES, planeb = d.plane * ES;
 
-    // Result accumulators: value(i,j,r) for row w0+wy*64+i*16+mfma_row(lane,r),
-    // column x0+wx*64+j*16+lane%16.
-    double resd[4][4][4];
+    AT acc[4][4];
     long long resi[4][4][4];
-    (void)resd;
     (void)resi;
     if constexpr (PREC == 3) {
 #pragma unroll
@@ -634,7 +654,6 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc *D, int nprob) {
         const int nla = d.la_p ? *d.la_p : d.la, nlb = d.lb_p ? *d.lb_p : d.lb;
         for (int la = 0; la < nla; ++la)
             for (int lb = 0; lb < nlb; ++lb) {
-                AT acc[4][4];
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -651,21 +670,19 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc *D, int nprob) {
                         for (int r = 0; r < 4; ++r) resi[i][j][r] += wgt * (long long)acc[i][j][r];
             }
     } else {
-        AT acc[4][4];
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int j = 0; j < 4; ++j) acc[i][j] = AT{0, 0, 0, 0};
         gemm_pass<PREC>(acc, static_cast<const char *>(d.A), static_cast<const char *>(d.B), ldb,
                         planeb, w0, x0, d.npad, lds);
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) resd[i][j][r] = (double)acc[i][j][r];
     }
-    (void)STAGE;
+    // value(i, j, r) of row w0+wy*64+i*16+mfma_row(lane,r), column
+    // x0+wx*64+j*16+lane%16
+    auto value = [&](int i, int j, int r) {
+        if constexpr (PREC == 3) return resi[i][j][r];
+        else return (double)acc[i][j][r];
+    };
 
     const int64_t n = d.n;
     if (!d.final_) {
@@ -695,9 +712,9 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc *D, int nprob) {
                     int64_t x = x0 + wx * 64 + j * 16 + (lane & 15);
                     if (w < n && x < n) {
                         int64_t o = w * d.ldc + x;
-                        if constexpr (PREC == 3) static_cast<long long *>(d.C)[o] = resi[i][j][r];
-                        else if (d.dtype_c == DT_F64) static_cast<double *>(d.C)[o] = resd[i][j][r];
-                        else static_cast<float *>(d.C)[o] = (float)resd[i][j][r];
+                        if constexpr (PREC == 3) static_cast<long long *>(d.C)[o] = value(i, j, r);
+                        else if (d.dtype_c == DT_F64) static_cast<double *>(d.C)[o] = value(i, j, r);
+                        else static_cast<float *>(d.C)[o] = (float)value(i, j, r);
                     }
                 }
         return;
@@ -714,9 +731,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc *D, int nprob) {
                 int64_t w = w0 + wy * 64 + i * 16 + mfma_row<PREC>(lane, r);
                 int64_t x = x0 + wx * 64 + j * 16 + (lane & 15);
                 if (w >= n || x >= n) continue;
-                Wd val;
-                if constexpr (PREC == 3) val = (Wd)resi[i][j][r];
-                else val = resd[i][j][r];
+                Wd val = (Wd)value(i, j, r);
                 for (int k = 0; k < d.nZ; ++k) {
                     const MatRef &z = d.Z[k];
                     int64_t idx = z.trans ? (x * z.ld + w) : (w * z.ld + x);
@@ -740,11 +755,12 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc *D, int nprob) {
     Wd *red = reinterpret_cast<Wd *>(lds);
     red[threadIdx.x] = part;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        Wd s = 0;
-        for (int q = 0; q < 256; ++q) s += red[q];
-        static_cast<Wd *>(d.part)[local] = s;
+    // fixed-order tree over the 256 partial sums
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
     }
+    if (threadIdx.x == 0) static_cast<Wd *>(d.part)[local] = red[0];
 }
 
 // ----------------------------------------------------------------- combine
@@ -820,7 +836,7 @@ hipError_t launch_prep(const PrepDesc *d, int nprob, int64_t total_tiles, int do
 
 template <int PREC>
 static hipError_t launch_gemm_t(const GemmDesc *d, int nprob, int64_t total_tiles, hipStream_t s) {
-    constexpr int STAGE = TileIO<PREC>::PLANEB * GemmCfg<PREC>::PLANES;
+    constexpr int STAGE = TileIO<PREC>::STAGE;
     size_t lds = (size_t)4 * STAGE;
     size_t red = 256 * 16;
     if (lds < red) lds = red;
