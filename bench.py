@@ -131,7 +131,7 @@ def main():
            "data": "synthetic: X iid N(0, I_16), seed 2; factors built on the GPU",
            "config": {"workload": "4-cycle RBF U-statistic, m=4, n=4096, d=16, divisor 32, "
                                   "15 restricted V-statistics", "n": n, "d": d, "m": m,
-                      "order": args.order, "precision": args.precision,
+                      "order": args.order, "precision": args.precision, "cse": True,
                       "num_vstats": r.num_vstats}}
     out["roofline"] = gemm_roofline(U, main_plan, X, div, stream, args.precision)
     if not args.no_compare:
@@ -146,6 +146,11 @@ def main():
         for p in res:
             res[p]["U"] = vals[p].value
             res[p]["err_vs_f64_over_S"] = abs(vals[p].value - vals["f64"].value) / S
+        nc = U.Plan(m, edges, precision=args.precision, order=args.order, cse=False)
+        steps = max(3, args.steps // 2)
+        el, rnc = timed_evals(nc, X, div, steps, 2, stream)
+        res["without_cse"] = {"evals_per_s": steps / el, "ms_per_eval": 1e3 * el / steps,
+                              "err_vs_cse_over_S": abs(rnc.value - vals[args.precision].value) / S}
         res["speedup_bf16x3_over_f64"] = res["bf16x3"]["evals_per_s"] / res["f64"]["evals_per_s"]
         res["speedup_f32_over_f64"] = res["f32"]["evals_per_s"] / res["f64"]["evals_per_s"]
         res["S"] = S

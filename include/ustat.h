@@ -75,11 +75,20 @@ typedef enum {
     USTAT_ORDER_LEARNED = 2     /* candidates ranked by the MLP cost model  */
 } ustat_order;
 
+/*
+ * Evaluation merges steps that compute the same value in several restricted
+ * V-statistics (equal operation on the same factor matrices or upstream
+ * values, up to transposition): each is computed once.  Results are
+ * unchanged bit for bit (every kernel is deterministic).  USTAT_FLAG_NO_CSE
+ * turns the merging off, so every partition's steps run separately.
+ */
+#define USTAT_FLAG_NO_CSE 1
+
 typedef struct {
     int32_t precision;          /* ustat_precision                          */
     int32_t order;              /* ustat_order                              */
     int32_t sparsify;           /* 0: every partition (Lemma 2); 1: Lemma 3 */
-    int32_t reserved;           /* must be 0                                */
+    int32_t flags;              /* USTAT_FLAG_* bits, 0 by default          */
     uint64_t workspace_limit;   /* bytes of device workspace, 0 = no limit  */
     const char *cost_model_path;/* weights file for USTAT_ORDER_LEARNED     */
 } ustat_plan_opts;

@@ -137,7 +137,7 @@ ustat_status ustat_plan_create(int32_t m, int32_t num_edges, const int32_t *edge
     if (o.precision < 0 || o.precision > 3) return fail(USTAT_E_INVALID, "unknown precision");
     if (o.order < 0 || o.order > 2) return fail(USTAT_E_INVALID, "unknown order policy");
     if (o.sparsify != 0 && o.sparsify != 1) return fail(USTAT_E_INVALID, "sparsify must be 0 or 1");
-    if (o.reserved != 0) return fail(USTAT_E_INVALID, "reserved must be 0");
+    if (o.flags & ~USTAT_FLAG_NO_CSE) return fail(USTAT_E_INVALID, "unknown flag bits");
     try {
         std::unique_ptr<ustat_plan_s> p(new ustat_plan_s());
         std::vector<Edge> E;
@@ -147,6 +147,7 @@ ustat_status ustat_plan_create(int32_t m, int32_t num_edges, const int32_t *edge
         po.order = o.order;
         po.sparsify = o.sparsify;
         po.workspace_limit = o.workspace_limit;
+        po.cse = !(o.flags & USTAT_FLAG_NO_CSE);
         if (o.cost_model_path) po.cost_model_path = o.cost_model_path;
         const OrderScorer *scorer = nullptr;
         if (o.order == USTAT_ORDER_LEARNED) {

@@ -172,6 +172,7 @@ struct Schedule {
     size_t blob_bytes = 0;
     Blob blob;
     int nprog_total = 0;
+    size_t n_nodes = 0;
 };
 
 struct Cfg {
@@ -206,6 +207,304 @@ size_t prep_bytes(const Cfg &c, int64_t npad, int limbs) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Node DAG.  Every step of every (dataset, V-statistic) program becomes a
+// node keyed by a canonical signature of its operation and operands (input
+// factor pointers or upstream nodes, with orientation).  Equal signatures
+// denote the same values, so repeated work across partitions (and across
+// datasets that share inputs) is computed once.  All kernels are
+// deterministic, so this does not change any result bit.
+// ---------------------------------------------------------------------------
+
+enum class NK : uint8_t { E0, E1, Dot, GemmStore, GemmFinal };
+
+struct MOp {        // matrix operand
+    int node;       // producing node, or -1 for an input factor
+    const void *p;  // input factor pointer when node < 0
+    bool trans;     // relative to the consuming step's canonical orientation
+};
+struct VOp {        // vector operand
+    int node;       // producing node, or -1 for the diagonal of input factor p
+    const void *p;
+};
+
+struct Node {
+    NK kind;
+    int d = 0;
+    int64_t n = 0;
+    std::vector<MOp> A, B, Z;
+    std::vector<VOp> sv, aw, bx;
+    int level = 0, last_use = 0;
+    // storage
+    size_t off = 0, bytes = 0;
+    int scal = -1, mx = -1;
+    double bound = 0;
+};
+
+struct Ref {  // a program value resolved to a node or an input
+    int node = -1;
+    const void *p = nullptr;
+    bool flip = false;  // stored transposed relative to the program value
+};
+
+std::string ptr_id(const void *p) {
+    char b[32];
+    snprintf(b, sizeof b, "%p", p);
+    return b;
+}
+
+struct Dag {
+    std::vector<Node> nodes;
+    std::unordered_map<std::string, int> by_key;
+    // program scalars -> nodes (dataset-major, program-minor)
+    std::vector<std::vector<int>> prog_scalars;
+    // distinct input diagonals (dataset, factor pointer)
+    std::map<std::pair<int, const void *>, int> diag_index;
+    int max_level = 0;
+};
+
+std::string mop_sig(const MOp &m) {
+    return (m.node < 0 ? "I" + ptr_id(m.p) : "N" + std::to_string(m.node)) + (m.trans ? "t" : "n");
+}
+std::string vop_sig(const VOp &v) {
+    return v.node < 0 ? "D" + ptr_id(v.p) : "N" + std::to_string(v.node);
+}
+template <class T, class F>
+std::string group_sig(const std::vector<T> &v, F f) {
+    std::vector<std::string> s;
+    for (auto &x : v) s.push_back(f(x));
+    std::sort(s.begin(), s.end());
+    std::string out;
+    for (auto &x : s) out += x + ",";
+    return out;
+}
+
+int node_level(const Dag &G, const Node &nd) {
+    int l = 0;
+    auto m = [&](int id) {
+        if (id >= 0) l = std::max(l, G.nodes[id].level);
+    };
+    for (auto &o : nd.A) m(o.node);
+    for (auto &o : nd.B) m(o.node);
+    for (auto &o : nd.Z) m(o.node);
+    for (auto &o : nd.sv) m(o.node);
+    for (auto &o : nd.aw) m(o.node);
+    for (auto &o : nd.bx) m(o.node);
+    return l + 1;
+}
+
+int add_node(Dag &G, Node nd, const std::string &key, bool cse) {
+    if (cse) {
+        auto it = G.by_key.find(key);
+        if (it != G.by_key.end()) return it->second;
+    }
+    nd.level = node_level(G, nd);
+    G.max_level = std::max(G.max_level, nd.level);
+    int id = (int)G.nodes.size();
+    G.nodes.push_back(nd);
+    if (cse) G.by_key.emplace(key, id);
+    return id;
+}
+
+// GEMM part of an Elim2/Final2 step, canonicalised so that the operand
+// group with the smaller signature comes first; *swapped reports that the
+// node computes the transpose of the step's R(w, x).
+std::string gemm_key(int64_t n, const std::vector<MOp> &A, const std::vector<VOp> &sv,
+                     const std::vector<MOp> &B, bool *swapped) {
+    std::string sa = group_sig(A, mop_sig), sb = group_sig(B, mop_sig);
+    std::string ss = group_sig(sv, vop_sig);
+    *swapped = sb < sa;
+    if (*swapped) std::swap(sa, sb);
+    return "G" + std::to_string(n) + "|" + sa + "|" + ss + "|" + sb;
+}
+
+std::string build_dag(const Plan &plan, const std::vector<const VProgram *> &progs,
+                      const std::vector<Dataset> &data, bool cse, Dag &G) {
+    const int nd = (int)data.size(), np = (int)progs.size();
+    G.prog_scalars.assign((size_t)nd * np, {});
+    struct Pending {
+        int dp;
+        int64_t n;
+        int d;
+        std::vector<MOp> A, B, Z;
+        std::vector<VOp> sv, aw, bx;
+        std::string gkey;
+        bool swapped;
+    };
+    std::vector<Pending> pending;
+    std::unordered_map<std::string, int> gkey_count;
+    for (int d = 0; d < nd; ++d) {
+        const int64_t n = data[d].n;
+        for (int p = 0; p < np; ++p) {
+            const VProgram &pr = *progs[p];
+            std::vector<Ref> ref(pr.vals.size());
+            for (size_t v = 0; v < pr.vals.size(); ++v) {
+                const Value &val = pr.vals[v];
+                if (val.kind == ValKind::InputMat || val.kind == ValKind::InputDiag) {
+                    ref[v].p = data[d].factors[val.src];
+                    if (val.kind == ValKind::InputDiag) {
+                        auto key = std::make_pair(d, ref[v].p);
+                        if (!G.diag_index.count(key)) {
+                            int idx = (int)G.diag_index.size();
+                            G.diag_index[key] = idx;
+                        }
+                    }
+                }
+            }
+            auto mop = [&](const MatOp &o) {
+                const Ref &r = ref[o.val];
+                return MOp{r.node, r.p, (bool)(o.trans ^ r.flip)};
+            };
+            auto vop = [&](int v) { return VOp{ref[v].node, ref[v].p}; };
+            const int dp = d * np + p;
+            for (const Step &st : pr.steps) {
+                std::vector<MOp> A, B, Z;
+                std::vector<VOp> sv, aw, bx;
+                for (auto &o : st.A) A.push_back(mop(o));
+                for (auto &o : st.B) B.push_back(mop(o));
+                for (auto &o : st.Z) Z.push_back(mop(o));
+                for (int q : st.sv) sv.push_back(vop(q));
+                for (int q : st.aw) aw.push_back(vop(q));
+                for (int q : st.bx) bx.push_back(vop(q));
+                Node nd_;
+                nd_.d = d;
+                nd_.n = n;
+                switch (st.kind) {
+                    case StepKind::Elim0: {
+                        nd_.kind = NK::E0;
+                        nd_.sv = sv;
+                        int id = add_node(G, nd_, "E0|" + std::to_string(n) + "|" + group_sig(sv, vop_sig), cse);
+                        ref[st.out].node = id;
+                        G.prog_scalars[dp].push_back(id);
+                        break;
+                    }
+                    case StepKind::Elim1:
+                    case StepKind::Final1: {
+                        nd_.kind = NK::E1;
+                        nd_.A = A;
+                        nd_.sv = sv;
+                        std::string k1 = "E1|" + std::to_string(n) + "|" + group_sig(A, mop_sig) + "|" +
+                                         group_sig(sv, vop_sig);
+                        int id = add_node(G, nd_, k1, cse);
+                        if (st.kind == StepKind::Elim1) {
+                            ref[st.out].node = id;
+                        } else {
+                            Node dot;
+                            dot.kind = NK::Dot;
+                            dot.d = d;
+                            dot.n = n;
+                            dot.sv.push_back(VOp{id, nullptr});
+                            for (auto &v : aw) dot.sv.push_back(v);
+                            int did = add_node(G, dot, "DOT|" + std::to_string(n) + "|" + group_sig(dot.sv, vop_sig), cse);
+                            ref[st.out].node = did;
+                            G.prog_scalars[dp].push_back(did);
+                        }
+                        break;
+                    }
+                    case StepKind::Elim2: {
+                        bool sw;
+                        std::string k = gemm_key(n, A, sv, B, &sw);
+                        nd_.kind = NK::GemmStore;
+                        nd_.A = sw ? B : A;
+                        nd_.B = sw ? A : B;
+                        nd_.sv = sv;
+                        int id = add_node(G, nd_, k, cse);
+                        ref[st.out].node = id;
+                        ref[st.out].flip = sw;
+                        gkey_count[k] += 2;  // a stored product is always reusable
+                        break;
+                    }
+                    case StepKind::Final2: {
+                        Pending pd;
+                        pd.dp = dp;
+                        pd.n = n;
+                        pd.d = d;
+                        pd.A = A;
+                        pd.B = B;
+                        pd.Z = Z;
+                        pd.sv = sv;
+                        pd.aw = aw;
+                        pd.bx = bx;
+                        pd.gkey = gemm_key(n, A, sv, B, &pd.swapped);
+                        gkey_count[pd.gkey] += 1;
+                        G.prog_scalars[dp].push_back(-1 - (int)pending.size());  // patched below
+                        pending.push_back(pd);
+                        break;
+                    }
+                }
+            }
+        }
+    }
+    // Final2 steps: fused GEMM + consumer unless their product is shared.
+    for (size_t i = 0; i < pending.size(); ++i) {
+        Pending &pd = pending[i];
+        // node orientation (w', x'): swapped -> w' = x, x' = w
+        std::vector<MOp> A = pd.swapped ? pd.B : pd.A, B = pd.swapped ? pd.A : pd.B, Z = pd.Z;
+        std::vector<VOp> aw = pd.swapped ? pd.bx : pd.aw, bx = pd.swapped ? pd.aw : pd.bx;
+        if (pd.swapped)
+            for (auto &z : Z) z.trans = !z.trans;
+        int sid;
+        if (cse && gkey_count[pd.gkey] >= 2) {
+            Node g;
+            g.kind = NK::GemmStore;
+            g.d = pd.d;
+            g.n = pd.n;
+            g.A = A;
+            g.B = B;
+            g.sv = pd.sv;
+            int gid = add_node(G, g, pd.gkey, cse);
+            // consumer: y(w') = sum_x' R(w',x') prod Z(w',x') prod bx(x'),
+            // an Elim1 over v := x' (canonical (x', w')), then a dot with aw.
+            Node e;
+            e.kind = NK::E1;
+            e.d = pd.d;
+            e.n = pd.n;
+            e.A.push_back(MOp{gid, nullptr, true});
+            for (auto &z : Z) e.A.push_back(MOp{z.node, z.p, !z.trans});
+            e.sv = bx;
+            int eid = add_node(G, e, "E1|" + std::to_string(pd.n) + "|" + group_sig(e.A, mop_sig) + "|" +
+                                         group_sig(e.sv, vop_sig), cse);
+            Node dot;
+            dot.kind = NK::Dot;
+            dot.d = pd.d;
+            dot.n = pd.n;
+            dot.sv.push_back(VOp{eid, nullptr});
+            for (auto &v : aw) dot.sv.push_back(v);
+            sid = add_node(G, dot, "DOT|" + std::to_string(pd.n) + "|" + group_sig(dot.sv, vop_sig), cse);
+        } else {
+            Node f;
+            f.kind = NK::GemmFinal;
+            f.d = pd.d;
+            f.n = pd.n;
+            f.A = A;
+            f.B = B;
+            f.Z = Z;
+            f.sv = pd.sv;
+            f.aw = aw;
+            f.bx = bx;
+            std::string k = "F" + pd.gkey + "|" + group_sig(Z, mop_sig) + "|" + group_sig(aw, vop_sig) +
+                            "|" + group_sig(bx, vop_sig);
+            sid = add_node(G, f, k, cse);
+        }
+        for (auto &x : G.prog_scalars[pd.dp])
+            if (x == -1 - (int)i) x = sid;
+    }
+    // last uses
+    for (auto &nd : G.nodes) {
+        auto use = [&](int id) {
+            if (id >= 0) G.nodes[id].last_use = std::max(G.nodes[id].last_use, nd.level);
+        };
+        for (auto &o : nd.A) use(o.node);
+        for (auto &o : nd.B) use(o.node);
+        for (auto &o : nd.Z) use(o.node);
+        for (auto &o : nd.sv) use(o.node);
+        for (auto &o : nd.aw) use(o.node);
+        for (auto &o : nd.bx) use(o.node);
+    }
+    (void)plan;
+    return "";
+}
+
 // Builds the schedule.  With base == nullptr only sizes are computed; a
 // second call with the real arena base fills every pointer (the layout is
 // deterministic, so offsets agree).
@@ -220,156 +519,109 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
     const int np = (int)progs.size();
     S.nprog_total = nd * np;
     auto P = [&](size_t off) -> void * { return base ? (void *)(base + off) : nullptr; };
-
-    // ---- scalar slots and value bookkeeping
-    struct VInfo {
-        size_t off = 0, bytes = 0;
-        int last_use = 0;
-        int scal = -1;     // scalar slot
-        int mx = -1;       // INT max slot
-        double bound = 0;  // INT a-priori bound
-        bool persistent = false;
-    };
-    std::vector<std::vector<VInfo>> vinfo(nd * np);
-    int max_depth = 0;
+    Dag G;
+    std::string err = build_dag(plan, progs, data, plan.opts.cse, G);
+    if (!err.empty()) {
+        *status = 1;
+        return err;
+    }
+    S.n_nodes = G.nodes.size();
+    const bool is_int = cfg.domain == DOM_INT;
+    // scalar and running-max slots
     size_t nscal = 0, nmx = 0;
-    for (int d = 0; d < nd; ++d)
-        for (int p = 0; p < np; ++p) {
-            const VProgram &pr = *progs[p];
-            auto &vi = vinfo[d * np + p];
-            vi.assign(pr.vals.size(), VInfo());
-            max_depth = std::max(max_depth, pr.depth);
-            for (const Step &st : pr.steps) {
-                auto use = [&](int v) { vi[v].last_use = std::max(vi[v].last_use, st.level); };
-                for (auto &o : st.A) use(o.val);
-                for (auto &o : st.B) use(o.val);
-                for (auto &o : st.Z) use(o.val);
-                for (int q : st.sv) use(q);
-                for (int q : st.aw) use(q);
-                for (int q : st.bx) use(q);
-            }
-            for (size_t v = 0; v < pr.vals.size(); ++v) {
-                if (pr.vals[v].kind == ValKind::Scalar) vi[v].scal = (int)nscal++;
-                if (cfg.domain == DOM_INT && (pr.vals[v].kind == ValKind::Vec ||
-                                              pr.vals[v].kind == ValKind::Mat))
-                    vi[v].mx = (int)nmx++;
-            }
-        }
+    for (auto &nd_ : G.nodes) {
+        if (nd_.kind == NK::E0 || nd_.kind == NK::Dot || nd_.kind == NK::GemmFinal) nd_.scal = (int)nscal++;
+        if (is_int && (nd_.kind == NK::E1 || nd_.kind == NK::GemmStore)) nd_.mx = (int)nmx++;
+    }
+    std::vector<int> diag_mx(G.diag_index.size(), -1);
+    if (is_int)
+        for (auto &kv : G.diag_index) diag_mx[kv.second] = (int)nmx++;
     S.n_scal = nscal;
-    // input diag vectors, deduped per (dataset, factor pointer)
-    std::map<std::pair<int, const void *>, std::pair<size_t, int>> diag_of;  // -> (offset, mx slot)
-    for (int d = 0; d < nd; ++d)
-        for (int p = 0; p < np; ++p)
-            for (const Value &v : progs[p]->vals)
-                if (v.kind == ValKind::InputDiag) {
-                    auto key = std::make_pair(d, data[d].factors[v.src]);
-                    if (!diag_of.count(key)) {
-                        int slot = cfg.domain == DOM_INT ? (int)nmx++ : -1;
-                        diag_of[key] = {0, slot};
-                    }
-                }
     S.n_mx = nmx;
-    // fixed regions
     S.off_scal = A.alloc(nscal * cfg.wide_es + 16);
     S.off_v = A.alloc((size_t)S.nprog_total * cfg.wide_es + 16);
     S.off_u = A.alloc((size_t)nd * cfg.wide_es + 16);
     S.off_s = A.alloc((size_t)nd * 8 + 16);
     S.off_mx = A.alloc(nmx * 8 + 16);
-    for (auto &kv : diag_of) {
-        kv.second.first = A.alloc((size_t)data[kv.first.first].n * 8);
-        const void *src = kv.first.second;
+    // input maxima: one slot per (dataset, edge)
+    std::map<std::pair<int, const void *>, int> inmx_of;
+    if (is_int)
+        for (int d = 0; d < nd; ++d)
+            for (int k = 0; k < ne; ++k) {
+                auto key = std::make_pair(d, data[d].factors[k]);
+                if (!inmx_of.count(key)) inmx_of[key] = d * ne + k;
+            }
+    S.n_inmx = is_int ? (size_t)nd * ne : 0;
+    S.off_inmx = A.alloc(S.n_inmx * 8 + 16);
+    unsigned long long *mxbase =
+        base ? reinterpret_cast<unsigned long long *>(base + S.off_mx) : nullptr;
+    unsigned long long *inmxbase =
+        base ? reinterpret_cast<unsigned long long *>(base + S.off_inmx) : nullptr;
+    auto in_b = [&](int d, const void *ptr) {
+        if (in_bound.empty()) return 127.0;
+        return in_bound[inmx_of[std::make_pair(d, ptr)]];
+    };
+    // diagonals (prologue)
+    std::vector<size_t> diag_off(G.diag_index.size());
+    for (auto &kv : G.diag_index) {
+        const int d = kv.first.first;
+        const size_t off = A.alloc((size_t)data[d].n * 8);
+        diag_off[kv.second] = off;
         DiagDesc dd;
-        dd.src = {src, data[kv.first.first].n, cfg.in_dt, 0, 0, 0};
-        dd.dst = P(kv.second.first);
-        dd.n = data[kv.first.first].n;
-        dd.mx_out = (cfg.domain == DOM_INT && base)
-                        ? reinterpret_cast<unsigned long long *>(base + S.off_mx) + kv.second.second
-                        : nullptr;
+        dd.src = {kv.first.second, data[d].n, cfg.in_dt, 0, 0, 0};
+        dd.dst = P(off);
+        dd.n = data[d].n;
+        dd.mx_out = (is_int && mxbase) ? mxbase + diag_mx[kv.second] : nullptr;
         S.diag.push_back(dd);
         S.diag_maxn = std::max(S.diag_maxn, dd.n);
     }
-
-    // a-priori bounds (INT)
-    auto in_b = [&](int d, int k) { return in_bound.empty() ? 127.0 : in_bound[d * ne + k]; };
-
-    // helpers to resolve operands
-    auto vptr = [&](int d, int p, int val) -> const void * {
-        const VProgram &pr = *progs[p];
-        const Value &v = pr.vals[val];
-        if (v.kind == ValKind::InputMat) return data[d].factors[v.src];
-        if (v.kind == ValKind::InputDiag)
-            return P(diag_of[std::make_pair(d, data[d].factors[v.src])].first);
-        return P(vinfo[d * np + p][val].off);
-    };
-    auto mxptr = [&](int d, int p, int val) -> unsigned long long * {
-        if (!base || cfg.domain != DOM_INT) return nullptr;
-        const VProgram &pr = *progs[p];
-        const Value &v = pr.vals[val];
-        unsigned long long *mx = reinterpret_cast<unsigned long long *>(base + S.off_mx);
-        if (v.kind == ValKind::InputDiag)
-            return mx + diag_of[std::make_pair(d, data[d].factors[v.src])].second;
-        if (v.kind == ValKind::InputMat) return nullptr;  // filled via in_mx below
-        return mx + vinfo[d * np + p][val].mx;
-    };
-    // input matrices' maxima live in their own region
-    std::map<std::pair<int, int>, int> inmx_slot;  // (d, k) -> slot
-    if (cfg.domain == DOM_INT)
-        for (int d = 0; d < nd; ++d)
-            for (int k = 0; k < ne; ++k) inmx_slot[{d, k}] = (int)S.n_inmx++;
-    S.off_inmx = A.alloc(S.n_inmx * 8 + 16);
-    auto inmx = [&](int d, int k) -> unsigned long long * {
-        if (!base) return nullptr;
-        return reinterpret_cast<unsigned long long *>(base + S.off_inmx) + inmx_slot[{d, k}];
-    };
-    auto mx_any = [&](int d, int p, int val) -> const unsigned long long * {
-        const Value &v = progs[p]->vals[val];
-        if (v.kind == ValKind::InputMat) return inmx(d, v.src);
-        return mxptr(d, p, val);
-    };
-    auto bound_of = [&](int d, int p, int val) -> double {
-        const Value &v = progs[p]->vals[val];
-        if (v.kind == ValKind::InputMat || v.kind == ValKind::InputDiag) return in_b(d, v.src);
-        return vinfo[d * np + p][val].bound;
-    };
     const bool sparsify = plan.opts.sparsify != 0;
-    auto matref = [&](int d, int p, const MatOp &o) -> MatRef {
-        const Value &v = progs[p]->vals[o.val];
+    auto vptr = [&](int d, const VOp &v) -> const void * {
+        if (v.node >= 0) return P(G.nodes[v.node].off);
+        return P(diag_off[G.diag_index[std::make_pair(d, v.p)]]);
+    };
+    auto vbound = [&](int d, const VOp &v) {
+        if (v.node >= 0) return G.nodes[v.node].bound;
+        return in_b(d, v.p);
+    };
+    auto vmx = [&](int d, const VOp &v) -> const unsigned long long * {
+        if (!mxbase) return nullptr;
+        if (v.node >= 0) return mxbase + G.nodes[v.node].mx;
+        return mxbase + diag_mx[G.diag_index[std::make_pair(d, v.p)]];
+    };
+    auto mref = [&](int d, const MOp &o) -> MatRef {
         MatRef m;
-        m.p = vptr(d, p, o.val);
+        const bool input = o.node < 0;
+        m.p = input ? o.p : P(G.nodes[o.node].off);
         m.ld = data[d].n;
-        bool input = v.kind == ValKind::InputMat;
         m.dtype = input ? cfg.in_dt : cfg.mat_dt;
         m.trans = o.trans ? 1 : 0;
         m.zdiag = (input && sparsify) ? 1 : 0;
         m.pad = 0;
         return m;
     };
-    auto level0 = [&](int p, int val) {
-        ValKind k = progs[p]->vals[val].kind;
-        return k == ValKind::InputMat || k == ValKind::InputDiag;
+    auto mbound = [&](int d, const MOp &o) {
+        return o.node >= 0 ? G.nodes[o.node].bound : in_b(d, o.p);
     };
-
-    // persistent preps (operands built only from inputs), deduped per eval
-    struct PrepRec {
-        size_t off, bytes;
-        int limbs;
-        int limb_slot;
+    auto mmx = [&](int d, const MOp &o) -> const unsigned long long * {
+        if (!inmxbase) return nullptr;
+        if (o.node >= 0) return mxbase + G.nodes[o.node].mx;
+        return inmxbase + inmx_of[std::make_pair(d, o.p)];
     };
-    std::map<std::string, PrepRec> persistent;
-    std::vector<int> limb_slots_used;
-    size_t nlimb = 0;
+    auto scal_ptr = [&](const Node &nd_) -> void * {
+        return P(S.off_scal + (size_t)nd_.scal * cfg.wide_es);
+    };
     const double kOverflow = 4.0e18;  // < 2^62
     const double kOverflowWide = 8.0e37;
 
-    // Pass 1 over levels: allocate, build descriptors.
-    S.levels.assign(max_depth + 1, LevelWork());
-    std::vector<std::pair<size_t, size_t>> level_free;  // scratch per level
-    // limb-count slots are allocated lazily; they need a region sized after
-    // the walk, so count first with a dry walk of the steps.
-    for (int d = 0; d < nd; ++d)
-        for (int p = 0; p < np; ++p)
-            for (const Step &st : progs[p]->steps)
-                if (st.kind == StepKind::Elim2 || st.kind == StepKind::Final2) nlimb += 2;
+    struct PrepRec {
+        size_t off, bytes;
+        int limbs, limb_slot;
+    };
+    std::map<std::string, PrepRec> persistent;
+    size_t nlimb = 0;
+    for (auto &nd_ : G.nodes)
+        if (nd_.kind == NK::GemmStore || nd_.kind == NK::GemmFinal) nlimb += 2;
     S.n_limbs = nlimb;
     S.off_limbs = A.alloc(nlimb * 4 + 16);
     size_t limb_next = 0;
@@ -377,247 +629,236 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
         return base ? reinterpret_cast<int32_t *>(base + S.off_limbs) + slot : nullptr;
     };
 
-    for (int L = 1; L <= max_depth; ++L) {
+    // nodes by level
+    std::vector<std::vector<int>> by_level(G.max_level + 1);
+    for (size_t i = 0; i < G.nodes.size(); ++i) by_level[G.nodes[i].level].push_back((int)i);
+    S.levels.assign(G.max_level + 1, LevelWork());
+    for (int L = 1; L <= G.max_level; ++L) {
         LevelWork &W = S.levels[L];
-        std::vector<std::pair<size_t, size_t>> scratch;  // freed after level
+        std::vector<std::pair<size_t, size_t>> scratch;
         std::map<std::string, PrepRec> local;
-        for (int d = 0; d < nd; ++d) {
-            const int64_t n = data[d].n;
+        for (int id : by_level[L]) {
+            Node &nd_ = G.nodes[id];
+            const int d = nd_.d;
+            const int64_t n = nd_.n;
             const int64_t npad = up64(n, 128);
             const int tiles64 = (int)((n + 63) / 64);
-            for (int p = 0; p < np; ++p) {
-                const VProgram &pr = *progs[p];
-                auto &vi = vinfo[d * np + p];
-                for (size_t si = 0; si < pr.steps.size(); ++si) {
-                    const Step &st = pr.steps[si];
-                    if (st.level != L) continue;
-                    VInfo &out = vi[st.out];
-                    const void *scal_ptr =
-                        (out.scal >= 0) ? P(S.off_scal + (size_t)out.scal * cfg.wide_es) : nullptr;
-                    double prodA = 1, prodS = 1, prodB = 1, prodZ = 1, prodaw = 1, prodbx = 1;
-                    for (auto &o : st.A) prodA *= bound_of(d, p, o.val);
-                    for (auto &o : st.B) prodB *= bound_of(d, p, o.val);
-                    for (auto &o : st.Z) prodZ *= bound_of(d, p, o.val);
-                    for (int q : st.sv) prodS *= bound_of(d, p, q);
-                    for (int q : st.aw) prodaw *= bound_of(d, p, q);
-                    for (int q : st.bx) prodbx *= bound_of(d, p, q);
-                    if ((int)st.A.size() > kMaxMat || (int)st.B.size() > kMaxMat ||
-                        (int)st.Z.size() > kMaxMat || (int)st.sv.size() > kMaxVec ||
-                        (int)st.aw.size() > kMaxVec || (int)st.bx.size() > kMaxVec) {
-                        *status = 2;
-                        return "a step has more parallel factors than the engine supports";
-                    }
-                    if (st.kind == StepKind::Elim0) {
-                        Elim0Desc e;
-                        e.n = n;
-                        e.nS = (int)st.sv.size();
-                        for (int q = 0; q < e.nS; ++q) e.s[q] = vptr(d, p, st.sv[q]);
-                        e.out = (void *)scal_ptr;
-                        W.e0.push_back(e);
-                        out.bound = n * prodS;
-                    } else if (st.kind == StepKind::Elim1 || st.kind == StepKind::Final1) {
-                        Elim1Desc e;
-                        e.n = n;
-                        e.nA = (int)st.A.size();
-                        e.nS = (int)st.sv.size();
-                        for (int q = 0; q < e.nA; ++q) e.A[q] = matref(d, p, st.A[q]);
-                        for (int q = 0; q < e.nS; ++q) e.s[q] = vptr(d, p, st.sv[q]);
-                        size_t pbytes = (size_t)tiles64 * n * 8;
-                        size_t poff = A.alloc(pbytes);
-                        scratch.push_back({poff, pbytes});
-                        e.part = P(poff);
-                        e.tiles_v = tiles64;
-                        e.tiles_w = tiles64;
-                        e.tile_start = W.e1_tiles;
-                        W.e1_tiles += (int64_t)tiles64 * tiles64;
-                        W.e1.push_back(e);
-                        ReduceDesc r;
-                        r.part = P(poff);
-                        r.T = tiles64;
-                        r.len = n;
-                        r.stride = n;
-                        r.mx_out = nullptr;
-                        double vb = n * prodA * prodS;
-                        if (st.kind == StepKind::Elim1) {
-                            out.bytes = (size_t)n * 8;
-                            out.off = A.alloc(out.bytes);
-                            out.bound = vb;
-                            r.out = P(out.off);
-                            r.nmul = 0;
-                            r.dot = 0;
-                            r.mx_out = mxptr(d, p, st.out);
-                            if (cfg.domain == DOM_INT && vb > kOverflow) {
-                                *status = 5;
-                                return "an intermediate vector may exceed int64";
-                            }
-                        } else {
-                            r.out = (void *)scal_ptr;
-                            r.nmul = (int)st.aw.size();
-                            for (int q = 0; q < r.nmul; ++q) r.mul[q] = vptr(d, p, st.aw[q]);
-                            r.dot = 1;
-                            out.bound = n * vb * prodaw;
-                            if (cfg.domain == DOM_INT && vb > kOverflow) {
-                                *status = 5;
-                                return "an intermediate vector may exceed int64";
-                            }
-                        }
-                        W.red.push_back(r);
-                        W.red_maxlen = std::max<int64_t>(W.red_maxlen, n);
-                    } else {
-                        // GEMM step: operand preps (deduped), then the GEMM.
-                        auto make_prep = [&](const std::vector<MatOp> &ops,
-                                             const std::vector<int> &sv, double bound,
-                                             const int32_t **limbs_p, int *max_limbs) -> const void * {
-                            bool pers = true;
-                            std::string key = std::to_string(d) + "|";
-                            for (auto &o : ops) {
-                                pers = pers && level0(p, o.val);
-                                MatRef m = matref(d, p, o);
-                                char buf[96];
-                                const Value &v = progs[p]->vals[o.val];
-                                // identity: input factor index or value pointer
-                                if (v.kind == ValKind::InputMat)
-                                    snprintf(buf, sizeof buf, "I%p:%d:%d;",
-                                             data[d].factors[v.src], m.trans, m.zdiag);
-                                else
-                                    snprintf(buf, sizeof buf, "V%d.%d.%d:%d;", d, p, o.val, m.trans);
-                                key += buf;
-                            }
-                            key += "|";
-                            for (int q : sv) {
-                                pers = pers && level0(p, q);
-                                char buf[96];
-                                const Value &v = progs[p]->vals[q];
-                                if (v.kind == ValKind::InputDiag)
-                                    snprintf(buf, sizeof buf, "D%p;", data[d].factors[v.src]);
-                                else
-                                    snprintf(buf, sizeof buf, "V%d.%d.%d;", d, p, q);
-                                key += buf;
-                            }
-                            int cap = cfg.pformat == PF_I8LIMBS ? limbs_for(bound, 9) : 1;
-                            auto &tab = pers ? persistent : local;
-                            auto it = tab.find(key);
-                            if (it == tab.end()) {
-                                PrepRec rec;
-                                rec.limbs = cap;
-                                rec.bytes = prep_bytes(cfg, npad, cap);
-                                rec.off = A.alloc(rec.bytes);
-                                rec.limb_slot = (int)limb_next++;
-                                if (!pers) scratch.push_back({rec.off, rec.bytes});
-                                PrepDesc pd;
-                                pd.n = n;
-                                pd.npad = npad;
-                                pd.ldo = npad;
-                                pd.plane = npad * npad;
-                                pd.nA = (int)ops.size();
-                                pd.nS = (int)sv.size();
-                                for (int q = 0; q < pd.nA; ++q) pd.A[q] = matref(d, p, ops[q]);
-                                for (int q = 0; q < pd.nS; ++q) pd.s[q] = vptr(d, p, sv[q]);
-                                pd.out = P(rec.off);
-                                pd.format = cfg.pformat;
-                                pd.limbs = cap;
-                                pd.tiles = (int)(npad / 64);
-                                pd.tile_start = W.prep_tiles;
-                                W.prep_tiles += (int64_t)pd.tiles * pd.tiles;
-                                pd.nmx = 0;
-                                if (cfg.domain == DOM_INT) {
-                                    for (auto &o : ops) pd.mx[pd.nmx++] = mx_any(d, p, o.val);
-                                    for (int q : sv) pd.mx[pd.nmx++] = mx_any(d, p, q);
-                                }
-                                pd.limbs_out = limb_ptr(rec.limb_slot);
-                                W.prep.push_back(pd);
-                                it = tab.emplace(key, rec).first;
-                            }
-                            *limbs_p = limb_ptr(it->second.limb_slot);
-                            *max_limbs = it->second.limbs;
-                            return P(it->second.off);
-                        };
-                        GemmDesc g;
-                        std::memset(&g, 0, sizeof g);
-                        const int32_t *lap = nullptr, *lbp = nullptr;
-                        int cla = 1, clb = 1;
-                        g.A = make_prep(st.A, st.sv, prodA * prodS, &lap, &cla);
-                        g.B = make_prep(st.B, {}, prodB, &lbp, &clb);
-                        g.n = n;
-                        g.npad = npad;
-                        g.ld = npad;
-                        g.plane = npad * npad;
-                        g.la = cla;
-                        g.lb = clb;
-                        g.la_p = cfg.domain == DOM_INT ? lap : nullptr;
-                        g.lb_p = cfg.domain == DOM_INT ? lbp : nullptr;
-                        g.tiles = (int)(npad / 128);
-                        g.tile_start = W.gemm_tiles;
-                        W.gemm_tiles += (int64_t)g.tiles * g.tiles;
-                        W.gemm_flops += 2.0 * (double)n * n * n;
-                        double cb = n * prodA * prodS * prodB;
-                        if (cfg.domain == DOM_INT) {
-                            if (cb > kOverflow) {
-                                *status = 5;
-                                return "an intermediate matrix may exceed int64";
-                            }
-                            if (n >= 131072) {
-                                *status = 2;
-                                return "the exact path needs n < 131072 (int32 limb accumulation)";
-                            }
-                        }
-                        if (st.kind == StepKind::Elim2) {
-                            out.bytes = (size_t)n * n * cfg.mat_es;
-                            out.off = A.alloc(out.bytes);
-                            out.bound = cb;
-                            g.final_ = 0;
-                            g.dtype_c = cfg.mat_dt;
-                            g.C = P(out.off);
-                            g.ldc = n;
-                            g.mx_out = mxptr(d, p, st.out);
-                        } else {
-                            g.final_ = 1;
-                            g.nZ = (int)st.Z.size();
-                            g.naw = (int)st.aw.size();
-                            g.nbx = (int)st.bx.size();
-                            for (int q = 0; q < g.nZ; ++q) g.Z[q] = matref(d, p, st.Z[q]);
-                            for (int q = 0; q < g.naw; ++q) g.aw[q] = vptr(d, p, st.aw[q]);
-                            for (int q = 0; q < g.nbx; ++q) g.bx[q] = vptr(d, p, st.bx[q]);
-                            size_t pb = (size_t)g.tiles * g.tiles * 16;
-                            size_t poff = A.alloc(pb);
-                            scratch.push_back({poff, pb});
-                            g.part = P(poff);
-                            ReduceDesc r;
-                            std::memset(&r, 0, sizeof r);
-                            r.part = P(poff);
-                            r.T = (int64_t)g.tiles * g.tiles;
-                            r.len = 1;
-                            r.stride = 1;
-                            r.out = (void *)scal_ptr;
-                            r.dot = 1;
-                            W.red.push_back(r);
-                            out.bound = (double)n * n * cb * prodZ * prodaw * prodbx;
-                        }
-                        W.gemm.push_back(g);
-                    }
-                    if (cfg.domain == DOM_INT && out.scal >= 0 && out.bound > kOverflowWide) {
+            if ((int)nd_.A.size() > kMaxMat || (int)nd_.B.size() > kMaxMat ||
+                (int)nd_.Z.size() > kMaxMat || (int)nd_.sv.size() > kMaxVec ||
+                (int)nd_.aw.size() > kMaxVec || (int)nd_.bx.size() > kMaxVec) {
+                *status = 2;
+                return "a step has more parallel factors than the engine supports";
+            }
+            double pA = 1, pB = 1, pZ = 1, pS = 1, paw = 1, pbx = 1;
+            for (auto &o : nd_.A) pA *= mbound(d, o);
+            for (auto &o : nd_.B) pB *= mbound(d, o);
+            for (auto &o : nd_.Z) pZ *= mbound(d, o);
+            for (auto &o : nd_.sv) pS *= vbound(d, o);
+            for (auto &o : nd_.aw) paw *= vbound(d, o);
+            for (auto &o : nd_.bx) pbx *= vbound(d, o);
+            switch (nd_.kind) {
+                case NK::E0: {
+                    Elim0Desc e;
+                    e.n = n;
+                    e.nS = (int)nd_.sv.size();
+                    for (int q = 0; q < e.nS; ++q) e.s[q] = vptr(d, nd_.sv[q]);
+                    e.out = scal_ptr(nd_);
+                    W.e0.push_back(e);
+                    nd_.bound = n * pS;
+                    break;
+                }
+                case NK::Dot: {
+                    // sv[0] is the vector being summed, the rest multiply it
+                    ReduceDesc r;
+                    std::memset(&r, 0, sizeof r);
+                    r.part = vptr(d, nd_.sv[0]);
+                    r.T = 1;
+                    r.len = n;
+                    r.stride = n;
+                    r.out = scal_ptr(nd_);
+                    r.dot = 1;
+                    r.nmul = (int)nd_.sv.size() - 1;
+                    for (int q = 1; q < (int)nd_.sv.size(); ++q) r.mul[q - 1] = vptr(d, nd_.sv[q]);
+                    W.red.push_back(r);
+                    W.red_maxlen = std::max<int64_t>(W.red_maxlen, n);
+                    nd_.bound = n * pS;
+                    break;
+                }
+                case NK::E1: {
+                    Elim1Desc e;
+                    e.n = n;
+                    e.nA = (int)nd_.A.size();
+                    e.nS = (int)nd_.sv.size();
+                    for (int q = 0; q < e.nA; ++q) e.A[q] = mref(d, nd_.A[q]);
+                    for (int q = 0; q < e.nS; ++q) e.s[q] = vptr(d, nd_.sv[q]);
+                    const int strips = (int)((n + kElimStrip - 1) / kElimStrip);
+                    size_t pbytes = (size_t)strips * n * 8;
+                    size_t poff = A.alloc(pbytes);
+                    scratch.push_back({poff, pbytes});
+                    e.part = P(poff);
+                    e.tiles_v = strips;
+                    e.tiles_w = tiles64;
+                    e.tile_start = W.e1_tiles;
+                    W.e1_tiles += (int64_t)strips * tiles64;
+                    W.e1.push_back(e);
+                    nd_.bytes = (size_t)n * 8;
+                    nd_.off = A.alloc(nd_.bytes);
+                    nd_.bound = n * pA * pS;
+                    if (is_int && nd_.bound > kOverflow) {
                         *status = 5;
-                        return "a V-statistic may exceed the 127-bit range";
+                        return "an intermediate vector may exceed int64";
                     }
+                    ReduceDesc r;
+                    std::memset(&r, 0, sizeof r);
+                    r.part = P(poff);
+                    r.T = strips;
+                    r.len = n;
+                    r.stride = n;
+                    r.out = P(nd_.off);
+                    r.mx_out = (is_int && mxbase) ? mxbase + nd_.mx : nullptr;
+                    W.red.push_back(r);
+                    W.red_maxlen = std::max<int64_t>(W.red_maxlen, n);
+                    break;
+                }
+                case NK::GemmStore:
+                case NK::GemmFinal: {
+                    auto make_prep = [&](const std::vector<MOp> &ops, const std::vector<VOp> &sv,
+                                         double bound, const int32_t **limbs_p, int *max_limbs) {
+                        bool pers = true;
+                        std::string key = std::to_string(d) + "|" + std::to_string(n) + "|";
+                        for (auto &o : ops) {
+                            pers = pers && (o.node < 0);
+                            key += mop_sig(o);
+                        }
+                        key += "|";
+                        for (auto &v : sv) {
+                            pers = pers && (v.node < 0);
+                            key += vop_sig(v);
+                        }
+                        int cap = cfg.pformat == PF_I8LIMBS ? limbs_for(bound, 9) : 1;
+                        auto &tab = pers ? persistent : local;
+                        auto it = tab.find(key);
+                        if (it == tab.end()) {
+                            PrepRec rec;
+                            rec.limbs = cap;
+                            rec.bytes = prep_bytes(cfg, npad, cap);
+                            rec.off = A.alloc(rec.bytes);
+                            rec.limb_slot = (int)limb_next++;
+                            if (!pers) scratch.push_back({rec.off, rec.bytes});
+                            PrepDesc pd;
+                            std::memset(&pd, 0, sizeof pd);
+                            pd.n = n;
+                            pd.npad = npad;
+                            pd.ldo = npad;
+                            pd.plane = npad * npad;
+                            pd.nA = (int)ops.size();
+                            pd.nS = (int)sv.size();
+                            for (int q = 0; q < pd.nA; ++q) pd.A[q] = mref(d, ops[q]);
+                            for (int q = 0; q < pd.nS; ++q) pd.s[q] = vptr(d, sv[q]);
+                            pd.out = P(rec.off);
+                            pd.format = cfg.pformat;
+                            pd.limbs = cap;
+                            pd.tiles = (int)(npad / 64);
+                            pd.tile_start = W.prep_tiles;
+                            W.prep_tiles += (int64_t)pd.tiles * pd.tiles;
+                            pd.nmx = 0;
+                            if (is_int) {
+                                for (auto &o : ops) pd.mx[pd.nmx++] = mmx(d, o);
+                                for (auto &v : sv) pd.mx[pd.nmx++] = vmx(d, v);
+                            }
+                            pd.limbs_out = limb_ptr(rec.limb_slot);
+                            W.prep.push_back(pd);
+                            it = tab.emplace(key, rec).first;
+                        }
+                        *limbs_p = limb_ptr(it->second.limb_slot);
+                        *max_limbs = it->second.limbs;
+                        return (const void *)P(it->second.off);
+                    };
+                    GemmDesc g;
+                    std::memset(&g, 0, sizeof g);
+                    const int32_t *lap = nullptr, *lbp = nullptr;
+                    int cla = 1, clb = 1;
+                    g.A = make_prep(nd_.A, nd_.sv, pA * pS, &lap, &cla);
+                    g.B = make_prep(nd_.B, {}, pB, &lbp, &clb);
+                    g.n = n;
+                    g.npad = npad;
+                    g.ld = npad;
+                    g.plane = npad * npad;
+                    g.la = cla;
+                    g.lb = clb;
+                    g.la_p = is_int ? lap : nullptr;
+                    g.lb_p = is_int ? lbp : nullptr;
+                    g.tiles = (int)(npad / 128);
+                    g.tile_start = W.gemm_tiles;
+                    W.gemm_tiles += (int64_t)g.tiles * g.tiles;
+                    W.gemm_flops += 2.0 * (double)n * n * n;
+                    const double cb = n * pA * pS * pB;
+                    if (is_int) {
+                        if (cb > kOverflow) {
+                            *status = 5;
+                            return "an intermediate matrix may exceed int64";
+                        }
+                        if (n >= 131072) {
+                            *status = 2;
+                            return "the exact path needs n < 131072 (int32 limb accumulation)";
+                        }
+                    }
+                    if (nd_.kind == NK::GemmStore) {
+                        nd_.bytes = (size_t)n * n * cfg.mat_es;
+                        nd_.off = A.alloc(nd_.bytes);
+                        nd_.bound = cb;
+                        g.final_ = 0;
+                        g.dtype_c = cfg.mat_dt;
+                        g.C = P(nd_.off);
+                        g.ldc = n;
+                        g.mx_out = (is_int && mxbase) ? mxbase + nd_.mx : nullptr;
+                    } else {
+                        g.final_ = 1;
+                        g.nZ = (int)nd_.Z.size();
+                        g.naw = (int)nd_.aw.size();
+                        g.nbx = (int)nd_.bx.size();
+                        for (int q = 0; q < g.nZ; ++q) g.Z[q] = mref(d, nd_.Z[q]);
+                        for (int q = 0; q < g.naw; ++q) g.aw[q] = vptr(d, nd_.aw[q]);
+                        for (int q = 0; q < g.nbx; ++q) g.bx[q] = vptr(d, nd_.bx[q]);
+                        size_t pb = (size_t)g.tiles * g.tiles * 16;
+                        size_t poff = A.alloc(pb);
+                        scratch.push_back({poff, pb});
+                        g.part = P(poff);
+                        ReduceDesc r;
+                        std::memset(&r, 0, sizeof r);
+                        r.part = P(poff);
+                        r.T = (int64_t)g.tiles * g.tiles;
+                        r.len = 1;
+                        r.stride = 1;
+                        r.out = scal_ptr(nd_);
+                        r.dot = 1;
+                        W.red.push_back(r);
+                        nd_.bound = (double)n * n * cb * pZ * paw * pbx;
+                    }
+                    W.gemm.push_back(g);
+                    break;
                 }
             }
-        }
-        // free scratch and values whose last use is this level
-        for (auto &sc : scratch) A.release(sc.first, sc.second);
-        for (int d = 0; d < nd; ++d)
-            for (int p = 0; p < np; ++p) {
-                auto &vi = vinfo[d * np + p];
-                const VProgram &pr = *progs[p];
-                for (size_t v = 0; v < pr.vals.size(); ++v)
-                    if ((pr.vals[v].kind == ValKind::Vec || pr.vals[v].kind == ValKind::Mat) &&
-                        vi[v].bytes && vi[v].last_use == L) {
-                        A.release(vi[v].off, vi[v].bytes);
-                        vi[v].bytes = 0;
-                    }
+            if (is_int && nd_.scal >= 0 && nd_.bound > kOverflowWide) {
+                *status = 5;
+                return "a V-statistic may exceed the 127-bit range";
             }
+        }
+        for (auto &sc : scratch) A.release(sc.first, sc.second);
+        for (int id : by_level[L]) (void)id;
+        for (auto &nd_ : G.nodes)
+            if (nd_.bytes && nd_.last_use == L) {
+                A.release(nd_.off, nd_.bytes);
+                nd_.bytes = 0;
+            }
+        // nodes never consumed (possible only for vectors of unused results)
+        for (int id : by_level[L]) {
+            Node &nd_ = G.nodes[id];
+            if (nd_.bytes && nd_.last_use == 0) {
+                // keep until the end; released implicitly
+            }
+        }
     }
-    (void)limb_slots_used;
-    (void)level_free;
     // combine tables
     for (int d = 0; d < nd; ++d) {
         CombineDesc c;
@@ -625,23 +866,22 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
         c.p_end = (d + 1) * np;
         S.comb.push_back(c);
         for (int p = 0; p < np; ++p) {
-            const VProgram &pr = *progs[p];
+            const auto &sc = G.prog_scalars[d * np + p];
             S.scal_off.push_back((int32_t)S.scal_idx.size());
-            S.scal_cnt.push_back((int32_t)pr.scalars.size());
-            for (int v : pr.scalars) S.scal_idx.push_back(vinfo[d * np + p][v].scal);
-            S.mu.push_back(pr.mu);
-            if (cfg.domain == DOM_INT) {
-                double b = 1;
-                for (int v : pr.scalars) b *= vinfo[d * np + p][v].bound;
-                if (b * std::fabs((double)pr.mu) * np > kOverflowWide) {
-                    *status = 5;
-                    return "the combined U-statistic may exceed the 127-bit range";
-                }
+            S.scal_cnt.push_back((int32_t)sc.size());
+            double b = 1;
+            for (int id : sc) {
+                S.scal_idx.push_back(G.nodes[id].scal);
+                b *= G.nodes[id].bound;
+            }
+            S.mu.push_back(progs[p]->mu);
+            if (is_int && b * std::fabs((double)progs[p]->mu) * np > kOverflowWide) {
+                *status = 5;
+                return "the combined U-statistic may exceed the 127-bit range";
             }
         }
     }
     S.arena_bytes = A.top;
-    // descriptor blob
     S.off_diag = S.blob.put(S.diag);
     for (auto &W : S.levels) {
         W.off_prep = S.blob.put(W.prep);

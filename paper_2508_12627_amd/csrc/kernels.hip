@@ -67,6 +67,19 @@ __device__ __forceinline__ typename Dom<DOM>::acc load_vec(const void *p, int64_
     return static_cast<const typename Dom<DOM>::acc *>(p)[i];
 }
 
+
+// Call f(T()) with T the element type named by dtype, so that loops over a
+// matrix compile once per element type with no per-element branch.
+template <class F>
+__device__ __forceinline__ void with_dtype(int32_t dt, F &&f) {
+    switch (dt) {
+        case DT_F64: f(double()); break;
+        case DT_F32: f(float()); break;
+        case DT_I8: f(int8_t()); break;
+        default: f((long long)0); break;
+    }
+}
+
 // Locate the problem owning flat block index b (descriptors sorted by
 // tile_start, first one at 0).
 template <class D>
@@ -177,56 +190,95 @@ __global__ void k_absmax_i8(const int8_t *const *src, const int64_t *n, int npro
 
 // ----------------------------------------------------------------- elim1
 
-// Tile partials of y(w) = sum_v prod_k A_k(v,w) prod_j s_j(v) over a 64 x 64
-// (v, w) tile.  Matrices are read coalesced in their stored orientation and
-// transposed through LDS.
+// Rows of one column strip handled by a block (and thus the number of
+// partial rows left for the fixed-order reduction: ceil(n / kStripRows)).
+constexpr int kStripRows = kElimStrip;
+
+// Partials of y(w) = sum_v prod_k A_k(v,w) prod_j s_j(v) for a strip of 64
+// columns w and kStripRows rows v.  Thread t owns column t%64 and rows
+// t/64 + 4i (i < 16) of each 64-row chunk and keeps their products in
+// registers; operands stored (v, w) are read directly (coalesced along w),
+// operands stored (w, v) are transposed through one LDS tile.
 template <int DOM>
 __global__ __launch_bounds__(256) void k_elim1(const Elim1Desc *D, int nprob) {
     typedef typename Dom<DOM>::acc A;
-    __shared__ A prod[64][65];
+    __shared__ A tile[64][65];
     __shared__ A red[4][64];
     const int64_t b = blockIdx.x;
     const int p = find_problem(D, nprob, b);
     const Elim1Desc &d = D[p];
     const int64_t local = b - d.tile_start;
     const int64_t tv = local / d.tiles_w, tw = local % d.tiles_w;
-    const int64_t n = d.n, v0 = tv * 64, w0 = tw * 64;
-    const int t = threadIdx.x;
-    for (int e = t; e < 4096; e += 256) {
-        int r = e >> 6, c = e & 63;
-        int64_t v = v0 + r, w = w0 + c;
-        A val = (v < n && w < n) ? (A)1 : (A)0;
-        if (v < n)
-            for (int j = 0; j < d.nS; ++j) val *= load_vec<DOM>(d.s[j], v);
-        prod[r][c] = val;
-    }
-    __syncthreads();
-    for (int k = 0; k < d.nA; ++k) {
-        const MatRef m = d.A[k];
-        for (int e = t; e < 4096; e += 256) {
-            int r = e >> 6, c = e & 63;
-            // trans == 0: stored (v, w), row r over v.  trans == 1: stored
-            // (w, v), row r over w.
-            int rv = m.trans ? c : r, cw = m.trans ? r : c;
-            int64_t v = v0 + rv, w = w0 + cw;
-            if (v < n && w < n) {
-                int64_t idx = m.trans ? (w * m.ld + v) : (v * m.ld + w);
-                A x = load_elem<DOM>(m.p, m.dtype, idx);
-                if (m.zdiag && v == w) x = 0;
-                prod[rv][cw] *= x;
+    const int64_t n = d.n, w0 = tw * 64;
+    const int t = threadIdx.x, c = t & 63, g = t >> 6;
+    const int64_t w = w0 + c;
+    const int64_t vbeg = tv * kStripRows, vend = min(n, vbeg + kStripRows);
+    A sum = 0;
+    for (int64_t v0 = vbeg; v0 < vend; v0 += 64) {
+        A pr[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            int64_t v = v0 + g + 4 * i;
+            A val = (v < n && w < n) ? (A)1 : (A)0;
+            if (v < n && w < n)
+                for (int j = 0; j < d.nS; ++j) val *= load_vec<DOM>(d.s[j], v);
+            pr[i] = val;
+        }
+        for (int k = 0; k < d.nA; ++k) {
+            const MatRef m = d.A[k];
+            if (!m.trans) {
+                with_dtype(m.dtype, [&](auto tag) {
+                    typedef decltype(tag) T;
+                    const T *mp = static_cast<const T *>(m.p);
+                    T x[16];
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) {
+                        int64_t v = v0 + g + 4 * i;
+                        x[i] = (v < n && w < n) ? mp[v * m.ld + w] : (T)0;
+                    }
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) {
+                        int64_t v = v0 + g + 4 * i;
+                        A xv = (A)x[i];
+                        if (m.zdiag && v == w) xv = 0;
+                        pr[i] *= xv;
+                    }
+                });
+            } else {
+                __syncthreads();
+                with_dtype(m.dtype, [&](auto tag) {
+                    typedef decltype(tag) T;
+                    const T *mp = static_cast<const T *>(m.p);
+                    T x[16];
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) {
+                        int e = t + 256 * q;
+                        int rw = e >> 6, cv = e & 63;
+                        int64_t ww = w0 + rw, vv = v0 + cv;
+                        x[q] = (ww < n && vv < n) ? mp[ww * m.ld + vv] : (T)0;
+                    }
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) {
+                        int e = t + 256 * q;
+                        int rw = e >> 6, cv = e & 63;
+                        A xv = (A)x[q];
+                        if (m.zdiag && w0 + rw == v0 + cv) xv = 0;
+                        tile[cv][rw] = xv;
+                    }
+                });
+                __syncthreads();
+#pragma unroll
+                for (int i = 0; i < 16; ++i) pr[i] *= tile[g + 4 * i][c];
             }
         }
-        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 16; ++i) sum += pr[i];
     }
-    const int c = t & 63, g = t >> 6;
-    A sum = 0;
-#pragma unroll 4
-    for (int r = g * 16; r < g * 16 + 16; ++r) sum += prod[r][c];
     red[g][c] = sum;
     __syncthreads();
-    if (g == 0 && w0 + c < n) {
+    if (g == 0 && w < n) {
         A tot = red[0][c] + red[1][c] + red[2][c] + red[3][c];
-        static_cast<A *>(d.part)[tv * n + w0 + c] = tot;
+        static_cast<A *>(d.part)[tv * n + w] = tot;
     }
 }
 
@@ -303,17 +355,22 @@ __global__ __launch_bounds__(256) void k_elim0(const Elim0Desc *D, int nprob) {
 
 // ----------------------------------------------------------------- prep
 
+// One 64 x 64 tile of a GEMM operand out[w][v] = prod_j s_j(v) prod_k
+// A_k(v, w).  Thread t owns output column v = t%64 (contiguous in memory)
+// and rows w = t/64 + 4i; operands stored (w, v) are read directly,
+// operands stored (v, w) are transposed through one LDS tile.
 template <int DOM>
 __global__ __launch_bounds__(256) void k_prep(const PrepDesc *D, int nprob) {
     typedef typename Dom<DOM>::acc A;
-    __shared__ A prod[64][65];  // [w offset][v offset]
+    __shared__ A tile[64][65];  // [w offset][v offset]
     const int64_t b = blockIdx.x;
     const int p = find_problem(D, nprob, b);
     const PrepDesc &d = D[p];
     const int64_t local = b - d.tile_start;
     const int64_t tw = local / d.tiles, tv = local % d.tiles;
     const int64_t n = d.n, w0 = tw * 64, v0 = tv * 64;
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, c = t & 63, g = t >> 6;
+    const int64_t v = v0 + c;
     int limbs = d.limbs;
     if (d.format == PF_I8LIMBS) {
         // Digits needed for |x| <= prod of the operands' maxima: a top digit
@@ -329,38 +386,71 @@ __global__ __launch_bounds__(256) void k_prep(const PrepDesc *D, int nprob) {
         limbs = L;
         if (local == 0 && t == 0) *d.limbs_out = L;
     }
-    for (int e = t; e < 4096; e += 256) {
-        int r = e >> 6, c = e & 63;
-        int64_t w = w0 + r, v = v0 + c;
-        A val = (v < n && w < n) ? (A)1 : (A)0;
-        if (v < n && w < n)
-            for (int j = 0; j < d.nS; ++j) val *= load_vec<DOM>(d.s[j], v);
-        prod[r][c] = val;
+    A sv = 0;
+    if (v < n) {
+        sv = 1;
+        for (int j = 0; j < d.nS; ++j) sv *= load_vec<DOM>(d.s[j], v);
     }
-    __syncthreads();
+    A pr[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        int64_t w = w0 + g + 4 * i;
+        pr[i] = (w < n) ? sv : (A)0;
+    }
     for (int k = 0; k < d.nA; ++k) {
         const MatRef m = d.A[k];
-        for (int e = t; e < 4096; e += 256) {
-            int r = e >> 6, c = e & 63;
-            // canonical operand orientation is (v, w).  trans == 0: stored
-            // (v, w), row r over v; trans == 1: stored (w, v), row r over w.
-            int rw = m.trans ? r : c, cv = m.trans ? c : r;
-            int64_t w = w0 + rw, v = v0 + cv;
-            if (v < n && w < n) {
-                int64_t idx = m.trans ? (w * m.ld + v) : (v * m.ld + w);
-                A x = load_elem<DOM>(m.p, m.dtype, idx);
-                if (m.zdiag && v == w) x = 0;
-                prod[rw][cv] *= x;
-            }
+        if (m.trans) {  // stored (w, v)
+            with_dtype(m.dtype, [&](auto tag) {
+                typedef decltype(tag) T;
+                const T *mp = static_cast<const T *>(m.p);
+                T x[16];
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    int64_t w = w0 + g + 4 * i;
+                    x[i] = (v < n && w < n) ? mp[w * m.ld + v] : (T)0;
+                }
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    int64_t w = w0 + g + 4 * i;
+                    A xv = (A)x[i];
+                    if (m.zdiag && v == w) xv = 0;
+                    pr[i] *= xv;
+                }
+            });
+        } else {  // stored (v, w)
+            __syncthreads();
+            with_dtype(m.dtype, [&](auto tag) {
+                typedef decltype(tag) T;
+                const T *mp = static_cast<const T *>(m.p);
+                T x[16];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    int e = t + 256 * q;
+                    int rv = e >> 6, cw = e & 63;
+                    int64_t vv = v0 + rv, ww = w0 + cw;
+                    x[q] = (vv < n && ww < n) ? mp[vv * m.ld + ww] : (T)0;
+                }
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    int e = t + 256 * q;
+                    int rv = e >> 6, cw = e & 63;
+                    A xv = (A)x[q];
+                    if (m.zdiag && v0 + rv == w0 + cw) xv = 0;
+                    tile[cw][rv] = xv;
+                }
+            });
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < 16; ++i) pr[i] *= tile[g + 4 * i][c];
         }
-        __syncthreads();
     }
-    for (int e = t; e < 4096; e += 256) {
-        int r = e >> 6, c = e & 63;
-        int64_t w = w0 + r, v = v0 + c;
-        if (w >= d.npad || v >= d.npad) continue;
+    if (v >= d.npad) return;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        int64_t w = w0 + g + 4 * i;
+        if (w >= d.npad) continue;
         int64_t o = w * d.ldo + v;
-        A x = prod[r][c];
+        A x = pr[i];
         switch (d.format) {
             case PF_F64: static_cast<double *>(d.out)[o] = (double)x; break;
             case PF_F32: static_cast<float *>(d.out)[o] = (float)x; break;

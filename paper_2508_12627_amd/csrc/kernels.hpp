@@ -40,8 +40,9 @@ struct DiagDesc {
     unsigned long long *mx_out;  // DOM_INT: running max |dst|, or null
 };
 
-// Tile partials of y(w) = sum_v prod_k A_k(v, w) prod_j s_j(v):
-// part[tv * n + w] holds the sum over the 64 rows of tile tv.
+// Strip partials of y(w) = sum_v prod_k A_k(v, w) prod_j s_j(v):
+// part[tv * n + w] holds the sum over rows [tv*kElimStrip, (tv+1)*kElimStrip)
+// for the 64 columns of strip tw; tiles_v = ceil(n / kElimStrip).
 struct Elim1Desc {
     int64_t n;
     int32_t nA, nS;
@@ -127,6 +128,7 @@ struct CombineDesc {
 
 constexpr int kGemmTile = 128;
 constexpr int kTile = 64;
+constexpr int kElimStrip = 512;
 
 hipError_t launch_rbf(const double *X, int64_t n, int32_t d, double divisor, void *out,
                       int32_t dtype, hipStream_t s);

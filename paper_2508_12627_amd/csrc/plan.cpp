@@ -108,8 +108,14 @@ std::vector<uint32_t> quotient_adjacency(const std::vector<Edge> &edges,
     return adj;
 }
 
-std::vector<int> minfill_order(int J, std::vector<uint32_t> adj) {
+// Greedy min-fill.  Ties are broken by degree, then by how many of the
+// vertex's factors are intermediates (results of earlier eliminations), then
+// by whether it carries a vector (a self-loop diagonal or a degree-1
+// result), then by id.  The last two keys favour contractions of input
+// factors without diagonal scaling, which different partitions share.
+std::vector<int> minfill_order(int J, std::vector<uint32_t> adj, std::vector<char> hasvec) {
     std::vector<int> order;
+    std::vector<uint32_t> interm(J, 0);
     uint32_t alive = (J >= 32) ? 0xffffffffu : ((1u << J) - 1);
     while (alive) {
         int best = -1;
@@ -123,17 +129,21 @@ std::vector<int> minfill_order(int J, std::vector<uint32_t> adj) {
                 fill += __builtin_popcount(nb & ~adj[x] & ~(1u << x));
             }
             fill /= 2;
-            long key = ((long)fill << 20) | ((long)__builtin_popcount(nb) << 8) | v;
+            long key = ((long)fill << 40) | ((long)__builtin_popcount(nb) << 32) |
+                       ((long)__builtin_popcount(interm[v] & alive) << 24) |
+                       ((long)(hasvec[v] ? 1 : 0) << 16) | v;
             if (key < best_key) {
                 best_key = key;
                 best = v;
             }
         }
-        uint32_t nb = adj[best] & alive;
+        uint32_t nb = adj[best] & alive & ~(1u << best);
         for (uint32_t p = nb; p; p &= p - 1) {
             int x = __builtin_ctz(p);
             adj[x] |= nb & ~(1u << x);
+            interm[x] |= nb & ~(1u << x);
         }
+        if (__builtin_popcount(nb) == 1) hasvec[__builtin_ctz(nb)] = 1;
         alive &= ~(1u << best);
         order.push_back(best);
     }
@@ -336,6 +346,23 @@ std::vector<float> program_features(const VProgram &p, double n) {
     return f;
 }
 
+// Count of GEMM steps with a diagonal scaling plus GEMM operand groups that
+// contain an intermediate value.
+static int sharing_penalty(const VProgram &p) {
+    int pen = 0;
+    for (const Step &s : p.steps) {
+        if (s.kind != StepKind::Elim2 && s.kind != StepKind::Final2) continue;
+        if (!s.sv.empty()) ++pen;
+        auto interm = [&](const std::vector<MatOp> &g) {
+            for (auto &o : g)
+                if (p.vals[o.val].kind == ValKind::Mat) return true;
+            return false;
+        };
+        pen += interm(s.A) + interm(s.B);
+    }
+    return pen;
+}
+
 std::string build_program(const std::vector<Edge> &edges, int m, const std::vector<int> &block_of,
                           const PlanOptions &opts, const OrderScorer *scorer, VProgram &out) {
     int J = 0;
@@ -346,7 +373,10 @@ std::string build_program(const std::vector<Edge> &edges, int m, const std::vect
     auto adj = quotient_adjacency(edges, block_of, J);
     out.tw = exact_treewidth(J, adj);
     (void)m;
-    std::vector<int> mf = minfill_order(J, adj);
+    std::vector<char> hasvec(J, 0);
+    for (const Edge &e : edges)
+        if (block_of[e.u] == block_of[e.v]) hasvec[block_of[e.u]] = 1;
+    std::vector<int> mf = minfill_order(J, adj, hasvec);
     auto finish = [&](const std::vector<int> &ord) {
         std::string err = lower_order(edges, block_of, J, ord, out);
         out.executable = err.empty();
@@ -376,8 +406,10 @@ std::string build_program(const std::vector<Edge> &edges, int m, const std::vect
             double f, b;
             program_cost(tmp, nref, 4.0, &f, &b);
             // Time proxy: MFMA work plus memory traffic plus a per-level
-            // launch latency, in seconds at nominal rates.
-            key = f / 100e12 + b / 5e12 + tmp.depth * 8e-6;
+            // launch latency, in seconds at nominal rates; among equal
+            // proxies, prefer contractions of input factors without diagonal
+            // scaling (shareable across partitions).
+            key = f / 100e12 + b / 5e12 + tmp.depth * 8e-6 + 1e-9 * sharing_penalty(tmp);
         }
         if (key < best - 1e-15) {
             best = key;

@@ -75,6 +75,7 @@ struct PlanOptions {
     int precision = 0;
     int order = 0;
     int sparsify = 0;
+    bool cse = true;  // merge equal steps across partitions at evaluation
     uint64_t workspace_limit = 0;
     std::string cost_model_path;
 };

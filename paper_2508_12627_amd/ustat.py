@@ -26,6 +26,7 @@ PRECISIONS = {"f64": F64, "f32": F32, "bf16x3": BF16X3, "i8": I8}
 ORDERS = {"minfill": ORDER_MINFILL, "exhaustive": ORDER_EXHAUSTIVE, "learned": ORDER_LEARNED}
 STATUS = {0: "ok", 1: "invalid", 2: "unsupported", 3: "nomem", 4: "hip", 5: "overflow",
           6: "infeasible"}
+FLAG_NO_CSE = 1
 FACTOR_DTYPE = {F64: torch.float64, F32: torch.float32, BF16X3: torch.float32, I8: torch.int8}
 PROFILE_KINDS = {"prep": 0, "gemm": 1, "elim1": 2, "reduce": 3, "rbf": 4}
 
@@ -39,7 +40,7 @@ class UstatError(RuntimeError):
 
 class PlanOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("order", ctypes.c_int32),
-                ("sparsify", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("sparsify", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("workspace_limit", ctypes.c_uint64), ("cost_model_path", ctypes.c_char_p)]
 
 
@@ -126,13 +127,15 @@ def _edges_array(edges: Sequence[Tuple[int, int]]):
 # ------------------------------------------------------------------ C names
 
 def ustat_plan_create(m: int, edges, precision="f64", order="minfill", sparsify=False,
-                      workspace_limit: int = 0, cost_model_path: Optional[str] = None):
+                      workspace_limit: int = 0, cost_model_path: Optional[str] = None,
+                      cse: bool = True):
     L = load_library()
     o = PlanOpts()
     _check(L.ustat_plan_opts_default(ctypes.byref(o)))
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     o.order = ORDERS[order] if isinstance(order, str) else int(order)
     o.sparsify = 1 if sparsify else 0
+    o.flags = 0 if cse else FLAG_NO_CSE
     o.workspace_limit = int(workspace_limit)
     o.cost_model_path = cost_model_path.encode() if cost_model_path else None
     h = ctypes.c_void_p()
@@ -252,12 +255,13 @@ class Plan:
     """Owning wrapper of a ustat_plan handle."""
 
     def __init__(self, m: int, edges, precision="f64", order="minfill", sparsify=False,
-                 workspace_limit: int = 0, cost_model_path: Optional[str] = None):
+                 workspace_limit: int = 0, cost_model_path: Optional[str] = None,
+                 cse: bool = True):
         self.m = int(m)
         self.edges = [tuple(e) for e in edges]
         self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         self.h = ustat_plan_create(m, edges, precision, order, sparsify, workspace_limit,
-                                   cost_model_path)
+                                   cost_model_path, cse)
 
     def __del__(self):
         h = getattr(self, "h", None)

@@ -256,3 +256,24 @@ def test_lowrank_full_size(U, prec):
     res = P.eval([dev(K, P.factor_dtype)] * 6)
     # |U| <= S, so a relative-to-|U| bound is at least as strict
     assert abs(res.value - ref) <= TOL[prec] * abs(ref) * (1 if prec == "f64" else 1) + 0.0
+
+
+@pytest.mark.parametrize("name", ["cycle4", "c5chord", "bowtie"])
+def test_cse_matches_separate_evaluation(U, name):
+    """Merging equal steps across partitions gives the same U as evaluating
+    every partition separately (fp64 to 1e-12 S; int8 exactly)."""
+    import torch
+    edges = GRAPHS[name]
+    m = nverts(edges)
+    n = 150
+    (M,) = W.random_matrices(1, n, seed=17, lo=0.0, hi=1.0)
+    Kd = dev(M, torch.float64)
+    say(f"cse {name} n={n}")
+    a = U.Plan(m, edges, precision="f64").eval([Kd] * len(edges))
+    b = U.Plan(m, edges, precision="f64", cse=False).eval([Kd] * len(edges))
+    assert abs(a.value - b.value) <= 1e-12 * b.err_scale
+    A = W.erdos_renyi(n, 0.2, seed=5)
+    Ad = dev(A, torch.int8)
+    ai = U.Plan(m, edges, precision="i8").eval([Ad] * len(edges))
+    bi = U.Plan(m, edges, precision="i8", cse=False).eval([Ad] * len(edges))
+    assert ai.exact == bi.exact
