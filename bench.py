@@ -38,25 +38,46 @@ def timed_evals(plan, X, div, steps, warmup, stream):
     return time.perf_counter() - t0, r
 
 
-def gemm_roofline(U, plan, X, div, stream, prec, reps=3):
-    """Per-launch GEMM durations from HIP events recorded on the launch
-    stream (kernel-by-kernel launches, no graph)."""
+HBM_PEAK = 8.0e12  # bytes/s
+KERNELS = {"gemm": "k_gemm", "elim1": "k_elim1", "prep": "k_prep", "reduce": "k_reduce",
+           "rbf": "k_rbf"}
+
+
+def kernel_rooflines(U, plan, X, div, stream, prec, reps=5):
+    """Per-kernel-kind durations from HIP events recorded around every
+    launch on the launch stream (kernel-by-kernel launches, no graph)."""
     U.ustat_profile_enable(True)
     U.ustat_profile_reset()
     for _ in range(reps):
         plan.eval_samples(X, div, stream=stream)
-    g = U.ustat_profile_read("gemm")
-    others = {k: U.ustat_profile_read(k) for k in ("prep", "elim1", "reduce", "rbf")}
+    stats = {k: U.ustat_profile_read(k) for k in KERNELS}
     U.ustat_profile_enable(False)
-    achieved = g["flops"] / (g["ms"] * 1e-3)
-    return {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAKS[prec] / 1e12,
-            "unit": "TFLOP/s", "frac": achieved / PEAKS[prec], "traffic": None,
-            "kernel": f"k_gemm<{prec}>", "launches": g["launches"],
-            "avg_launch_ms": g["ms"] / max(1, g["launches"]),
-            "flops_per_launch": g["flops"] / max(1, g["launches"]),
-            "executed_frac": achieved * (3 if prec == "bf16x3" else 1) / PEAKS[prec],
-            "other_kernels_ms_per_eval": {k: v["ms"] / reps for k, v in others.items()},
-            "gemm_ms_per_eval": g["ms"] / reps}
+    return summarize(stats, reps, prec)
+
+
+def summarize(stats, reps, prec):
+    out = {}
+    for k, g in stats.items():
+        if g["launches"] == 0:
+            continue
+        sec = g["ms"] * 1e-3
+        e = {"kernel": KERNELS[k] + (f"<{prec}>" if k == "gemm" else ""),
+             "ms_per_eval": g["ms"] / reps, "launches_per_eval": g["launches"] / reps,
+             "avg_launch_ms": g["ms"] / g["launches"], "traffic": None}
+        if k == "gemm":
+            achieved = g["flops"] / sec
+            e.update({"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAKS[prec] / 1e12,
+                      "unit": "TFLOP/s", "frac": achieved / PEAKS[prec],
+                      "flops_per_launch": g["flops"] / g["launches"],
+                      "executed_frac": achieved * (3 if prec == "bf16x3" else 1) / PEAKS[prec]})
+        elif g["bytes"] > 0:
+            achieved = g["bytes"] / sec
+            e.update({"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
+                      "unit": "GB/s", "frac": achieved / HBM_PEAK,
+                      "bytes_per_launch": g["bytes"] / g["launches"]})
+        out[k] = e
+    dominant = max(out, key=lambda k: out[k]["ms_per_eval"])
+    return dominant, out
 
 
 def cpu_baseline(X, div, budget_s=15.0):
@@ -84,6 +105,82 @@ def cpu_baseline(X, div, budget_s=15.0):
                       f"the prefix fraction"}
 
 
+def bench_batched(args):
+    """256 independent datasets, n ~ U{128..4096} (seed 4), d = 32, iid
+    Student-t(5) coordinates, kernel on the 5-cycle plus chord (0,2), RBF
+    divisor 64; every (dataset, partition) pair in one HIP graph replay."""
+    import numpy as np
+    import torch
+    from paper_2508_12627_amd import ustat as U, workloads as W
+    ns = [int(x) for x in W.ragged_sizes(256, 128, 4096, seed=4)]
+    d, div = 32, 64.0
+    stream = torch.cuda.Stream()
+    Xs = [torch.tensor(W.student_t_samples(n, d, seed=1000 + i), dtype=torch.float64,
+                       device="cuda") for i, n in enumerate(ns)]
+    out = {"metric": "datasets/s (batched U-statistics)", "unit": "datasets/s",
+           "config": {"workload": "256 datasets, n~U{128..4096}, d=32, Student-t(5), "
+                                  "5-cycle + chord kernel, 52 restricted V-statistics each",
+                      "precision": args.precision}}
+    plan = U.Plan(5, W.CYCLE5_CHORD, precision=args.precision, order=args.order)
+    steps = max(2, args.steps // 10)
+    for _ in range(max(1, args.warmup // 2)):
+        r = plan.eval_batched(Xs, div, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = plan.eval_batched(Xs, div, stream=stream)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    flops = sum(plan.cost(n)["flops"] for n in ns)
+    out.update({"value": len(ns) / el, "ms_per_batch": 1e3 * el, "steps": steps,
+                "algorithmic_flops_per_batch_without_cse": flops})
+    # reference: f64 path of the same batch, error relative to S
+    p64 = U.Plan(5, W.CYCLE5_CHORD, precision="f64", order=args.order)
+    r64 = p64.eval_batched(Xs, div, stream=stream)
+    out["max_err_vs_f64_over_S"] = max(abs(a.value - b.value) / b.err_scale for a, b in zip(r, r64))
+    dom, kr = kernel_rooflines_batched(U, plan, Xs, div, stream, args.precision)
+    out["roofline"] = dict(kr[dom])
+    out["roofline"]["dominant_kind"] = dom
+    out["kernels"] = kr
+    print(json.dumps(out))
+
+
+def kernel_rooflines_batched(U, plan, Xs, div, stream, prec, reps=1):
+    U.ustat_profile_enable(True)
+    U.ustat_profile_reset()
+    for _ in range(reps):
+        plan.eval_batched(Xs, div, stream=stream)
+    stats = {k: U.ustat_profile_read(k) for k in KERNELS}
+    U.ustat_profile_enable(False)
+    return summarize(stats, reps, prec)
+
+
+def bench_cycle5_exact(args):
+    """Exact 5-cycle count of G(8192, 0.01) (seed 3) on the int8 path."""
+    import numpy as np
+    import torch
+    from paper_2508_12627_amd import ustat as U, workloads as W
+    A = W.erdos_renyi(8192, 0.01, seed=3)
+    Ad = torch.tensor(A, dtype=torch.int8, device="cuda")
+    out = {"metric": "exact 5-cycle count, G(8192, 0.01)", "unit": "evals/s",
+           "config": {"workload": "G(8192,0.01) seed 3, 5-cycle kernel, int8 MFMA limbs"}}
+    for sp in (False, True):
+        plan = U.Plan(5, W.CYCLE5, precision="i8", sparsify=sp)
+        r = plan.eval([Ad] * 5)
+        torch.cuda.synchronize()
+        steps = max(3, args.steps // 5)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            r = plan.eval([Ad] * 5)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / steps
+        out["sparsified" if sp else "full"] = {"ms_per_eval": 1e3 * el, "U": str(r.exact),
+                                               "cycles": str(r.exact // 10),
+                                               "num_vstats": r.num_vstats}
+    out["value"] = 1e3 / out["full"]["ms_per_eval"]
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +190,9 @@ def main():
     ap.add_argument("--order", default="exhaustive", choices=["minfill", "exhaustive"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--workload", default="cycle4",
+                    choices=["cycle4", "batched", "cycle5-exact"],
+                    help="cycle4: the headline line; the others print their own line")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many plain steps (for external profilers)")
     args = ap.parse_args()
@@ -106,6 +206,10 @@ def main():
     from paper_2508_12627_amd import ustat as U, workloads as W
 
     torch.cuda.set_device(0)
+    if args.workload == "batched":
+        return bench_batched(args)
+    if args.workload == "cycle5-exact":
+        return bench_cycle5_exact(args)
     m, edges, n, d = WORKLOAD["m"], WORKLOAD["edges"], WORKLOAD["n"], WORKLOAD["d"]
     div = 2.0 * d
     Xh = W.gaussian_samples(n, d, seed=WORKLOAD["seed"])
@@ -133,7 +237,11 @@ def main():
                                   "15 restricted V-statistics", "n": n, "d": d, "m": m,
                       "order": args.order, "precision": args.precision, "cse": True,
                       "num_vstats": r.num_vstats}}
-    out["roofline"] = gemm_roofline(U, main_plan, X, div, stream, args.precision)
+    dom, kr = kernel_rooflines(U, main_plan, X, div, stream, args.precision)
+    out["roofline"] = dict(kr[dom])
+    out["roofline"]["dominant_kind"] = dom
+    out["roofline_mfma_gemm"] = kr.get("gemm")
+    out["kernels"] = kr
     if not args.no_compare:
         res = {}
         vals = {}

@@ -143,6 +143,15 @@ ustat_status ustat_plan_cost(ustat_plan plan, int64_t n, double *flops, double *
                              uint64_t *workspace);
 
 /*
+ * Device workspace (bytes) of one evaluation of `batch` datasets with sizes
+ * n (host int64 array), as ustat_eval_batched would allocate it.
+ * shared_factor = 1 models every edge reading one factor matrix per dataset
+ * (the sample entry points); 0 models independent factors per edge.
+ */
+ustat_status ustat_plan_workspace(ustat_plan plan, int32_t batch, const int64_t *n,
+                                  int32_t shared_factor, uint64_t *bytes);
+
+/*
  * Partition idx (0 <= idx < num_vstats) in restricted-growth form:
  * block_of (host int32 [m]) gives each vertex's block, blocks numbered in
  * order of first appearance; *mu its Moebius coefficient; *tw the exact
@@ -216,11 +225,15 @@ ustat_status ustat_build_rbf(int64_t n, int32_t d, const double *X, double rbf_d
  * launch stream; off by default, never active inside graph capture).
  * kind: 0 operand prep, 1 GEMM, 2 column reduction, 3 partial reduction,
  * 4 factor build.  ustat_profile_read returns totals since the last reset:
- * milliseconds, number of launches and algorithmic flops (2 n^3 per GEMM).
+ * milliseconds, number of launches, algorithmic flops (2 n^3 per GEMM) and
+ * algorithmic bytes (every operand element read once plus the outputs
+ * written, for the column reduction and operand prep kernels).  Any output
+ * pointer may be NULL.
  */
 ustat_status ustat_profile_enable(int32_t on);
 ustat_status ustat_profile_reset(void);
-ustat_status ustat_profile_read(int32_t kind, double *ms, int64_t *launches, double *flops);
+ustat_status ustat_profile_read(int32_t kind, double *ms, int64_t *launches, double *flops,
+                                double *bytes);
 
 const char *ustat_status_string(ustat_status s);
 const char *ustat_last_error(void);

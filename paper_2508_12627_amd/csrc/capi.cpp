@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstring>
 #include <functional>
+#include <map>
 #include <memory>
 #include <new>
 #include <string>
@@ -93,8 +94,9 @@ bool canonical_rgs(const int32_t *block_of, int m, std::vector<int> &out) {
     return true;
 }
 
-hipError_t grow(char **p, size_t *have, size_t need) {
+hipError_t grow(char **p, size_t *have, size_t need, Runtime *rt = nullptr) {
     if (*p && *have >= need) return hipSuccess;
+    if (rt) rt->drop_graphs();  // captured graphs reference the old buffer
     if (*p) (void)hipFree(*p);
     *p = nullptr;
     *have = 0;
@@ -202,8 +204,19 @@ ustat_status ustat_plan_cost(ustat_plan plan, int64_t n, double *flops, double *
     if (bytes) *bytes = b;
     if (workspace) {
         if (!plan->plan.executable) *workspace = 0;
-        else *workspace = workspace_bytes(plan->plan, plan->all, {n});
+        else *workspace = workspace_bytes(plan->plan, plan->all, {n}, false);
     }
+    return ok();
+}
+
+ustat_status ustat_plan_workspace(ustat_plan plan, int32_t batch, const int64_t *n,
+                                  int32_t shared_factor, uint64_t *bytes) {
+    if (!plan || batch < 1 || !n || !bytes) return fail(USTAT_E_INVALID, "bad arguments");
+    if (!plan->plan.executable) return fail(USTAT_E_UNSUPPORTED, plan->plan.lower_error);
+    for (int b = 0; b < batch; ++b)
+        if (n[b] < plan->plan.m) return fail(USTAT_E_INVALID, "n must be at least m");
+    std::vector<int64_t> ns(n, n + batch);
+    *bytes = workspace_bytes(plan->plan, plan->all, ns, shared_factor != 0);
     return ok();
 }
 
@@ -326,11 +339,8 @@ ustat_status ustat_eval_samples(ustat_plan plan, int64_t n, int32_t d, const dou
         return fail(USTAT_E_INVALID, "samples with an RBF kernel need a floating-point precision");
     const int dt = plan->plan.opts.precision == USTAT_F64 ? DT_F64 : DT_F32;
     const size_t es = dt == DT_F64 ? 8 : 4;
-    hipError_t e = grow(&plan->factors, &plan->factors_bytes, (size_t)n * n * es);
+    hipError_t e = grow(&plan->factors, &plan->factors_bytes, (size_t)n * n * es, &plan->rt);
     if (e != hipSuccess) return fail(USTAT_E_NOMEM, hipGetErrorString(e));
-    if (plan->rt.graph) {
-        // the factor buffer may have moved; a stale graph is rebuilt by key
-    }
     std::vector<Dataset> data(1);
     data[0].n = n;
     for (size_t k = 0; k < plan->plan.edges.size(); ++k) data[0].factors.push_back(plan->factors);
@@ -400,37 +410,94 @@ ustat_status ustat_eval_batched(ustat_plan plan, int32_t batch, const int64_t *n
     }
     const int dt = plan->plan.opts.precision == USTAT_F64 ? DT_F64 : DT_F32;
     const size_t es = dt == DT_F64 ? 8 : 4;
-    std::vector<size_t> off(batch);
-    size_t tot = 0;
-    for (int b = 0; b < batch; ++b) {
-        off[b] = tot;
-        tot += ((size_t)n[b] * n[b] * es + 255) / 256 * 256;
+    auto fbytes = [&](int64_t nn) { return ((size_t)nn * nn * es + 255) / 256 * 256; };
+    // Split the batch into chunks whose factor matrices and workspace fit
+    // the budget: opts.workspace_limit, else half of the free device memory
+    // (counting the buffers this plan already holds as free).
+    size_t budget = plan->plan.opts.workspace_limit;
+    if (!budget) {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) return fail(USTAT_E_HIP, "hipMemGetInfo failed");
+        budget = (fr + plan->rt.arena_bytes + plan->factors_bytes) / 2;
     }
-    hipError_t e = grow(&plan->factors, &plan->factors_bytes, tot);
-    if (e != hipSuccess) return fail(USTAT_E_NOMEM, hipGetErrorString(e));
-    std::vector<Dataset> data(batch);
-    std::string key = "batch:" + std::to_string(d) + ":" + std::to_string(rbf_divisor) + ":" +
-                      std::to_string((uintptr_t)plan->factors);
-    for (int b = 0; b < batch; ++b) {
-        data[b].n = n[b];
-        for (size_t k = 0; k < plan->plan.edges.size(); ++k)
-            data[b].factors.push_back(plan->factors + off[b]);
-        key += ":" + std::to_string(n[b]) + "@" + std::to_string((uintptr_t)X[b]);
-    }
-    std::vector<const double *> xs(X, X + batch);
-    std::vector<int64_t> ns(n, n + batch);
-    char *fb = plan->factors;
-    auto pre = [=](hipStream_t s) -> hipError_t {
-        for (int b = 0; b < batch; ++b) {
-            hipError_t e2 = launch_rbf(xs[b], ns[b], d, rbf_divisor, fb + off[b], dt, s);
-            if (e2 != hipSuccess) return e2;
-        }
-        return hipSuccess;
+    std::map<int64_t, size_t> ws_one;
+    auto per_dataset = [&](int64_t nn) {
+        auto it = ws_one.find(nn);
+        if (it != ws_one.end()) return it->second;
+        size_t w = workspace_bytes(plan->plan, plan->all, {nn}, true) + fbytes(nn);
+        ws_one[nn] = w;
+        return w;
     };
-    std::vector<DatasetResult> res;
-    ustat_status st = run(plan, plan->all, data, (hipStream_t)stream, res, nullptr, pre, key);
-    if (st != USTAT_OK) return st;
-    for (int b = 0; b < batch; ++b) fill_result(&out[b], res[b], plan->plan, n[b], (int)plan->all.size());
+    std::vector<std::pair<int, int>> chunks;  // [begin, end)
+    {
+        int b0 = 0;
+        size_t acc = 0;
+        for (int b = 0; b < batch; ++b) {
+            size_t w = per_dataset(n[b]);
+            if (b > b0 && acc + w > budget) {
+                chunks.push_back({b0, b});
+                b0 = b;
+                acc = 0;
+            }
+            acc += w;
+        }
+        chunks.push_back({b0, batch});
+    }
+    // Sizes of every chunk, so that all buffers are reserved once and the
+    // graphs captured for the chunks stay valid across calls.
+    size_t max_f = 0, max_arena = 0, max_blob = 0, max_res = 0;
+    std::vector<std::vector<Dataset>> cdata(chunks.size());
+    std::vector<std::vector<size_t>> coff(chunks.size());
+    for (size_t c = 0; c < chunks.size(); ++c) {
+        size_t tot = 0;
+        for (int b = chunks[c].first; b < chunks[c].second; ++b) {
+            coff[c].push_back(tot);
+            tot += fbytes(n[b]);
+        }
+        max_f = std::max(max_f, tot);
+    }
+    hipError_t e = grow(&plan->factors, &plan->factors_bytes, max_f, &plan->rt);
+    if (e != hipSuccess) return fail(USTAT_E_NOMEM, hipGetErrorString(e));
+    for (size_t c = 0; c < chunks.size(); ++c) {
+        for (int b = chunks[c].first, i = 0; b < chunks[c].second; ++b, ++i) {
+            Dataset ds;
+            ds.n = n[b];
+            for (size_t k = 0; k < plan->plan.edges.size(); ++k)
+                ds.factors.push_back(plan->factors + coff[c][i]);
+            cdata[c].push_back(ds);
+        }
+        ScheduleSizes z = schedule_sizes(plan->plan, plan->all, cdata[c]);
+        max_arena = std::max(max_arena, z.arena);
+        max_blob = std::max(max_blob, z.blob);
+        max_res = std::max(max_res, z.results);
+    }
+    if ((e = plan->rt.reserve_arena(max_arena)) != hipSuccess)
+        return fail(USTAT_E_NOMEM, std::string("device workspace allocation failed: ") + hipGetErrorString(e));
+    if ((e = plan->rt.reserve_desc(max_blob + 1024)) != hipSuccess) return fail(USTAT_E_NOMEM, hipGetErrorString(e));
+    if ((e = plan->rt.reserve_hres(max_res + 64)) != hipSuccess) return fail(USTAT_E_NOMEM, hipGetErrorString(e));
+    for (size_t c = 0; c < chunks.size(); ++c) {
+        const int b0 = chunks[c].first, b1 = chunks[c].second;
+        std::string key = "batch:" + std::to_string(d) + ":" + std::to_string(rbf_divisor) + ":" +
+                          std::to_string((uintptr_t)plan->factors);
+        for (int b = b0; b < b1; ++b)
+            key += ":" + std::to_string(n[b]) + "@" + std::to_string((uintptr_t)X[b]);
+        std::vector<const double *> xs(X + b0, X + b1);
+        std::vector<int64_t> ns(n + b0, n + b1);
+        std::vector<char *> fps;
+        for (size_t i = 0; i < ns.size(); ++i) fps.push_back(plan->factors + coff[c][i]);
+        auto pre = [=](hipStream_t s) -> hipError_t {
+            for (size_t i = 0; i < xs.size(); ++i) {
+                hipError_t e2 = launch_rbf(xs[i], ns[i], d, rbf_divisor, fps[i], dt, s);
+                if (e2 != hipSuccess) return e2;
+            }
+            return hipSuccess;
+        };
+        std::vector<DatasetResult> res;
+        ustat_status st = run(plan, plan->all, cdata[c], (hipStream_t)stream, res, nullptr, pre, key);
+        if (st != USTAT_OK) return st;
+        for (int b = b0; b < b1; ++b)
+            fill_result(&out[b], res[b - b0], plan->plan, n[b], (int)plan->all.size());
+    }
     return ok();
 }
 
@@ -445,13 +512,15 @@ ustat_status ustat_profile_reset(void) {
     return ok();
 }
 
-ustat_status ustat_profile_read(int32_t kind, double *ms, int64_t *launches, double *flops) {
+ustat_status ustat_profile_read(int32_t kind, double *ms, int64_t *launches, double *flops,
+                                double *bytes) {
     if (kind < 0 || kind >= KIND_COUNT) return fail(USTAT_E_INVALID, "unknown kind");
     Profiler *p = Profiler::active();
     if (!p) return fail(USTAT_E_INVALID, "profiling is not enabled");
     if (ms) *ms = p->ms[kind];
     if (launches) *launches = p->launches[kind];
     if (flops) *flops = p->flops[kind];
+    if (bytes) *bytes = p->bytes[kind];
     return ok();
 }
 

@@ -8,6 +8,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <unordered_map>
@@ -17,22 +19,25 @@
 
 namespace ustat {
 
+void Runtime::drop_graphs() {
+    for (auto &kv : graphs) {
+        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+        if (kv.second.blob) (void)hipHostFree(kv.second.blob);
+    }
+    graphs.clear();
+}
+
 Runtime::~Runtime() {
-    if (graph) (void)hipGraphExecDestroy(graph);
+    drop_graphs();
     if (arena) (void)hipFree(arena);
     if (ddesc) (void)hipFree(ddesc);
     if (hdesc) (void)hipHostFree(hdesc);
     if (hres) (void)hipHostFree(hres);
-    if (gblob) (void)hipHostFree(gblob);
 }
 
 hipError_t Runtime::reserve_arena(size_t bytes) {
     if (bytes <= arena_bytes && arena) return hipSuccess;
-    if (graph) {
-        (void)hipGraphExecDestroy(graph);
-        graph = nullptr;
-        graph_key.clear();
-    }
+    drop_graphs();
     if (arena) (void)hipFree(arena);
     arena = nullptr;
     arena_bytes = 0;
@@ -43,11 +48,7 @@ hipError_t Runtime::reserve_arena(size_t bytes) {
 
 hipError_t Runtime::reserve_desc(size_t bytes) {
     if (bytes <= ddesc_bytes && ddesc) return hipSuccess;
-    if (graph) {
-        (void)hipGraphExecDestroy(graph);
-        graph = nullptr;
-        graph_key.clear();
-    }
+    drop_graphs();
     if (ddesc) (void)hipFree(ddesc);
     if (hdesc) (void)hipHostFree(hdesc);
     ddesc = hdesc = nullptr;
@@ -63,11 +64,7 @@ hipError_t Runtime::reserve_desc(size_t bytes) {
 
 hipError_t Runtime::reserve_hres(size_t bytes) {
     if (bytes <= hres_bytes && hres) return hipSuccess;
-    if (graph) {
-        (void)hipGraphExecDestroy(graph);
-        graph = nullptr;
-        graph_key.clear();
-    }
+    drop_graphs();
     if (hres) (void)hipHostFree(hres);
     hres = nullptr;
     size_t b = std::max<size_t>(bytes * 3 / 2, 4096);
@@ -139,6 +136,10 @@ struct LevelWork {
     double gemm_flops = 0;
     std::vector<Elim1Desc> e1;
     int64_t e1_tiles = 0;
+    double e1_bytes = 0, prep_bytes = 0, tr_bytes = 0;  // algorithmic HBM bytes
+    std::vector<TransDesc> tr;
+    int64_t tr_tiles = 0;
+    size_t off_tr = 0;
     std::vector<Elim0Desc> e0;
     std::vector<ReduceDesc> red;
     int64_t red_maxlen = 1;
@@ -176,6 +177,7 @@ struct Schedule {
 };
 
 struct Cfg {
+    int in_es;     // input element size (set in make_cfg)
     int prec;      // ustat_precision
     int domain;    // DOM_FP / DOM_INT
     int in_dt;     // input factor dtype
@@ -187,12 +189,11 @@ struct Cfg {
 
 Cfg make_cfg(int prec) {
     Cfg c;
-    c.prec = prec;
     switch (prec) {
-        case 0: c = {0, DOM_FP, DT_F64, DT_F64, 8, PF_F64, 8}; break;
-        case 1: c = {1, DOM_FP, DT_F32, DT_F32, 4, PF_F32, 8}; break;
-        case 2: c = {2, DOM_FP, DT_F32, DT_F32, 4, PF_BF16X2, 8}; break;
-        default: c = {3, DOM_INT, DT_I8, DT_I64, 8, PF_I8LIMBS, 16}; break;
+        case 0: c = {8, 0, DOM_FP, DT_F64, DT_F64, 8, PF_F64, 8}; break;
+        case 1: c = {4, 1, DOM_FP, DT_F32, DT_F32, 4, PF_F32, 8}; break;
+        case 2: c = {4, 2, DOM_FP, DT_F32, DT_F32, 4, PF_BF16X2, 8}; break;
+        default: c = {1, 3, DOM_INT, DT_I8, DT_I64, 8, PF_I8LIMBS, 16}; break;
     }
     return c;
 }
@@ -216,7 +217,7 @@ size_t prep_bytes(const Cfg &c, int64_t npad, int limbs) {
 // deterministic, so this does not change any result bit.
 // ---------------------------------------------------------------------------
 
-enum class NK : uint8_t { E0, E1, Dot, GemmStore, GemmFinal };
+enum class NK : uint8_t { E0, E1, Dot, GemmStore, GemmFinal, Transpose };
 
 struct MOp {        // matrix operand
     int node;       // producing node, or -1 for an input factor
@@ -239,6 +240,7 @@ struct Node {
     size_t off = 0, bytes = 0;
     int scal = -1, mx = -1;
     double bound = 0;
+    // Transpose: source (node or input pointer) in A[0]
 };
 
 struct Ref {  // a program value resolved to a node or an input
@@ -291,6 +293,24 @@ int node_level(const Dag &G, const Node &nd) {
     for (auto &o : nd.aw) m(o.node);
     for (auto &o : nd.bx) m(o.node);
     return l + 1;
+}
+
+int add_node(Dag &G, Node nd, const std::string &key, bool cse);
+
+// An operand read in the orientation the consuming kernel streams:
+// want_trans == false for column reductions (stored (v, w)), true for GEMM
+// operand prep (stored (w, v)).  Otherwise the matrix is replaced by its
+// materialised transpose (one per matrix, shared by all consumers).
+MOp direct(Dag &G, const MOp &o, bool want_trans, int d, int64_t n, bool cse) {
+    if (o.trans == want_trans) return o;
+    Node t;
+    t.kind = NK::Transpose;
+    t.d = d;
+    t.n = n;
+    t.A.push_back(MOp{o.node, o.p, false});
+    std::string key = "T|" + std::to_string(n) + "|" + (o.node < 0 ? "I" + ptr_id(o.p) : "N" + std::to_string(o.node));
+    int id = add_node(G, t, key, cse);
+    return MOp{id, nullptr, want_trans};
 }
 
 int add_node(Dag &G, Node nd, const std::string &key, bool cse) {
@@ -381,9 +401,9 @@ std::string build_dag(const Plan &plan, const std::vector<const VProgram *> &pro
                     case StepKind::Elim1:
                     case StepKind::Final1: {
                         nd_.kind = NK::E1;
-                        nd_.A = A;
+                        for (auto &o : A) nd_.A.push_back(direct(G, o, false, d, n, cse));
                         nd_.sv = sv;
-                        std::string k1 = "E1|" + std::to_string(n) + "|" + group_sig(A, mop_sig) + "|" +
+                        std::string k1 = "E1|" + std::to_string(n) + "|" + group_sig(nd_.A, mop_sig) + "|" +
                                          group_sig(sv, vop_sig);
                         int id = add_node(G, nd_, k1, cse);
                         if (st.kind == StepKind::Elim1) {
@@ -402,6 +422,8 @@ std::string build_dag(const Plan &plan, const std::vector<const VProgram *> &pro
                         break;
                     }
                     case StepKind::Elim2: {
+                        for (auto &o : A) o = direct(G, o, true, d, n, cse);
+                        for (auto &o : B) o = direct(G, o, true, d, n, cse);
                         bool sw;
                         std::string k = gemm_key(n, A, sv, B, &sw);
                         nd_.kind = NK::GemmStore;
@@ -415,6 +437,8 @@ std::string build_dag(const Plan &plan, const std::vector<const VProgram *> &pro
                         break;
                     }
                     case StepKind::Final2: {
+                        for (auto &o : A) o = direct(G, o, true, d, n, cse);
+                        for (auto &o : B) o = direct(G, o, true, d, n, cse);
                         Pending pd;
                         pd.dp = dp;
                         pd.n = n;
@@ -453,15 +477,16 @@ std::string build_dag(const Plan &plan, const std::vector<const VProgram *> &pro
             g.B = B;
             g.sv = pd.sv;
             int gid = add_node(G, g, pd.gkey, cse);
-            // consumer: y(w') = sum_x' R(w',x') prod Z(w',x') prod bx(x'),
-            // an Elim1 over v := x' (canonical (x', w')), then a dot with aw.
+            // consumer: y(x') = sum_w' R(w',x') prod Z(w',x') prod aw(w'), an
+            // Elim1 over v := w' (R is stored with rows over w'), then a dot
+            // with bx.
             Node e;
             e.kind = NK::E1;
             e.d = pd.d;
             e.n = pd.n;
-            e.A.push_back(MOp{gid, nullptr, true});
-            for (auto &z : Z) e.A.push_back(MOp{z.node, z.p, !z.trans});
-            e.sv = bx;
+            e.A.push_back(MOp{gid, nullptr, false});
+            for (auto &z : Z) e.A.push_back(direct(G, z, false, pd.d, pd.n, cse));
+            e.sv = aw;
             int eid = add_node(G, e, "E1|" + std::to_string(pd.n) + "|" + group_sig(e.A, mop_sig) + "|" +
                                          group_sig(e.sv, vop_sig), cse);
             Node dot;
@@ -469,7 +494,7 @@ std::string build_dag(const Plan &plan, const std::vector<const VProgram *> &pro
             dot.d = pd.d;
             dot.n = pd.n;
             dot.sv.push_back(VOp{eid, nullptr});
-            for (auto &v : aw) dot.sv.push_back(v);
+            for (auto &v : bx) dot.sv.push_back(v);
             sid = add_node(G, dot, "DOT|" + std::to_string(pd.n) + "|" + group_sig(dot.sv, vop_sig), cse);
         } else {
             Node f;
@@ -527,6 +552,18 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
     }
     S.n_nodes = G.nodes.size();
     const bool is_int = cfg.domain == DOM_INT;
+    if ((base || getenv("USTAT_DEBUG_DAG_DRY")) && getenv("USTAT_DEBUG_DAG")) {
+        int cnt[6] = {0, 0, 0, 0, 0, 0};
+        for (auto &x : G.nodes) cnt[(int)x.kind]++;
+        fprintf(stderr, "dag: nodes=%zu E0=%d E1=%d Dot=%d GemmStore=%d GemmFinal=%d Transpose=%d levels=%d\n",
+                G.nodes.size(), cnt[0], cnt[1], cnt[2], cnt[3], cnt[4], cnt[5], G.max_level);
+        for (size_t i = 0; i < G.nodes.size(); ++i) {
+            auto &x = G.nodes[i];
+            if (x.kind != NK::E1 && x.kind != NK::GemmStore && x.kind != NK::GemmFinal) continue;
+            fprintf(stderr, "  node %zu kind=%d level=%d nA=%zu nB=%zu nZ=%zu nsv=%zu\n", i,
+                    (int)x.kind, x.level, x.A.size(), x.B.size(), x.Z.size(), x.sv.size());
+        }
+    }
     // scalar and running-max slots
     size_t nscal = 0, nmx = 0;
     for (auto &nd_ : G.nodes) {
@@ -589,10 +626,17 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
         if (v.node >= 0) return mxbase + G.nodes[v.node].mx;
         return mxbase + diag_mx[G.diag_index[std::make_pair(d, v.p)]];
     };
+    // A transpose node stands for its source matrix read the other way:
+    // same element type, bound, running maximum and diagonal handling.
+    auto src_of = [&](MOp o) {
+        while (o.node >= 0 && G.nodes[o.node].kind == NK::Transpose) o = G.nodes[o.node].A[0];
+        return o;
+    };
     auto mref = [&](int d, const MOp &o) -> MatRef {
         MatRef m;
-        const bool input = o.node < 0;
-        m.p = input ? o.p : P(G.nodes[o.node].off);
+        const MOp s0 = src_of(o);
+        const bool input = s0.node < 0;
+        m.p = o.node < 0 ? o.p : P(G.nodes[o.node].off);
         m.ld = data[d].n;
         m.dtype = input ? cfg.in_dt : cfg.mat_dt;
         m.trans = o.trans ? 1 : 0;
@@ -601,12 +645,14 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
         return m;
     };
     auto mbound = [&](int d, const MOp &o) {
-        return o.node >= 0 ? G.nodes[o.node].bound : in_b(d, o.p);
+        const MOp s0 = src_of(o);
+        return s0.node >= 0 ? G.nodes[s0.node].bound : in_b(d, s0.p);
     };
     auto mmx = [&](int d, const MOp &o) -> const unsigned long long * {
         if (!inmxbase) return nullptr;
-        if (o.node >= 0) return mxbase + G.nodes[o.node].mx;
-        return inmxbase + inmx_of[std::make_pair(d, o.p)];
+        const MOp s0 = src_of(o);
+        if (s0.node >= 0) return mxbase + G.nodes[s0.node].mx;
+        return inmxbase + inmx_of[std::make_pair(d, s0.p)];
     };
     auto scal_ptr = [&](const Node &nd_) -> void * {
         return P(S.off_scal + (size_t)nd_.scal * cfg.wide_es);
@@ -628,6 +674,31 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
     auto limb_ptr = [&](size_t slot) -> int32_t * {
         return base ? reinterpret_cast<int32_t *>(base + S.off_limbs) + slot : nullptr;
     };
+
+    // last GEMM level of every operand prep built only from inputs, so that
+    // it can be released after that level
+    auto prep_key = [&](int d, int64_t n, const std::vector<MOp> &ops, const std::vector<VOp> &sv) {
+        std::string key = std::to_string(d) + "|" + std::to_string(n) + "|";
+        bool pers = true;
+        for (auto &o : ops) {
+            pers = pers && (o.node < 0);
+            key += mop_sig(o);
+        }
+        key += "|";
+        for (auto &v : sv) {
+            pers = pers && (v.node < 0);
+            key += vop_sig(v);
+        }
+        return std::make_pair(key, pers);
+    };
+    std::map<std::string, int> prep_last;
+    for (auto &nd_ : G.nodes)
+        if (nd_.kind == NK::GemmStore || nd_.kind == NK::GemmFinal) {
+            auto ka = prep_key(nd_.d, nd_.n, nd_.A, nd_.sv);
+            auto kb = prep_key(nd_.d, nd_.n, nd_.B, {});
+            prep_last[ka.first] = std::max(prep_last[ka.first], nd_.level);
+            prep_last[kb.first] = std::max(prep_last[kb.first], nd_.level);
+        }
 
     // nodes by level
     std::vector<std::vector<int>> by_level(G.max_level + 1);
@@ -692,15 +763,19 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
                     for (int q = 0; q < e.nA; ++q) e.A[q] = mref(d, nd_.A[q]);
                     for (int q = 0; q < e.nS; ++q) e.s[q] = vptr(d, nd_.sv[q]);
                     const int strips = (int)((n + kElimStrip - 1) / kElimStrip);
+                    const int wstrips = (int)((n + 255) / 256);
                     size_t pbytes = (size_t)strips * n * 8;
                     size_t poff = A.alloc(pbytes);
                     scratch.push_back({poff, pbytes});
                     e.part = P(poff);
                     e.tiles_v = strips;
-                    e.tiles_w = tiles64;
+                    e.tiles_w = wstrips;
                     e.tile_start = W.e1_tiles;
-                    W.e1_tiles += (int64_t)strips * tiles64;
+                    W.e1_tiles += (int64_t)strips * wstrips;
                     W.e1.push_back(e);
+                    for (auto &o : nd_.A)
+                        W.e1_bytes += (double)n * n * (src_of(o).node < 0 ? cfg.in_es : cfg.mat_es);
+                    W.e1_bytes += (double)n * 8 * (nd_.sv.size() + strips);
                     nd_.bytes = (size_t)n * 8;
                     nd_.off = A.alloc(nd_.bytes);
                     nd_.bound = n * pA * pS;
@@ -720,21 +795,32 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
                     W.red_maxlen = std::max<int64_t>(W.red_maxlen, n);
                     break;
                 }
+                case NK::Transpose: {
+                    const MOp s0 = src_of(nd_.A[0]);
+                    const int es = s0.node < 0 ? cfg.in_es : cfg.mat_es;
+                    TransDesc td;
+                    td.src = nd_.A[0].node < 0 ? nd_.A[0].p : P(G.nodes[nd_.A[0].node].off);
+                    td.n = n;
+                    td.ld = n;
+                    td.dtype = s0.node < 0 ? cfg.in_dt : cfg.mat_dt;
+                    td.tiles = tiles64;
+                    nd_.bytes = (size_t)n * n * es;
+                    nd_.off = A.alloc(nd_.bytes);
+                    td.dst = P(nd_.off);
+                    td.tile_start = W.tr_tiles;
+                    W.tr_tiles += (int64_t)tiles64 * tiles64;
+                    W.tr.push_back(td);
+                    W.tr_bytes += 2.0 * (double)n * n * es;
+                    nd_.bound = mbound(d, nd_.A[0]);
+                    break;
+                }
                 case NK::GemmStore:
                 case NK::GemmFinal: {
                     auto make_prep = [&](const std::vector<MOp> &ops, const std::vector<VOp> &sv,
                                          double bound, const int32_t **limbs_p, int *max_limbs) {
-                        bool pers = true;
-                        std::string key = std::to_string(d) + "|" + std::to_string(n) + "|";
-                        for (auto &o : ops) {
-                            pers = pers && (o.node < 0);
-                            key += mop_sig(o);
-                        }
-                        key += "|";
-                        for (auto &v : sv) {
-                            pers = pers && (v.node < 0);
-                            key += vop_sig(v);
-                        }
+                        auto kp = prep_key(d, n, ops, sv);
+                        const std::string &key = kp.first;
+                        const bool pers = kp.second;
                         int cap = cfg.pformat == PF_I8LIMBS ? limbs_for(bound, 9) : 1;
                         auto &tab = pers ? persistent : local;
                         auto it = tab.find(key);
@@ -760,7 +846,7 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
                             pd.limbs = cap;
                             pd.tiles = (int)(npad / 64);
                             pd.tile_start = W.prep_tiles;
-                            W.prep_tiles += (int64_t)pd.tiles * pd.tiles;
+                            W.prep_tiles += (int64_t)(npad / 64) * (npad / 128);
                             pd.nmx = 0;
                             if (is_int) {
                                 for (auto &o : ops) pd.mx[pd.nmx++] = mmx(d, o);
@@ -768,6 +854,9 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
                             }
                             pd.limbs_out = limb_ptr(rec.limb_slot);
                             W.prep.push_back(pd);
+                            for (auto &o : ops)
+                                W.prep_bytes += (double)n * n * (src_of(o).node < 0 ? cfg.in_es : cfg.mat_es);
+                            W.prep_bytes += (double)rec.bytes;
                             it = tab.emplace(key, rec).first;
                         }
                         *limbs_p = limb_ptr(it->second.limb_slot);
@@ -845,7 +934,14 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
             }
         }
         for (auto &sc : scratch) A.release(sc.first, sc.second);
-        for (int id : by_level[L]) (void)id;
+        for (auto it = persistent.begin(); it != persistent.end();) {
+            if (prep_last[it->first] <= L) {
+                A.release(it->second.off, it->second.bytes);
+                it = persistent.erase(it);
+            } else {
+                ++it;
+            }
+        }
         for (auto &nd_ : G.nodes)
             if (nd_.bytes && nd_.last_use == L) {
                 A.release(nd_.off, nd_.bytes);
@@ -884,6 +980,7 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
     S.arena_bytes = A.top;
     S.off_diag = S.blob.put(S.diag);
     for (auto &W : S.levels) {
+        W.off_tr = S.blob.put(W.tr);
         W.off_prep = S.blob.put(W.prep);
         W.off_gemm = S.blob.put(W.gemm);
         W.off_e1 = S.blob.put(W.e1);
@@ -907,15 +1004,34 @@ __global__ void k_fill_zero(unsigned long long *p, size_t n) {
 
 }  // namespace
 
+ScheduleSizes schedule_sizes(const Plan &plan, const std::vector<const VProgram *> &progs,
+                             const std::vector<Dataset> &data) {
+    Schedule S;
+    int st = 0;
+    const Cfg cfg = make_cfg(plan.opts.precision);
+    ScheduleSizes z;
+    std::string err = build_schedule(plan, progs, data, cfg, {}, nullptr, S, &st);
+    if (!err.empty()) return z;
+    z.arena = S.arena_bytes;
+    z.blob = S.blob_bytes;
+    z.results = (size_t)S.nprog_total * cfg.wide_es + data.size() * (cfg.wide_es + 8);
+    return z;
+}
+
 size_t workspace_bytes(const Plan &plan, const std::vector<const VProgram *> &progs,
-                       const std::vector<int64_t> &ns) {
+                       const std::vector<int64_t> &ns, bool shared_factor) {
     std::vector<Dataset> data;
-    static char fake;
+    static char fake[1 << 16];
+    size_t slot = 0;
     for (int64_t n : ns) {
         Dataset d;
         d.n = n;
-        // distinct placeholder pointers per edge
-        for (size_t k = 0; k < plan.edges.size(); ++k) d.factors.push_back(&fake + k);
+        // distinct placeholder pointers per dataset (and per edge unless shared)
+        for (size_t k = 0; k < plan.edges.size(); ++k) {
+            d.factors.push_back(&fake[slot % sizeof fake]);
+            if (!shared_factor) ++slot;
+        }
+        if (shared_factor) ++slot;
         data.push_back(d);
     }
     Schedule S;
@@ -941,24 +1057,27 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
                     const std::function<hipError_t(hipStream_t)> &pre) {
     *status = 0;
     const Cfg cfg = make_cfg(plan.opts.precision);
-    if (capture && rt.graph && rt.graph_key == capture_key && rt.g_nd == (int)data.size()) {
-        // Replay: the graph uploads its own descriptor blob and recomputes
-        // everything in the workspace from the inputs.
-        HIPCHK(hipGraphLaunch(rt.graph, stream));
-        HIPCHK(hipStreamSynchronize(stream));
-        const int nd = rt.g_nd, nprog = rt.g_nprog;
-        out.assign(nd, DatasetResult());
-        size_t vbytes = (size_t)nprog * cfg.wide_es, ubytes = (size_t)nd * cfg.wide_es;
-        const char *h = rt.hres;
-        if (vout) {
-            vout->assign(nprog, 0.0);
-            for (int i = 0; i < nprog; ++i) (*vout)[i] = reinterpret_cast<const double *>(h)[i];
+    if (capture) {
+        auto git = rt.graphs.find(capture_key);
+        if (git != rt.graphs.end() && git->second.nd == (int)data.size()) {
+            // Replay: the graph uploads its own descriptor blob and
+            // recomputes everything in the workspace from the inputs.
+            HIPCHK(hipGraphLaunch(git->second.exec, stream));
+            HIPCHK(hipStreamSynchronize(stream));
+            const int nd = git->second.nd, nprog = git->second.nprog;
+            out.assign(nd, DatasetResult());
+            size_t vbytes = (size_t)nprog * cfg.wide_es, ubytes = (size_t)nd * cfg.wide_es;
+            const char *h = rt.hres;
+            if (vout) {
+                vout->assign(nprog, 0.0);
+                for (int i = 0; i < nprog; ++i) (*vout)[i] = reinterpret_cast<const double *>(h)[i];
+            }
+            for (int d = 0; d < nd; ++d) {
+                out[d].value = reinterpret_cast<const double *>(h + vbytes)[d];
+                out[d].scale = reinterpret_cast<const double *>(h + vbytes + ubytes)[d];
+            }
+            return "";
         }
-        for (int d = 0; d < nd; ++d) {
-            out[d].value = reinterpret_cast<const double *>(h + vbytes)[d];
-            out[d].scale = reinterpret_cast<const double *>(h + vbytes + ubytes)[d];
-        }
-        return "";
     }
     const int ne = (int)plan.edges.size();
     std::vector<double> in_bound;
@@ -1017,20 +1136,18 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
 
     {
         char *hblob = rt.hdesc;
+        Runtime::GraphEntry entry;
         if (capture) {
-            if (rt.graph) {
-                (void)hipGraphExecDestroy(rt.graph);
-                rt.graph = nullptr;
-                rt.graph_key.clear();
+            auto old = rt.graphs.find(capture_key);
+            if (old != rt.graphs.end()) {
+                if (old->second.exec) (void)hipGraphExecDestroy(old->second.exec);
+                if (old->second.blob) (void)hipHostFree(old->second.blob);
+                rt.graphs.erase(old);
             }
-            if (rt.gblob_bytes < S.blob_bytes + 64) {
-                if (rt.gblob) (void)hipHostFree(rt.gblob);
-                rt.gblob = nullptr;
-                rt.gblob_bytes = 0;
-                HIPCHK(hipHostMalloc((void **)&rt.gblob, S.blob_bytes * 3 / 2 + 64, hipHostMallocDefault));
-                rt.gblob_bytes = S.blob_bytes * 3 / 2 + 64;
-            }
-            hblob = rt.gblob;
+            if (rt.graphs.size() >= 64) rt.drop_graphs();
+            HIPCHK(hipHostMalloc((void **)&entry.blob, S.blob_bytes + 64, hipHostMallocDefault));
+            entry.blob_bytes = S.blob_bytes + 64;
+            hblob = entry.blob;
         }
         std::memcpy(hblob, S.blob.h.data(), S.blob_bytes);
         hipGraph_t g = nullptr;
@@ -1041,6 +1158,8 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
                 hipGraph_t junk = nullptr;
                 (void)hipStreamEndCapture(stream, &junk);
                 if (junk) (void)hipGraphDestroy(junk);
+                if (entry.blob) (void)hipHostFree(entry.blob);
+                entry.blob = nullptr;
             }
             *status = 4;
             return std::string(what) + ": " + hipGetErrorString(e);
@@ -1075,8 +1194,14 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
             if (e != hipSuccess) return fail(e, "diag");
         }
         for (auto &W : S.levels) {
+            if (!W.tr.empty()) {
+                ProfScope ps(prof, KIND_PREP, stream, 0, W.tr_bytes);
+                e = launch_transpose(reinterpret_cast<TransDesc *>(dd + W.off_tr), (int)W.tr.size(),
+                                     W.tr_tiles, stream);
+                if (e != hipSuccess) return fail(e, "transpose");
+            }
             if (!W.prep.empty()) {
-                ProfScope ps(prof, KIND_PREP, stream, 0);
+                ProfScope ps(prof, KIND_PREP, stream, 0, W.prep_bytes);
                 e = launch_prep(reinterpret_cast<PrepDesc *>(dd + W.off_prep), (int)W.prep.size(),
                                 W.prep_tiles, cfg.domain, stream);
                 if (e != hipSuccess) return fail(e, "prep");
@@ -1088,7 +1213,7 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
                 if (e != hipSuccess) return fail(e, "gemm");
             }
             if (!W.e1.empty()) {
-                ProfScope ps(prof, KIND_ELIM1, stream, 0);
+                ProfScope ps(prof, KIND_ELIM1, stream, 0, W.e1_bytes);
                 e = launch_elim1(reinterpret_cast<Elim1Desc *>(dd + W.off_e1), (int)W.e1.size(),
                                  W.e1_tiles, cfg.domain, stream);
                 if (e != hipSuccess) return fail(e, "elim1");
@@ -1124,20 +1249,23 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
                                hipMemcpyDeviceToHost, stream);
         if (e != hipSuccess) return fail(e, "result copy");
         if (capture) {
-            HIPCHK(hipStreamEndCapture(stream, &g));
-            if (rt.graph) (void)hipGraphExecDestroy(rt.graph);
-            rt.graph = nullptr;
-            hipError_t ie = hipGraphInstantiate(&rt.graph, g, nullptr, nullptr, 0);
+            e = hipStreamEndCapture(stream, &g);
+            if (e != hipSuccess) {
+                (void)hipHostFree(entry.blob);
+                *status = 4;
+                return std::string("end capture: ") + hipGetErrorString(e);
+            }
+            hipError_t ie = hipGraphInstantiate(&entry.exec, g, nullptr, nullptr, 0);
             (void)hipGraphDestroy(g);
             if (ie != hipSuccess) {
-                rt.graph = nullptr;
+                (void)hipHostFree(entry.blob);
                 *status = 4;
                 return std::string("graph instantiate: ") + hipGetErrorString(ie);
             }
-            rt.graph_key = capture_key;
-            rt.g_nd = nd;
-            rt.g_nprog = S.nprog_total;
-            HIPCHK(hipGraphLaunch(rt.graph, stream));
+            entry.nd = nd;
+            entry.nprog = S.nprog_total;
+            rt.graphs[capture_key] = entry;
+            HIPCHK(hipGraphLaunch(entry.exec, stream));
         }
     }
     HIPCHK(hipStreamSynchronize(stream));

@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <functional>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -36,13 +37,17 @@ struct Runtime {
     size_t hdesc_bytes = 0;
     char *hres = nullptr;   // pinned host result buffer
     size_t hres_bytes = 0;
-    // Captured graph of the last captured run, the key it was built for,
-    // its own pinned descriptor blob and its result layout.
-    hipGraphExec_t graph = nullptr;
-    std::string graph_key;
-    char *gblob = nullptr;
-    size_t gblob_bytes = 0;
-    int g_nprog = 0, g_nd = 0;
+    // Captured graphs by key, each with its own pinned descriptor blob and
+    // result layout.  Any reallocation of the buffers they reference drops
+    // them all.
+    struct GraphEntry {
+        hipGraphExec_t exec = nullptr;
+        char *blob = nullptr;
+        size_t blob_bytes = 0;
+        int nd = 0, nprog = 0;
+    };
+    std::map<std::string, GraphEntry> graphs;
+    void drop_graphs();
     ~Runtime();
     hipError_t reserve_arena(size_t bytes);
     hipError_t reserve_desc(size_t bytes);
@@ -68,8 +73,16 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
                     bool capture = false, const std::string &capture_key = "",
                     const std::function<hipError_t(hipStream_t)> &pre = nullptr);
 
+// Sizes an evaluation of `data` needs: arena, descriptor blob, pinned
+// result bytes (a dry schedule; pointers only fix the sharing pattern).
+struct ScheduleSizes {
+    size_t arena = 0, blob = 0, results = 0;
+};
+ScheduleSizes schedule_sizes(const Plan &plan, const std::vector<const VProgram *> &progs,
+                             const std::vector<Dataset> &data);
+
 // Upper bound of the workspace bytes an evaluation at size n needs.
 size_t workspace_bytes(const Plan &plan, const std::vector<const VProgram *> &progs,
-                       const std::vector<int64_t> &ns);
+                       const std::vector<int64_t> &ns, bool shared_factor);
 
 }  // namespace ustat

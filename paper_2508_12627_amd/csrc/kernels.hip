@@ -194,92 +194,168 @@ __global__ void k_absmax_i8(const int8_t *const *src, const int64_t *n, int npro
 // partial rows left for the fixed-order reduction: ceil(n / kStripRows)).
 constexpr int kStripRows = kElimStrip;
 
-// Partials of y(w) = sum_v prod_k A_k(v,w) prod_j s_j(v) for a strip of 64
-// columns w and kStripRows rows v.  Thread t owns column t%64 and rows
-// t/64 + 4i (i < 16) of each 64-row chunk and keeps their products in
-// registers; operands stored (v, w) are read directly (coalesced along w),
-// operands stored (w, v) are transposed through one LDS tile.
+// Four consecutive elements p[i .. i+3] of a row as the accumulation type;
+// `vec` selects one wide load (the caller guarantees alignment and that all
+// four lie inside the row), otherwise elements at or beyond `lim` read 0.
+template <class T, class A>
+__device__ __forceinline__ void load4(const T *p, int64_t i, bool vec, int64_t col, int64_t lim,
+                                      A (&x)[4]) {
+    if (vec) {
+        if constexpr (sizeof(T) == 4) {
+            typedef T v4 __attribute__((ext_vector_type(4)));
+            v4 q = *reinterpret_cast<const v4 *>(p + i);
+            x[0] = (A)q[0]; x[1] = (A)q[1]; x[2] = (A)q[2]; x[3] = (A)q[3];
+        } else if constexpr (sizeof(T) == 8) {
+            typedef T v2 __attribute__((ext_vector_type(2)));
+            v2 q0 = *reinterpret_cast<const v2 *>(p + i);
+            v2 q1 = *reinterpret_cast<const v2 *>(p + i + 2);
+            x[0] = (A)q0[0]; x[1] = (A)q0[1]; x[2] = (A)q1[0]; x[3] = (A)q1[1];
+        } else {
+            typedef T v4 __attribute__((ext_vector_type(4)));
+            v4 q = *reinterpret_cast<const v4 *>(p + i);
+            x[0] = (A)q[0]; x[1] = (A)q[1]; x[2] = (A)q[2]; x[3] = (A)q[3];
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) x[j] = (col + j < lim) ? (A)p[i + j] : (A)0;
+    }
+}
+
+// Partials of y(w) = sum_v prod_k A_k(v,w) prod_j s_j(v) over a strip of
+// 256 columns w and kStripRows rows v.  Every operand is stored (v, w)
+// (transposed operands arrive as materialised transposes), so each wave
+// reads whole 1 KB row segments, four consecutive columns per lane.  Thread
+// t owns columns w0 + 4 (t%64) .. +3 and rows v0 + t/64 + 4i of each 32-row
+// chunk.
 template <int DOM>
 __global__ __launch_bounds__(256) void k_elim1(const Elim1Desc *D, int nprob) {
     typedef typename Dom<DOM>::acc A;
-    __shared__ A tile[64][65];
-    __shared__ A red[4][64];
+    __shared__ A red[4][256];
     const int64_t b = blockIdx.x;
     const int p = find_problem(D, nprob, b);
     const Elim1Desc &d = D[p];
     const int64_t local = b - d.tile_start;
     const int64_t tv = local / d.tiles_w, tw = local % d.tiles_w;
-    const int64_t n = d.n, w0 = tw * 64;
-    const int t = threadIdx.x, c = t & 63, g = t >> 6;
-    const int64_t w = w0 + c;
+    const int64_t n = d.n, w0 = tw * 256;
+    const int t = threadIdx.x, cg = t & 63, g = t >> 6;
+    const int64_t w = w0 + 4 * cg;
     const int64_t vbeg = tv * kStripRows, vend = min(n, vbeg + kStripRows);
-    A sum = 0;
-    for (int64_t v0 = vbeg; v0 < vend; v0 += 64) {
-        A pr[16];
+    A sum[4] = {0, 0, 0, 0};
+    for (int64_t v0 = vbeg; v0 < vend; v0 += 32) {
+        A pr[8][4];
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
+        for (int i = 0; i < 8; ++i) {
             int64_t v = v0 + g + 4 * i;
-            A val = (v < n && w < n) ? (A)1 : (A)0;
-            if (v < n && w < n)
-                for (int j = 0; j < d.nS; ++j) val *= load_vec<DOM>(d.s[j], v);
-            pr[i] = val;
+            A sv = (v < vend) ? (A)1 : (A)0;
+            if (v < vend)
+                for (int j = 0; j < d.nS; ++j) sv *= load_vec<DOM>(d.s[j], v);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) pr[i][j] = (w + j < n) ? sv : (A)0;
         }
-        for (int k = 0; k < d.nA; ++k) {
+        // Fast path: up to two operands of one element type have all their
+        // loads of the chunk in flight before any multiply.
+        int k0 = 0;
+        if (d.nA >= 2 && d.A[0].dtype == d.A[1].dtype) {
+            const MatRef m0 = d.A[0], m1 = d.A[1];
+            with_dtype(m0.dtype, [&](auto tag) {
+                typedef decltype(tag) T;
+                const T *p0 = static_cast<const T *>(m0.p);
+                const T *p1 = static_cast<const T *>(m1.p);
+                const bool vec0 = (w + 3 < n) && (m0.ld % 4 == 0);
+                const bool vec1 = (w + 3 < n) && (m1.ld % 4 == 0);
+                A x0[8][4], x1[8][4];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    int64_t v = v0 + g + 4 * i;
+                    if (v < vend) {
+                        load4<T, A>(p0, v * m0.ld + w, vec0, w, n, x0[i]);
+                        load4<T, A>(p1, v * m1.ld + w, vec1, w, n, x1[i]);
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) x0[i][j] = x1[i][j] = 0;
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const bool dg = v0 + g + 4 * i == w + j;
+                        A a0 = (m0.zdiag && dg) ? (A)0 : x0[i][j];
+                        A a1 = (m1.zdiag && dg) ? (A)0 : x1[i][j];
+                        pr[i][j] *= a0 * a1;
+                    }
+            });
+            k0 = 2;
+        }
+        for (int k = k0; k < d.nA; ++k) {
             const MatRef m = d.A[k];
-            if (!m.trans) {
-                with_dtype(m.dtype, [&](auto tag) {
-                    typedef decltype(tag) T;
-                    const T *mp = static_cast<const T *>(m.p);
-                    T x[16];
+            with_dtype(m.dtype, [&](auto tag) {
+                typedef decltype(tag) T;
+                const T *mp = static_cast<const T *>(m.p);
+                const bool vec = (w + 3 < n) && (m.ld % 4 == 0);
+                A x[8][4];
 #pragma unroll
-                    for (int i = 0; i < 16; ++i) {
-                        int64_t v = v0 + g + 4 * i;
-                        x[i] = (v < n && w < n) ? mp[v * m.ld + w] : (T)0;
+                for (int i = 0; i < 8; ++i) {
+                    int64_t v = v0 + g + 4 * i;
+                    if (v < vend) load4<T, A>(mp, v * m.ld + w, vec, w, n, x[i]);
+                    else x[i][0] = x[i][1] = x[i][2] = x[i][3] = 0;
+                }
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        A xv = x[i][j];
+                        if (m.zdiag && v0 + g + 4 * i == w + j) xv = 0;
+                        pr[i][j] *= xv;
                     }
-#pragma unroll
-                    for (int i = 0; i < 16; ++i) {
-                        int64_t v = v0 + g + 4 * i;
-                        A xv = (A)x[i];
-                        if (m.zdiag && v == w) xv = 0;
-                        pr[i] *= xv;
-                    }
-                });
-            } else {
-                __syncthreads();
-                with_dtype(m.dtype, [&](auto tag) {
-                    typedef decltype(tag) T;
-                    const T *mp = static_cast<const T *>(m.p);
-                    T x[16];
-#pragma unroll
-                    for (int q = 0; q < 16; ++q) {
-                        int e = t + 256 * q;
-                        int rw = e >> 6, cv = e & 63;
-                        int64_t ww = w0 + rw, vv = v0 + cv;
-                        x[q] = (ww < n && vv < n) ? mp[ww * m.ld + vv] : (T)0;
-                    }
-#pragma unroll
-                    for (int q = 0; q < 16; ++q) {
-                        int e = t + 256 * q;
-                        int rw = e >> 6, cv = e & 63;
-                        A xv = (A)x[q];
-                        if (m.zdiag && w0 + rw == v0 + cv) xv = 0;
-                        tile[cv][rw] = xv;
-                    }
-                });
-                __syncthreads();
-#pragma unroll
-                for (int i = 0; i < 16; ++i) pr[i] *= tile[g + 4 * i][c];
-            }
+            });
         }
 #pragma unroll
-        for (int i = 0; i < 16; ++i) sum += pr[i];
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) sum[j] += pr[i][j];
     }
-    red[g][c] = sum;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) red[g][4 * cg + j] = sum[j];
     __syncthreads();
-    if (g == 0 && w < n) {
-        A tot = red[0][c] + red[1][c] + red[2][c] + red[3][c];
-        static_cast<A *>(d.part)[tv * n + w] = tot;
+    const int64_t wc = w0 + t;
+    if (wc < n) {
+        A tot = red[0][t] + red[1][t] + red[2][t] + red[3][t];
+        static_cast<A *>(d.part)[tv * n + wc] = tot;
     }
+}
+
+// Transpose: out[b * n + a] = in[a * ld + b] for a, b < n (64 x 64 tiles
+// through LDS, both sides coalesced).
+__global__ __launch_bounds__(256) void k_transpose(const TransDesc *D, int nprob) {
+    __shared__ long long tile[64][65];
+    const int64_t b = blockIdx.x;
+    const int p = find_problem(D, nprob, b);
+    const TransDesc &d = D[p];
+    const int64_t local = b - d.tile_start;
+    const int64_t ta = local / d.tiles, tb = local % d.tiles;
+    const int64_t n = d.n, a0 = ta * 64, b0 = tb * 64;
+    const int t = threadIdx.x;
+    with_dtype(d.dtype, [&](auto tag) {
+        typedef decltype(tag) T;
+        const T *src = static_cast<const T *>(d.src);
+        T *dst = static_cast<T *>(d.dst);
+#pragma unroll 4
+        for (int e = t; e < 4096; e += 256) {
+            int r = e >> 6, c = e & 63;
+            int64_t aa = a0 + r, bb = b0 + c;
+            T v = (aa < n && bb < n) ? src[aa * d.ld + bb] : (T)0;
+            tile[c][r] = (long long)0;
+            *reinterpret_cast<T *>(&tile[c][r]) = v;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int e = t; e < 4096; e += 256) {
+            int r = e >> 6, c = e & 63;  // output row b0 + r, column a0 + c
+            int64_t bb = b0 + r, aa = a0 + c;
+            if (aa < n && bb < n) dst[bb * n + aa] = *reinterpret_cast<const T *>(&tile[r][c]);
+        }
+    });
 }
 
 // ----------------------------------------------------------------- reduce
@@ -355,22 +431,22 @@ __global__ __launch_bounds__(256) void k_elim0(const Elim0Desc *D, int nprob) {
 
 // ----------------------------------------------------------------- prep
 
-// One 64 x 64 tile of a GEMM operand out[w][v] = prod_j s_j(v) prod_k
-// A_k(v, w).  Thread t owns output column v = t%64 (contiguous in memory)
-// and rows w = t/64 + 4i; operands stored (w, v) are read directly,
-// operands stored (v, w) are transposed through one LDS tile.
+// One 64 x 128 tile (rows w, columns v) of a GEMM operand
+// out[w][v] = prod_j s_j(v) prod_k A_k(v, w) with every operand stored
+// (w, v), so rows are read and written in order, four consecutive v per
+// lane.  Thread t owns columns v0 + 4 (t%32) .. +3 and rows w0 + t/32 + 8i.
 template <int DOM>
 __global__ __launch_bounds__(256) void k_prep(const PrepDesc *D, int nprob) {
     typedef typename Dom<DOM>::acc A;
-    __shared__ A tile[64][65];  // [w offset][v offset]
     const int64_t b = blockIdx.x;
     const int p = find_problem(D, nprob, b);
     const PrepDesc &d = D[p];
     const int64_t local = b - d.tile_start;
-    const int64_t tw = local / d.tiles, tv = local % d.tiles;
-    const int64_t n = d.n, w0 = tw * 64, v0 = tv * 64;
-    const int t = threadIdx.x, c = t & 63, g = t >> 6;
-    const int64_t v = v0 + c;
+    const int64_t tcol = d.npad / 128;
+    const int64_t tw = local / tcol, tv = local % tcol;
+    const int64_t n = d.n, w0 = tw * 64, v0 = tv * 128;
+    const int t = threadIdx.x, cg = t & 31, rg = t >> 5;
+    const int64_t v = v0 + 4 * cg;
     int limbs = d.limbs;
     if (d.format == PF_I8LIMBS) {
         // Digits needed for |x| <= prod of the operands' maxima: a top digit
@@ -386,90 +462,86 @@ __global__ __launch_bounds__(256) void k_prep(const PrepDesc *D, int nprob) {
         limbs = L;
         if (local == 0 && t == 0) *d.limbs_out = L;
     }
-    A sv = 0;
-    if (v < n) {
-        sv = 1;
-        for (int j = 0; j < d.nS; ++j) sv *= load_vec<DOM>(d.s[j], v);
-    }
-    A pr[16];
+    A sv[4];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        int64_t w = w0 + g + 4 * i;
-        pr[i] = (w < n) ? sv : (A)0;
+    for (int j = 0; j < 4; ++j) {
+        A x = (v + j < n) ? (A)1 : (A)0;
+        if (v + j < n)
+            for (int q = 0; q < d.nS; ++q) x *= load_vec<DOM>(d.s[q], v + j);
+        sv[j] = x;
+    }
+    A pr[8][4];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        int64_t w = w0 + rg + 8 * i;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) pr[i][j] = (w < n) ? sv[j] : (A)0;
     }
     for (int k = 0; k < d.nA; ++k) {
         const MatRef m = d.A[k];
-        if (m.trans) {  // stored (w, v)
-            with_dtype(m.dtype, [&](auto tag) {
-                typedef decltype(tag) T;
-                const T *mp = static_cast<const T *>(m.p);
-                T x[16];
+        with_dtype(m.dtype, [&](auto tag) {
+            typedef decltype(tag) T;
+            const T *mp = static_cast<const T *>(m.p);
+            const bool vec = (v + 3 < n) && (m.ld % 4 == 0);
+            A x[8][4];
 #pragma unroll
-                for (int i = 0; i < 16; ++i) {
-                    int64_t w = w0 + g + 4 * i;
-                    x[i] = (v < n && w < n) ? mp[w * m.ld + v] : (T)0;
+            for (int i = 0; i < 8; ++i) {
+                int64_t w = w0 + rg + 8 * i;
+                if (w < n && v < n) load4<T, A>(mp, w * m.ld + v, vec, v, n, x[i]);
+                else x[i][0] = x[i][1] = x[i][2] = x[i][3] = 0;
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    A xv = x[i][j];
+                    if (m.zdiag && w0 + rg + 8 * i == v + j) xv = 0;
+                    pr[i][j] *= xv;
                 }
-#pragma unroll
-                for (int i = 0; i < 16; ++i) {
-                    int64_t w = w0 + g + 4 * i;
-                    A xv = (A)x[i];
-                    if (m.zdiag && v == w) xv = 0;
-                    pr[i] *= xv;
-                }
-            });
-        } else {  // stored (v, w)
-            __syncthreads();
-            with_dtype(m.dtype, [&](auto tag) {
-                typedef decltype(tag) T;
-                const T *mp = static_cast<const T *>(m.p);
-                T x[16];
-#pragma unroll
-                for (int q = 0; q < 16; ++q) {
-                    int e = t + 256 * q;
-                    int rv = e >> 6, cw = e & 63;
-                    int64_t vv = v0 + rv, ww = w0 + cw;
-                    x[q] = (vv < n && ww < n) ? mp[vv * m.ld + ww] : (T)0;
-                }
-#pragma unroll
-                for (int q = 0; q < 16; ++q) {
-                    int e = t + 256 * q;
-                    int rv = e >> 6, cw = e & 63;
-                    A xv = (A)x[q];
-                    if (m.zdiag && v0 + rv == w0 + cw) xv = 0;
-                    tile[cw][rv] = xv;
-                }
-            });
-            __syncthreads();
-#pragma unroll
-            for (int i = 0; i < 16; ++i) pr[i] *= tile[g + 4 * i][c];
-        }
+        });
     }
-    if (v >= d.npad) return;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        int64_t w = w0 + g + 4 * i;
+    for (int i = 0; i < 8; ++i) {
+        int64_t w = w0 + rg + 8 * i;
         if (w >= d.npad) continue;
         int64_t o = w * d.ldo + v;
-        A x = pr[i];
         switch (d.format) {
-            case PF_F64: static_cast<double *>(d.out)[o] = (double)x; break;
-            case PF_F32: static_cast<float *>(d.out)[o] = (float)x; break;
+            case PF_F64: {
+                typedef double v2 __attribute__((ext_vector_type(2)));
+                *reinterpret_cast<v2 *>(static_cast<double *>(d.out) + o) = v2{(double)pr[i][0], (double)pr[i][1]};
+                *reinterpret_cast<v2 *>(static_cast<double *>(d.out) + o + 2) = v2{(double)pr[i][2], (double)pr[i][3]};
+                break;
+            }
+            case PF_F32: {
+                *reinterpret_cast<f32x4 *>(static_cast<float *>(d.out) + o) =
+                    f32x4{(float)pr[i][0], (float)pr[i][1], (float)pr[i][2], (float)pr[i][3]};
+                break;
+            }
             case PF_BF16X2: {
-                double xd = (double)x;
-                uint16_t hi = f32_to_bf16_rne((float)xd);
-                uint16_t lo = f32_to_bf16_rne((float)(xd - (double)bf16_to_f32(hi)));
-                static_cast<uint16_t *>(d.out)[o] = hi;
-                static_cast<uint16_t *>(d.out)[o + d.plane] = lo;
+                typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
+                u16x4 hi, lo;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    double xd = (double)pr[i][j];
+                    uint16_t h = f32_to_bf16_rne((float)xd);
+                    hi[j] = h;
+                    lo[j] = f32_to_bf16_rne((float)(xd - (double)bf16_to_f32(h)));
+                }
+                *reinterpret_cast<u16x4 *>(static_cast<uint16_t *>(d.out) + o) = hi;
+                *reinterpret_cast<u16x4 *>(static_cast<uint16_t *>(d.out) + o + d.plane) = lo;
                 break;
             }
             default: {
-                long long xi = (long long)x;
-                for (int l = 0; l + 1 < limbs; ++l) {
-                    long long md = ((xi % 128) + 128 + 64) % 128 - 64;  // balanced digit
-                    static_cast<int8_t *>(d.out)[o + l * d.plane] = (int8_t)md;
-                    xi = (xi - md) / 128;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    long long xi = (long long)pr[i][j];
+                    for (int l = 0; l + 1 < limbs; ++l) {
+                        long long md = ((xi % 128) + 128 + 64) % 128 - 64;  // balanced digit
+                        static_cast<int8_t *>(d.out)[o + j + l * d.plane] = (int8_t)md;
+                        xi = (xi - md) / 128;
+                    }
+                    static_cast<int8_t *>(d.out)[o + j + (int64_t)(limbs - 1) * d.plane] = (int8_t)xi;
                 }
-                static_cast<int8_t *>(d.out)[o + (int64_t)(limbs - 1) * d.plane] = (int8_t)xi;
                 break;
             }
         }
@@ -913,6 +985,11 @@ hipError_t launch_reduce(const ReduceDesc *d, int nprob, int64_t max_len, int do
 hipError_t launch_elim0(const Elim0Desc *d, int nprob, int domain, hipStream_t s) {
     if (domain == DOM_FP) hipLaunchKernelGGL(k_elim0<DOM_FP>, dim3(nprob), dim3(256), 0, s, d, nprob);
     else hipLaunchKernelGGL(k_elim0<DOM_INT>, dim3(nprob), dim3(256), 0, s, d, nprob);
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose(const TransDesc *d, int nprob, int64_t total_tiles, hipStream_t s) {
+    hipLaunchKernelGGL(k_transpose, dim3((unsigned)total_tiles), dim3(256), 0, s, d, nprob);
     return hipGetLastError();
 }
 

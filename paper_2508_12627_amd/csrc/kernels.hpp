@@ -40,9 +40,10 @@ struct DiagDesc {
     unsigned long long *mx_out;  // DOM_INT: running max |dst|, or null
 };
 
-// Strip partials of y(w) = sum_v prod_k A_k(v, w) prod_j s_j(v):
-// part[tv * n + w] holds the sum over rows [tv*kElimStrip, (tv+1)*kElimStrip)
-// for the 64 columns of strip tw; tiles_v = ceil(n / kElimStrip).
+// Strip partials of y(w) = sum_v prod_k A_k(v, w) prod_j s_j(v) with every
+// operand stored (v, w) (trans == 0): part[tv * n + w] holds the sum over
+// rows [tv*kElimStrip, (tv+1)*kElimStrip) for the 256 columns of strip tw;
+// tiles_v = ceil(n / kElimStrip), tiles_w = ceil(n / 256).
 struct Elim1Desc {
     int64_t n;
     int32_t nA, nS;
@@ -65,6 +66,16 @@ struct ReduceDesc {
     unsigned long long *mx_out;  // DOM_INT vectors: running max |out|, or null
 };
 
+// Materialised transpose: dst[b * n + a] = src[a * ld + b], a, b < n, in
+// 64 x 64 tiles (tiles = ceil(n / 64) per side).
+struct TransDesc {
+    const void *src;
+    void *dst;
+    int64_t n, ld;
+    int32_t dtype, tiles;
+    int64_t tile_start;
+};
+
 // out = sum_v prod_j s_j(v) (one block per problem).
 struct Elim0Desc {
     int64_t n;
@@ -76,7 +87,9 @@ struct Elim0Desc {
 enum PrepFormat : int32_t { PF_F64 = 0, PF_F32 = 1, PF_BF16X2 = 2, PF_I8LIMBS = 3 };
 
 // GEMM operand: out[w * ldo + v] = prod_j s_j(v) prod_k A_k(v, w) for
-// w, v < n and 0 in the padding up to npad.  PF_BF16X2 writes hi at out and
+// w, v < n and 0 in the padding up to npad, every operand stored (w, v)
+// (trans == 1); tiles of 64 rows x 128 columns, (npad/64) * (npad/128) per
+// problem; ldo a multiple of 4.  PF_BF16X2 writes hi at out and
 // lo at out + plane (elements); PF_I8LIMBS writes `limbs` planes of 7-bit
 // digits (balanced for all but the top one).
 struct PrepDesc {
@@ -138,6 +151,7 @@ hipError_t launch_elim1(const Elim1Desc *d, int nprob, int64_t total_tiles, int 
 hipError_t launch_reduce(const ReduceDesc *d, int nprob, int64_t max_len, int domain,
                          hipStream_t s);
 hipError_t launch_elim0(const Elim0Desc *d, int nprob, int domain, hipStream_t s);
+hipError_t launch_transpose(const TransDesc *d, int nprob, int64_t total_tiles, hipStream_t s);
 hipError_t launch_prep(const PrepDesc *d, int nprob, int64_t total_tiles, int domain,
                        hipStream_t s);
 hipError_t launch_gemm(const GemmDesc *d, int nprob, int64_t total_tiles, int precision,

@@ -24,12 +24,13 @@ hipEvent_t Profiler::get() {
     return e;
 }
 
-void Profiler::begin(int kind, hipStream_t s, double fl) {
+void Profiler::begin(int kind, hipStream_t s, double fl, double by) {
     Rec r;
     r.kind = kind;
     r.a = get();
     r.b = get();
     r.flops = fl;
+    r.bytes = by;
     (void)hipEventRecord(r.a, s);
     pending_.push_back(r);
 }
@@ -49,6 +50,7 @@ void Profiler::collect() {
             ms[r.kind] += t;
             launches[r.kind] += 1;
             flops[r.kind] += r.flops;
+            bytes[r.kind] += r.bytes;
         }
         pool_.push_back(r.a);
         pool_.push_back(r.b);
@@ -61,6 +63,7 @@ void Profiler::reset() {
         ms[k] = 0;
         launches[k] = 0;
         flops[k] = 0;
+        bytes[k] = 0;
     }
 }
 

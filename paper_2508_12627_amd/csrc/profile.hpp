@@ -19,19 +19,20 @@ public:
     static void enable(bool on);
     static bool enabled();
     static void suspend(bool s);
-    void begin(int kind, hipStream_t s, double flops);
+    void begin(int kind, hipStream_t s, double flops, double bytes = 0);
     void end(int kind, hipStream_t s);
     void collect();  // after the stream has been synchronised
     void reset();
     double ms[KIND_COUNT] = {0};
     int64_t launches[KIND_COUNT] = {0};
     double flops[KIND_COUNT] = {0};
+    double bytes[KIND_COUNT] = {0};
 
 private:
     struct Rec {
         int kind;
         hipEvent_t a, b;
-        double flops;
+        double flops, bytes;
     };
     std::vector<Rec> pending_;
     std::vector<hipEvent_t> pool_;
@@ -42,8 +43,9 @@ struct ProfScope {
     Profiler *p;
     int kind;
     hipStream_t s;
-    ProfScope(Profiler *p_, int k, hipStream_t s_, double flops) : p(p_), kind(k), s(s_) {
-        if (p) p->begin(kind, s, flops);
+    ProfScope(Profiler *p_, int k, hipStream_t s_, double flops, double bytes = 0)
+        : p(p_), kind(k), s(s_) {
+        if (p) p->begin(kind, s, flops, bytes);
     }
     ~ProfScope() {
         if (p) p->end(kind, s);

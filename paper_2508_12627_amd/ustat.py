@@ -62,7 +62,7 @@ class Result(ctypes.Structure):
 _lib = None
 
 EXPORTS = ["ustat_plan_opts_default", "ustat_plan_create", "ustat_plan_destroy", "ustat_plan_info",
-           "ustat_plan_cost", "ustat_plan_partition", "ustat_plan_order", "ustat_graph_treewidth",
+           "ustat_plan_cost", "ustat_plan_workspace", "ustat_plan_partition", "ustat_plan_order", "ustat_graph_treewidth",
            "ustat_eval", "ustat_eval_samples", "vstat_eval", "ustat_eval_batched",
            "ustat_build_rbf", "ustat_profile_enable", "ustat_profile_reset", "ustat_profile_read",
            "ustat_status_string", "ustat_last_error"]
@@ -83,6 +83,7 @@ def load_library(path: str = LIB_PATH):
     L.ustat_plan_destroy.argtypes = [P]
     L.ustat_plan_info.argtypes = [P, pi32, pi32, pi64, pi32]
     L.ustat_plan_cost.argtypes = [P, i64, pdbl, pdbl, ctypes.POINTER(u64)]
+    L.ustat_plan_workspace.argtypes = [P, i32, pi64, i32, ctypes.POINTER(u64)]
     L.ustat_plan_partition.argtypes = [P, i32, pi32, pi64, pi32, pi32]
     L.ustat_plan_order.argtypes = [P, i32, pi32, pi32]
     L.ustat_graph_treewidth.argtypes = [i32, i32, pi32, pi32]
@@ -94,7 +95,7 @@ def load_library(path: str = LIB_PATH):
     L.ustat_build_rbf.argtypes = [i64, i32, P, dbl, i32, P, P]
     L.ustat_profile_enable.argtypes = [i32]
     L.ustat_profile_reset.argtypes = []
-    L.ustat_profile_read.argtypes = [i32, pdbl, pi64, pdbl]
+    L.ustat_profile_read.argtypes = [i32, pdbl, pi64, pdbl, pdbl]
     L.ustat_status_string.argtypes = [i32]
     L.ustat_status_string.restype = ctypes.c_char_p
     L.ustat_last_error.argtypes = []
@@ -160,6 +161,14 @@ def ustat_plan_cost(h, n: int) -> dict:
     f, b, ws = ctypes.c_double(), ctypes.c_double(), ctypes.c_uint64()
     _check(load_library().ustat_plan_cost(h, int(n), ctypes.byref(f), ctypes.byref(b), ctypes.byref(ws)))
     return {"flops": f.value, "bytes": b.value, "workspace": ws.value}
+
+
+def ustat_plan_workspace(h, ns, shared_factor: bool = True) -> int:
+    arr = (ctypes.c_int64 * len(ns))(*[int(x) for x in ns])
+    b = ctypes.c_uint64()
+    _check(load_library().ustat_plan_workspace(h, len(ns), arr, 1 if shared_factor else 0,
+                                               ctypes.byref(b)))
+    return b.value
 
 
 def ustat_plan_partition(h, idx: int, m: int) -> dict:
@@ -244,9 +253,10 @@ def ustat_profile_reset():
 
 def ustat_profile_read(kind) -> dict:
     k = PROFILE_KINDS[kind] if isinstance(kind, str) else int(kind)
-    ms, nl, fl = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
-    _check(load_library().ustat_profile_read(k, ctypes.byref(ms), ctypes.byref(nl), ctypes.byref(fl)))
-    return {"ms": ms.value, "launches": nl.value, "flops": fl.value}
+    ms, nl, fl, by = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+    _check(load_library().ustat_profile_read(k, ctypes.byref(ms), ctypes.byref(nl), ctypes.byref(fl),
+                                             ctypes.byref(by)))
+    return {"ms": ms.value, "launches": nl.value, "flops": fl.value, "bytes": by.value}
 
 
 # ------------------------------------------------------------------ wrapper
@@ -278,6 +288,9 @@ class Plan:
 
     def cost(self, n: int) -> dict:
         return ustat_plan_cost(self.h, n)
+
+    def workspace(self, ns, shared_factor: bool = True) -> int:
+        return ustat_plan_workspace(self.h, ns, shared_factor)
 
     def partition(self, idx: int) -> dict:
         return ustat_plan_partition(self.h, idx, self.m)

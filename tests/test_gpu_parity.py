@@ -277,3 +277,47 @@ def test_cse_matches_separate_evaluation(U, name):
     ai = U.Plan(m, edges, precision="i8").eval([Ad] * len(edges))
     bi = U.Plan(m, edges, precision="i8", cse=False).eval([Ad] * len(edges))
     assert ai.exact == bi.exact
+
+
+@pytest.mark.parametrize("prec", ["f64", "bf16x3"])
+def test_batched_equals_single_and_oracle(U, prec):
+    """Datasets of uneven n through ustat_eval_batched (one graph replay)
+    give bitwise the results of one-by-one evaluation, and match the
+    oracle's brute force on small datasets."""
+    import torch
+    edges = W.CYCLE5_CHORD
+    ns = [int(x) for x in W.ragged_sizes(6, 17, 29, seed=4)]
+    d, div = 3, 6.0
+    Xs = [W.student_t_samples(n, d, seed=40 + i) for i, n in enumerate(ns)]
+    P = U.Plan(5, edges, precision=prec)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        Xd = [dev(X, torch.float64) for X in Xs]
+        say(f"batched {prec} ns={ns}")
+        rb = P.eval_batched(Xd, div, stream=s)
+        rb2 = P.eval_batched(Xd, div, stream=s)  # replay
+        singles = [P.eval_samples(X, div, stream=s) for X in Xd]
+    for i, (X, n) in enumerate(zip(Xs, ns)):
+        assert rb[i].value == singles[i].value
+        assert rb2[i].value == rb[i].value
+        K = oracle.rbf_matrix(X, div)
+        ref = oracle.ustat_bruteforce(edges, [K] * 6)
+        assert abs(rb[i].value - ref) <= TOL[prec] * rb[i].err_scale
+
+
+def test_batched_large_ragged(U):
+    """A batch with n spanning several GEMM tiles and ragged tails: batched
+    equals one-by-one evaluation bitwise."""
+    import torch
+    ns = [130, 257, 385, 512, 64, 1000]
+    d, div = 32, 64.0
+    Xs = [W.student_t_samples(n, d, seed=70 + i) for i, n in enumerate(ns)]
+    P = U.Plan(5, W.CYCLE5_CHORD, precision="bf16x3")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        Xd = [dev(X, torch.float64) for X in Xs]
+        say(f"batched large ns={ns}")
+        rb = P.eval_batched(Xd, div, stream=s)
+        singles = [P.eval_samples(X, div, stream=s) for X in Xd]
+    for i in range(len(ns)):
+        assert rb[i].value == singles[i].value
