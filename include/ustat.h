@@ -235,6 +235,50 @@ ustat_status ustat_profile_reset(void);
 ustat_status ustat_profile_read(int32_t kind, double *ms, int64_t *launches, double *flops,
                                 double *bytes);
 
+/*
+ * Features of partition block_of (any labelling) eliminated in the given
+ * order (quotient vertices, labels as in ustat_plan_order; len = number of
+ * quotient vertices) at sample size n: feat (host float array of at least
+ * USTAT_NUM_FEATURES entries) receives step-kind counts, operand and
+ * transposition counts, dependency depth, width and log-size terms.
+ * USTAT_E_UNSUPPORTED if the order needs a step of degree above 2.
+ */
+#define USTAT_NUM_FEATURES 15
+ustat_status ustat_order_features(ustat_plan plan, const int32_t *block_of, const int32_t *order,
+                                  int32_t len, int64_t n, float *feat);
+
+/* vstat_eval with an explicit elimination order (as above). */
+ustat_status vstat_eval_ordered(ustat_plan plan, const int32_t *block_of, const int32_t *order,
+                                int32_t len, int64_t n, const void *const *factors,
+                                ustat_stream stream, ustat_result *out);
+
+/*
+ * Cost-model MLP, F -> H1 -> H2 -> 1 with ReLU hidden layers, on the GPU
+ * (its own forward, backward and Adam kernels).  params is one host fp32
+ * array of ustat_mlp_num_params(F, H1, H2) entries:
+ *   mean[F] inv_std[F] W1[H1*F] b1[H1] W2[H2*H1] b2[H2] W3[H2] b3[1]
+ * (inputs are standardised with mean/inv_std, which are not trained).
+ * X is host fp32 N x F row-major, y host fp32 [N].  The loss is the mean
+ * squared error.  Reductions over samples use a fixed order, so results
+ * are reproducible.
+ */
+size_t ustat_mlp_num_params(int32_t F, int32_t H1, int32_t H2);
+/* out[i] = network output for row i of X. */
+ustat_status ustat_mlp_predict(int32_t F, int32_t H1, int32_t H2, const float *params,
+                               const float *X, int64_t N, float *out);
+/* *loss = mean squared error; grad (host, num_params entries) = its gradient
+ * with respect to every parameter (zero for mean and inv_std). */
+ustat_status ustat_mlp_loss_grad(int32_t F, int32_t H1, int32_t H2, const float *params,
+                                 const float *X, const float *y, int64_t N, double *loss,
+                                 float *grad);
+/* steps full-batch Adam steps (learning rate lr) updating params in place;
+ * losses (host, may be NULL) receives the loss before each step. */
+ustat_status ustat_mlp_train(int32_t F, int32_t H1, int32_t H2, float *params, const float *X,
+                             const float *y, int64_t N, int32_t steps, float lr, double *losses);
+/* Write params as a cost-model file readable through opts.cost_model_path. */
+ustat_status ustat_mlp_save(const char *path, int32_t F, int32_t H1, int32_t H2,
+                            const float *params);
+
 const char *ustat_status_string(ustat_status s);
 const char *ustat_last_error(void);
 

@@ -3,6 +3,7 @@
 // exec.cpp / kernels.hip (device).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <functional>
@@ -37,6 +38,12 @@ struct ustat_plan_s {
 namespace {
 
 thread_local std::string g_err;
+
+}  // namespace
+
+void ustat::set_last_error(const std::string &msg) { g_err = msg; }
+
+namespace {
 
 ustat_status fail(ustat_status s, const std::string &msg) {
     g_err = msg;
@@ -276,7 +283,7 @@ static ustat_status run(ustat_plan plan, const std::vector<const VProgram *> &pr
     std::string err;
     try {
         if (capture) Profiler::suspend(true);
-        err = execute(plan->plan, progs, data, s, plan->rt, res, vout, &st, capture, key, pre);
+        err = execute_all(plan->plan, progs, data, s, plan->rt, res, vout, &st, capture, key, pre);
         if (capture) Profiler::suspend(false);
     } catch (const std::bad_alloc &) {
         Profiler::suspend(false);
@@ -387,6 +394,61 @@ ustat_status vstat_eval(ustat_plan plan, const int32_t *block_of, int64_t n,
     std::vector<DatasetResult> res;
     std::vector<const VProgram *> progs = {&prog};
     ustat_status st = run(plan, progs, data, (hipStream_t)stream, res, nullptr, nullptr, "");
+    if (st != USTAT_OK) return st;
+    fill_result(out, res[0], plan->plan, n, 1);
+    out->err_scale = std::fabs(res[0].value);
+    return ok();
+}
+
+static ustat_status lower_given(ustat_plan plan, const int32_t *block_of, const int32_t *order,
+                                int32_t len, VProgram &prog) {
+    if (!plan || !block_of || !order) return fail(USTAT_E_INVALID, "NULL argument");
+    std::vector<int> rgs;
+    canonical_rgs(block_of, plan->plan.m, rgs);
+    int J = 0;
+    for (int b : rgs) J = std::max(J, b + 1);
+    if (len != J) return fail(USTAT_E_INVALID, "order length must equal the number of blocks");
+    std::vector<int> ord(order, order + len), chk = ord;
+    std::sort(chk.begin(), chk.end());
+    for (int i = 0; i < J; ++i)
+        if (chk[i] != i) return fail(USTAT_E_INVALID, "order is not a permutation of the blocks");
+    prog.block_of = rgs;
+    prog.J = J;
+    prog.mu = mobius_mu(rgs);
+    std::string err = lower_order(plan->plan.edges, rgs, J, ord, prog);
+    if (!err.empty()) return fail(USTAT_E_UNSUPPORTED, err);
+    return USTAT_OK;
+}
+
+ustat_status ustat_order_features(ustat_plan plan, const int32_t *block_of, const int32_t *order,
+                                  int32_t len, int64_t n, float *feat) {
+    if (!feat || n < 1) return fail(USTAT_E_INVALID, "bad arguments");
+    VProgram prog;
+    ustat_status st = lower_given(plan, block_of, order, len, prog);
+    if (st != USTAT_OK) return st;
+    std::vector<float> f = program_features(prog, (double)n);
+    if ((int)f.size() != USTAT_NUM_FEATURES) return fail(USTAT_E_INVALID, "feature size mismatch");
+    std::copy(f.begin(), f.end(), feat);
+    return ok();
+}
+
+ustat_status vstat_eval_ordered(ustat_plan plan, const int32_t *block_of, const int32_t *order,
+                                int32_t len, int64_t n, const void *const *factors,
+                                ustat_stream stream, ustat_result *out) {
+    if (!factors || !out) return fail(USTAT_E_INVALID, "NULL argument");
+    if (n < 1 || n > (1ll << 20)) return fail(USTAT_E_INVALID, "n out of range");
+    VProgram prog;
+    ustat_status st = lower_given(plan, block_of, order, len, prog);
+    if (st != USTAT_OK) return st;
+    for (size_t k = 0; k < plan->plan.edges.size(); ++k)
+        if (!factors[k]) return fail(USTAT_E_INVALID, "a factor pointer is NULL");
+    prog.mu = 1;
+    std::vector<Dataset> data(1);
+    data[0].n = n;
+    for (size_t k = 0; k < plan->plan.edges.size(); ++k) data[0].factors.push_back(factors[k]);
+    std::vector<DatasetResult> res;
+    std::vector<const VProgram *> progs = {&prog};
+    st = run(plan, progs, data, (hipStream_t)stream, res, nullptr, nullptr, "");
     if (st != USTAT_OK) return st;
     fill_result(out, res[0], plan->plan, n, 1);
     out->err_scale = std::fabs(res[0].value);

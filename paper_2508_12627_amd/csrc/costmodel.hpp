@@ -25,6 +25,9 @@ std::string load_mlp(const std::string &path, MLPWeights &w);
 std::string save_mlp(const std::string &path, const MLPWeights &w);
 float mlp_forward(const MLPWeights &w, const float *x);
 
+// Thread-local detail message returned by ustat_last_error().
+void set_last_error(const std::string &msg);
+
 class CostModel : public OrderScorer {
 public:
     std::string load(const std::string &path) { return load_mlp(path, w_); }

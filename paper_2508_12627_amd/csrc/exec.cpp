@@ -33,6 +33,7 @@ Runtime::~Runtime() {
     if (ddesc) (void)hipFree(ddesc);
     if (hdesc) (void)hipHostFree(hdesc);
     if (hres) (void)hipHostFree(hres);
+    if (vacc) (void)hipFree(vacc);
 }
 
 hipError_t Runtime::reserve_arena(size_t bytes) {
@@ -60,6 +61,17 @@ hipError_t Runtime::reserve_desc(size_t bytes) {
     if (e != hipSuccess) return e;
     ddesc_bytes = hdesc_bytes = b;
     return hipSuccess;
+}
+
+hipError_t Runtime::reserve_vacc(size_t bytes) {
+    if (bytes <= vacc_bytes && vacc) return hipSuccess;
+    drop_graphs();
+    if (vacc) (void)hipFree(vacc);
+    vacc = nullptr;
+    vacc_bytes = 0;
+    hipError_t e = hipMalloc(&vacc, std::max<size_t>(bytes, 256));
+    if (e == hipSuccess) vacc_bytes = bytes;
+    return e;
 }
 
 hipError_t Runtime::reserve_hres(size_t bytes) {
@@ -140,6 +152,9 @@ struct LevelWork {
     std::vector<TransDesc> tr;
     int64_t tr_tiles = 0;
     size_t off_tr = 0;
+    std::vector<SliceDesc> sl;
+    int64_t sl_tiles = 0;
+    size_t off_sl = 0;
     std::vector<Elim0Desc> e0;
     std::vector<ReduceDesc> red;
     int64_t red_maxlen = 1;
@@ -167,9 +182,10 @@ struct Schedule {
     int64_t diag_maxn = 1;
     std::vector<LevelWork> levels;
     std::vector<CombineDesc> comb;
-    std::vector<int32_t> scal_off, scal_cnt, scal_idx;
+    std::vector<int32_t> term_off, term_cnt, scal_off, scal_cnt, scal_idx;
     std::vector<int64_t> mu;
-    size_t off_diag = 0, off_comb = 0, off_soff = 0, off_scnt = 0, off_sidx = 0, off_mu = 0;
+    size_t off_diag = 0, off_comb = 0, off_toff = 0, off_tcnt = 0, off_soff = 0, off_scnt = 0,
+           off_sidx = 0, off_mu = 0;
     size_t blob_bytes = 0;
     Blob blob;
     int nprog_total = 0;
@@ -217,7 +233,7 @@ size_t prep_bytes(const Cfg &c, int64_t npad, int limbs) {
 // deterministic, so this does not change any result bit.
 // ---------------------------------------------------------------------------
 
-enum class NK : uint8_t { E0, E1, Dot, GemmStore, GemmFinal, Transpose };
+enum class NK : uint8_t { E0, E1, Dot, GemmStore, GemmFinal, Transpose, SliceSrc };
 
 struct MOp {        // matrix operand
     int node;       // producing node, or -1 for an input factor
@@ -227,6 +243,7 @@ struct MOp {        // matrix operand
 struct VOp {        // vector operand
     int node;       // producing node, or -1 for the diagonal of input factor p
     const void *p;
+    int64_t off = 0;  // element offset into the node's buffer (slice rows)
 };
 
 struct Node {
@@ -247,6 +264,7 @@ struct Ref {  // a program value resolved to a node or an input
     int node = -1;
     const void *p = nullptr;
     bool flip = false;  // stored transposed relative to the program value
+    int64_t off = 0;    // slice row offset (slice vectors)
 };
 
 std::string ptr_id(const void *p) {
@@ -258,8 +276,9 @@ std::string ptr_id(const void *p) {
 struct Dag {
     std::vector<Node> nodes;
     std::unordered_map<std::string, int> by_key;
-    // program scalars -> nodes (dataset-major, program-minor)
-    std::vector<std::vector<int>> prog_scalars;
+    // per (dataset, program), dataset-major: terms, each a list of scalar
+    // nodes whose product is the term (one term, or one per slice)
+    std::vector<std::vector<std::vector<int>>> prog_terms;
     // distinct input diagonals (dataset, factor pointer)
     std::map<std::pair<int, const void *>, int> diag_index;
     int max_level = 0;
@@ -269,7 +288,9 @@ std::string mop_sig(const MOp &m) {
     return (m.node < 0 ? "I" + ptr_id(m.p) : "N" + std::to_string(m.node)) + (m.trans ? "t" : "n");
 }
 std::string vop_sig(const VOp &v) {
-    return v.node < 0 ? "D" + ptr_id(v.p) : "N" + std::to_string(v.node);
+    std::string s = v.node < 0 ? "D" + ptr_id(v.p) : "N" + std::to_string(v.node);
+    if (v.off) s += "+" + std::to_string(v.off);
+    return s;
 }
 template <class T, class F>
 std::string group_sig(const std::vector<T> &v, F f) {
@@ -339,11 +360,11 @@ std::string gemm_key(int64_t n, const std::vector<MOp> &A, const std::vector<VOp
 }
 
 std::string build_dag(const Plan &plan, const std::vector<const VProgram *> &progs,
-                      const std::vector<Dataset> &data, bool cse, Dag &G) {
+                      const std::vector<Dataset> &data, bool cse, const SliceRange &range, Dag &G) {
     const int nd = (int)data.size(), np = (int)progs.size();
-    G.prog_scalars.assign((size_t)nd * np, {});
+    G.prog_terms.assign((size_t)nd * np, {});
     struct Pending {
-        int dp;
+        int dp, term, pos;
         int64_t n;
         int d;
         std::vector<MOp> A, B, Z;
@@ -353,30 +374,53 @@ std::string build_dag(const Plan &plan, const std::vector<const VProgram *> &pro
     };
     std::vector<Pending> pending;
     std::unordered_map<std::string, int> gkey_count;
+    auto use_diag = [&](int d, const void *ptr) {
+        auto key = std::make_pair(d, ptr);
+        if (!G.diag_index.count(key)) {
+            int idx = (int)G.diag_index.size();
+            G.diag_index[key] = idx;
+        }
+    };
     for (int d = 0; d < nd; ++d) {
         const int64_t n = data[d].n;
         for (int p = 0; p < np; ++p) {
-            const VProgram &pr = *progs[p];
+          const VProgram &pr = *progs[p];
+          const bool sliced = pr.slice_var >= 0;
+          if (!sliced && !range.include_unsliced) continue;
+          const int64_t s_lo = sliced ? std::max<int64_t>(0, range.lo) : -1;
+          const int64_t s_hi = sliced ? std::min<int64_t>(n, range.hi) : 0;
+          for (int64_t slice = s_lo; slice < s_hi; ++slice) {
             std::vector<Ref> ref(pr.vals.size());
             for (size_t v = 0; v < pr.vals.size(); ++v) {
                 const Value &val = pr.vals[v];
                 if (val.kind == ValKind::InputMat || val.kind == ValKind::InputDiag) {
                     ref[v].p = data[d].factors[val.src];
-                    if (val.kind == ValKind::InputDiag) {
-                        auto key = std::make_pair(d, ref[v].p);
-                        if (!G.diag_index.count(key)) {
-                            int idx = (int)G.diag_index.size();
-                            G.diag_index[key] = idx;
-                        }
+                    if (val.kind == ValKind::InputDiag) use_diag(d, ref[v].p);
+                } else if (val.kind == ValKind::SliceVec) {
+                    Node sn;
+                    sn.kind = NK::SliceSrc;
+                    sn.d = d;
+                    sn.n = n;
+                    const void *mp = data[d].factors[val.src];
+                    sn.A.push_back(MOp{-1, mp, val.c == 1});
+                    std::string key = "S|" + std::to_string(n) + "|" + ptr_id(mp) + "|" + std::to_string(val.c);
+                    for (int k : val.scale) {
+                        const void *dp_ = data[d].factors[k];
+                        use_diag(d, dp_);
+                        sn.sv.push_back(VOp{-1, dp_});
                     }
+                    key += "|" + group_sig(sn.sv, vop_sig);
+                    ref[v].node = add_node(G, sn, key, cse);
+                    ref[v].off = slice * n;
                 }
             }
             auto mop = [&](const MatOp &o) {
                 const Ref &r = ref[o.val];
                 return MOp{r.node, r.p, (bool)(o.trans ^ r.flip)};
             };
-            auto vop = [&](int v) { return VOp{ref[v].node, ref[v].p}; };
+            auto vop = [&](int v) { return VOp{ref[v].node, ref[v].p, ref[v].off}; };
             const int dp = d * np + p;
+            std::vector<int> term;
             for (const Step &st : pr.steps) {
                 std::vector<MOp> A, B, Z;
                 std::vector<VOp> sv, aw, bx;
@@ -395,7 +439,7 @@ std::string build_dag(const Plan &plan, const std::vector<const VProgram *> &pro
                         nd_.sv = sv;
                         int id = add_node(G, nd_, "E0|" + std::to_string(n) + "|" + group_sig(sv, vop_sig), cse);
                         ref[st.out].node = id;
-                        G.prog_scalars[dp].push_back(id);
+                        term.push_back(id);
                         break;
                     }
                     case StepKind::Elim1:
@@ -417,7 +461,7 @@ std::string build_dag(const Plan &plan, const std::vector<const VProgram *> &pro
                             for (auto &v : aw) dot.sv.push_back(v);
                             int did = add_node(G, dot, "DOT|" + std::to_string(n) + "|" + group_sig(dot.sv, vop_sig), cse);
                             ref[st.out].node = did;
-                            G.prog_scalars[dp].push_back(did);
+                            term.push_back(did);
                         }
                         break;
                     }
@@ -441,6 +485,8 @@ std::string build_dag(const Plan &plan, const std::vector<const VProgram *> &pro
                         for (auto &o : B) o = direct(G, o, true, d, n, cse);
                         Pending pd;
                         pd.dp = dp;
+                        pd.term = (int)G.prog_terms[dp].size();
+                        pd.pos = (int)term.size();
                         pd.n = n;
                         pd.d = d;
                         pd.A = A;
@@ -451,12 +497,14 @@ std::string build_dag(const Plan &plan, const std::vector<const VProgram *> &pro
                         pd.bx = bx;
                         pd.gkey = gemm_key(n, A, sv, B, &pd.swapped);
                         gkey_count[pd.gkey] += 1;
-                        G.prog_scalars[dp].push_back(-1 - (int)pending.size());  // patched below
+                        term.push_back(-1);  // patched below
                         pending.push_back(pd);
                         break;
                     }
                 }
             }
+            G.prog_terms[dp].push_back(term);
+          }
         }
     }
     // Final2 steps: fused GEMM + consumer unless their product is shared.
@@ -511,8 +559,7 @@ std::string build_dag(const Plan &plan, const std::vector<const VProgram *> &pro
                             "|" + group_sig(bx, vop_sig);
             sid = add_node(G, f, k, cse);
         }
-        for (auto &x : G.prog_scalars[pd.dp])
-            if (x == -1 - (int)i) x = sid;
+        G.prog_terms[pd.dp][pd.term][pd.pos] = sid;
     }
     // last uses
     for (auto &nd : G.nodes) {
@@ -536,7 +583,8 @@ std::string build_dag(const Plan &plan, const std::vector<const VProgram *> &pro
 std::string build_schedule(const Plan &plan, const std::vector<const VProgram *> &progs,
                            const std::vector<Dataset> &data, const Cfg &cfg,
                            const std::vector<double> &in_bound,  // per dataset*edge (INT)
-                           char *base, Schedule &S, int *status) {
+                           char *base, Schedule &S, int *status,
+                           const SliceRange &range = SliceRange()) {
     S = Schedule();
     Arena A;
     const int ne = (int)plan.edges.size();
@@ -545,7 +593,7 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
     S.nprog_total = nd * np;
     auto P = [&](size_t off) -> void * { return base ? (void *)(base + off) : nullptr; };
     Dag G;
-    std::string err = build_dag(plan, progs, data, plan.opts.cse, G);
+    std::string err = build_dag(plan, progs, data, plan.opts.cse, range, G);
     if (!err.empty()) {
         *status = 1;
         return err;
@@ -568,7 +616,8 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
     size_t nscal = 0, nmx = 0;
     for (auto &nd_ : G.nodes) {
         if (nd_.kind == NK::E0 || nd_.kind == NK::Dot || nd_.kind == NK::GemmFinal) nd_.scal = (int)nscal++;
-        if (is_int && (nd_.kind == NK::E1 || nd_.kind == NK::GemmStore)) nd_.mx = (int)nmx++;
+        if (is_int && (nd_.kind == NK::E1 || nd_.kind == NK::GemmStore || nd_.kind == NK::SliceSrc))
+            nd_.mx = (int)nmx++;
     }
     std::vector<int> diag_mx(G.diag_index.size(), -1);
     if (is_int)
@@ -576,7 +625,6 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
     S.n_scal = nscal;
     S.n_mx = nmx;
     S.off_scal = A.alloc(nscal * cfg.wide_es + 16);
-    S.off_v = A.alloc((size_t)S.nprog_total * cfg.wide_es + 16);
     S.off_u = A.alloc((size_t)nd * cfg.wide_es + 16);
     S.off_s = A.alloc((size_t)nd * 8 + 16);
     S.off_mx = A.alloc(nmx * 8 + 16);
@@ -614,7 +662,7 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
     }
     const bool sparsify = plan.opts.sparsify != 0;
     auto vptr = [&](int d, const VOp &v) -> const void * {
-        if (v.node >= 0) return P(G.nodes[v.node].off);
+        if (v.node >= 0) return base ? (const void *)(base + G.nodes[v.node].off + v.off * 8) : nullptr;
         return P(diag_off[G.diag_index[std::make_pair(d, v.p)]]);
     };
     auto vbound = [&](int d, const VOp &v) {
@@ -795,6 +843,24 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
                     W.red_maxlen = std::max<int64_t>(W.red_maxlen, n);
                     break;
                 }
+                case NK::SliceSrc: {
+                    SliceDesc sd;
+                    std::memset(&sd, 0, sizeof sd);
+                    sd.src = {nd_.A[0].p, n, cfg.in_dt, nd_.A[0].trans ? 1 : 0, 0, 0};
+                    sd.nscale = (int)nd_.sv.size();
+                    for (int q = 0; q < sd.nscale; ++q) sd.scale[q] = vptr(d, nd_.sv[q]);
+                    sd.tiles = tiles64;
+                    sd.n = n;
+                    nd_.bytes = (size_t)n * n * 8;
+                    nd_.off = A.alloc(nd_.bytes);
+                    sd.out = P(nd_.off);
+                    sd.tile_start = W.sl_tiles;
+                    W.sl_tiles += (int64_t)tiles64 * tiles64;
+                    sd.mx_out = (is_int && mxbase) ? mxbase + nd_.mx : nullptr;
+                    W.sl.push_back(sd);
+                    nd_.bound = in_b(d, nd_.A[0].p) * pS;
+                    break;
+                }
                 case NK::Transpose: {
                     const MOp s0 = src_of(nd_.A[0]);
                     const int es = s0.node < 0 ? cfg.in_es : cfg.mat_es;
@@ -955,23 +1021,31 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
             }
         }
     }
-    // combine tables
+    // combine tables: programs -> terms -> scalar slots
     for (int d = 0; d < nd; ++d) {
         CombineDesc c;
         c.p_begin = d * np;
         c.p_end = (d + 1) * np;
         S.comb.push_back(c);
         for (int p = 0; p < np; ++p) {
-            const auto &sc = G.prog_scalars[d * np + p];
-            S.scal_off.push_back((int32_t)S.scal_idx.size());
-            S.scal_cnt.push_back((int32_t)sc.size());
-            double b = 1;
-            for (int id : sc) {
-                S.scal_idx.push_back(G.nodes[id].scal);
-                b *= G.nodes[id].bound;
+            const auto &terms = G.prog_terms[d * np + p];
+            S.term_off.push_back((int32_t)S.scal_off.size());
+            S.term_cnt.push_back((int32_t)terms.size());
+            double bsum = 0;
+            for (const auto &sc : terms) {
+                S.scal_off.push_back((int32_t)S.scal_idx.size());
+                S.scal_cnt.push_back((int32_t)sc.size());
+                double b = 1;
+                for (int id : sc) {
+                    S.scal_idx.push_back(G.nodes[id].scal);
+                    b *= G.nodes[id].bound;
+                }
+                bsum += b;
             }
+            if (progs[p]->slice_var >= 0 && !terms.empty())
+                bsum *= (double)data[d].n / (double)terms.size();  // all slices, every chunk
             S.mu.push_back(progs[p]->mu);
-            if (is_int && b * std::fabs((double)progs[p]->mu) * np > kOverflowWide) {
+            if (is_int && bsum * std::fabs((double)progs[p]->mu) * np > kOverflowWide) {
                 *status = 5;
                 return "the combined U-statistic may exceed the 127-bit range";
             }
@@ -980,6 +1054,7 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
     S.arena_bytes = A.top;
     S.off_diag = S.blob.put(S.diag);
     for (auto &W : S.levels) {
+        W.off_sl = S.blob.put(W.sl);
         W.off_tr = S.blob.put(W.tr);
         W.off_prep = S.blob.put(W.prep);
         W.off_gemm = S.blob.put(W.gemm);
@@ -988,6 +1063,8 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
         W.off_red = S.blob.put(W.red);
     }
     S.off_comb = S.blob.put(S.comb);
+    S.off_toff = S.blob.put(S.term_off);
+    S.off_tcnt = S.blob.put(S.term_cnt);
     S.off_soff = S.blob.put(S.scal_off);
     S.off_scnt = S.blob.put(S.scal_cnt);
     S.off_sidx = S.blob.put(S.scal_idx);
@@ -1005,12 +1082,12 @@ __global__ void k_fill_zero(unsigned long long *p, size_t n) {
 }  // namespace
 
 ScheduleSizes schedule_sizes(const Plan &plan, const std::vector<const VProgram *> &progs,
-                             const std::vector<Dataset> &data) {
+                             const std::vector<Dataset> &data, const SliceRange &range) {
     Schedule S;
     int st = 0;
     const Cfg cfg = make_cfg(plan.opts.precision);
     ScheduleSizes z;
-    std::string err = build_schedule(plan, progs, data, cfg, {}, nullptr, S, &st);
+    std::string err = build_schedule(plan, progs, data, cfg, {}, nullptr, S, &st, range);
     if (!err.empty()) return z;
     z.arena = S.arena_bytes;
     z.blob = S.blob_bytes;
@@ -1034,10 +1111,18 @@ size_t workspace_bytes(const Plan &plan, const std::vector<const VProgram *> &pr
         if (shared_factor) ++slot;
         data.push_back(d);
     }
+    // Conditioned programs run in slice chunks; report the one-slice chunk.
+    SliceRange rg;
+    for (const VProgram *p : progs)
+        if (p->slice_var >= 0) rg.hi = 1;
     Schedule S;
     int st = 0;
-    std::string err = build_schedule(plan, progs, data, make_cfg(plan.opts.precision), {}, nullptr, S, &st);
-    if (!err.empty()) return 0;
+    std::string err = build_schedule(plan, progs, data, make_cfg(plan.opts.precision), {}, nullptr, S,
+                                     &st, rg);
+    if (!err.empty()) {
+        if (getenv("USTAT_DEBUG_DAG")) fprintf(stderr, "workspace: %s\n", err.c_str());
+        return 0;
+    }
     return S.arena_bytes;
 }
 
@@ -1054,7 +1139,7 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
                     const std::vector<Dataset> &data, hipStream_t stream, Runtime &rt,
                     std::vector<DatasetResult> &out, std::vector<double> *vout, int *status,
                     bool capture, const std::string &capture_key,
-                    const std::function<hipError_t(hipStream_t)> &pre) {
+                    const std::function<hipError_t(hipStream_t)> &pre, const SliceRange &range) {
     *status = 0;
     const Cfg cfg = make_cfg(plan.opts.precision);
     if (capture) {
@@ -1112,7 +1197,7 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
             in_bound[i] = (double)reinterpret_cast<unsigned long long *>(rt.hres)[i];
     }
     Schedule S;
-    std::string err = build_schedule(plan, progs, data, cfg, in_bound, nullptr, S, status);
+    std::string err = build_schedule(plan, progs, data, cfg, in_bound, nullptr, S, status, range);
     if (!err.empty()) return err;
     if (plan.opts.workspace_limit && S.arena_bytes > plan.opts.workspace_limit) {
         *status = 6;
@@ -1125,7 +1210,7 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
             return std::string("device workspace allocation failed: ") + hipGetErrorString(e);
         }
     }
-    err = build_schedule(plan, progs, data, cfg, in_bound, rt.arena, S, status);
+    err = build_schedule(plan, progs, data, cfg, in_bound, rt.arena, S, status, range);
     if (!err.empty()) return err;
     // room for the blob and, behind it, the staged input maxima (reserved
     // before any asynchronous copy reads the pinned buffer)
@@ -1133,6 +1218,7 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
     const int nd = (int)data.size();
     const size_t nres = (size_t)S.nprog_total * cfg.wide_es + (size_t)nd * cfg.wide_es + nd * 8;
     HIPCHK(rt.reserve_hres(nres + 64));
+    if (range.first) HIPCHK(rt.reserve_vacc((size_t)S.nprog_total * cfg.wide_es + 64));
 
     {
         char *hblob = rt.hdesc;
@@ -1194,6 +1280,11 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
             if (e != hipSuccess) return fail(e, "diag");
         }
         for (auto &W : S.levels) {
+            if (!W.sl.empty()) {
+                e = launch_slicesrc(reinterpret_cast<SliceDesc *>(dd + W.off_sl), (int)W.sl.size(),
+                                    W.sl_tiles, cfg.domain, stream);
+                if (e != hipSuccess) return fail(e, "slice sources");
+            }
             if (!W.tr.empty()) {
                 ProfScope ps(prof, KIND_PREP, stream, 0, W.tr_bytes);
                 e = launch_transpose(reinterpret_cast<TransDesc *>(dd + W.off_tr), (int)W.tr.size(),
@@ -1231,16 +1322,18 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
             }
         }
         e = launch_combine(reinterpret_cast<CombineDesc *>(dd + S.off_comb), nd,
+                           reinterpret_cast<int32_t *>(dd + S.off_toff),
+                           reinterpret_cast<int32_t *>(dd + S.off_tcnt),
                            reinterpret_cast<int32_t *>(dd + S.off_soff),
                            reinterpret_cast<int32_t *>(dd + S.off_scnt),
                            reinterpret_cast<int32_t *>(dd + S.off_sidx),
                            reinterpret_cast<int64_t *>(dd + S.off_mu), rt.arena + S.off_scal,
-                           rt.arena + S.off_v, rt.arena + S.off_u,
+                           rt.vacc, range.first ? 1 : 0, range.last ? 1 : 0, rt.arena + S.off_u,
                            reinterpret_cast<double *>(rt.arena + S.off_s), cfg.domain, stream);
         if (e != hipSuccess) return fail(e, "combine");
         // results: V (all), U (per dataset), S (per dataset)
         size_t vbytes = (size_t)S.nprog_total * cfg.wide_es, ubytes = (size_t)nd * cfg.wide_es;
-        e = hipMemcpyAsync(rt.hres, rt.arena + S.off_v, vbytes, hipMemcpyDeviceToHost, stream);
+        e = hipMemcpyAsync(rt.hres, rt.vacc, vbytes, hipMemcpyDeviceToHost, stream);
         if (e == hipSuccess)
             e = hipMemcpyAsync(rt.hres + vbytes, rt.arena + S.off_u, ubytes, hipMemcpyDeviceToHost,
                                stream);
@@ -1289,6 +1382,49 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
             out[d].exact_lo = (uint64_t)u;
         }
         out[d].scale = reinterpret_cast<const double *>(h + vbytes + ubytes)[d];
+    }
+    return "";
+}
+
+std::string execute_all(const Plan &plan, const std::vector<const VProgram *> &progs,
+                        const std::vector<Dataset> &data, hipStream_t stream, Runtime &rt,
+                        std::vector<DatasetResult> &out, std::vector<double> *vout, int *status,
+                        bool capture, const std::string &capture_key,
+                        const std::function<hipError_t(hipStream_t)> &pre) {
+    bool sliced = false;
+    for (const VProgram *p : progs) sliced = sliced || p->slice_var >= 0;
+    if (!sliced) return execute(plan, progs, data, stream, rt, out, vout, status, capture, capture_key, pre);
+    // Slice chunks sized to the budget: opts.workspace_limit, else half of
+    // the free device memory (plus what this runtime already holds).
+    int64_t nmax = 0;
+    for (auto &d : data) nmax = std::max(nmax, d.n);
+    size_t budget = plan.opts.workspace_limit;
+    if (!budget) {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+            *status = 4;
+            return "hipMemGetInfo failed";
+        }
+        budget = (fr + rt.arena_bytes) / 2;
+    }
+    SliceRange r1, r2;
+    r1.hi = 1;
+    r2.hi = 2;
+    const size_t a1 = schedule_sizes(plan, progs, data, r1).arena;
+    const size_t a2 = schedule_sizes(plan, progs, data, r2).arena;
+    const size_t per = a2 > a1 ? a2 - a1 : 1;
+    int64_t chunk = a1 >= budget ? 1 : (int64_t)((budget - a1) / per) + 1;
+    chunk = std::max<int64_t>(1, std::min<int64_t>(chunk, nmax));
+    for (int64_t lo = 0; lo < nmax; lo += chunk) {
+        SliceRange rg;
+        rg.lo = lo;
+        rg.hi = std::min(nmax, lo + chunk);
+        rg.include_unsliced = lo == 0;
+        rg.first = lo == 0;
+        rg.last = rg.hi >= nmax;
+        std::string err = execute(plan, progs, data, stream, rt, out, vout, status, false, "",
+                                  lo == 0 ? pre : nullptr, rg);
+        if (!err.empty()) return err;
     }
     return "";
 }

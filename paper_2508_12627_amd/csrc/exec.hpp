@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <cstdint>
 #include <functional>
 #include <map>
@@ -37,6 +38,8 @@ struct Runtime {
     size_t hdesc_bytes = 0;
     char *hres = nullptr;   // pinned host result buffer
     size_t hres_bytes = 0;
+    char *vacc = nullptr;   // device accumulators of V_pi across slice chunks
+    size_t vacc_bytes = 0;
     // Captured graphs by key, each with its own pinned descriptor blob and
     // result layout.  Any reallocation of the buffers they reference drops
     // them all.
@@ -52,6 +55,7 @@ struct Runtime {
     hipError_t reserve_arena(size_t bytes);
     hipError_t reserve_desc(size_t bytes);
     hipError_t reserve_hres(size_t bytes);
+    hipError_t reserve_vacc(size_t bytes);
 };
 
 // Optional per-launch timing, filled when non-null (milliseconds per step
@@ -67,11 +71,28 @@ struct LaunchStats {
 // matrices of each dataset must be ready on `stream`.  Results per dataset
 // and, when vout is non-null, every V_pi (dataset-major).
 // Returns "" or an error message; *status receives a ustat_status code.
+// One pass over slices [slice_lo, slice_hi) of the programs conditioned on
+// a vertex (and over the unconditioned programs when include_unsliced);
+// `first` starts the V accumulators, `last` forms U and S.
+struct SliceRange {
+    int64_t lo = 0, hi = INT64_MAX;
+    bool include_unsliced = true, first = true, last = true;
+};
+
 std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs,
                     const std::vector<Dataset> &data, hipStream_t stream, Runtime &rt,
                     std::vector<DatasetResult> &out, std::vector<double> *vout, int *status,
                     bool capture = false, const std::string &capture_key = "",
-                    const std::function<hipError_t(hipStream_t)> &pre = nullptr);
+                    const std::function<hipError_t(hipStream_t)> &pre = nullptr,
+                    const SliceRange &range = SliceRange());
+
+// Whole evaluation: programs conditioned on a vertex run in slice chunks
+// sized to the workspace budget (no graph capture); otherwise one pass.
+std::string execute_all(const Plan &plan, const std::vector<const VProgram *> &progs,
+                        const std::vector<Dataset> &data, hipStream_t stream, Runtime &rt,
+                        std::vector<DatasetResult> &out, std::vector<double> *vout, int *status,
+                        bool capture, const std::string &capture_key,
+                        const std::function<hipError_t(hipStream_t)> &pre);
 
 // Sizes an evaluation of `data` needs: arena, descriptor blob, pinned
 // result bytes (a dry schedule; pointers only fix the sharing pattern).
@@ -79,7 +100,7 @@ struct ScheduleSizes {
     size_t arena = 0, blob = 0, results = 0;
 };
 ScheduleSizes schedule_sizes(const Plan &plan, const std::vector<const VProgram *> &progs,
-                             const std::vector<Dataset> &data);
+                             const std::vector<Dataset> &data, const SliceRange &range = SliceRange());
 
 // Upper bound of the workspace bytes an evaluation at size n needs.
 size_t workspace_bytes(const Plan &plan, const std::vector<const VProgram *> &progs,

@@ -928,26 +928,72 @@ void k_gemm(const GemmDesc *D, int nprob) {
 // ----------------------------------------------------------------- combine
 
 template <int DOM>
-__global__ void k_combine(const CombineDesc *D, int ndata, const int32_t *off, const int32_t *cnt,
-                          const int32_t *idx, const int64_t *mu, const void *scal, void *vout,
-                          void *uout, double *sout) {
+__global__ void k_combine(const CombineDesc *D, int ndata, const int32_t *term_off,
+                          const int32_t *term_cnt, const int32_t *off, const int32_t *cnt,
+                          const int32_t *idx, const int64_t *mu, const void *scal, void *accv,
+                          int first, int last, void *uout, double *sout) {
     typedef typename Dom<DOM>::wide Wd;
     int ds = blockIdx.x * blockDim.x + threadIdx.x;
     if (ds >= ndata) return;
     const Wd *sc = static_cast<const Wd *>(scal);
+    Wd *acc = static_cast<Wd *>(accv);
     Wd U = 0;
     double S = 0;
     for (int p = D[ds].p_begin; p < D[ds].p_end; ++p) {
-        Wd V = 1;
-        for (int q = 0; q < cnt[p]; ++q) V *= sc[idx[off[p] + q]];
-        static_cast<Wd *>(vout)[p] = V;
-        Wd t = (Wd)mu[p] * V;
-        U += t;
-        double td = (double)t;
+        Wd V = 0;
+        for (int t = term_off[p]; t < term_off[p] + term_cnt[p]; ++t) {
+            Wd prod = 1;
+            for (int q = 0; q < cnt[t]; ++q) prod *= sc[idx[off[t] + q]];
+            V += prod;
+        }
+        Wd a = first ? V : acc[p] + V;
+        acc[p] = a;
+        Wd tv = (Wd)mu[p] * a;
+        U += tv;
+        double td = (double)tv;
         S += td < 0 ? -td : td;
     }
-    static_cast<Wd *>(uout)[ds] = U;
-    sout[ds] = S;
+    if (last) {
+        static_cast<Wd *>(uout)[ds] = U;
+        sout[ds] = S;
+    }
+}
+
+// Slice sources, 64 x 64 tiles through LDS so that both orientations read
+// and write whole rows.
+template <int DOM>
+__global__ __launch_bounds__(256) void k_slicesrc(const SliceDesc *D, int nprob) {
+    typedef typename Dom<DOM>::acc A;
+    __shared__ A tile[64][65];
+    const int64_t b = blockIdx.x;
+    const int p = find_problem(D, nprob, b);
+    const SliceDesc &d = D[p];
+    const int64_t local = b - d.tile_start;
+    const int64_t ti = local / d.tiles, tu = local % d.tiles;
+    const int64_t n = d.n, i0 = ti * 64, u0 = tu * 64;
+    const int t = threadIdx.x;
+    const MatRef m = d.src;
+    for (int e = t; e < 4096; e += 256) {
+        int r = e >> 6, c = e & 63;
+        // trans == 0: element (i0 + r, u0 + c) at row i; trans == 1: element
+        // (u0 + r, i0 + c) of the stored matrix, i.e. slice i0 + c, entry u0 + r
+        int64_t a = (m.trans ? u0 : i0) + r, bb = (m.trans ? i0 : u0) + c;
+        A x = (a < n && bb < n) ? load_elem<DOM>(m.p, m.dtype, a * m.ld + bb) : (A)0;
+        if (m.trans) tile[c][r] = x;
+        else tile[r][c] = x;
+    }
+    __syncthreads();
+    for (int e = t; e < 4096; e += 256) {
+        int r = e >> 6, c = e & 63;  // slice i0 + r, entry u0 + c
+        int64_t i = i0 + r, u = u0 + c;
+        if (i >= n || u >= n) continue;
+        A x = tile[r][c];
+        for (int q = 0; q < d.nscale; ++q) x *= load_vec<DOM>(d.scale[q], i);
+        static_cast<A *>(d.out)[i * n + u] = x;
+        if constexpr (DOM == DOM_INT) {
+            if (d.mx_out) atomicMax(d.mx_out, (unsigned long long)(x < 0 ? -x : x));
+        }
+    }
 }
 
 // ----------------------------------------------------------------- launchers
@@ -1034,17 +1080,27 @@ hipError_t launch_absmax_i8(const int8_t *const *src, const int64_t *n, int npro
     return hipGetLastError();
 }
 
-hipError_t launch_combine(const CombineDesc *d, int ndata, const int32_t *scal_off,
+hipError_t launch_slicesrc(const SliceDesc *d, int nprob, int64_t total_tiles, int domain,
+                           hipStream_t s) {
+    if (domain == DOM_FP)
+        hipLaunchKernelGGL(k_slicesrc<DOM_FP>, dim3((unsigned)total_tiles), dim3(256), 0, s, d, nprob);
+    else
+        hipLaunchKernelGGL(k_slicesrc<DOM_INT>, dim3((unsigned)total_tiles), dim3(256), 0, s, d, nprob);
+    return hipGetLastError();
+}
+
+hipError_t launch_combine(const CombineDesc *d, int ndata, const int32_t *term_off,
+                          const int32_t *term_cnt, const int32_t *scal_off,
                           const int32_t *scal_cnt, const int32_t *scal_idx, const int64_t *mu,
-                          const void *scal, void *vout, void *uout, double *sout, int domain,
-                          hipStream_t s) {
+                          const void *scal, void *acc, int first, int last, void *uout,
+                          double *sout, int domain, hipStream_t s) {
     dim3 grid((unsigned)((ndata + 63) / 64));
     if (domain == DOM_FP)
-        hipLaunchKernelGGL(k_combine<DOM_FP>, grid, dim3(64), 0, s, d, ndata, scal_off, scal_cnt,
-                           scal_idx, mu, scal, vout, uout, sout);
+        hipLaunchKernelGGL(k_combine<DOM_FP>, grid, dim3(64), 0, s, d, ndata, term_off, term_cnt,
+                           scal_off, scal_cnt, scal_idx, mu, scal, acc, first, last, uout, sout);
     else
-        hipLaunchKernelGGL(k_combine<DOM_INT>, grid, dim3(64), 0, s, d, ndata, scal_off, scal_cnt,
-                           scal_idx, mu, scal, vout, uout, sout);
+        hipLaunchKernelGGL(k_combine<DOM_INT>, grid, dim3(64), 0, s, d, ndata, term_off, term_cnt,
+                           scal_off, scal_cnt, scal_idx, mu, scal, acc, first, last, uout, sout);
     return hipGetLastError();
 }
 

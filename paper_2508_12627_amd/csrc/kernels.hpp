@@ -17,8 +17,8 @@ enum DType : int32_t { DT_F64 = 0, DT_F32 = 1, DT_I8 = 2, DT_I64 = 3 };
 // integers (int64 values, 128-bit scalars).
 enum Domain : int32_t { DOM_FP = 0, DOM_INT = 1 };
 
-constexpr int kMaxMat = 6;  // matrices per Hadamard group
-constexpr int kMaxVec = 6;  // vectors multiplied on one variable
+constexpr int kMaxMat = 12;  // matrices per Hadamard group
+constexpr int kMaxVec = 12;  // vectors multiplied on one variable
 
 // Matrix operand addressed in its step's canonical orientation (a, b):
 // trans == 0 reads p[a*ld + b], trans == 1 reads p[b*ld + a].  zdiag
@@ -131,12 +131,26 @@ struct GemmDesc {
     unsigned long long *mx_out;  // int8 path: running max |C|, or null
 };
 
-// V_p = prod of scal[idx[off_p .. off_p + cnt_p)], then per dataset d:
-//   U_d = sum_{p in d} mu_p V_p,  S_d = sum |mu_p V_p|
-// (in order of p).  DOM_FP scalars are doubles; DOM_INT scalars are int128
-// stored as two int64 (lo, hi).
+// Per dataset d, for its programs p in order:
+//   V_p = sum over terms t of p (in order) of prod_j scal[term scalars],
+//   acc[p] = (first ? 0 : acc[p]) + V_p,
+// and when `last`: U_d = sum_p mu_p acc[p], S_d = sum_p |mu_p acc[p]|.
+// A program conditioned on one vertex has one term per slice; slices may
+// arrive over several launches (chunks), accumulated in acc in chunk order.
+// DOM_FP scalars are doubles; DOM_INT scalars are int128.
 struct CombineDesc {
     int32_t p_begin, p_end;  // V-statistics of this dataset
+};
+
+// Slice source for conditioning: out[i * n + u] = M(i, u) (trans == 0) or
+// M(u, i) (trans == 1), times prod_q scale_q[i]; accumulation type output.
+struct SliceDesc {
+    MatRef src;
+    int32_t nscale, tiles;
+    const void *scale[kMaxVec];
+    void *out;
+    int64_t n, tile_start;
+    unsigned long long *mx_out;  // DOM_INT: running max |out|, or null
 };
 
 constexpr int kGemmTile = 128;
@@ -158,9 +172,12 @@ hipError_t launch_gemm(const GemmDesc *d, int nprob, int64_t total_tiles, int pr
                        hipStream_t s);
 hipError_t launch_absmax_i8(const int8_t *const *src, const int64_t *n, int nprob,
                             unsigned long long *mx, hipStream_t s);
-hipError_t launch_combine(const CombineDesc *d, int ndata, const int32_t *scal_off,
+hipError_t launch_slicesrc(const SliceDesc *d, int nprob, int64_t total_tiles, int domain,
+                           hipStream_t s);
+hipError_t launch_combine(const CombineDesc *d, int ndata, const int32_t *term_off,
+                          const int32_t *term_cnt, const int32_t *scal_off,
                           const int32_t *scal_cnt, const int32_t *scal_idx, const int64_t *mu,
-                          const void *scal, void *vout, void *uout, double *sout, int domain,
-                          hipStream_t s);
+                          const void *scal, void *acc, int first, int last, void *uout,
+                          double *sout, int domain, hipStream_t s);
 
 }  // namespace ustat

@@ -153,17 +153,39 @@ std::vector<int> minfill_order(int J, std::vector<uint32_t> adj, std::vector<cha
 }  // namespace
 
 std::string lower_order(const std::vector<Edge> &edges, const std::vector<int> &block_of, int J,
-                        const std::vector<int> &order, VProgram &out) {
+                        const std::vector<int> &order, VProgram &out, int slice_var) {
     out.vals.clear();
     out.steps.clear();
     out.scalars.clear();
     out.order = order;
     out.width = 0;
+    out.slice_var = slice_var;
     std::vector<LiveFactor> live;
+    // Conditioning on slice_var: its self-loop diagonals scale one slice
+    // vector (every edge at slice_var becomes a slice vector).
+    std::vector<int> slice_diag;
+    int first_slice = -1;
+    if (slice_var >= 0)
+        for (size_t k = 0; k < edges.size(); ++k) {
+            int a = block_of[edges[k].u], b = block_of[edges[k].v];
+            if (a == slice_var && b == slice_var) slice_diag.push_back((int)k);
+            else if ((a == slice_var || b == slice_var) && first_slice < 0) first_slice = (int)k;
+        }
+    if (slice_var >= 0 && first_slice < 0) return "conditioning on a vertex without edges";
     for (size_t k = 0; k < edges.size(); ++k) {
         int a = block_of[edges[k].u], b = block_of[edges[k].v];
         Value val;
         val.src = (int)k;
+        if (slice_var >= 0 && (a == slice_var || b == slice_var)) {
+            if (a == b) continue;  // folded into the first slice vector
+            val.kind = ValKind::SliceVec;
+            val.r = (a == slice_var) ? b : a;
+            val.c = (a == slice_var) ? 0 : 1;
+            if ((int)k == first_slice) val.scale = slice_diag;
+            live.push_back({(int)out.vals.size(), 1, val.r, -1});
+            out.vals.push_back(val);
+            continue;
+        }
         if (a == b) {
             val.kind = ValKind::InputDiag;
             val.r = a;
@@ -178,14 +200,18 @@ std::string lower_order(const std::vector<Edge> &edges, const std::vector<int> &
         out.vals.push_back(val);
     }
     std::vector<char> gone(J, 0);
+    if (slice_var >= 0) gone[slice_var] = 1;
     std::vector<int> val_level;  // level of each value
     auto level_of = [&](int val) {
         const Value &v = out.vals[val];
-        if (v.kind == ValKind::InputMat || v.kind == ValKind::InputDiag) return 0;
+        if (v.kind == ValKind::InputMat || v.kind == ValKind::InputDiag ||
+            v.kind == ValKind::SliceVec)
+            return 0;
         return out.steps[v.src].level;
     };
     for (int v : order) {
         if (v < 0 || v >= J) return "order names a vertex outside the quotient";
+        if (v == slice_var) continue;
         if (gone[v]) continue;
         std::vector<LiveFactor> touch, keep;
         for (const LiveFactor &f : live) {
@@ -298,6 +324,7 @@ std::string lower_order(const std::vector<Edge> &edges, const std::vector<int> &
 
 void program_cost(const VProgram &p, double n, double elem_bytes, double *flops, double *bytes) {
     double f = 0, b = 0;
+    const double slices = p.slice_var >= 0 ? n : 1.0;
     for (const Step &s : p.steps) {
         switch (s.kind) {
             case StepKind::Elim0:
@@ -317,8 +344,8 @@ void program_cost(const VProgram &p, double n, double elem_bytes, double *flops,
                 break;
         }
     }
-    if (flops) *flops = f;
-    if (bytes) *bytes = b;
+    if (flops) *flops = f * slices;
+    if (bytes) *bytes = b * slices;
 }
 
 std::vector<float> program_features(const VProgram &p, double n) {
@@ -379,12 +406,49 @@ std::string build_program(const std::vector<Edge> &edges, int m, const std::vect
     std::vector<int> mf = minfill_order(J, adj, hasvec);
     auto finish = [&](const std::vector<int> &ord) {
         std::string err = lower_order(edges, block_of, J, ord, out);
-        out.executable = err.empty();
-        out.lower_error = err;
-        if (!err.empty()) {
-            // Keep the order and its width for reporting.
-            out.order = ord;
+        if (err.empty()) {
+            out.executable = true;
+            out.lower_error.clear();
+            return std::string();
         }
+        // Condition on one vertex: try every choice and keep the cheapest
+        // conditioned program whose elimination stays within degree 2.
+        double best = std::numeric_limits<double>::infinity();
+        VProgram keep;
+        for (int c = 0; c < J; ++c) {
+            std::vector<uint32_t> a2 = adj;
+            for (int q = 0; q < J; ++q) a2[q] &= ~(1u << c);
+            a2[c] = 0;
+            std::vector<char> hv = hasvec;
+            for (int q = 0; q < J; ++q)
+                if (adj[c] & (1u << q)) hv[q] = 1;
+            std::vector<int> ord2;
+            for (int v : minfill_order(J, a2, hv))
+                if (v != c) ord2.push_back(v);
+            VProgram cand;
+            cand.block_of = out.block_of;
+            cand.J = out.J;
+            cand.mu = out.mu;
+            cand.tw = out.tw;
+            std::string e2 = lower_order(edges, block_of, J, ord2, cand, c);
+            if (!e2.empty()) continue;
+            double f, b;
+            program_cost(cand, 4096.0, 4.0, &f, &b);
+            if (f < best) {
+                best = f;
+                keep = cand;
+            }
+        }
+        if (best < std::numeric_limits<double>::infinity()) {
+            out = keep;
+            out.width += 1;  // one summed-over conditioned vertex
+            out.executable = true;
+            out.lower_error.clear();
+            return std::string();
+        }
+        out.executable = false;
+        out.lower_error = err;
+        out.order = ord;
         return std::string();
     };
     if (opts.order == 0 || J <= 1) return finish(mf);

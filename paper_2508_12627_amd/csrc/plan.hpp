@@ -20,13 +20,17 @@ enum class ValKind : uint8_t {
     InputDiag,  // diagonal of factor matrix `src` (a self-loop of the quotient)
     Vec,        // n-vector over quotient var `r`, produced by step `src`
     Mat,        // n x n matrix, rows var r, columns var c, produced by step `src`
-    Scalar      // produced by step `src`
+    Scalar,     // produced by step `src`
+    SliceVec    // slice i of factor matrix `src` as a vector over var r: row i
+                // (c == 0, factor stored (slice var, r)) or column i (c == 1);
+                // scaled by the diagonals of the factors in `scale` at i
 };
 
 struct Value {
     ValKind kind;
     int src;  // input factor index or producing step index
     int r, c; // variables (Mat/InputMat: row, col; Vec/InputDiag: r)
+    std::vector<int> scale;  // SliceVec: factors whose diagonal scales slice i
 };
 
 // A matrix operand of an elimination step.  `trans` says how the stored
@@ -69,6 +73,9 @@ struct VProgram {
     int depth = 0;              // max step level
     bool executable = true;     // false when lowering needs a step kind the
     std::string lower_error;    // engine lacks (reason in lower_error)
+    // Conditioning: V_pi = sum_i (V of the quotient with var slice_var fixed
+    // to sample i); -1 when the quotient is eliminated directly.
+    int slice_var = -1;
 };
 
 struct PlanOptions {
@@ -120,7 +127,7 @@ std::string build_program(const std::vector<Edge> &edges, int m, const std::vect
 // Lower a given elimination order to steps (used by build_program and by
 // the ordering search).
 std::string lower_order(const std::vector<Edge> &edges, const std::vector<int> &block_of, int J,
-                        const std::vector<int> &order, VProgram &out);
+                        const std::vector<int> &order, VProgram &out, int slice_var = -1);
 
 // Cost of a program at size n: multiply-add count of contraction steps
 // and minimum bytes touched (elements, scaled by `elem_bytes`).

@@ -65,7 +65,10 @@ EXPORTS = ["ustat_plan_opts_default", "ustat_plan_create", "ustat_plan_destroy",
            "ustat_plan_cost", "ustat_plan_workspace", "ustat_plan_partition", "ustat_plan_order", "ustat_graph_treewidth",
            "ustat_eval", "ustat_eval_samples", "vstat_eval", "ustat_eval_batched",
            "ustat_build_rbf", "ustat_profile_enable", "ustat_profile_reset", "ustat_profile_read",
+           "ustat_order_features", "vstat_eval_ordered", "ustat_mlp_num_params",
+           "ustat_mlp_predict", "ustat_mlp_loss_grad", "ustat_mlp_train", "ustat_mlp_save",
            "ustat_status_string", "ustat_last_error"]
+NUM_FEATURES = 15
 
 
 def load_library(path: str = LIB_PATH):
@@ -96,13 +99,23 @@ def load_library(path: str = LIB_PATH):
     L.ustat_profile_enable.argtypes = [i32]
     L.ustat_profile_reset.argtypes = []
     L.ustat_profile_read.argtypes = [i32, pdbl, pi64, pdbl, pdbl]
+    pf32 = ctypes.POINTER(ctypes.c_float)
+    L.ustat_order_features.argtypes = [P, pi32, pi32, i32, i64, pf32]
+    L.vstat_eval_ordered.argtypes = [P, pi32, pi32, i32, i64, ctypes.POINTER(P), P,
+                                     ctypes.POINTER(Result)]
+    L.ustat_mlp_num_params.argtypes = [i32, i32, i32]
+    L.ustat_mlp_num_params.restype = ctypes.c_size_t
+    L.ustat_mlp_predict.argtypes = [i32, i32, i32, pf32, pf32, i64, pf32]
+    L.ustat_mlp_loss_grad.argtypes = [i32, i32, i32, pf32, pf32, pf32, i64, pdbl, pf32]
+    L.ustat_mlp_train.argtypes = [i32, i32, i32, pf32, pf32, pf32, i64, i32, ctypes.c_float, pdbl]
+    L.ustat_mlp_save.argtypes = [ctypes.c_char_p, i32, i32, i32, pf32]
     L.ustat_status_string.argtypes = [i32]
     L.ustat_status_string.restype = ctypes.c_char_p
     L.ustat_last_error.argtypes = []
     L.ustat_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
         f = getattr(L, name)
-        if f.restype is None or f.restype is ctypes.c_int:
+        if name != "ustat_mlp_num_params" and (f.restype is None or f.restype is ctypes.c_int):
             f.restype = ctypes.c_int
     _lib = L
     return L
@@ -257,6 +270,71 @@ def ustat_profile_read(kind) -> dict:
     _check(load_library().ustat_profile_read(k, ctypes.byref(ms), ctypes.byref(nl), ctypes.byref(fl),
                                              ctypes.byref(by)))
     return {"ms": ms.value, "launches": nl.value, "flops": fl.value, "bytes": by.value}
+
+
+def ustat_order_features(h, block_of, order, n: int):
+    import numpy as np
+    blk = (ctypes.c_int32 * len(block_of))(*[int(b) for b in block_of])
+    od = (ctypes.c_int32 * len(order))(*[int(o) for o in order])
+    out = np.zeros(NUM_FEATURES, dtype=np.float32)
+    _check(load_library().ustat_order_features(h, blk, od, len(order), int(n),
+                                               out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+    return out
+
+
+def vstat_eval_ordered(h, block_of, order, n: int, factors, stream=None) -> Result:
+    blk = (ctypes.c_int32 * len(block_of))(*[int(b) for b in block_of])
+    od = (ctypes.c_int32 * len(order))(*[int(o) for o in order])
+    r = Result()
+    _check(load_library().vstat_eval_ordered(h, blk, od, len(order), int(n), _factor_ptrs(factors),
+                                             _stream_handle(stream), ctypes.byref(r)))
+    return r
+
+
+def _f32p(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def ustat_mlp_num_params(F: int, H1: int, H2: int) -> int:
+    return int(load_library().ustat_mlp_num_params(F, H1, H2))
+
+
+def ustat_mlp_predict(F, H1, H2, params, X):
+    import numpy as np
+    params = np.ascontiguousarray(params, dtype=np.float32)
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    out = np.zeros(X.shape[0], dtype=np.float32)
+    _check(load_library().ustat_mlp_predict(F, H1, H2, _f32p(params), _f32p(X), X.shape[0], _f32p(out)))
+    return out
+
+
+def ustat_mlp_loss_grad(F, H1, H2, params, X, y):
+    import numpy as np
+    params = np.ascontiguousarray(params, dtype=np.float32)
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    y = np.ascontiguousarray(y, dtype=np.float32)
+    g = np.zeros_like(params)
+    loss = ctypes.c_double()
+    _check(load_library().ustat_mlp_loss_grad(F, H1, H2, _f32p(params), _f32p(X), _f32p(y), X.shape[0],
+                                              ctypes.byref(loss), _f32p(g)))
+    return loss.value, g
+
+
+def ustat_mlp_train(F, H1, H2, params, X, y, steps: int, lr: float):
+    import numpy as np
+    p = np.array(params, dtype=np.float32, copy=True)
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    y = np.ascontiguousarray(y, dtype=np.float32)
+    losses = np.zeros(steps, dtype=np.float64)
+    _check(load_library().ustat_mlp_train(F, H1, H2, _f32p(p), _f32p(X), _f32p(y), X.shape[0], steps,
+                                          float(lr), losses.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return p, losses
+
+
+def ustat_mlp_save(path: str, F, H1, H2, params):
+    import numpy as np
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    _check(load_library().ustat_mlp_save(path.encode(), F, H1, H2, _f32p(p)))
 
 
 # ------------------------------------------------------------------ wrapper

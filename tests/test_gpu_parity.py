@@ -321,3 +321,55 @@ def test_batched_large_ragged(U):
         singles = [P.eval_samples(X, div, stream=s) for X in Xd]
     for i in range(len(ns)):
         assert rb[i].value == singles[i].value
+
+
+K4 = [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)]
+
+
+@pytest.mark.parametrize("prec", ["f64", "bf16x3"])
+def test_conditioned_treewidth3_small(U, prec):
+    """Quotients of treewidth 3 are evaluated by conditioning on one vertex
+    (a sum over its n values of width-2 eliminations): K4 and random m = 6
+    workload graphs against brute force."""
+    import torch
+    graphs = [K4] + W.random_kernel_graphs(3, 6, 6, 10, seed=5)
+    for edges in graphs:
+        m = nverts(edges)
+        n = {4: 37, 6: 13}[m]
+        P = U.Plan(m, edges, precision=prec)
+        assert P.info()["M"] >= 3
+        mats = W.random_matrices(len(edges), n, seed=8, lo=0.0, hi=1.0)
+        ref = oracle.ustat_bruteforce(edges, mats)
+        say(f"conditioned {prec} m={m} n={n} edges={edges}")
+        r = P.eval([dev(M, P.factor_dtype) for M in mats])
+        assert abs(r.value - ref) <= TOL[prec] * r.err_scale
+
+
+def test_conditioned_exact_and_chunked(U):
+    """Exact int8 counts through conditioning, and slice chunking giving the
+    same result: a workspace limit equal to the one-slice workspace forces one
+    slice per chunk, three times it a few slices per chunk with a ragged last
+    chunk; a limit below the one-slice workspace is rejected as infeasible."""
+    import torch
+    A = W.erdos_renyi(40, 0.3, seed=9).astype(np.int64)
+    Ad = dev(A, torch.int8)
+    ref = oracle.ustat_bruteforce_int(K4, [A] * 6)
+    say("conditioned int8 K4 n=40")
+    r = U.Plan(4, K4, precision="i8").eval([Ad] * 6)
+    assert r.exact == ref
+    ws1 = U.Plan(4, K4, precision="i8").workspace([40])
+    for lim in (ws1, 3 * ws1):
+        say(f"conditioned int8 K4 n=40 workspace_limit={lim}")
+        r2 = U.Plan(4, K4, precision="i8", workspace_limit=lim).eval([Ad] * 6)
+        assert r2.exact == ref
+    with pytest.raises(U.UstatError) as ei:
+        U.Plan(4, K4, precision="i8", workspace_limit=1).eval([Ad] * 6)
+    assert ei.value.code == 6
+    X = W.gaussian_samples(150, 4, seed=3)
+    Xd = dev(X, torch.float64)
+    a = U.Plan(4, K4, precision="f64").eval_samples(Xd, 8.0)
+    ws1 = U.Plan(4, K4, precision="f64").workspace([150])
+    for lim in (ws1, 3 * ws1):
+        say(f"conditioned f64 K4 n=150 workspace_limit={lim}")
+        b = U.Plan(4, K4, precision="f64", workspace_limit=lim).eval_samples(Xd, 8.0)
+        assert abs(a.value - b.value) <= 1e-12 * a.err_scale
