@@ -181,6 +181,61 @@ def bench_cycle5_exact(args):
     print(json.dumps(out))
 
 
+def bench_learned_order(args):
+    """Learned order choice, end to end.  64 random kernel graphs on 6
+    vertices (6-10 edges, seed 5, draws with an isolated vertex rejected);
+    graphs whose largest quotient treewidth M is 4 are skipped, M <= 2
+    graphs run at n = 8192 and M = 3 graphs (conditioned steps, n^4 work)
+    at n = 2048; x iid N(0, I_16), RBF divisor 32, split-bf16x3.  For each
+    order policy the time is plan creation plus the first evaluation, and
+    the U values of the policies must agree."""
+    import torch
+    from paper_2508_12627_amd import ustat as U, workloads as W
+    graphs = W.random_kernel_graphs(64, 6, 6, 10, seed=5)
+    lo, hi = (int(x) for x in args.graph_range.split(":"))
+    policies = ["minfill", "exhaustive", "learned"]
+    tot = {p: 0.0 for p in policies}
+    per, skipped, worst = [], [], 0.0
+    xs = {}
+    for gi in range(lo, min(hi, len(graphs))):
+        edges = graphs[gi]
+        M = U.Plan(6, edges).info()["M"]
+        if M > 3:
+            skipped.append(gi)
+            continue
+        n = 8192 if M <= 2 else 2048
+        if n not in xs:
+            xs[n] = torch.tensor(W.gaussian_samples(n, 16, seed=50), dtype=torch.float64,
+                                 device="cuda")
+        rec = {"graph": gi, "M": M, "n": n}
+        vals = {}
+        for pol in policies:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            P = U.Plan(6, edges, precision="bf16x3", order=pol, n_hint=n)
+            r = P.eval_samples(xs[n], 32.0)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            tot[pol] += el
+            rec[pol + "_s"] = el
+            vals[pol] = (r.value, r.err_scale)
+            del P
+        S = vals["minfill"][1]
+        dev = max(abs(v[0] - vals["minfill"][0]) for v in vals.values()) / S
+        worst = max(worst, dev)
+        rec["max_policy_diff_over_S"] = dev
+        per.append(rec)
+        print(json.dumps(rec), file=sys.stderr, flush=True)
+    out = {"metric": "end-to-end seconds (plan + eval) over the graphs, per order policy",
+           "unit": "s", "higher_is_better": False,
+           "config": {"workload": "64 random 6-vertex kernel graphs (6-10 edges, seed 5), "
+                                  "203 restricted V-statistics each; n=8192 (M<=2) / 2048 (M=3), "
+                                  "d=16, bf16x3", "graphs": f"{lo}:{hi}"},
+           "value": tot["learned"], "totals_s": tot, "skipped_M4": skipped,
+           "max_policy_diff_over_S": worst, "graphs_run": len(per), "per_graph": per}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -191,10 +246,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--workload", default="cycle4",
-                    choices=["cycle4", "batched", "cycle5-exact"],
+                    choices=["cycle4", "batched", "cycle5-exact", "learned-order"],
                     help="cycle4: the headline line; the others print their own line")
+    ap.add_argument("--graph-range", default="0:64",
+                    help="learned-order workload: graphs lo:hi of the 64")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many plain steps (for external profilers)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-mebibyte device buffer 4 times (the reference "
+                         "kernel for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this engine has no multi-GPU path "
@@ -206,10 +266,21 @@ def main():
     from paper_2508_12627_amd import ustat as U, workloads as W
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        nb = args.calibrate_copy << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": nb, "launches": 4}))
+        return
     if args.workload == "batched":
         return bench_batched(args)
     if args.workload == "cycle5-exact":
         return bench_cycle5_exact(args)
+    if args.workload == "learned-order":
+        return bench_learned_order(args)
     m, edges, n, d = WORKLOAD["m"], WORKLOAD["edges"], WORKLOAD["n"], WORKLOAD["d"]
     div = 2.0 * d
     Xh = W.gaussian_samples(n, d, seed=WORKLOAD["seed"])

@@ -91,6 +91,8 @@ typedef struct {
     int32_t flags;              /* USTAT_FLAG_* bits, 0 by default          */
     uint64_t workspace_limit;   /* bytes of device workspace, 0 = no limit  */
     const char *cost_model_path;/* weights file for USTAT_ORDER_LEARNED     */
+    int64_t n_hint;             /* sample size the exhaustive and learned
+                                   order policies rank for, 0 = 4096        */
 } ustat_plan_opts;
 
 typedef struct {
@@ -164,9 +166,13 @@ ustat_status ustat_plan_partition(ustat_plan plan, int32_t idx, int32_t *block_o
 /*
  * Elimination order chosen for partition idx: order (host int32 array of
  * at least m entries) receives the quotient vertices in elimination order;
- * *len their number.
+ * *len their number.  *slice_var is -1, or the quotient vertex the program
+ * conditions on when no order stays within degree 2 (its n values are
+ * summed outside the elimination, which then lists the other vertices).
+ * Any output pointer may be NULL.
  */
-ustat_status ustat_plan_order(ustat_plan plan, int32_t idx, int32_t *order, int32_t *len);
+ustat_status ustat_plan_order(ustat_plan plan, int32_t idx, int32_t *order, int32_t *len,
+                              int32_t *slice_var);
 
 /* Exact treewidth of the simple graph underlying an edge list (m <= 16);
  * self-loops and repeated edges are ignored (Definition "Treewidth"). */
@@ -237,20 +243,23 @@ ustat_status ustat_profile_read(int32_t kind, double *ms, int64_t *launches, dou
 
 /*
  * Features of partition block_of (any labelling) eliminated in the given
- * order (quotient vertices, labels as in ustat_plan_order; len = number of
- * quotient vertices) at sample size n: feat (host float array of at least
- * USTAT_NUM_FEATURES entries) receives step-kind counts, operand and
- * transposition counts, dependency depth, width and log-size terms.
- * USTAT_E_UNSUPPORTED if the order needs a step of degree above 2.
+ * order (quotient vertices, labels as in ustat_plan_order) at sample size
+ * n.  slice_var is -1 (order lists all len = J quotient vertices) or a
+ * vertex to condition on (order lists the other len = J - 1 vertices).
+ * feat (host float array of at least USTAT_NUM_FEATURES entries) receives
+ * step-kind counts, operand and transposition counts, dependency depth,
+ * width (conditioning counts one) and log-size terms.  USTAT_E_UNSUPPORTED
+ * if the order needs a step of degree above 2.
  */
 #define USTAT_NUM_FEATURES 15
 ustat_status ustat_order_features(ustat_plan plan, const int32_t *block_of, const int32_t *order,
-                                  int32_t len, int64_t n, float *feat);
+                                  int32_t len, int32_t slice_var, int64_t n, float *feat);
 
-/* vstat_eval with an explicit elimination order (as above). */
+/* vstat_eval with an explicit elimination order (arguments as above). */
 ustat_status vstat_eval_ordered(ustat_plan plan, const int32_t *block_of, const int32_t *order,
-                                int32_t len, int64_t n, const void *const *factors,
-                                ustat_stream stream, ustat_result *out);
+                                int32_t len, int32_t slice_var, int64_t n,
+                                const void *const *factors, ustat_stream stream,
+                                ustat_result *out);
 
 /*
  * Cost-model MLP, F -> H1 -> H2 -> 1 with ReLU hidden layers, on the GPU

@@ -156,6 +156,8 @@ ustat_status ustat_plan_create(int32_t m, int32_t num_edges, const int32_t *edge
         po.order = o.order;
         po.sparsify = o.sparsify;
         po.workspace_limit = o.workspace_limit;
+        if (o.n_hint < 0 || o.n_hint > (1ll << 20)) return fail(USTAT_E_INVALID, "n_hint out of range");
+        if (o.n_hint > 0) po.n_hint = (double)o.n_hint;
         po.cse = !(o.flags & USTAT_FLAG_NO_CSE);
         if (o.cost_model_path) po.cost_model_path = o.cost_model_path;
         const OrderScorer *scorer = nullptr;
@@ -241,7 +243,8 @@ ustat_status ustat_plan_partition(ustat_plan plan, int32_t idx, int32_t *block_o
     return ok();
 }
 
-ustat_status ustat_plan_order(ustat_plan plan, int32_t idx, int32_t *order, int32_t *len) {
+ustat_status ustat_plan_order(ustat_plan plan, int32_t idx, int32_t *order, int32_t *len,
+                              int32_t *slice_var) {
     if (!plan) return fail(USTAT_E_INVALID, "plan is NULL");
     if (idx < 0 || idx >= (int32_t)plan->plan.progs.size())
         return fail(USTAT_E_INVALID, "partition index out of range");
@@ -249,6 +252,7 @@ ustat_status ustat_plan_order(ustat_plan plan, int32_t idx, int32_t *order, int3
     if (order)
         for (size_t i = 0; i < p.order.size(); ++i) order[i] = p.order[i];
     if (len) *len = (int32_t)p.order.size();
+    if (slice_var) *slice_var = p.slice_var;
     return ok();
 }
 
@@ -401,30 +405,34 @@ ustat_status vstat_eval(ustat_plan plan, const int32_t *block_of, int64_t n,
 }
 
 static ustat_status lower_given(ustat_plan plan, const int32_t *block_of, const int32_t *order,
-                                int32_t len, VProgram &prog) {
-    if (!plan || !block_of || !order) return fail(USTAT_E_INVALID, "NULL argument");
+                                int32_t len, int32_t slice_var, VProgram &prog) {
+    if (!plan || !block_of || (!order && len > 0)) return fail(USTAT_E_INVALID, "NULL argument");
     std::vector<int> rgs;
     canonical_rgs(block_of, plan->plan.m, rgs);
     int J = 0;
     for (int b : rgs) J = std::max(J, b + 1);
-    if (len != J) return fail(USTAT_E_INVALID, "order length must equal the number of blocks");
+    if (slice_var < -1 || slice_var >= J) return fail(USTAT_E_INVALID, "slice_var out of range");
+    const int want = slice_var >= 0 ? J - 1 : J;
+    if (len != want)
+        return fail(USTAT_E_INVALID, "order must list every block (but the conditioned one)");
     std::vector<int> ord(order, order + len), chk = ord;
+    if (slice_var >= 0) chk.push_back(slice_var);
     std::sort(chk.begin(), chk.end());
     for (int i = 0; i < J; ++i)
         if (chk[i] != i) return fail(USTAT_E_INVALID, "order is not a permutation of the blocks");
     prog.block_of = rgs;
     prog.J = J;
     prog.mu = mobius_mu(rgs);
-    std::string err = lower_order(plan->plan.edges, rgs, J, ord, prog);
+    std::string err = lower_order(plan->plan.edges, rgs, J, ord, prog, slice_var);
     if (!err.empty()) return fail(USTAT_E_UNSUPPORTED, err);
     return USTAT_OK;
 }
 
 ustat_status ustat_order_features(ustat_plan plan, const int32_t *block_of, const int32_t *order,
-                                  int32_t len, int64_t n, float *feat) {
+                                  int32_t len, int32_t slice_var, int64_t n, float *feat) {
     if (!feat || n < 1) return fail(USTAT_E_INVALID, "bad arguments");
     VProgram prog;
-    ustat_status st = lower_given(plan, block_of, order, len, prog);
+    ustat_status st = lower_given(plan, block_of, order, len, slice_var, prog);
     if (st != USTAT_OK) return st;
     std::vector<float> f = program_features(prog, (double)n);
     if ((int)f.size() != USTAT_NUM_FEATURES) return fail(USTAT_E_INVALID, "feature size mismatch");
@@ -433,12 +441,13 @@ ustat_status ustat_order_features(ustat_plan plan, const int32_t *block_of, cons
 }
 
 ustat_status vstat_eval_ordered(ustat_plan plan, const int32_t *block_of, const int32_t *order,
-                                int32_t len, int64_t n, const void *const *factors,
-                                ustat_stream stream, ustat_result *out) {
+                                int32_t len, int32_t slice_var, int64_t n,
+                                const void *const *factors, ustat_stream stream,
+                                ustat_result *out) {
     if (!factors || !out) return fail(USTAT_E_INVALID, "NULL argument");
     if (n < 1 || n > (1ll << 20)) return fail(USTAT_E_INVALID, "n out of range");
     VProgram prog;
-    ustat_status st = lower_given(plan, block_of, order, len, prog);
+    ustat_status st = lower_given(plan, block_of, order, len, slice_var, prog);
     if (st != USTAT_OK) return st;
     for (size_t k = 0; k < plan->plan.edges.size(); ++k)
         if (!factors[k]) return fail(USTAT_E_INVALID, "a factor pointer is NULL");

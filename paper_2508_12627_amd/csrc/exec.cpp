@@ -267,11 +267,11 @@ struct Ref {  // a program value resolved to a node or an input
     int64_t off = 0;    // slice row offset (slice vectors)
 };
 
-std::string ptr_id(const void *p) {
-    char b[32];
-    snprintf(b, sizeof b, "%p", p);
-    return b;
-}
+// Fixed-width binary key fragments (keys are only compared and hashed):
+// every fragment starts with a tag byte that never equals a separator, so
+// concatenations stay unambiguous.
+std::string ptr_id(const void *p) { return std::string(reinterpret_cast<const char *>(&p), sizeof p); }
+std::string int_id(int64_t v) { return std::string(reinterpret_cast<const char *>(&v), sizeof v); }
 
 struct Dag {
     std::vector<Node> nodes;
@@ -285,11 +285,11 @@ struct Dag {
 };
 
 std::string mop_sig(const MOp &m) {
-    return (m.node < 0 ? "I" + ptr_id(m.p) : "N" + std::to_string(m.node)) + (m.trans ? "t" : "n");
+    return (m.node < 0 ? "I" + ptr_id(m.p) : "N" + int_id(m.node)) + (m.trans ? "t" : "n");
 }
 std::string vop_sig(const VOp &v) {
-    std::string s = v.node < 0 ? "D" + ptr_id(v.p) : "N" + std::to_string(v.node);
-    if (v.off) s += "+" + std::to_string(v.off);
+    std::string s = v.node < 0 ? "D" + ptr_id(v.p) : "N" + int_id(v.node);
+    if (v.off) s += "+" + int_id(v.off);
     return s;
 }
 template <class T, class F>
@@ -329,7 +329,7 @@ MOp direct(Dag &G, const MOp &o, bool want_trans, int d, int64_t n, bool cse) {
     t.d = d;
     t.n = n;
     t.A.push_back(MOp{o.node, o.p, false});
-    std::string key = "T|" + std::to_string(n) + "|" + (o.node < 0 ? "I" + ptr_id(o.p) : "N" + std::to_string(o.node));
+    std::string key = "T|" + std::to_string(n) + "|" + (o.node < 0 ? "I" + ptr_id(o.p) : "N" + int_id(o.node));
     int id = add_node(G, t, key, cse);
     return MOp{id, nullptr, want_trans};
 }
@@ -359,6 +359,98 @@ std::string gemm_key(int64_t n, const std::vector<MOp> &A, const std::vector<VOp
     return "G" + std::to_string(n) + "|" + sa + "|" + ss + "|" + sb;
 }
 
+// Replicates the first slice of every conditioned program over the other
+// slices of the range.  A node depends on the slice when it reads a slice
+// source vector or a node that does; slice-independent nodes stay shared.
+// Each clone reads the clones of its slice-dependent inputs and the slice
+// source at the next row offset, so slice s + k is the first slice's
+// computation with the conditioned index advanced by k.
+template <class Inst>
+void clone_slices(Dag &G, const std::vector<Inst> &insts) {
+    const int T = (int)G.nodes.size();
+    auto slice_vop = [&](const VOp &v) { return v.node >= 0 && G.nodes[v.node].kind == NK::SliceSrc; };
+    std::vector<char> dep(T, 0);
+    for (int i = 0; i < T; ++i) {
+        const Node &x = G.nodes[i];
+        bool dd = false;
+        auto m = [&](int id) { dd = dd || (id >= 0 && dep[id]); };
+        for (auto *g : {&x.A, &x.B, &x.Z})
+            for (auto &o : *g) m(o.node);
+        for (auto *g : {&x.sv, &x.aw, &x.bx})
+            for (auto &o : *g) {
+                m(o.node);
+                dd = dd || slice_vop(o);
+            }
+        dep[i] = dd;
+    }
+    // per dataset: its slice-dependent nodes (reachable from the first
+    // slice's terms) in creation order, which is topological
+    std::map<int, std::vector<int>> tmpl;
+    std::map<int, int64_t> extra;
+    {
+        std::map<int, std::vector<char>> seen;
+        for (const Inst &si : insts) {
+            extra[si.d] = std::max(extra[si.d], si.extra);
+            std::vector<char> &sn = seen[si.d];
+            sn.resize(T, 0);
+            std::vector<int> stack;
+            for (int id : G.prog_terms[si.dp][0])
+                if (dep[id]) stack.push_back(id);
+            while (!stack.empty()) {
+                int id = stack.back();
+                stack.pop_back();
+                if (sn[id]) continue;
+                sn[id] = 1;
+                const Node &x = G.nodes[id];
+                auto push = [&](int u) {
+                    if (u >= 0 && dep[u] && !sn[u]) stack.push_back(u);
+                };
+                for (auto *g : {&x.A, &x.B, &x.Z})
+                    for (auto &o : *g) push(o.node);
+                for (auto *g : {&x.sv, &x.aw, &x.bx})
+                    for (auto &o : *g) push(o.node);
+            }
+        }
+        for (auto &kv : seen)
+            for (int i = 0; i < T; ++i)
+                if (kv.second[i]) tmpl[kv.first].push_back(i);
+    }
+    int64_t max_extra = 0;
+    for (auto &kv : extra) max_extra = std::max(max_extra, kv.second);
+    std::vector<int> cmap(T, -1);
+    for (int64_t k = 1; k <= max_extra; ++k) {
+        std::fill(cmap.begin(), cmap.end(), -1);
+        for (auto &kv : tmpl) {
+            if (k > extra[kv.first]) continue;
+            for (int t : kv.second) {
+                if (cmap[t] >= 0) continue;
+                Node c = G.nodes[t];
+                auto rm = [&](int &id) {
+                    if (id >= 0 && id < T && dep[id]) id = cmap[id];
+                };
+                for (auto *g : {&c.A, &c.B, &c.Z})
+                    for (auto &o : *g) rm(o.node);
+                for (auto *g : {&c.sv, &c.aw, &c.bx})
+                    for (auto &o : *g) {
+                        if (slice_vop(o)) o.off += k * c.n;
+                        rm(o.node);
+                    }
+                c.level = node_level(G, c);
+                c.last_use = 0;
+                cmap[t] = (int)G.nodes.size();
+                G.nodes.push_back(std::move(c));
+            }
+        }
+        for (const Inst &si : insts) {
+            if (k > si.extra) continue;
+            std::vector<int> term = G.prog_terms[si.dp][0];
+            for (int &id : term)
+                if (dep[id]) id = cmap[id];
+            G.prog_terms[si.dp].push_back(std::move(term));
+        }
+    }
+}
+
 std::string build_dag(const Plan &plan, const std::vector<const VProgram *> &progs,
                       const std::vector<Dataset> &data, bool cse, const SliceRange &range, Dag &G) {
     const int nd = (int)data.size(), np = (int)progs.size();
@@ -374,6 +466,13 @@ std::string build_dag(const Plan &plan, const std::vector<const VProgram *> &pro
     };
     std::vector<Pending> pending;
     std::unordered_map<std::string, int> gkey_count;
+    // Conditioned programs: only the first slice of the range is built with
+    // CSE keys; the other slices are clones of its slice-dependent nodes.
+    struct SlicedInst {
+        int dp, d;
+        int64_t extra;  // slices after the first one in the range
+    };
+    std::vector<SlicedInst> sliced_insts;
     auto use_diag = [&](int d, const void *ptr) {
         auto key = std::make_pair(d, ptr);
         if (!G.diag_index.count(key)) {
@@ -389,7 +488,8 @@ std::string build_dag(const Plan &plan, const std::vector<const VProgram *> &pro
           if (!sliced && !range.include_unsliced) continue;
           const int64_t s_lo = sliced ? std::max<int64_t>(0, range.lo) : -1;
           const int64_t s_hi = sliced ? std::min<int64_t>(n, range.hi) : 0;
-          for (int64_t slice = s_lo; slice < s_hi; ++slice) {
+          if (sliced && s_hi - s_lo > 1) sliced_insts.push_back({d * np + p, d, s_hi - s_lo - 1});
+          for (int64_t slice = s_lo; slice < std::min(s_hi, s_lo + 1); ++slice) {
             std::vector<Ref> ref(pr.vals.size());
             for (size_t v = 0; v < pr.vals.size(); ++v) {
                 const Value &val = pr.vals[v];
@@ -561,6 +661,7 @@ std::string build_dag(const Plan &plan, const std::vector<const VProgram *> &pro
         }
         G.prog_terms[pd.dp][pd.term][pd.pos] = sid;
     }
+    if (!sliced_insts.empty()) clone_slices(G, sliced_insts);
     // last uses
     for (auto &nd : G.nodes) {
         auto use = [&](int id) {
@@ -1196,22 +1297,33 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
         for (size_t i = 0; i < cnt; ++i)
             in_bound[i] = (double)reinterpret_cast<unsigned long long *>(rt.hres)[i];
     }
+    // The layout is deterministic: build once against the arena already
+    // held and keep the result when it fits; otherwise size it, grow the
+    // arena and build again with the new base.
     Schedule S;
-    std::string err = build_schedule(plan, progs, data, cfg, in_bound, nullptr, S, status, range);
-    if (!err.empty()) return err;
+    std::string err;
+    bool built = false;
+    if (rt.arena) {
+        err = build_schedule(plan, progs, data, cfg, in_bound, rt.arena, S, status, range);
+        if (!err.empty()) return err;
+        built = S.arena_bytes <= rt.arena_bytes;
+    } else {
+        err = build_schedule(plan, progs, data, cfg, in_bound, nullptr, S, status, range);
+        if (!err.empty()) return err;
+    }
     if (plan.opts.workspace_limit && S.arena_bytes > plan.opts.workspace_limit) {
         *status = 6;
         return "workspace of " + std::to_string(S.arena_bytes) + " bytes exceeds the limit";
     }
-    {
+    if (!built) {
         hipError_t e = rt.reserve_arena(S.arena_bytes);
         if (e != hipSuccess) {
             *status = 3;
             return std::string("device workspace allocation failed: ") + hipGetErrorString(e);
         }
+        err = build_schedule(plan, progs, data, cfg, in_bound, rt.arena, S, status, range);
+        if (!err.empty()) return err;
     }
-    err = build_schedule(plan, progs, data, cfg, in_bound, rt.arena, S, status, range);
-    if (!err.empty()) return err;
     // room for the blob and, behind it, the staged input maxima (reserved
     // before any asynchronous copy reads the pinned buffer)
     HIPCHK(rt.reserve_desc(up(S.blob_bytes, 64) + S.n_inmx * 8 + 1024));

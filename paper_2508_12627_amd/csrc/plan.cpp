@@ -318,6 +318,7 @@ std::string lower_order(const std::vector<Edge> &edges, const std::vector<int> &
     if (!live.empty()) return "elimination order left factors unconsumed";
     out.depth = 0;
     for (const Step &s : out.steps) out.depth = std::max(out.depth, s.level);
+    if (slice_var >= 0) out.width += 1;  // the summed-over conditioned vertex
     (void)val_level;
     return "";
 }
@@ -403,18 +404,71 @@ std::string build_program(const std::vector<Edge> &edges, int m, const std::vect
     std::vector<char> hasvec(J, 0);
     for (const Edge &e : edges)
         if (block_of[e.u] == block_of[e.v]) hasvec[block_of[e.u]] = 1;
+    const double nref = opts.n_hint;
+    // Ranking key of a lowered program: the learned model's predicted
+    // log-time, else a time proxy (MFMA work plus memory traffic plus a
+    // per-level launch latency, in seconds at nominal rates; among equal
+    // proxies, contractions of input factors without diagonal scaling are
+    // preferred, since they can be shared across partitions).
+    auto rank_key = [&](const VProgram &p) {
+        if (opts.order == 2 && scorer) return scorer->score(program_features(p, nref));
+        double f, b;
+        program_cost(p, nref, 4.0, &f, &b);
+        const double slices = p.slice_var >= 0 ? nref : 1.0;
+        return f / 100e12 + b / 5e12 + slices * p.depth * 8e-6 + 1e-9 * sharing_penalty(p);
+    };
+    auto keep_program = [&](VProgram &p) {
+        p.block_of = out.block_of;
+        p.J = out.J;
+        p.mu = out.mu;
+        p.tw = out.tw;
+        p.executable = true;
+        p.lower_error.clear();
+        out = std::move(p);
+    };
+    // Plain orders first.  Min-fill takes its own order; exhaustive and
+    // learned policies enumerate every order (J <= 8) and keep the best key
+    // among the orders of smallest width (the width sets the power of n in
+    // the work, so ranking is only among equal-width orders).
     std::vector<int> mf = minfill_order(J, adj, hasvec);
-    auto finish = [&](const std::vector<int> &ord) {
-        std::string err = lower_order(edges, block_of, J, ord, out);
-        if (err.empty()) {
-            out.executable = true;
-            out.lower_error.clear();
-            return std::string();
-        }
-        // Condition on one vertex: try every choice and keep the cheapest
-        // conditioned program whose elimination stays within degree 2.
+    const bool search = opts.order != 0 && J > 1 && J <= 8;
+    std::string first_err;
+    {
+        VProgram best_p;
         double best = std::numeric_limits<double>::infinity();
-        VProgram keep;
+        int best_w = std::numeric_limits<int>::max();
+        std::vector<int> perm(J);
+        std::iota(perm.begin(), perm.end(), 0);
+        const std::vector<int> &start = search ? perm : mf;
+        std::vector<int> cur = start;
+        do {
+            VProgram tmp;
+            std::string err = lower_order(edges, block_of, J, cur, tmp);
+            if (!err.empty()) {
+                if (first_err.empty()) first_err = err;
+                continue;
+            }
+            if (tmp.width > best_w) continue;
+            double key = search ? rank_key(tmp) : 0.0;
+            if (tmp.width < best_w || key < best - 1e-15) {
+                best_w = tmp.width;
+                best = key;
+                best_p = std::move(tmp);
+            }
+        } while (search && std::next_permutation(cur.begin(), cur.end()));
+        if (std::isfinite(best)) {
+            keep_program(best_p);
+            return "";
+        }
+    }
+    // No order stays within degree 2: condition on one vertex c (sum over
+    // its n values outside the program) and eliminate the rest.  Min-fill
+    // tries min-fill orders of the graph without c for every c and keeps the
+    // smallest work; the search policies rank every (c, order) pair.
+    {
+        VProgram best_p;
+        double best = std::numeric_limits<double>::infinity();
+        int best_w = std::numeric_limits<int>::max();
         for (int c = 0; c < J; ++c) {
             std::vector<uint32_t> a2 = adj;
             for (int q = 0; q < J; ++q) a2[q] &= ~(1u << c);
@@ -422,65 +476,42 @@ std::string build_program(const std::vector<Edge> &edges, int m, const std::vect
             std::vector<char> hv = hasvec;
             for (int q = 0; q < J; ++q)
                 if (adj[c] & (1u << q)) hv[q] = 1;
-            std::vector<int> ord2;
-            for (int v : minfill_order(J, a2, hv))
-                if (v != c) ord2.push_back(v);
-            VProgram cand;
-            cand.block_of = out.block_of;
-            cand.J = out.J;
-            cand.mu = out.mu;
-            cand.tw = out.tw;
-            std::string e2 = lower_order(edges, block_of, J, ord2, cand, c);
-            if (!e2.empty()) continue;
-            double f, b;
-            program_cost(cand, 4096.0, 4.0, &f, &b);
-            if (f < best) {
-                best = f;
-                keep = cand;
+            std::vector<int> rest;
+            if (search) {
+                for (int q = 0; q < J; ++q)
+                    if (q != c) rest.push_back(q);
+            } else {
+                for (int v : minfill_order(J, a2, hv))
+                    if (v != c) rest.push_back(v);
             }
+            do {
+                VProgram cand;
+                if (!lower_order(edges, block_of, J, rest, cand, c).empty()) continue;
+                if (cand.width > best_w) continue;
+                double key;
+                if (search) {
+                    key = rank_key(cand);
+                } else {
+                    double f, b;
+                    program_cost(cand, nref, 4.0, &f, &b);
+                    key = f;
+                }
+                if (cand.width < best_w || key < best - 1e-15) {
+                    best_w = cand.width;
+                    best = key;
+                    best_p = std::move(cand);
+                }
+            } while (search && std::next_permutation(rest.begin(), rest.end()));
         }
-        if (best < std::numeric_limits<double>::infinity()) {
-            out = keep;
-            out.width += 1;  // one summed-over conditioned vertex
-            out.executable = true;
-            out.lower_error.clear();
-            return std::string();
+        if (std::isfinite(best)) {
+            keep_program(best_p);
+            return "";
         }
-        out.executable = false;
-        out.lower_error = err;
-        out.order = ord;
-        return std::string();
-    };
-    if (opts.order == 0 || J <= 1) return finish(mf);
-    // Exhaustive or learned: enumerate every order (J <= 8) and keep the best.
-    if (J > 8) return finish(mf);
-    std::vector<int> perm(J);
-    std::iota(perm.begin(), perm.end(), 0);
-    const double nref = 4096.0;
-    double best = std::numeric_limits<double>::infinity();
-    std::vector<int> best_order = mf;
-    VProgram tmp;
-    do {
-        std::string err = lower_order(edges, block_of, J, perm, tmp);
-        if (!err.empty()) continue;
-        double key;
-        if (opts.order == 2 && scorer) {
-            key = scorer->score(program_features(tmp, nref));
-        } else {
-            double f, b;
-            program_cost(tmp, nref, 4.0, &f, &b);
-            // Time proxy: MFMA work plus memory traffic plus a per-level
-            // launch latency, in seconds at nominal rates; among equal
-            // proxies, prefer contractions of input factors without diagonal
-            // scaling (shareable across partitions).
-            key = f / 100e12 + b / 5e12 + tmp.depth * 8e-6 + 1e-9 * sharing_penalty(tmp);
-        }
-        if (key < best - 1e-15) {
-            best = key;
-            best_order = perm;
-        }
-    } while (std::next_permutation(perm.begin(), perm.end()));
-    return finish(best_order);
+    }
+    out.executable = false;
+    out.lower_error = first_err;
+    out.order = mf;
+    return "";
 }
 
 std::string make_plan(int m, const std::vector<Edge> &edges, const PlanOptions &opts,

@@ -85,6 +85,7 @@ struct PlanOptions {
     bool cse = true;  // merge equal steps across partitions at evaluation
     uint64_t workspace_limit = 0;
     std::string cost_model_path;
+    double n_hint = 4096.0;  // sample size orders are ranked for
 };
 
 // Candidate-order scorer used by the learned ordering policy.

@@ -19,6 +19,9 @@ import torch  # loads the HIP runtime the library shares
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libustat.so")
+# Order cost model trained on MI355X timings (written by costmodel_train);
+# the default weights of order="learned" plans.
+DEFAULT_COST_MODEL = os.path.join(HERE, "costmodel_mi355x.txt")
 
 F64, F32, BF16X3, I8 = 0, 1, 2, 3
 ORDER_MINFILL, ORDER_EXHAUSTIVE, ORDER_LEARNED = 0, 1, 2
@@ -41,7 +44,8 @@ class UstatError(RuntimeError):
 class PlanOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("order", ctypes.c_int32),
                 ("sparsify", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("workspace_limit", ctypes.c_uint64), ("cost_model_path", ctypes.c_char_p)]
+                ("workspace_limit", ctypes.c_uint64), ("cost_model_path", ctypes.c_char_p),
+                ("n_hint", ctypes.c_int64)]
 
 
 class Result(ctypes.Structure):
@@ -88,7 +92,7 @@ def load_library(path: str = LIB_PATH):
     L.ustat_plan_cost.argtypes = [P, i64, pdbl, pdbl, ctypes.POINTER(u64)]
     L.ustat_plan_workspace.argtypes = [P, i32, pi64, i32, ctypes.POINTER(u64)]
     L.ustat_plan_partition.argtypes = [P, i32, pi32, pi64, pi32, pi32]
-    L.ustat_plan_order.argtypes = [P, i32, pi32, pi32]
+    L.ustat_plan_order.argtypes = [P, i32, pi32, pi32, pi32]
     L.ustat_graph_treewidth.argtypes = [i32, i32, pi32, pi32]
     L.ustat_eval.argtypes = [P, i64, ctypes.POINTER(P), P, ctypes.POINTER(Result)]
     L.ustat_eval_samples.argtypes = [P, i64, i32, P, dbl, P, ctypes.POINTER(Result)]
@@ -100,8 +104,8 @@ def load_library(path: str = LIB_PATH):
     L.ustat_profile_reset.argtypes = []
     L.ustat_profile_read.argtypes = [i32, pdbl, pi64, pdbl, pdbl]
     pf32 = ctypes.POINTER(ctypes.c_float)
-    L.ustat_order_features.argtypes = [P, pi32, pi32, i32, i64, pf32]
-    L.vstat_eval_ordered.argtypes = [P, pi32, pi32, i32, i64, ctypes.POINTER(P), P,
+    L.ustat_order_features.argtypes = [P, pi32, pi32, i32, i32, i64, pf32]
+    L.vstat_eval_ordered.argtypes = [P, pi32, pi32, i32, i32, i64, ctypes.POINTER(P), P,
                                      ctypes.POINTER(Result)]
     L.ustat_mlp_num_params.argtypes = [i32, i32, i32]
     L.ustat_mlp_num_params.restype = ctypes.c_size_t
@@ -142,7 +146,7 @@ def _edges_array(edges: Sequence[Tuple[int, int]]):
 
 def ustat_plan_create(m: int, edges, precision="f64", order="minfill", sparsify=False,
                       workspace_limit: int = 0, cost_model_path: Optional[str] = None,
-                      cse: bool = True):
+                      cse: bool = True, n_hint: int = 0):
     L = load_library()
     o = PlanOpts()
     _check(L.ustat_plan_opts_default(ctypes.byref(o)))
@@ -151,7 +155,10 @@ def ustat_plan_create(m: int, edges, precision="f64", order="minfill", sparsify=
     o.sparsify = 1 if sparsify else 0
     o.flags = 0 if cse else FLAG_NO_CSE
     o.workspace_limit = int(workspace_limit)
+    if o.order == ORDER_LEARNED and not cost_model_path:
+        cost_model_path = DEFAULT_COST_MODEL
     o.cost_model_path = cost_model_path.encode() if cost_model_path else None
+    o.n_hint = int(n_hint)
     h = ctypes.c_void_p()
     _check(L.ustat_plan_create(int(m), len(edges), _edges_array(edges), ctypes.byref(o),
                                ctypes.byref(h)))
@@ -192,11 +199,14 @@ def ustat_plan_partition(h, idx: int, m: int) -> dict:
     return {"block_of": list(blk), "mu": mu.value, "tw": tw.value, "width": w.value}
 
 
-def ustat_plan_order(h, idx: int, m: int) -> List[int]:
+def ustat_plan_order(h, idx: int, m: int):
+    """(order, slice_var): the elimination order of partition idx and the
+    quotient vertex it conditions on (-1 for none)."""
     buf = (ctypes.c_int32 * m)()
     ln = ctypes.c_int32()
-    _check(load_library().ustat_plan_order(h, int(idx), buf, ctypes.byref(ln)))
-    return list(buf)[: ln.value]
+    sv = ctypes.c_int32()
+    _check(load_library().ustat_plan_order(h, int(idx), buf, ctypes.byref(ln), ctypes.byref(sv)))
+    return list(buf)[: ln.value], sv.value
 
 
 def ustat_graph_treewidth(m: int, edges) -> int:
@@ -272,21 +282,23 @@ def ustat_profile_read(kind) -> dict:
     return {"ms": ms.value, "launches": nl.value, "flops": fl.value, "bytes": by.value}
 
 
-def ustat_order_features(h, block_of, order, n: int):
+def ustat_order_features(h, block_of, order, n: int, slice_var: int = -1):
     import numpy as np
     blk = (ctypes.c_int32 * len(block_of))(*[int(b) for b in block_of])
-    od = (ctypes.c_int32 * len(order))(*[int(o) for o in order])
+    od = (ctypes.c_int32 * max(1, len(order)))(*[int(o) for o in order])
     out = np.zeros(NUM_FEATURES, dtype=np.float32)
-    _check(load_library().ustat_order_features(h, blk, od, len(order), int(n),
+    _check(load_library().ustat_order_features(h, blk, od, len(order), int(slice_var), int(n),
                                                out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
     return out
 
 
-def vstat_eval_ordered(h, block_of, order, n: int, factors, stream=None) -> Result:
+def vstat_eval_ordered(h, block_of, order, n: int, factors, stream=None,
+                       slice_var: int = -1) -> Result:
     blk = (ctypes.c_int32 * len(block_of))(*[int(b) for b in block_of])
-    od = (ctypes.c_int32 * len(order))(*[int(o) for o in order])
+    od = (ctypes.c_int32 * max(1, len(order)))(*[int(o) for o in order])
     r = Result()
-    _check(load_library().vstat_eval_ordered(h, blk, od, len(order), int(n), _factor_ptrs(factors),
+    _check(load_library().vstat_eval_ordered(h, blk, od, len(order), int(slice_var), int(n),
+                                             _factor_ptrs(factors),
                                              _stream_handle(stream), ctypes.byref(r)))
     return r
 
@@ -344,12 +356,12 @@ class Plan:
 
     def __init__(self, m: int, edges, precision="f64", order="minfill", sparsify=False,
                  workspace_limit: int = 0, cost_model_path: Optional[str] = None,
-                 cse: bool = True):
+                 cse: bool = True, n_hint: int = 0):
         self.m = int(m)
         self.edges = [tuple(e) for e in edges]
         self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         self.h = ustat_plan_create(m, edges, precision, order, sparsify, workspace_limit,
-                                   cost_model_path, cse)
+                                   cost_model_path, cse, n_hint)
 
     def __del__(self):
         h = getattr(self, "h", None)
@@ -374,7 +386,10 @@ class Plan:
         return ustat_plan_partition(self.h, idx, self.m)
 
     def order(self, idx: int) -> List[int]:
-        return ustat_plan_order(self.h, idx, self.m)
+        return ustat_plan_order(self.h, idx, self.m)[0]
+
+    def slice_var(self, idx: int) -> int:
+        return ustat_plan_order(self.h, idx, self.m)[1]
 
     def partitions(self) -> list:
         return [self.partition(i) for i in range(self.info()["num_vstats"])]

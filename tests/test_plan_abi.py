@@ -11,6 +11,7 @@ import os
 import re
 import subprocess
 
+import numpy as np
 import pytest
 
 import oracle
@@ -152,6 +153,31 @@ def test_orders_are_permutations_and_widths_bounded(U):
                 assert p["width"] >= p["tw"]
                 # min-fill reaches the exact treewidth on these graphs
                 assert p["width"] == p["tw"]
+                assert P.slice_var(i) == -1
+
+
+def test_m6_graphs_condition_treewidth3_quotients(U):
+    """Random 6-vertex kernel graphs (6-10 edges, the learned-order
+    workload's generator): every partition whose quotient has treewidth at
+    most 3 gets an executable program; treewidth-3 quotients are conditioned
+    on one vertex (order lists the other J-1 vertices) and keep width equal to
+    the treewidth, under every order policy."""
+    graphs = W.random_kernel_graphs(12, 6, 6, 10, seed=5)
+    for edges in graphs:
+        for order in ("minfill", "exhaustive"):
+            P = U.Plan(6, edges, order=order)
+            info = P.info()
+            if info["M"] > 3:
+                continue
+            assert info["num_vstats"] == 203
+            for i, p in enumerate(P.partitions()):
+                J = 1 + max(p["block_of"])
+                o, sv = U.ustat_plan_order(P.h, i, 6)
+                assert p["width"] == p["tw"]
+                if p["tw"] <= 2:
+                    assert sv == -1 and sorted(o) == list(range(J))
+                else:
+                    assert 0 <= sv < J and sorted(o + [sv]) == list(range(J))
 
 
 def test_config_step_counts(U):
@@ -193,9 +219,20 @@ def test_invalid_options(U):
         U.Plan(3, W.TRIANGLE, precision=7)
     with pytest.raises(U.UstatError):
         U.Plan(3, W.TRIANGLE, order=9)
+    # the C ABI needs a weights file for the learned policy (the binding
+    # passes the shipped one by default)
+    import ctypes
+    L = U.load_library()
+    o = U.PlanOpts()
+    L.ustat_plan_opts_default(ctypes.byref(o))
+    o.order = U.ORDER_LEARNED
+    h = ctypes.c_void_p()
+    rc = L.ustat_plan_create(3, 3, U._edges_array(W.TRIANGLE), ctypes.byref(o), ctypes.byref(h))
+    assert rc == 1 and "cost_model_path" in L.ustat_last_error().decode()
+    assert h.value is None
     with pytest.raises(U.UstatError) as ei:
-        U.Plan(3, W.TRIANGLE, order="learned")
-    assert "cost_model_path" in str(ei.value)
+        U.Plan(3, W.TRIANGLE, n_hint=-5)
+    assert "n_hint" in str(ei.value)
     with pytest.raises(U.UstatError) as ei:
         U.Plan(3, W.TRIANGLE, order="learned", cost_model_path="/nonexistent/model.txt")
     assert "cost model" in str(ei.value)
@@ -235,3 +272,33 @@ def test_unsupported_width_reported(U):
     ptrs = (ctypes.c_void_p * len(k5))(*([1] * len(k5)))
     rc = U.load_library().ustat_eval(P.h, 16, ptrs, None, ctypes.byref(r))
     assert rc == 2
+
+
+def test_shipped_cost_model_ranks_orders(U):
+    """The shipped MI355X weights load, learned plans are complete, and
+    their predicted log-times are finite and ordered sensibly in n."""
+    import os
+    assert os.path.exists(U.DEFAULT_COST_MODEL)
+    for edges in W.random_kernel_graphs(4, 6, 6, 10, seed=5):
+        P = U.Plan(6, edges, order="learned", n_hint=2048)
+        info = P.info()
+        if info["M"] > 3:
+            continue
+        assert info["num_vstats"] == 203
+        for i, p in enumerate(P.partitions()):
+            assert p["width"] == p["tw"]
+    with open(U.DEFAULT_COST_MODEL) as f:
+        assert f.readline().split() == ["ustat-mlp", "1"]
+        F, H1, H2 = (int(x) for x in f.readline().split())
+    assert F == U.NUM_FEATURES
+    # the same plain order at growing n is predicted to take longer
+    P = U.Plan(4, W.CYCLE4)
+    i = max(range(15), key=lambda k: max(P.partition(k)["block_of"]))
+    blk, order = P.partition(i)["block_of"], P.order(i)
+    X = np.stack([U.ustat_order_features(P.h, blk, order, n) for n in (512, 1024, 2048, 4096)])
+    params = np.array(open(U.DEFAULT_COST_MODEL).read().split()[5:], dtype=np.float64)
+    assert params.size == U.ustat_mlp_num_params(F, H1, H2)
+    from oracle import mlp_ref
+    pred, _ = mlp_ref.forward(params, F, H1, H2, X.astype(np.float64))
+    assert np.all(np.isfinite(pred)) and np.all(np.diff(pred) > 0)
+
