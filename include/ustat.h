@@ -83,6 +83,16 @@ typedef enum {
  * turns the merging off, so every partition's steps run separately.
  */
 #define USTAT_FLAG_NO_CSE 1
+/*
+ * USTAT_FLAG_SYMMETRIC: every factor matrix given to ustat_eval, vstat_eval
+ * and vstat_eval_ordered is symmetric (T(i,j) == T(j,i)), so the engine
+ * reads it in whichever orientation a step streams: no transposed copies,
+ * and steps that differ only by the orientation of an input are merged.
+ * Values change at most by rounding (exact results not at all).  The RBF
+ * factors that ustat_eval_samples and ustat_eval_batched build are
+ * symmetric by construction and always read this way.
+ */
+#define USTAT_FLAG_SYMMETRIC 2
 
 typedef struct {
     int32_t precision;          /* ustat_precision                          */

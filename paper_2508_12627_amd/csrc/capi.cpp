@@ -146,7 +146,8 @@ ustat_status ustat_plan_create(int32_t m, int32_t num_edges, const int32_t *edge
     if (o.precision < 0 || o.precision > 3) return fail(USTAT_E_INVALID, "unknown precision");
     if (o.order < 0 || o.order > 2) return fail(USTAT_E_INVALID, "unknown order policy");
     if (o.sparsify != 0 && o.sparsify != 1) return fail(USTAT_E_INVALID, "sparsify must be 0 or 1");
-    if (o.flags & ~USTAT_FLAG_NO_CSE) return fail(USTAT_E_INVALID, "unknown flag bits");
+    if (o.flags & ~(USTAT_FLAG_NO_CSE | USTAT_FLAG_SYMMETRIC))
+        return fail(USTAT_E_INVALID, "unknown flag bits");
     try {
         std::unique_ptr<ustat_plan_s> p(new ustat_plan_s());
         std::vector<Edge> E;
@@ -159,6 +160,7 @@ ustat_status ustat_plan_create(int32_t m, int32_t num_edges, const int32_t *edge
         if (o.n_hint < 0 || o.n_hint > (1ll << 20)) return fail(USTAT_E_INVALID, "n_hint out of range");
         if (o.n_hint > 0) po.n_hint = (double)o.n_hint;
         po.cse = !(o.flags & USTAT_FLAG_NO_CSE);
+        po.symmetric = (o.flags & USTAT_FLAG_SYMMETRIC) != 0;
         if (o.cost_model_path) po.cost_model_path = o.cost_model_path;
         const OrderScorer *scorer = nullptr;
         if (o.order == USTAT_ORDER_LEARNED) {
@@ -313,6 +315,7 @@ ustat_status ustat_eval(ustat_plan plan, int64_t n, const void *const *factors, 
     if (!factors || !out) return fail(USTAT_E_INVALID, "factors and out must be non-NULL");
     std::vector<Dataset> data(1);
     data[0].n = n;
+    data[0].symmetric = plan->plan.opts.symmetric;
     for (size_t k = 0; k < plan->plan.edges.size(); ++k) {
         if (!factors[k]) return fail(USTAT_E_INVALID, "a factor pointer is NULL");
         data[0].factors.push_back(factors[k]);
@@ -354,6 +357,7 @@ ustat_status ustat_eval_samples(ustat_plan plan, int64_t n, int32_t d, const dou
     if (e != hipSuccess) return fail(USTAT_E_NOMEM, hipGetErrorString(e));
     std::vector<Dataset> data(1);
     data[0].n = n;
+    data[0].symmetric = true;  // the RBF factor is symmetric bit for bit
     for (size_t k = 0; k < plan->plan.edges.size(); ++k) data[0].factors.push_back(plan->factors);
     char *fb = plan->factors;
     auto pre = [=](hipStream_t s) -> hipError_t {
@@ -394,6 +398,7 @@ ustat_status vstat_eval(ustat_plan plan, const int32_t *block_of, int64_t n,
     sub.opts.sparsify = plan->plan.opts.sparsify;
     std::vector<Dataset> data(1);
     data[0].n = n;
+    data[0].symmetric = plan->plan.opts.symmetric;
     for (size_t k = 0; k < plan->plan.edges.size(); ++k) data[0].factors.push_back(factors[k]);
     std::vector<DatasetResult> res;
     std::vector<const VProgram *> progs = {&prog};
@@ -454,6 +459,7 @@ ustat_status vstat_eval_ordered(ustat_plan plan, const int32_t *block_of, const 
     prog.mu = 1;
     std::vector<Dataset> data(1);
     data[0].n = n;
+    data[0].symmetric = plan->plan.opts.symmetric;
     for (size_t k = 0; k < plan->plan.edges.size(); ++k) data[0].factors.push_back(factors[k]);
     std::vector<DatasetResult> res;
     std::vector<const VProgram *> progs = {&prog};
@@ -533,6 +539,7 @@ ustat_status ustat_eval_batched(ustat_plan plan, int32_t batch, const int64_t *n
         for (int b = chunks[c].first, i = 0; b < chunks[c].second; ++b, ++i) {
             Dataset ds;
             ds.n = n[b];
+            ds.symmetric = true;  // RBF factors
             for (size_t k = 0; k < plan->plan.edges.size(); ++k)
                 ds.factors.push_back(plan->factors + coff[c][i]);
             cdata[c].push_back(ds);

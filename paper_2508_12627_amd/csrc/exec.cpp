@@ -91,6 +91,17 @@ constexpr size_t kAlign = 256;
 inline size_t up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 inline int64_t up64(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
+// Smallest number of 256-wide tiles for which a GEMM level uses them: one
+// per compute unit by default; USTAT_GEMM_BIG_MIN overrides it (a tuning
+// knob: 0 always takes 256-wide tiles where allowed, a huge value never).
+int64_t gemm_big_tiles_min() {
+    static const int64_t v = [] {
+        const char *e = getenv("USTAT_GEMM_BIG_MIN");
+        return e ? (int64_t)atoll(e) : (int64_t)256;
+    }();
+    return v;
+}
+
 // First-fit offset allocator with coalescing (host-side bookkeeping of the
 // device arena; offsets only).
 struct Arena {
@@ -145,9 +156,14 @@ struct LevelWork {
     int64_t prep_tiles = 0;
     std::vector<GemmDesc> gemm;
     int64_t gemm_tiles = 0;
+    int gemm_tile = 128;  // block tile side of the level's GEMM launch
     double gemm_flops = 0;
-    std::vector<Elim1Desc> e1;
+    std::vector<Elim1Desc> e1;  // column reductions over more than kColMat matrices
     int64_t e1_tiles = 0;
+    std::vector<ColDesc> col[kColMat];  // grouped column reductions, by matrix count
+    int64_t col_tiles[kColMat] = {0, 0, 0};
+    double col_bytes[kColMat] = {0, 0, 0};  // algorithmic HBM bytes per launch
+    size_t off_col[kColMat] = {0, 0, 0};
     double e1_bytes = 0, prep_bytes = 0, tr_bytes = 0;  // algorithmic HBM bytes
     std::vector<TransDesc> tr;
     int64_t tr_tiles = 0;
@@ -322,8 +338,9 @@ int add_node(Dag &G, Node nd, const std::string &key, bool cse);
 // want_trans == false for column reductions (stored (v, w)), true for GEMM
 // operand prep (stored (w, v)).  Otherwise the matrix is replaced by its
 // materialised transpose (one per matrix, shared by all consumers).
-MOp direct(Dag &G, const MOp &o, bool want_trans, int d, int64_t n, bool cse) {
+MOp direct(Dag &G, const MOp &o, bool want_trans, int d, int64_t n, bool cse, bool sym) {
     if (o.trans == want_trans) return o;
+    if (sym && o.node < 0) return MOp{o.node, o.p, want_trans};  // symmetric input
     Node t;
     t.kind = NK::Transpose;
     t.d = d;
@@ -482,6 +499,7 @@ std::string build_dag(const Plan &plan, const std::vector<const VProgram *> &pro
     };
     for (int d = 0; d < nd; ++d) {
         const int64_t n = data[d].n;
+        const bool sym = data[d].symmetric;
         for (int p = 0; p < np; ++p) {
           const VProgram &pr = *progs[p];
           const bool sliced = pr.slice_var >= 0;
@@ -502,8 +520,9 @@ std::string build_dag(const Plan &plan, const std::vector<const VProgram *> &pro
                     sn.d = d;
                     sn.n = n;
                     const void *mp = data[d].factors[val.src];
-                    sn.A.push_back(MOp{-1, mp, val.c == 1});
-                    std::string key = "S|" + std::to_string(n) + "|" + ptr_id(mp) + "|" + std::to_string(val.c);
+                    const int col = sym ? 0 : val.c;  // rows and columns agree
+                    sn.A.push_back(MOp{-1, mp, col == 1});
+                    std::string key = "S|" + std::to_string(n) + "|" + ptr_id(mp) + "|" + std::to_string(col);
                     for (int k : val.scale) {
                         const void *dp_ = data[d].factors[k];
                         use_diag(d, dp_);
@@ -514,8 +533,11 @@ std::string build_dag(const Plan &plan, const std::vector<const VProgram *> &pro
                     ref[v].off = slice * n;
                 }
             }
+            // a symmetric input is keyed in one orientation, so that steps
+            // differing only by its orientation merge
             auto mop = [&](const MatOp &o) {
                 const Ref &r = ref[o.val];
+                if (sym && r.node < 0) return MOp{r.node, r.p, false};
                 return MOp{r.node, r.p, (bool)(o.trans ^ r.flip)};
             };
             auto vop = [&](int v) { return VOp{ref[v].node, ref[v].p, ref[v].off}; };
@@ -545,7 +567,7 @@ std::string build_dag(const Plan &plan, const std::vector<const VProgram *> &pro
                     case StepKind::Elim1:
                     case StepKind::Final1: {
                         nd_.kind = NK::E1;
-                        for (auto &o : A) nd_.A.push_back(direct(G, o, false, d, n, cse));
+                        for (auto &o : A) nd_.A.push_back(direct(G, o, false, d, n, cse, sym));
                         nd_.sv = sv;
                         std::string k1 = "E1|" + std::to_string(n) + "|" + group_sig(nd_.A, mop_sig) + "|" +
                                          group_sig(sv, vop_sig);
@@ -566,8 +588,8 @@ std::string build_dag(const Plan &plan, const std::vector<const VProgram *> &pro
                         break;
                     }
                     case StepKind::Elim2: {
-                        for (auto &o : A) o = direct(G, o, true, d, n, cse);
-                        for (auto &o : B) o = direct(G, o, true, d, n, cse);
+                        for (auto &o : A) o = direct(G, o, true, d, n, cse, sym);
+                        for (auto &o : B) o = direct(G, o, true, d, n, cse, sym);
                         bool sw;
                         std::string k = gemm_key(n, A, sv, B, &sw);
                         nd_.kind = NK::GemmStore;
@@ -581,8 +603,8 @@ std::string build_dag(const Plan &plan, const std::vector<const VProgram *> &pro
                         break;
                     }
                     case StepKind::Final2: {
-                        for (auto &o : A) o = direct(G, o, true, d, n, cse);
-                        for (auto &o : B) o = direct(G, o, true, d, n, cse);
+                        for (auto &o : A) o = direct(G, o, true, d, n, cse, sym);
+                        for (auto &o : B) o = direct(G, o, true, d, n, cse, sym);
                         Pending pd;
                         pd.dp = dp;
                         pd.term = (int)G.prog_terms[dp].size();
@@ -633,7 +655,7 @@ std::string build_dag(const Plan &plan, const std::vector<const VProgram *> &pro
             e.d = pd.d;
             e.n = pd.n;
             e.A.push_back(MOp{gid, nullptr, false});
-            for (auto &z : Z) e.A.push_back(direct(G, z, false, pd.d, pd.n, cse));
+            for (auto &z : Z) e.A.push_back(direct(G, z, false, pd.d, pd.n, cse, data[pd.d].symmetric));
             e.sv = aw;
             int eid = add_node(G, e, "E1|" + std::to_string(pd.n) + "|" + group_sig(e.A, mop_sig) + "|" +
                                          group_sig(e.sv, vop_sig), cse);
@@ -676,6 +698,160 @@ std::string build_dag(const Plan &plan, const std::vector<const VProgram *> &pro
     }
     (void)plan;
     return "";
+}
+
+bool same_matrix(const MatRef &a, const MatRef &b) {
+    return a.p == b.p && a.ld == b.ld && a.dtype == b.dtype && a.trans == b.trans &&
+           a.zdiag == b.zdiag;
+}
+
+size_t dtype_bytes(int32_t dt) {
+    return dt == DT_F64 || dt == DT_I64 ? 8 : dt == DT_F32 ? 4 : 1;
+}
+
+// A column reduction of one level before its blocks are laid out: the
+// descriptor (operands and vectors), where its result goes, and the
+// running-maximum slot of the exact path.
+struct ColPending {
+    Elim1Desc e;
+    void *out;
+    unsigned long long *mx;
+};
+
+// Lays out a level's column reductions.  Those reading few distinct
+// matrices are grouped greedily, in node order: a reduction joins the first
+// group of its size n whose matrices together with its own stay within
+// kColMat and that has an output slot left; the rest keep one launch entry
+// each.  The strip height is then chosen for the whole level: the largest
+// of 512, 256, ..., 32 rows that still gives at least 1024 blocks, so that a
+// lone problem fills the chip while batched levels keep few partial rows.
+// alloc_part(bytes) returns a scratch partial buffer of the level; each
+// output gets a fixed-order reduction of its partials into its result.
+template <class Alloc>
+void layout_column_reductions(const std::vector<ColPending> &recs, LevelWork &W,
+                              Alloc &&alloc_part) {
+    struct Out {
+        ColOut o;
+        int rec;
+    };
+    struct Grp {
+        int64_t n;
+        std::vector<MatRef> M;
+        std::vector<Out> outs;
+    };
+    std::vector<Grp> groups;
+    std::vector<int> single;  // records keeping their own launch entry
+    for (int ri = 0; ri < (int)recs.size(); ++ri) {
+        const Elim1Desc &e = recs[ri].e;
+        std::vector<MatRef> dm;
+        std::vector<int> cnt;
+        for (int q = 0; q < e.nA; ++q) {
+            int k = 0;
+            while (k < (int)dm.size() && !same_matrix(dm[k], e.A[q])) ++k;
+            if (k == (int)dm.size()) {
+                dm.push_back(e.A[q]);
+                cnt.push_back(0);
+            }
+            ++cnt[k];
+        }
+        if ((int)dm.size() > kColMat) {
+            single.push_back(ri);
+            continue;
+        }
+        Grp *home = nullptr;
+        for (Grp &g : groups) {
+            if (g.n != e.n || (int)g.outs.size() >= kColOut) continue;
+            std::vector<MatRef> un = g.M;
+            for (const MatRef &m : dm) {
+                bool have = false;
+                for (const MatRef &u : un) have = have || same_matrix(u, m);
+                if (!have) un.push_back(m);
+            }
+            if ((int)un.size() > kColMat) continue;
+            g.M = un;
+            home = &g;
+            break;
+        }
+        if (!home) {
+            groups.push_back(Grp{e.n, dm, {}});
+            home = &groups.back();
+        }
+        Out o;
+        std::memset(&o.o, 0, sizeof o.o);
+        o.rec = ri;
+        for (size_t k = 0; k < dm.size(); ++k)
+            for (size_t u = 0; u < home->M.size(); ++u)
+                if (same_matrix(home->M[u], dm[k])) {
+                    o.o.e[u] = (int8_t)cnt[k];
+                    o.o.zd[u] = (int8_t)dm[k].zdiag;
+                }
+        o.o.nS = e.nS;
+        for (int q = 0; q < e.nS; ++q) o.o.s[q] = e.s[q];
+        home->outs.push_back(o);
+    }
+    auto wstrips = [](int64_t n) { return (n + 255) / 256; };
+    auto blocks = [&](int S) {
+        int64_t b = 0;
+        for (const Grp &g : groups) b += ((g.n + S - 1) / S) * wstrips(g.n);
+        for (int ri : single) b += ((recs[ri].e.n + S - 1) / S) * wstrips(recs[ri].e.n);
+        return b;
+    };
+    int S = kElimStrip;
+    while (S > 32 && blocks(S) < 1024) S /= 2;
+    // partials of one output and the reduction that consumes them
+    auto partials = [&](const ColPending &r, int64_t strips) {
+        const int64_t n = r.e.n;
+        void *part = alloc_part((size_t)strips * n * 8);
+        ReduceDesc rd;
+        std::memset(&rd, 0, sizeof rd);
+        rd.part = part;
+        rd.T = strips;
+        rd.len = n;
+        rd.stride = n;
+        rd.out = r.out;
+        rd.mx_out = r.mx;
+        W.red.push_back(rd);
+        W.red_maxlen = std::max<int64_t>(W.red_maxlen, n);
+        return part;
+    };
+    for (int ri : single) {
+        Elim1Desc f = recs[ri].e;
+        f.strip = S;
+        f.tiles_v = (int)((f.n + S - 1) / S);
+        f.tiles_w = (int)wstrips(f.n);
+        f.part = partials(recs[ri], f.tiles_v);
+        f.tile_start = W.e1_tiles;
+        W.e1_tiles += (int64_t)f.tiles_v * f.tiles_w;
+        W.e1.push_back(f);
+        for (int q = 0; q < f.nA; ++q) W.e1_bytes += (double)f.n * f.n * dtype_bytes(f.A[q].dtype);
+        W.e1_bytes += (double)f.n * 8 * (f.nS + f.tiles_v);
+    }
+    for (const Grp &g : groups) {
+        ColDesc c;
+        std::memset(&c, 0, sizeof c);
+        c.n = g.n;
+        c.nm = (int)g.M.size();
+        c.nout = (int)g.outs.size();
+        for (int k = 0; k < c.nm; ++k) {
+            c.M[k] = g.M[k];
+            c.M[k].zdiag = 0;  // applied per output
+        }
+        c.strip = S;
+        c.tiles_v = (int)((g.n + S - 1) / S);
+        c.tiles_w = (int)wstrips(g.n);
+        for (int o = 0; o < c.nout; ++o) {
+            c.o[o] = g.outs[o].o;
+            c.o[o].part = partials(recs[g.outs[o].rec], c.tiles_v);
+        }
+        const int b = c.nm - 1;
+        c.tile_start = W.col_tiles[b];
+        W.col_tiles[b] += (int64_t)c.tiles_v * c.tiles_w;
+        W.col[b].push_back(c);
+        double bytes = 0;
+        for (int k = 0; k < c.nm; ++k) bytes += (double)g.n * g.n * dtype_bytes(g.M[k].dtype);
+        for (const Out &o : g.outs) bytes += (double)g.n * 8 * (o.o.nS + c.tiles_v);
+        W.col_bytes[b] += bytes;
+    }
 }
 
 // Builds the schedule.  With base == nullptr only sizes are computed; a
@@ -855,7 +1031,23 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
     S.levels.assign(G.max_level + 1, LevelWork());
     for (int L = 1; L <= G.max_level; ++L) {
         LevelWork &W = S.levels[L];
+        // 256-wide tiles for the level's GEMM launch when every problem's
+        // padded size is a multiple of 256 and they still give at least one
+        // tile per compute unit (fp32 and split-bf16 only)
+        {
+            int64_t t256 = 0;
+            bool ok = cfg.prec == 1 || cfg.prec == 2;
+            for (int id : by_level[L]) {
+                const Node &q = G.nodes[id];
+                if (q.kind != NK::GemmStore && q.kind != NK::GemmFinal) continue;
+                const int64_t np_ = up64(q.n, 128);
+                ok = ok && np_ % 256 == 0;
+                t256 += (np_ / 256) * (np_ / 256);
+            }
+            W.gemm_tile = (ok && t256 >= gemm_big_tiles_min()) ? 256 : 128;
+        }
         std::vector<std::pair<size_t, size_t>> scratch;
+        std::vector<ColPending> e1recs;  // this level's column reductions
         std::map<std::string, PrepRec> local;
         for (int id : by_level[L]) {
             Node &nd_ = G.nodes[id];
@@ -905,26 +1097,14 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
                     break;
                 }
                 case NK::E1: {
-                    Elim1Desc e;
+                    ColPending cp;
+                    Elim1Desc &e = cp.e;
+                    std::memset(&e, 0, sizeof e);
                     e.n = n;
                     e.nA = (int)nd_.A.size();
                     e.nS = (int)nd_.sv.size();
                     for (int q = 0; q < e.nA; ++q) e.A[q] = mref(d, nd_.A[q]);
                     for (int q = 0; q < e.nS; ++q) e.s[q] = vptr(d, nd_.sv[q]);
-                    const int strips = (int)((n + kElimStrip - 1) / kElimStrip);
-                    const int wstrips = (int)((n + 255) / 256);
-                    size_t pbytes = (size_t)strips * n * 8;
-                    size_t poff = A.alloc(pbytes);
-                    scratch.push_back({poff, pbytes});
-                    e.part = P(poff);
-                    e.tiles_v = strips;
-                    e.tiles_w = wstrips;
-                    e.tile_start = W.e1_tiles;
-                    W.e1_tiles += (int64_t)strips * wstrips;
-                    W.e1.push_back(e);
-                    for (auto &o : nd_.A)
-                        W.e1_bytes += (double)n * n * (src_of(o).node < 0 ? cfg.in_es : cfg.mat_es);
-                    W.e1_bytes += (double)n * 8 * (nd_.sv.size() + strips);
                     nd_.bytes = (size_t)n * 8;
                     nd_.off = A.alloc(nd_.bytes);
                     nd_.bound = n * pA * pS;
@@ -932,16 +1112,9 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
                         *status = 5;
                         return "an intermediate vector may exceed int64";
                     }
-                    ReduceDesc r;
-                    std::memset(&r, 0, sizeof r);
-                    r.part = P(poff);
-                    r.T = strips;
-                    r.len = n;
-                    r.stride = n;
-                    r.out = P(nd_.off);
-                    r.mx_out = (is_int && mxbase) ? mxbase + nd_.mx : nullptr;
-                    W.red.push_back(r);
-                    W.red_maxlen = std::max<int64_t>(W.red_maxlen, n);
+                    cp.out = P(nd_.off);
+                    cp.mx = (is_int && mxbase) ? mxbase + nd_.mx : nullptr;
+                    e1recs.push_back(cp);
                     break;
                 }
                 case NK::SliceSrc: {
@@ -1044,7 +1217,7 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
                     g.lb = clb;
                     g.la_p = is_int ? lap : nullptr;
                     g.lb_p = is_int ? lbp : nullptr;
-                    g.tiles = (int)(npad / 128);
+                    g.tiles = (int)(npad / W.gemm_tile);
                     g.tile_start = W.gemm_tiles;
                     W.gemm_tiles += (int64_t)g.tiles * g.tiles;
                     W.gemm_flops += 2.0 * (double)n * n * n;
@@ -1100,6 +1273,11 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
                 return "a V-statistic may exceed the 127-bit range";
             }
         }
+        layout_column_reductions(e1recs, W, [&](size_t bytes) {
+            const size_t off = A.alloc(bytes);
+            scratch.push_back({off, bytes});
+            return P(off);
+        });
         for (auto &sc : scratch) A.release(sc.first, sc.second);
         for (auto it = persistent.begin(); it != persistent.end();) {
             if (prep_last[it->first] <= L) {
@@ -1160,6 +1338,7 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
         W.off_prep = S.blob.put(W.prep);
         W.off_gemm = S.blob.put(W.gemm);
         W.off_e1 = S.blob.put(W.e1);
+        for (int k = 0; k < kColMat; ++k) W.off_col[k] = S.blob.put(W.col[k]);
         W.off_e0 = S.blob.put(W.e0);
         W.off_red = S.blob.put(W.red);
     }
@@ -1204,6 +1383,7 @@ size_t workspace_bytes(const Plan &plan, const std::vector<const VProgram *> &pr
     for (int64_t n : ns) {
         Dataset d;
         d.n = n;
+        d.symmetric = plan.opts.symmetric;
         // distinct placeholder pointers per dataset (and per edge unless shared)
         for (size_t k = 0; k < plan.edges.size(); ++k) {
             d.factors.push_back(&fake[slot % sizeof fake]);
@@ -1412,8 +1592,15 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
             if (!W.gemm.empty()) {
                 ProfScope ps(prof, KIND_GEMM, stream, W.gemm_flops);
                 e = launch_gemm(reinterpret_cast<GemmDesc *>(dd + W.off_gemm), (int)W.gemm.size(),
-                                W.gemm_tiles, cfg.prec, stream);
+                                W.gemm_tiles, cfg.prec, W.gemm_tile, stream);
                 if (e != hipSuccess) return fail(e, "gemm");
+            }
+            for (int k = 0; k < kColMat; ++k) {
+                if (W.col[k].empty()) continue;
+                ProfScope ps(prof, KIND_ELIM1, stream, 0, W.col_bytes[k]);
+                e = launch_colred(reinterpret_cast<ColDesc *>(dd + W.off_col[k]), (int)W.col[k].size(),
+                                  W.col_tiles[k], k + 1, cfg.domain, stream);
+                if (e != hipSuccess) return fail(e, "column reduction");
             }
             if (!W.e1.empty()) {
                 ProfScope ps(prof, KIND_ELIM1, stream, 0, W.e1_bytes);

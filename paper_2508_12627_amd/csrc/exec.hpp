@@ -18,6 +18,7 @@ namespace ustat {
 struct Dataset {
     int64_t n = 0;
     std::vector<const void *> factors;  // one device pointer per edge
+    bool symmetric = false;             // every factor matrix is symmetric
 };
 
 struct DatasetResult {

@@ -191,8 +191,7 @@ __global__ void k_absmax_i8(const int8_t *const *src, const int64_t *n, int npro
 // ----------------------------------------------------------------- elim1
 
 // Rows of one column strip handled by a block (and thus the number of
-// partial rows left for the fixed-order reduction: ceil(n / kStripRows)).
-constexpr int kStripRows = kElimStrip;
+// partial rows left for the fixed-order reduction: ceil(n / strip)).
 
 // Four consecutive elements p[i .. i+3] of a row as the accumulation type;
 // `vec` selects one wide load (the caller guarantees alignment and that all
@@ -222,7 +221,7 @@ __device__ __forceinline__ void load4(const T *p, int64_t i, bool vec, int64_t c
 }
 
 // Partials of y(w) = sum_v prod_k A_k(v,w) prod_j s_j(v) over a strip of
-// 256 columns w and kStripRows rows v.  Every operand is stored (v, w)
+// 256 columns w and d.strip rows v.  Every operand is stored (v, w)
 // (transposed operands arrive as materialised transposes), so each wave
 // reads whole 1 KB row segments, four consecutive columns per lane.  Thread
 // t owns columns w0 + 4 (t%64) .. +3 and rows v0 + t/64 + 4i of each 32-row
@@ -239,7 +238,7 @@ __global__ __launch_bounds__(256) void k_elim1(const Elim1Desc *D, int nprob) {
     const int64_t n = d.n, w0 = tw * 256;
     const int t = threadIdx.x, cg = t & 63, g = t >> 6;
     const int64_t w = w0 + 4 * cg;
-    const int64_t vbeg = tv * kStripRows, vend = min(n, vbeg + kStripRows);
+    const int64_t vbeg = tv * d.strip, vend = min(n, vbeg + d.strip);
     A sum[4] = {0, 0, 0, 0};
     for (int64_t v0 = vbeg; v0 < vend; v0 += 32) {
         A pr[8][4];
@@ -356,6 +355,85 @@ __global__ __launch_bounds__(256) void k_transpose(const TransDesc *D, int nprob
             if (aa < n && bb < n) dst[bb * n + aa] = *reinterpret_cast<const T *>(&tile[r][c]);
         }
     });
+}
+
+// Grouped column reductions: the NM distinct matrices of a group are read
+// once per element for all of its outputs.  Block = 256 columns (4 per
+// thread, 64 threads across) x d.strip rows (4 row groups); each chunk
+// holds ROWS rows per thread in registers.
+template <int DOM, int NM>
+__global__ __launch_bounds__(256) void k_colred(const ColDesc *D, int nprob) {
+    typedef typename Dom<DOM>::acc A;
+    constexpr int ROWS = NM == 1 ? 8 : 4;
+    __shared__ A red[4][256];
+    const int64_t b = blockIdx.x;
+    const int p = find_problem(D, nprob, b);
+    const ColDesc &d = D[p];
+    const int64_t local = b - d.tile_start;
+    const int64_t tv = local / d.tiles_w, tw = local % d.tiles_w;
+    const int64_t n = d.n, w0 = tw * 256;
+    const int t = threadIdx.x, cg = t & 63, g = t >> 6;
+    const int64_t w = w0 + 4 * cg;
+    const int64_t vbeg = tv * d.strip, vend = min(n, vbeg + d.strip);
+    const int nout = d.nout;
+    A sum[kColOut][4];
+#pragma unroll
+    for (int o = 0; o < kColOut; ++o)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) sum[o][j] = 0;
+    for (int64_t v0 = vbeg; v0 < vend; v0 += 4 * ROWS) {
+        A x[NM][ROWS][4];
+#pragma unroll
+        for (int k = 0; k < NM; ++k) {
+            const MatRef m = d.M[k];
+            with_dtype(m.dtype, [&](auto tag) {
+                typedef decltype(tag) T;
+                const T *mp = static_cast<const T *>(m.p);
+                const bool vec = (w + 3 < n) && (m.ld % 4 == 0);
+#pragma unroll
+                for (int i = 0; i < ROWS; ++i) {
+                    const int64_t v = v0 + g + 4 * i;
+                    if (v < vend) load4<T, A>(mp, v * m.ld + w, vec, w, n, x[k][i]);
+                    else x[k][i][0] = x[k][i][1] = x[k][i][2] = x[k][i][3] = 0;
+                }
+            });
+        }
+#pragma unroll
+        for (int o = 0; o < kColOut; ++o) {
+            if (o >= nout) break;
+            const ColOut &q = d.o[o];
+#pragma unroll
+            for (int i = 0; i < ROWS; ++i) {
+                const int64_t v = v0 + g + 4 * i;
+                if (v >= vend) continue;
+                A sv = 1;
+                for (int j = 0; j < q.nS; ++j) sv *= load_vec<DOM>(q.s[j], v);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    A pr = (w + j < n) ? sv : (A)0;
+#pragma unroll
+                    for (int k = 0; k < NM; ++k) {
+                        const A xv = (q.zd[k] && v == w + j) ? (A)0 : x[k][i][j];
+                        for (int e = 0; e < q.e[k]; ++e) pr *= xv;
+                    }
+                    sum[o][j] += pr;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int o = 0; o < kColOut; ++o) {
+        if (o >= nout) break;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) red[g][4 * cg + j] = sum[o][j];
+        __syncthreads();
+        const int64_t wc = w0 + t;
+        if (wc < n) {
+            A tot = red[0][t] + red[1][t] + red[2][t] + red[3][t];
+            static_cast<A *>(d.o[o].part)[tv * n + wc] = tot;
+        }
+        __syncthreads();
+    }
 }
 
 // ----------------------------------------------------------------- reduce
@@ -601,32 +679,46 @@ struct AccT<3> {
     typedef i32x4 T;
 };
 
-// Global <-> LDS staging of one 128 x BK tile (all planes) of an operand.
-// fp64 rows are padded to 144 bytes; the 64-byte rows of the other formats
-// are XOR-swizzled in 16-byte chunks so that the 16 rows read by one MFMA
-// fragment load fall in distinct banks.
-template <int PREC>
+// Block-tile shapes.  S128: 128 x 128, four waves (2 x 2) of 64 x 64.
+// S256: 256 x 256, eight waves (2 x 4) of 128 x 64; it halves the operand
+// re-reads per flop, for large problems whose tile count still fills the
+// chip (fp32 and split-bf16 accumulators only: 128 registers per lane).
+struct S128 {
+    static constexpr int BM = 128, BN = 128, WN = 2, NT = 256, FM = 4, FN = 4;
+};
+struct S256 {
+    static constexpr int BM = 256, BN = 256, WN = 4, NT = 512, FM = 8, FN = 4;
+};
+
+// Global <-> LDS staging of one R x BK tile (all planes) of an operand by
+// NT threads.  fp64 rows are padded to 144 bytes.  The 64-byte rows of the
+// other formats are XOR-swizzled in 16-byte chunks, chunk ^ s(row) with
+// s(row) = ((row >> 1) & 3) ^ ((row >> 3) & 1): a 16-byte fragment read by
+// lanes on consecutive rows then touches distinct banks whether the LDS
+// serves 8 lanes over 32 banks or 16 lanes over 64 banks per cycle.
+template <int PREC, int R, int NT>
 struct TileIO {
     typedef GemmCfg<PREC> C;
     static constexpr int ROWB = C::BK * (int)sizeof(typename C::E);  // bytes per row
     static constexpr int UPR = ROWB / 16;                            // 16B units per row
-    static constexpr int UNITS = 128 * UPR * C::PLANES;
-    static constexpr int PER = UNITS / 256;
+    static constexpr int UNITS = R * UPR * C::PLANES;
+    static constexpr int PER = UNITS / NT;
+    static_assert(UNITS % NT == 0, "tile units must divide over the threads");
     static constexpr int LROW = (PREC == 0) ? ROWB + 16 : ROWB;
-    static constexpr int PLANEB = 128 * LROW;
+    static constexpr int PLANEB = R * LROW;
     static constexpr int STAGE = PLANEB * C::PLANES;
 
     __device__ static __forceinline__ int off(int row, int chunk) {
         if constexpr (PREC == 0) return row * LROW + chunk * 16;
-        else return row * LROW + ((chunk ^ ((row >> 2) & 3)) << 4);
+        else return row * LROW + ((chunk ^ ((row >> 1) & 3) ^ ((row >> 3) & 1)) << 4);
     }
     __device__ static void load(u32x4 (&r)[PER], const char *base, int64_t ldb, int64_t planeb,
                                 int64_t row0, int64_t k0b) {
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
-            int u = threadIdx.x + 256 * i;
-            int pl = u / (128 * UPR);
-            int uu = u % (128 * UPR);
+            int u = threadIdx.x + NT * i;
+            int pl = u / (R * UPR);
+            int uu = u % (R * UPR);
             int row = uu / UPR, cu = uu % UPR;
             const char *g = base + pl * planeb + (row0 + row) * ldb + k0b + cu * 16;
             // global address space: these loads only count against vmcnt, so
@@ -637,139 +729,136 @@ struct TileIO {
     __device__ static void store(const u32x4 (&r)[PER], char *lds) {
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
-            int u = threadIdx.x + 256 * i;
-            int pl = u / (128 * UPR);
-            int uu = u % (128 * UPR);
+            int u = threadIdx.x + NT * i;
+            int pl = u / (R * UPR);
+            int uu = u % (R * UPR);
             int row = uu / UPR, cu = uu % UPR;
             *reinterpret_cast<u32x4 *>(lds + pl * PLANEB + off(row, cu)) = r[i];
         }
     }
 };
 
-template <int PREC>
-__device__ __forceinline__ void mma_tile(typename AccT<PREC>::T (&acc)[4][4], const char *As,
-                                         const char *Bs, int wy, int wx, int lane);
-
-template <>
-__device__ __forceinline__ void mma_tile<0>(f64x4 (&acc)[4][4], const char *As, const char *Bs,
-                                            int wy, int wx, int lane) {
-    typedef TileIO<0> IO;
+// One BK step of a wave's FM x FN blocks: A rows from ra0, B rows from rb0
+// (tile-local), fragments read from LDS with the staging layout of R-row
+// tiles (the layout does not depend on R).
+template <int PREC, int FM, int FN, int RA, int RB>
+__device__ __forceinline__ void mma_tile(typename AccT<PREC>::T (&acc)[FM][FN], const char *As,
+                                         const char *Bs, int ra0, int rb0, int lane) {
+    typedef TileIO<PREC, RA, 64> IOA;
+    typedef TileIO<PREC, RB, 64> IOB;
     const int lr = lane & 15, lg = lane >> 4;
+    if constexpr (PREC == 0) {
 #pragma unroll
-    for (int kk = 0; kk < 16; kk += 4) {
-        double a[4], b[4];
+        for (int kk = 0; kk < 16; kk += 4) {
+            double a[FM], b[FN];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            a[i] = *reinterpret_cast<const double *>(As + (wy * 64 + i * 16 + lr) * IO::LROW +
-                                                     (kk + lg) * 8);
-            b[i] = *reinterpret_cast<const double *>(Bs + (wx * 64 + i * 16 + lr) * IO::LROW +
-                                                     (kk + lg) * 8);
+            for (int i = 0; i < FM; ++i)
+                a[i] = *reinterpret_cast<const double *>(As + (ra0 + i * 16 + lr) * IOA::LROW +
+                                                         (kk + lg) * 8);
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+                b[j] = *reinterpret_cast<const double *>(Bs + (rb0 + j * 16 + lr) * IOB::LROW +
+                                                         (kk + lg) * 8);
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+    } else if constexpr (PREC == 1) {
+#pragma unroll
+        for (int kk = 0; kk < 16; kk += 4) {
+            float a[FM], b[FN];
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+                a[i] = *reinterpret_cast<const float *>(As + IOA::off(ra0 + i * 16 + lr, kk >> 2) +
+                                                        lg * 4);
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+                b[j] = *reinterpret_cast<const float *>(Bs + IOB::off(rb0 + j * 16 + lr, kk >> 2) +
+                                                        lg * 4);
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+    } else if constexpr (PREC == 2) {
+        bf16x8 bh[FN], bl[FN];
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            const int rb = IOB::off(rb0 + j * 16 + lr, lg);
+            bh[j] = *reinterpret_cast<const bf16x8 *>(Bs + rb);
+            bl[j] = *reinterpret_cast<const bf16x8 *>(Bs + IOB::PLANEB + rb);
         }
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < FM; ++i) {
+            const int ra = IOA::off(ra0 + i * 16 + lr, lg);
+            const bf16x8 ah = *reinterpret_cast<const bf16x8 *>(As + ra);
+            const bf16x8 al = *reinterpret_cast<const bf16x8 *>(As + IOA::PLANEB + ra);
+            // small cross terms first, then the leading hi*hi term
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+            for (int j = 0; j < FN; ++j) {
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
+            }
+        }
+    } else {
+        i32x4 a[FM], b[FN];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+            a[i] = *reinterpret_cast<const i32x4 *>(As + IOA::off(ra0 + i * 16 + lr, lg));
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+            b[j] = *reinterpret_cast<const i32x4 *>(Bs + IOB::off(rb0 + j * 16 + lr, lg));
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[i], b[j], acc[i][j], 0, 0, 0);
     }
 }
 
-template <>
-__device__ __forceinline__ void mma_tile<1>(f32x4 (&acc)[4][4], const char *As, const char *Bs,
-                                            int wy, int wx, int lane) {
-    typedef TileIO<1> IO;
-    const int lr = lane & 15, lg = lane >> 4;
-#pragma unroll
-    for (int kk = 0; kk < 16; kk += 4) {
-        float a[4], b[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            a[i] = *reinterpret_cast<const float *>(As + IO::off(wy * 64 + i * 16 + lr, kk >> 2) +
-                                                    lg * 4);
-            b[i] = *reinterpret_cast<const float *>(Bs + IO::off(wx * 64 + i * 16 + lr, kk >> 2) +
-                                                    lg * 4);
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
-    }
-}
-
-template <>
-__device__ __forceinline__ void mma_tile<2>(f32x4 (&acc)[4][4], const char *As, const char *Bs,
-                                            int wy, int wx, int lane) {
-    typedef TileIO<2> IO;
-    const int lr = lane & 15, lg = lane >> 4;
-    bf16x8 ah[4], al[4], bh[4], bl[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int ra = IO::off(wy * 64 + i * 16 + lr, lg);
-        const int rb = IO::off(wx * 64 + i * 16 + lr, lg);
-        ah[i] = *reinterpret_cast<const bf16x8 *>(As + ra);
-        al[i] = *reinterpret_cast<const bf16x8 *>(As + IO::PLANEB + ra);
-        bh[i] = *reinterpret_cast<const bf16x8 *>(Bs + rb);
-        bl[i] = *reinterpret_cast<const bf16x8 *>(Bs + IO::PLANEB + rb);
-    }
-    // small cross terms first, then the leading hi*hi term
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
-        }
-}
-
-template <>
-__device__ __forceinline__ void mma_tile<3>(i32x4 (&acc)[4][4], const char *As, const char *Bs,
-                                            int wy, int wx, int lane) {
-    typedef TileIO<3> IO;
-    const int lr = lane & 15, lg = lane >> 4;
-    i32x4 a[4], b[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        a[i] = *reinterpret_cast<const i32x4 *>(As + IO::off(wy * 64 + i * 16 + lr, lg));
-        b[i] = *reinterpret_cast<const i32x4 *>(Bs + IO::off(wx * 64 + i * 16 + lr, lg));
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[i], b[j], acc[i][j], 0, 0, 0);
+// LDS bytes of one double-buffered (A, B) stage pair for a shape.
+template <int PREC, class SH>
+constexpr int gemm_stage_bytes() {
+    return TileIO<PREC, SH::BM, SH::NT>::STAGE + TileIO<PREC, SH::BN, SH::NT>::STAGE;
 }
 
 // K loop of one (A plane set, B plane set) pass with register prefetch and
 // double-buffered LDS (one barrier per K step).
-template <int PREC>
-__device__ __forceinline__ void gemm_pass(typename AccT<PREC>::T (&acc)[4][4], const char *Ab,
-                                          const char *Bb, int64_t ldb, int64_t planeb,
-                                          int64_t w0, int64_t x0, int64_t npad, char *lds) {
-    typedef TileIO<PREC> IO;
-    constexpr int STAGE = IO::STAGE;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, wy = wv >> 1, wx = wv & 1;
+template <int PREC, class SH>
+__device__ __forceinline__ void gemm_pass(typename AccT<PREC>::T (&acc)[SH::FM][SH::FN],
+                                          const char *Ab, const char *Bb, int64_t ldb,
+                                          int64_t planeb, int64_t w0, int64_t x0, int64_t npad,
+                                          char *lds) {
+    typedef TileIO<PREC, SH::BM, SH::NT> IOA;
+    typedef TileIO<PREC, SH::BN, SH::NT> IOB;
+    constexpr int PAIR = IOA::STAGE + IOB::STAGE;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int ra0 = (wv / SH::WN) * SH::FM * 16, rb0 = (wv % SH::WN) * SH::FN * 16;
     constexpr int KB = GemmCfg<PREC>::BK * (int)sizeof(typename GemmCfg<PREC>::E);
     const int64_t nk = npad / GemmCfg<PREC>::BK;
-    u32x4 ra[IO::PER], rb[IO::PER];
-    IO::load(ra, Ab, ldb, planeb, w0, 0);
-    IO::load(rb, Bb, ldb, planeb, x0, 0);
-    IO::store(ra, lds);
-    IO::store(rb, lds + STAGE);
+    u32x4 ra[IOA::PER], rb[IOB::PER];
+    IOA::load(ra, Ab, ldb, planeb, w0, 0);
+    IOB::load(rb, Bb, ldb, planeb, x0, 0);
+    IOA::store(ra, lds);
+    IOB::store(rb, lds + IOA::STAGE);
     __syncthreads();
     for (int64_t kt = 0; kt < nk; ++kt) {
         const int cur = (int)(kt & 1);
-        char *As = lds + cur * 2 * STAGE;
-        char *Bs = As + STAGE;
+        char *As = lds + cur * PAIR;
+        char *Bs = As + IOA::STAGE;
         // Prefetch the next K tile (the last step re-reads its own tile into
         // the idle buffer, which keeps the loop free of branches).
         const int64_t kn = (kt + 1 < nk) ? kt + 1 : kt;
-        IO::load(ra, Ab, ldb, planeb, w0, kn * KB);
-        IO::load(rb, Bb, ldb, planeb, x0, kn * KB);
-        mma_tile<PREC>(acc, As, Bs, wy, wx, lane);
-        char *An = lds + (1 - cur) * 2 * STAGE;
-        IO::store(ra, An);
-        IO::store(rb, An + STAGE);
+        IOA::load(ra, Ab, ldb, planeb, w0, kn * KB);
+        IOB::load(rb, Bb, ldb, planeb, x0, kn * KB);
+        mma_tile<PREC, SH::FM, SH::FN, SH::BM, SH::BN>(acc, As, Bs, ra0, rb0, lane);
+        char *An = lds + (1 - cur) * PAIR;
+        IOA::store(ra, An);
+        IOB::store(rb, An + IOA::STAGE);
         __syncthreads();
     }
 }
@@ -782,11 +871,12 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t G) {
     return x * per + (x < rem ? x : rem) + idx;
 }
 
-template <int PREC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+template <int PREC, class SH>
+__global__ __launch_bounds__(SH::NT) __attribute__((amdgpu_waves_per_eu(2)))
 void k_gemm(const GemmDesc *D, int nprob) {
-    typedef TileIO<PREC> IO;
     typedef typename AccT<PREC>::T AT;
+    constexpr int FM = SH::FM, FN = SH::FN;
+    static_assert(PREC == 1 || PREC == 2 || SH::BM == 128, "large tiles: fp32 accumulators only");
     extern __shared__ __align__(16) char lds[];
     const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
     const int p = find_problem(D, nprob, b);
@@ -798,49 +888,49 @@ void k_gemm(const GemmDesc *D, int nprob) {
     const int64_t gsz = (T - first) < GM ? (T - first) : GM;
     const int64_t lg = local - first * T;
     const int64_t tm = first + lg % gsz, tn = lg / gsz;
-    const int64_t w0 = tm * 128, x0 = tn * 128;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, wy = wv >> 1, wx = wv & 1;
+    const int64_t w0 = tm * SH::BM, x0 = tn * SH::BN;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t wr0 = w0 + (wv / SH::WN) * FM * 16, xc0 = x0 + (wv % SH::WN) * FN * 16;
     constexpr int ES = (int)sizeof(typename GemmCfg<PREC>::E);
     const int64_t ldb = d.ld * ES, planeb = d.plane * ES;
 
-    AT acc[4][4];
-    long long resi[4][4][4];
+    AT acc[FM][FN];
+    long long resi[PREC == 3 ? FM : 1][PREC == 3 ? FN : 1][4];
     (void)resi;
     if constexpr (PREC == 3) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < FM; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
+            for (int j = 0; j < FN; ++j)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) resi[i][j][r] = 0;
         const int nla = d.la_p ? *d.la_p : d.la, nlb = d.lb_p ? *d.lb_p : d.lb;
         for (int la = 0; la < nla; ++la)
             for (int lb = 0; lb < nlb; ++lb) {
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
+                for (int i = 0; i < FM; ++i)
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) acc[i][j] = AT{0, 0, 0, 0};
-                gemm_pass<PREC>(acc, static_cast<const char *>(d.A) + la * planeb,
-                                static_cast<const char *>(d.B) + lb * planeb, ldb, planeb, w0, x0,
-                                d.npad, lds);
+                    for (int j = 0; j < FN; ++j) acc[i][j] = AT{0, 0, 0, 0};
+                gemm_pass<PREC, SH>(acc, static_cast<const char *>(d.A) + la * planeb,
+                                    static_cast<const char *>(d.B) + lb * planeb, ldb, planeb, w0,
+                                    x0, d.npad, lds);
                 const long long wgt = 1ll << (7 * (la + lb));
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
+                for (int i = 0; i < FM; ++i)
 #pragma unroll
-                    for (int j = 0; j < 4; ++j)
+                    for (int j = 0; j < FN; ++j)
 #pragma unroll
                         for (int r = 0; r < 4; ++r) resi[i][j][r] += wgt * (long long)acc[i][j][r];
             }
     } else {
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < FM; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] = AT{0, 0, 0, 0};
-        gemm_pass<PREC>(acc, static_cast<const char *>(d.A), static_cast<const char *>(d.B), ldb,
-                        planeb, w0, x0, d.npad, lds);
+            for (int j = 0; j < FN; ++j) acc[i][j] = AT{0, 0, 0, 0};
+        gemm_pass<PREC, SH>(acc, static_cast<const char *>(d.A), static_cast<const char *>(d.B),
+                            ldb, planeb, w0, x0, d.npad, lds);
     }
-    // value(i, j, r) of row w0+wy*64+i*16+mfma_row(lane,r), column
-    // x0+wx*64+j*16+lane%16
+    // value(i, j, r) of row wr0+i*16+mfma_row(lane,r), column xc0+j*16+lane%16
     auto value = [&](int i, int j, int r) {
         if constexpr (PREC == 3) return resi[i][j][r];
         else return (double)acc[i][j][r];
@@ -852,9 +942,9 @@ void k_gemm(const GemmDesc *D, int nprob) {
             if (d.mx_out) {
                 unsigned long long mloc = 0;
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
+                for (int i = 0; i < FM; ++i)
 #pragma unroll
-                    for (int j = 0; j < 4; ++j)
+                    for (int j = 0; j < FN; ++j)
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
                             long long v = resi[i][j][r];
@@ -864,14 +954,16 @@ void k_gemm(const GemmDesc *D, int nprob) {
                 atomicMax(d.mx_out, mloc);
             }
         }
+#pragma clang loop unroll(full)
+        for (int ib = 0; ib < FM; ib += 4)
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = ib; i < ib + 4; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
+            for (int j = 0; j < FN; ++j)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    int64_t w = w0 + wy * 64 + i * 16 + mfma_row<PREC>(lane, r);
-                    int64_t x = x0 + wx * 64 + j * 16 + (lane & 15);
+                    int64_t w = wr0 + i * 16 + mfma_row<PREC>(lane, r);
+                    int64_t x = xc0 + j * 16 + (lane & 15);
                     if (w < n && x < n) {
                         int64_t o = w * d.ldc + x;
                         if constexpr (PREC == 3) static_cast<long long *>(d.C)[o] = value(i, j, r);
@@ -884,14 +976,16 @@ void k_gemm(const GemmDesc *D, int nprob) {
     // Fused consumer: sum_{w,x} C(w,x) prod Z(w,x) prod aw(w) prod bx(x).
     typedef typename std::conditional<PREC == 3, i128, double>::type Wd;
     Wd part = 0;
+#pragma clang loop unroll(full)
+    for (int ib = 0; ib < FM; ib += 4)
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = ib; i < ib + 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < FN; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                int64_t w = w0 + wy * 64 + i * 16 + mfma_row<PREC>(lane, r);
-                int64_t x = x0 + wx * 64 + j * 16 + (lane & 15);
+                int64_t w = wr0 + i * 16 + mfma_row<PREC>(lane, r);
+                int64_t x = xc0 + j * 16 + (lane & 15);
                 if (w >= n || x >= n) continue;
                 Wd val = (Wd)value(i, j, r);
                 for (int k = 0; k < d.nZ; ++k) {
@@ -917,8 +1011,8 @@ void k_gemm(const GemmDesc *D, int nprob) {
     Wd *red = reinterpret_cast<Wd *>(lds);
     red[threadIdx.x] = part;
     __syncthreads();
-    // fixed-order tree over the 256 partial sums
-    for (int s = 128; s > 0; s >>= 1) {
+    // fixed-order tree over the NT partial sums
+    for (int s = SH::NT / 2; s > 0; s >>= 1) {
         if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
         __syncthreads();
     }
@@ -1020,6 +1114,22 @@ hipError_t launch_elim1(const Elim1Desc *d, int nprob, int64_t total_tiles, int 
     return hipGetLastError();
 }
 
+hipError_t launch_colred(const ColDesc *d, int nprob, int64_t total_tiles, int nm, int domain,
+                         hipStream_t s) {
+    dim3 grid((unsigned)total_tiles);
+#define USTAT_COLRED(NM_)                                                                   \
+    if (nm == NM_) {                                                                        \
+        if (domain == DOM_FP) hipLaunchKernelGGL((k_colred<DOM_FP, NM_>), grid, dim3(256), 0, s, d, nprob); \
+        else hipLaunchKernelGGL((k_colred<DOM_INT, NM_>), grid, dim3(256), 0, s, d, nprob);  \
+        return hipGetLastError();                                                           \
+    }
+    USTAT_COLRED(1)
+    USTAT_COLRED(2)
+    USTAT_COLRED(3)
+#undef USTAT_COLRED
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_reduce(const ReduceDesc *d, int nprob, int64_t max_len, int domain,
                          hipStream_t s) {
     dim3 grid((unsigned)nprob, (unsigned)std::max<int64_t>(1, std::min<int64_t>(64, (max_len + 255) / 256)));
@@ -1047,30 +1157,35 @@ hipError_t launch_prep(const PrepDesc *d, int nprob, int64_t total_tiles, int do
     return hipGetLastError();
 }
 
-template <int PREC>
+template <int PREC, class SH>
 static hipError_t launch_gemm_t(const GemmDesc *d, int nprob, int64_t total_tiles, hipStream_t s) {
-    constexpr int STAGE = TileIO<PREC>::STAGE;
-    size_t lds = (size_t)4 * STAGE;
-    size_t red = 256 * 16;
+    size_t lds = (size_t)2 * gemm_stage_bytes<PREC, SH>();
+    size_t red = (size_t)SH::NT * 16;
     if (lds < red) lds = red;
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_gemm<PREC>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_gemm<PREC, SH>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL(k_gemm<PREC>, dim3((unsigned)total_tiles), dim3(256), lds, s, d, nprob);
+    hipLaunchKernelGGL((k_gemm<PREC, SH>), dim3((unsigned)total_tiles), dim3(SH::NT), lds, s, d,
+                       nprob);
     return hipGetLastError();
 }
 
 hipError_t launch_gemm(const GemmDesc *d, int nprob, int64_t total_tiles, int precision,
-                       hipStream_t s) {
+                       int tile, hipStream_t s) {
+    if (tile == 256) {
+        if (precision == 1) return launch_gemm_t<1, S256>(d, nprob, total_tiles, s);
+        if (precision == 2) return launch_gemm_t<2, S256>(d, nprob, total_tiles, s);
+        return hipErrorInvalidValue;
+    }
     switch (precision) {
-        case 0: return launch_gemm_t<0>(d, nprob, total_tiles, s);
-        case 1: return launch_gemm_t<1>(d, nprob, total_tiles, s);
-        case 2: return launch_gemm_t<2>(d, nprob, total_tiles, s);
-        default: return launch_gemm_t<3>(d, nprob, total_tiles, s);
+        case 0: return launch_gemm_t<0, S128>(d, nprob, total_tiles, s);
+        case 1: return launch_gemm_t<1, S128>(d, nprob, total_tiles, s);
+        case 2: return launch_gemm_t<2, S128>(d, nprob, total_tiles, s);
+        default: return launch_gemm_t<3, S128>(d, nprob, total_tiles, s);
     }
 }
 

@@ -42,8 +42,8 @@ struct DiagDesc {
 
 // Strip partials of y(w) = sum_v prod_k A_k(v, w) prod_j s_j(v) with every
 // operand stored (v, w) (trans == 0): part[tv * n + w] holds the sum over
-// rows [tv*kElimStrip, (tv+1)*kElimStrip) for the 256 columns of strip tw;
-// tiles_v = ceil(n / kElimStrip), tiles_w = ceil(n / 256).
+// rows [tv*strip, (tv+1)*strip) for the 256 columns of strip tw;
+// tiles_v = ceil(n / strip), tiles_w = ceil(n / 256).
 struct Elim1Desc {
     int64_t n;
     int32_t nA, nS;
@@ -52,6 +52,31 @@ struct Elim1Desc {
     void *part;
     int64_t tile_start;  // first block index of this problem in the launch
     int32_t tiles_v, tiles_w;
+    int32_t strip;       // rows per block (a multiple of 32)
+};
+
+// Grouped column reductions over the same few matrices: for every output o
+// of the group, y_o(w) = sum_v prod_k M_k(v,w)^e[o][k] prod_j s_oj(v), with
+// the k-th factor taken as 0 on the diagonal where zd[o][k].  Each element
+// of each distinct matrix is read once for all outputs.  Partials as for
+// Elim1Desc, one buffer per output; strips and tiles as there.
+constexpr int kColMat = 3;  // distinct matrices per group
+constexpr int kColOut = 8;  // outputs per group
+struct ColOut {
+    int8_t e[kColMat];
+    int8_t zd[kColMat];
+    int32_t nS;
+    const void *s[kMaxVec];
+    void *part;
+};
+struct ColDesc {
+    int64_t n;
+    int32_t nm, nout;
+    MatRef M[kColMat];  // stored (v, w)
+    ColOut o[kColOut];
+    int64_t tile_start;
+    int32_t tiles_v, tiles_w;
+    int32_t strip;  // rows per block (a multiple of 32)
 };
 
 // out[j] = (sum_{t < T} part[t * stride + j]) * prod_q mul_q[j], j < len,
@@ -155,21 +180,37 @@ struct SliceDesc {
 
 constexpr int kGemmTile = 128;
 constexpr int kTile = 64;
-constexpr int kElimStrip = 512;
+constexpr int kElimStrip = 512;  // largest rows per column-reduction block
+
+// Rows per column-reduction block for size n: about 1024 blocks per
+// problem (so that even a single problem fills the chip), in multiples of
+// 32 rows, between 32 and kElimStrip.
+inline int elim_strip_rows(int64_t n) {
+    const int64_t wstrips = (n + 255) / 256;
+    int64_t s = (n * wstrips / 1024) / 32 * 32;
+    if (s < 32) s = 32;
+    if (s > kElimStrip) s = kElimStrip;
+    return (int)s;
+}
 
 hipError_t launch_rbf(const double *X, int64_t n, int32_t d, double divisor, void *out,
                       int32_t dtype, hipStream_t s);
 hipError_t launch_diag(const DiagDesc *d, int nprob, int64_t max_n, int domain, hipStream_t s);
 hipError_t launch_elim1(const Elim1Desc *d, int nprob, int64_t total_tiles, int domain,
                         hipStream_t s);
+// nm: the number of distinct matrices of every group in d (1..kColMat)
+hipError_t launch_colred(const ColDesc *d, int nprob, int64_t total_tiles, int nm, int domain,
+                         hipStream_t s);
 hipError_t launch_reduce(const ReduceDesc *d, int nprob, int64_t max_len, int domain,
                          hipStream_t s);
 hipError_t launch_elim0(const Elim0Desc *d, int nprob, int domain, hipStream_t s);
 hipError_t launch_transpose(const TransDesc *d, int nprob, int64_t total_tiles, hipStream_t s);
 hipError_t launch_prep(const PrepDesc *d, int nprob, int64_t total_tiles, int domain,
                        hipStream_t s);
+// tile: 128 (any precision) or 256 (fp32 and split-bf16; npad % 256 == 0,
+// GemmDesc::tiles counted in 256-row tiles)
 hipError_t launch_gemm(const GemmDesc *d, int nprob, int64_t total_tiles, int precision,
-                       hipStream_t s);
+                       int tile, hipStream_t s);
 hipError_t launch_absmax_i8(const int8_t *const *src, const int64_t *n, int nprob,
                             unsigned long long *mx, hipStream_t s);
 hipError_t launch_slicesrc(const SliceDesc *d, int nprob, int64_t total_tiles, int domain,

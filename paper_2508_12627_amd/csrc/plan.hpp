@@ -83,6 +83,7 @@ struct PlanOptions {
     int order = 0;
     int sparsify = 0;
     bool cse = true;  // merge equal steps across partitions at evaluation
+    bool symmetric = false;  // caller's factor matrices are symmetric
     uint64_t workspace_limit = 0;
     std::string cost_model_path;
     double n_hint = 4096.0;  // sample size orders are ranked for

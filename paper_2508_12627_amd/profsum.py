@@ -1,0 +1,123 @@
+"""Summaries of rocprofv3 results (its SQLite output) for the engine's kernels.
+
+    python -m paper_2508_12627_amd.profsum kernels RESULTS.db
+        per-kernel calls, total and average duration (kernel trace)
+    python -m paper_2508_12627_amd.profsum traffic --fetch F.db --write W.db \\
+        --cal-fetch CF.db --cal-write CW.db --cal-bytes B --kernel NAME [--out T.json]
+        [--meta KEY=VALUE ...]
+        HBM bytes per launch of the kernels whose name contains NAME, from
+        FETCH_SIZE and WRITE_SIZE runs, each scaled by what the same counter
+        reads for a plain device copy of B bytes (the calibration runs)
+
+The traffic record carries a hash of the kernel sources, so a reader can
+tell whether the counters still describe the current kernels.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import hashlib
+import json
+import os
+import sqlite3
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = [os.path.join(HERE, "csrc", "kernels.hip"), os.path.join(HERE, "csrc", "kernels.hpp")]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def kernel_stats(db: str):
+    """[(name, calls, total_us, average_us, percent)] from a kernel trace."""
+    con = sqlite3.connect(db)
+    rows = con.execute("select name, total_calls, total_duration, average, percentage "
+                       "from top_kernels").fetchall()
+    con.close()
+    # the view reports microseconds
+    return [(n, int(c), float(t), float(a), float(p)) for n, c, t, a, p in rows]
+
+
+def counter_per_dispatch(db: str, counter: str):
+    """{kernel name: [value per dispatch]} for one counter."""
+    con = sqlite3.connect(db)
+    rows = con.execute("select kernel_name, dispatch_id, value from counters_collection "
+                       "where counter_name = ?", (counter,)).fetchall()
+    con.close()
+    per = collections.defaultdict(lambda: collections.defaultdict(float))
+    for k, disp, v in rows:
+        per[k][disp] += v
+    return {k: list(d.values()) for k, d in per.items()}
+
+
+def _mean(v):
+    return sum(v) / len(v) if v else 0.0
+
+
+def traffic(fetch_db, write_db, cal_fetch_db, cal_write_db, cal_bytes, kernel):
+    """Per-launch HBM bytes of the matching kernels, calibrated on a copy."""
+    cf = counter_per_dispatch(cal_fetch_db, "FETCH_SIZE")
+    cw = counter_per_dispatch(cal_write_db, "WRITE_SIZE")
+    # the copy kernel is the one that moved the most bytes
+    cf_kib = max((_mean(v) for v in cf.values()), default=0.0)
+    cw_kib = max((_mean(v) for v in cw.values()), default=0.0)
+    fs = cal_bytes / (cf_kib * 1024.0) if cf_kib else None
+    ws = cal_bytes / (cw_kib * 1024.0) if cw_kib else None
+    f = counter_per_dispatch(fetch_db, "FETCH_SIZE")
+    w = counter_per_dispatch(write_db, "WRITE_SIZE")
+    out = {"calibration": {"copy_bytes": cal_bytes, "fetch_kib": cf_kib, "write_kib": cw_kib,
+                           "fetch_scale": fs, "write_scale": ws},
+           "source_hash": kernel_source_hash(), "kernels": {}}
+    for name in sorted(set(f) | set(w)):
+        if kernel not in name:
+            continue
+        fk, wk = _mean(f.get(name, [])), _mean(w.get(name, []))
+        out["kernels"][name] = {
+            "launches": max(len(f.get(name, [])), len(w.get(name, []))),
+            "fetch_kib_raw": fk, "write_kib_raw": wk,
+            "fetch_bytes": fk * 1024.0 * fs if fs else None,
+            "write_bytes": wk * 1024.0 * ws if ws else None,
+            "bytes_per_launch": (fk * 1024.0 * fs + wk * 1024.0 * ws) if fs and ws else None}
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    k = sub.add_parser("kernels")
+    k.add_argument("db")
+    t = sub.add_parser("traffic")
+    for a in ("--fetch", "--write", "--cal-fetch", "--cal-write"):
+        t.add_argument(a, required=True)
+    t.add_argument("--cal-bytes", type=float, required=True)
+    t.add_argument("--kernel", required=True)
+    t.add_argument("--out", default=None)
+    t.add_argument("--meta", action="append", default=[], metavar="KEY=VALUE",
+                   help="extra fields of the record (workload, precision, command)")
+    args = ap.parse_args(argv)
+    if args.cmd == "kernels":
+        print(f"{'kernel':<70} {'calls':>6} {'total_us':>11} {'avg_us':>9} {'pct':>6}")
+        for n, c, tot, avg, pct in kernel_stats(args.db):
+            print(f"{n[:70]:<70} {c:>6} {tot:>11.1f} {avg:>9.2f} {pct:>6.2f}")
+        return 0
+    rec = traffic(args.fetch, args.write, args.cal_fetch, args.cal_write, args.cal_bytes,
+                  args.kernel)
+    for kv in args.meta:
+        k, _, v = kv.partition("=")
+        rec[k] = v
+    text = json.dumps(rec, indent=1)
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(text + "\n")
+    print(text)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

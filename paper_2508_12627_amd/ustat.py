@@ -30,6 +30,7 @@ ORDERS = {"minfill": ORDER_MINFILL, "exhaustive": ORDER_EXHAUSTIVE, "learned": O
 STATUS = {0: "ok", 1: "invalid", 2: "unsupported", 3: "nomem", 4: "hip", 5: "overflow",
           6: "infeasible"}
 FLAG_NO_CSE = 1
+FLAG_SYMMETRIC = 2
 FACTOR_DTYPE = {F64: torch.float64, F32: torch.float32, BF16X3: torch.float32, I8: torch.int8}
 PROFILE_KINDS = {"prep": 0, "gemm": 1, "elim1": 2, "reduce": 3, "rbf": 4}
 
@@ -146,14 +147,14 @@ def _edges_array(edges: Sequence[Tuple[int, int]]):
 
 def ustat_plan_create(m: int, edges, precision="f64", order="minfill", sparsify=False,
                       workspace_limit: int = 0, cost_model_path: Optional[str] = None,
-                      cse: bool = True, n_hint: int = 0):
+                      cse: bool = True, n_hint: int = 0, symmetric: bool = False):
     L = load_library()
     o = PlanOpts()
     _check(L.ustat_plan_opts_default(ctypes.byref(o)))
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     o.order = ORDERS[order] if isinstance(order, str) else int(order)
     o.sparsify = 1 if sparsify else 0
-    o.flags = 0 if cse else FLAG_NO_CSE
+    o.flags = (0 if cse else FLAG_NO_CSE) | (FLAG_SYMMETRIC if symmetric else 0)
     o.workspace_limit = int(workspace_limit)
     if o.order == ORDER_LEARNED and not cost_model_path:
         cost_model_path = DEFAULT_COST_MODEL
@@ -356,12 +357,12 @@ class Plan:
 
     def __init__(self, m: int, edges, precision="f64", order="minfill", sparsify=False,
                  workspace_limit: int = 0, cost_model_path: Optional[str] = None,
-                 cse: bool = True, n_hint: int = 0):
+                 cse: bool = True, n_hint: int = 0, symmetric: bool = False):
         self.m = int(m)
         self.edges = [tuple(e) for e in edges]
         self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         self.h = ustat_plan_create(m, edges, precision, order, sparsify, workspace_limit,
-                                   cost_model_path, cse, n_hint)
+                                   cost_model_path, cse, n_hint, symmetric)
 
     def __del__(self):
         h = getattr(self, "h", None)

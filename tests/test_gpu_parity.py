@@ -229,6 +229,74 @@ def test_cycle4_workload_full_size(U, c2_data, prec):
     assert r2.value == r1.value  # replays are bitwise identical
 
 
+@pytest.mark.parametrize("prec", ["f32", "bf16x3"])
+def test_large_tiles_ragged(U, prec):
+    """n = 4000 pads to 4096, so the GEMM level takes 256-wide tiles whose
+    last row and column of tiles are partly outside the matrix: the 4-cycle
+    U against the oracle's closed form (stored product consumed by column
+    reductions) and rank-2 factors on the 5-cycle-with-chord kernel against
+    the subset DP (fused final GEMMs)."""
+    import torch
+    n, d = 4000, 16
+    X = W.gaussian_samples(n, d, seed=21)
+    K = oracle.rbf_matrix(X, 2.0 * d)
+    ref = oracle.cycle4_closed_form(K)
+    K2 = K @ K
+    vfin = float(np.sum(K2 * K2))
+    say(f"large tiles cycle4 n={n} {prec}")
+    r = U.Plan(4, W.CYCLE4, precision=prec).eval_samples(dev(X, torch.float64), 32.0)
+    assert abs(r.value - ref) / vfin <= TOL[prec]
+    (F, G), = W.lowrank_factors(1, n, 2, seed=22, lo=0.1, hi=1.0)
+    ref = oracle.ustat_lowrank(W.CYCLE5_CHORD, [F] * 6, [G] * 6)
+    say(f"large tiles lowrank c5chord n={n} {prec}")
+    P = U.Plan(5, W.CYCLE5_CHORD, precision=prec)
+    res = P.eval([dev(F @ G.T, P.factor_dtype)] * 6)
+    assert abs(res.value - ref) <= TOL[prec] * abs(ref)
+
+
+def test_large_tiles_batched_level(U):
+    """Four n = 2048 datasets put 4 x 64 tiles of 256 in each GEMM level, so
+    the batched launch takes 256-wide tiles while a single dataset (64 such
+    tiles) takes 128-wide ones: both agree to rounding and match the f64
+    path."""
+    import torch
+    ns = [2048] * 4
+    Xs = [dev(W.gaussian_samples(n, 16, seed=80 + i), torch.float64) for i, n in enumerate(ns)]
+    P = U.Plan(4, W.CYCLE4, precision="bf16x3")
+    say("large tiles batched 4 x 2048 bf16x3")
+    rb = P.eval_batched(Xs, 32.0)
+    r64 = U.Plan(4, W.CYCLE4, precision="f64").eval_batched(Xs, 32.0)
+    for i, X in enumerate(Xs):
+        single = P.eval_samples(X, 32.0)
+        assert abs(rb[i].value - single.value) <= 1e-6 * single.err_scale
+        assert abs(rb[i].value - r64[i].value) <= 1e-6 * r64[i].err_scale
+
+
+@pytest.mark.parametrize("name", ["cycle4", "c5chord", "bowtie"])
+def test_symmetric_factors_flag(U, name):
+    """With symmetric factor matrices the symmetric flag (no transposed
+    copies, orientation-merged steps) gives U within rounding of the default
+    path in fp64 and bit-identical exact counts, and matches brute force."""
+    import torch
+    edges = GRAPHS[name]
+    m = nverts(edges)
+    n = 21
+    (M,) = W.random_matrices(1, n, seed=31, lo=0.0, hi=1.0)
+    M = 0.5 * (M + M.T)
+    ref = oracle.ustat_bruteforce(edges, [M] * len(edges))
+    Kd = dev(M, torch.float64)
+    say(f"symmetric flag {name} n={n}")
+    a = U.Plan(m, edges, precision="f64", symmetric=True).eval([Kd] * len(edges))
+    b = U.Plan(m, edges, precision="f64").eval([Kd] * len(edges))
+    assert abs(a.value - b.value) <= 1e-12 * b.err_scale
+    assert abs(a.value - ref) <= 1e-12 * a.err_scale
+    A = W.erdos_renyi(300, 0.1, seed=6)
+    Ad = dev(A, torch.int8)
+    ai = U.Plan(m, edges, precision="i8", symmetric=True).eval([Ad] * len(edges))
+    bi = U.Plan(m, edges, precision="i8").eval([Ad] * len(edges))
+    assert ai.exact == bi.exact
+
+
 def test_cycle5_er_full_size_exact(U):
     """Exact 5-cycle count of G(8192, 0.01) on the int8 path."""
     import torch
@@ -239,6 +307,8 @@ def test_cycle5_er_full_size_exact(U):
     say("cycle5 ER n=8192 gpu")
     r = U.Plan(5, W.CYCLE5, precision="i8").eval([dev(A, torch.int8)] * 5)
     assert r.exact == ref
+    rs = U.Plan(5, W.CYCLE5, precision="i8", symmetric=True).eval([dev(A, torch.int8)] * 5)
+    assert rs.exact == ref
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3"])
