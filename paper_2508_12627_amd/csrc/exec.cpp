@@ -163,6 +163,8 @@ struct LevelWork {
     std::vector<ColDesc> col[kColMat];  // grouped column reductions, by matrix count
     int64_t col_tiles[kColMat] = {0, 0, 0};
     double col_bytes[kColMat] = {0, 0, 0};  // algorithmic HBM bytes per launch
+    int col_maxout[kColMat] = {0, 0, 0};     // largest output count of a group
+    int col_dtype[kColMat] = {-2, -2, -2};  // DType of every matrix, -1 if mixed, -2 none yet
     size_t off_col[kColMat] = {0, 0, 0};
     double e1_bytes = 0, prep_bytes = 0, tr_bytes = 0;  // algorithmic HBM bytes
     std::vector<TransDesc> tr;
@@ -844,6 +846,11 @@ void layout_column_reductions(const std::vector<ColPending> &recs, LevelWork &W,
             c.o[o].part = partials(recs[g.outs[o].rec], c.tiles_v);
         }
         const int b = c.nm - 1;
+        W.col_maxout[b] = std::max(W.col_maxout[b], c.nout);
+        for (int k = 0; k < c.nm; ++k) {
+            int &cd = W.col_dtype[b];
+            cd = cd == -2 ? c.M[k].dtype : (cd == c.M[k].dtype ? cd : -1);
+        }
         c.tile_start = W.col_tiles[b];
         W.col_tiles[b] += (int64_t)c.tiles_v * c.tiles_w;
         W.col[b].push_back(c);
@@ -1599,7 +1606,8 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
                 if (W.col[k].empty()) continue;
                 ProfScope ps(prof, KIND_ELIM1, stream, 0, W.col_bytes[k]);
                 e = launch_colred(reinterpret_cast<ColDesc *>(dd + W.off_col[k]), (int)W.col[k].size(),
-                                  W.col_tiles[k], k + 1, cfg.domain, stream);
+                                  W.col_tiles[k], k + 1, W.col_maxout[k], W.col_dtype[k],
+                                  cfg.domain, stream);
                 if (e != hipSuccess) return fail(e, "column reduction");
             }
             if (!W.e1.empty()) {

@@ -105,48 +105,87 @@ __device__ __forceinline__ float bf16_to_f32(uint16_t h) {
 
 // ----------------------------------------------------------------- RBF
 
-// K_ij = exp(-||x_i - x_j||^2 / divisor), squared distance from direct
-// differences in fp64 (so K_ii = 1 exactly); 64 x 64 output tile per block.
+// RBF factor K(i,j) = exp(-||x_i - x_j||^2 / divisor) (Algorithm 1 with the
+// kernel on an edge as the factor).  Only tiles on or above the diagonal
+// are computed; each is written at (i, j) and, staged through LDS, at
+// (j, i), so K is symmetric bit for bit and its diagonal is exactly 1.
+// Squared distances are summed over coordinates in increasing order, in
+// fp64, from direct differences.  Tile 64 x 64, each thread 4 x 4.
 __global__ __launch_bounds__(256) void k_rbf(const double *__restrict__ X, int64_t n, int32_t d,
                                              double inv_div, void *__restrict__ out,
                                              int32_t dtype) {
-    __shared__ double xi[64][33];
-    __shared__ double xj[64][33];
-    const int t = threadIdx.x;
+    if (blockIdx.y > blockIdx.x) return;  // lower-triangle tiles come from the mirror
+    __shared__ double sm[2 * 64 * 33];  // x rows of the tile's i and j ranges
+    double(*xi)[33] = reinterpret_cast<double(*)[33]>(sm);
+    double(*xj)[33] = reinterpret_cast<double(*)[33]>(sm + 64 * 33);
+    const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
     const int64_t i0 = (int64_t)blockIdx.y * 64, j0 = (int64_t)blockIdx.x * 64;
-    const int c = t & 63, rg = t >> 6;
-    double acc[16];
+    double acc[4][4];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) acc[r] = 0.0;
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[a][c] = 0.0;
     for (int k0 = 0; k0 < d; k0 += 32) {
         for (int e = t; e < 64 * 32; e += 256) {
-            int rr = e >> 5, kk = e & 31;
-            int64_t gi = i0 + rr, gj = j0 + rr;
-            int gk = k0 + kk;
+            const int rr = e >> 5, kk = e & 31;
+            const int64_t gi = i0 + rr, gj = j0 + rr;
+            const int gk = k0 + kk;
             xi[rr][kk] = (gi < n && gk < d) ? X[gi * d + gk] : 0.0;
             xj[rr][kk] = (gj < n && gk < d) ? X[gj * d + gk] : 0.0;
         }
         __syncthreads();
         const int kmax = min(32, d - k0);
         for (int kk = 0; kk < kmax; ++kk) {
-            double b = xj[c][kk];
+            double av[4], bv[4];
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                double diff = xi[rg + 4 * r][kk] - b;
-                acc[r] = fma(diff, diff, acc[r]);
-            }
+            for (int a = 0; a < 4; ++a) av[a] = xi[ty * 4 + a][kk];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) bv[c] = xj[tx * 4 + c][kk];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const double diff = av[a] - bv[c];
+                    acc[a][c] = fma(diff, diff, acc[a][c]);
+                }
         }
         __syncthreads();
     }
-    const int64_t j = j0 + c;
-    if (j >= n) return;
+    double val[4][4];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        int64_t i = i0 + rg + 4 * r;
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) val[a][c] = exp(-acc[a][c] * inv_div);
+    // direct tile: rows i0 + 4 ty + a, columns j0 + 4 tx + c
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const int64_t i = i0 + ty * 4 + a;
         if (i >= n) continue;
-        double v = exp(-acc[r] * inv_div);
-        if (dtype == DT_F64) static_cast<double *>(out)[i * n + j] = v;
-        else static_cast<float *>(out)[i * n + j] = (float)v;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int64_t j = j0 + tx * 4 + c;
+            if (j >= n) continue;
+            if (dtype == DT_F64) static_cast<double *>(out)[i * n + j] = val[a][c];
+            else static_cast<float *>(out)[i * n + j] = (float)val[a][c];
+        }
+    }
+    if (blockIdx.x == blockIdx.y) return;  // the diagonal tile is its own mirror
+    // mirror tile: stage transposed in LDS (reusing xi/xj), then write rows
+    // j0 + r, columns i0 + 4 tx' + c' with whole-row coalescing
+    double *st = sm;  // 64 x 65 doubles
+    static_assert(sizeof(sm) >= 64 * 65 * sizeof(double), "staging space");
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) st[(tx * 4 + c) * 65 + ty * 4 + a] = val[a][c];
+    __syncthreads();
+    for (int e = t; e < 64 * 64; e += 256) {
+        const int r = e >> 6, cc = e & 63;  // mirror row j0 + r, column i0 + cc
+        const int64_t j = j0 + r, i = i0 + cc;
+        if (j >= n || i >= n) continue;
+        const double v = st[r * 65 + cc];
+        if (dtype == DT_F64) static_cast<double *>(out)[j * n + i] = v;
+        else static_cast<float *>(out)[j * n + i] = (float)v;
     }
 }
 
@@ -359,73 +398,129 @@ __global__ __launch_bounds__(256) void k_transpose(const TransDesc *D, int nprob
 
 // Grouped column reductions: the NM distinct matrices of a group are read
 // once per element for all of its outputs.  Block = 256 columns (4 per
-// thread, 64 threads across) x d.strip rows (4 row groups); each chunk
-// holds ROWS rows per thread in registers.
-template <int DOM, int NM>
+// thread, 64 threads across) x d.strip rows (4 row groups).  The products
+// of each output's row vectors over the strip are formed once per block in
+// LDS (0 for rows past the end, which masks them).  T is the element type
+// of every matrix of the launch (void: mixed types, dispatched per load).
+// Rows are clamped into range instead of branched on, and 16-byte vector
+// loads through the global address space are used whenever the thread's 4
+// columns are in range and every row pitch is a multiple of 4 elements.
+template <typename T, typename A>
+__device__ __forceinline__ void load_row4(const MatRef &m, int64_t v, int64_t w, int64_t n,
+                                          bool vec, A (&x)[4]) {
+    if constexpr (std::is_void<T>::value) {
+        with_dtype(m.dtype, [&](auto tag) {
+            typedef decltype(tag) U;
+            load4<U, A>(static_cast<const U *>(m.p), v * m.ld + w, vec, w, n, x);
+        });
+    } else {
+        const T *p = static_cast<const T *>(m.p) + v * m.ld + w;
+        if (vec) {
+            if constexpr (sizeof(T) == 4) {
+                typedef T v4 __attribute__((ext_vector_type(4)));
+                const v4 q = *(const __attribute__((address_space(1))) v4 *)(p);
+                x[0] = (A)q[0]; x[1] = (A)q[1]; x[2] = (A)q[2]; x[3] = (A)q[3];
+            } else {
+                typedef T v2 __attribute__((ext_vector_type(2)));
+                const v2 q0 = *(const __attribute__((address_space(1))) v2 *)(p);
+                const v2 q1 = *(const __attribute__((address_space(1))) v2 *)(p + 2);
+                x[0] = (A)q0[0]; x[1] = (A)q0[1]; x[2] = (A)q1[0]; x[3] = (A)q1[1];
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) x[j] = (w + j < n) ? (A)p[j] : (A)0;
+        }
+    }
+}
+
+template <int DOM, typename T, int NM, int NOUT>
 __global__ __launch_bounds__(256) void k_colred(const ColDesc *D, int nprob) {
     typedef typename Dom<DOM>::acc A;
-    constexpr int ROWS = NM == 1 ? 8 : 4;
+    typedef typename std::conditional<std::is_void<T>::value, A, T>::type XT;
+    constexpr int ROWS = 4;
+    constexpr int CH = 4 * ROWS;  // rows per chunk of the block
     __shared__ A red[4][256];
+    __shared__ A svt[NOUT * kElimStrip];  // [output][strip row]
     const int64_t b = blockIdx.x;
-    const int p = find_problem(D, nprob, b);
+    // uniform over the block: descriptor fields become scalar loads
+    const int p = __builtin_amdgcn_readfirstlane(find_problem(D, nprob, b));
     const ColDesc &d = D[p];
     const int64_t local = b - d.tile_start;
     const int64_t tv = local / d.tiles_w, tw = local % d.tiles_w;
     const int64_t n = d.n, w0 = tw * 256;
     const int t = threadIdx.x, cg = t & 63, g = t >> 6;
     const int64_t w = w0 + 4 * cg;
-    const int64_t vbeg = tv * d.strip, vend = min(n, vbeg + d.strip);
+    const int strip = d.strip;
+    const int64_t vbeg = tv * strip, vend = min(n, vbeg + strip);
     const int nout = d.nout;
-    A sum[kColOut][4];
+    for (int idx = t; idx < NOUT * strip; idx += 256) {
+        const int o = idx / strip, r = idx - o * strip;
+        const int64_t v = vbeg + r;
+        A sv = 0;  // rows past the end and unused output slots stay 0
+        if (o < nout && v < vend) {
+            sv = 1;
+            for (int j = 0; j < d.o[o].nS; ++j) sv *= load_vec<DOM>(d.o[o].s[j], v);
+        }
+        svt[idx] = sv;
+    }
+    __syncthreads();
+    bool vec = w + 3 < n;
 #pragma unroll
-    for (int o = 0; o < kColOut; ++o)
+    for (int k = 0; k < NM; ++k) vec = vec && (d.M[k].ld % 4 == 0);
+    int ex[NOUT][NM];
+    bool zd[NOUT][NM];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) sum[o][j] = 0;
-    for (int64_t v0 = vbeg; v0 < vend; v0 += 4 * ROWS) {
-        A x[NM][ROWS][4];
+    for (int o = 0; o < NOUT; ++o)
 #pragma unroll
         for (int k = 0; k < NM; ++k) {
-            const MatRef m = d.M[k];
-            with_dtype(m.dtype, [&](auto tag) {
-                typedef decltype(tag) T;
-                const T *mp = static_cast<const T *>(m.p);
-                const bool vec = (w + 3 < n) && (m.ld % 4 == 0);
+            ex[o][k] = o < nout ? d.o[o].e[k] : 0;
+            zd[o][k] = o < nout && d.o[o].zd[k];
+        }
+    A sum[NOUT][4];
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) sum[o][j] = 0;
+    auto run = [&](auto vec_tag) {
+        constexpr bool VEC = decltype(vec_tag)::value;
+        for (int64_t v0 = vbeg; v0 < vend; v0 += CH) {
+            XT x[NM][ROWS][4];
+#pragma unroll
+            for (int k = 0; k < NM; ++k)
 #pragma unroll
                 for (int i = 0; i < ROWS; ++i) {
-                    const int64_t v = v0 + g + 4 * i;
-                    if (v < vend) load4<T, A>(mp, v * m.ld + w, vec, w, n, x[k][i]);
-                    else x[k][i][0] = x[k][i][1] = x[k][i][2] = x[k][i][3] = 0;
+                    const int64_t v = min(v0 + g + 4 * i, vend - 1);
+                    load_row4<T, XT>(d.M[k], v, w, n, VEC, x[k][i]);
                 }
-            });
-        }
-#pragma unroll
-        for (int o = 0; o < kColOut; ++o) {
-            if (o >= nout) break;
-            const ColOut &q = d.o[o];
 #pragma unroll
             for (int i = 0; i < ROWS; ++i) {
                 const int64_t v = v0 + g + 4 * i;
-                if (v >= vend) continue;
-                A sv = 1;
-                for (int j = 0; j < q.nS; ++j) sv *= load_vec<DOM>(q.s[j], v);
+                const int r = (int)min<int64_t>(v - vbeg, strip - 1);
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    A pr = (w + j < n) ? sv : (A)0;
+                    const bool diag = v == w + j;
 #pragma unroll
-                    for (int k = 0; k < NM; ++k) {
-                        const A xv = (q.zd[k] && v == w + j) ? (A)0 : x[k][i][j];
-                        for (int e = 0; e < q.e[k]; ++e) pr *= xv;
+                    for (int o = 0; o < NOUT; ++o) {
+                        if (o >= nout) break;
+                        A pr = svt[o * strip + r];
+#pragma unroll
+                        for (int k = 0; k < NM; ++k) {
+                            const A f = (zd[o][k] && diag) ? (A)0 : (A)x[k][i][j];
+                            for (int e = 0; e < ex[o][k]; ++e) pr *= f;
+                        }
+                        sum[o][j] += (v < vend) ? pr : (A)0;
                     }
-                    sum[o][j] += pr;
                 }
             }
         }
-    }
+    };
+    if (vec) run(std::true_type{});
+    else run(std::false_type{});
 #pragma unroll
-    for (int o = 0; o < kColOut; ++o) {
+    for (int o = 0; o < NOUT; ++o) {
         if (o >= nout) break;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) red[g][4 * cg + j] = sum[o][j];
+        for (int j = 0; j < 4; ++j) red[g][4 * cg + j] = (w + j < n) ? sum[o][j] : (A)0;
         __syncthreads();
         const int64_t wc = w0 + t;
         if (wc < n) {
@@ -448,14 +543,34 @@ __global__ __launch_bounds__(256) void k_reduce(const ReduceDesc *D, int nprob) 
     const ReduceDesc &d = D[blockIdx.x];
     const int t = threadIdx.x;
     if (!d.dot) {
-        for (int64_t j = (int64_t)blockIdx.y * 256 + t; j < d.len; j += (int64_t)gridDim.y * 256) {
-            A s = 0;
-            for (int64_t q = 0; q < d.T; ++q) s += static_cast<const A *>(d.part)[q * d.stride + j];
-            for (int q = 0; q < d.nmul; ++q) s *= load_vec<DOM>(d.mul[q], j);
-            static_cast<A *>(d.out)[j] = s;
-            if constexpr (DOM == DOM_INT) {
-                if (d.mx_out) atomicMax(d.mx_out, (unsigned long long)(s < 0 ? -s : s));
+        // 64 columns per block pass; row group g sums partials q = g, g+4,
+        // ... into two alternating accumulators, and the four groups are
+        // combined in LDS, all in a fixed order
+        __shared__ A cred[4][64];
+        const int c = t & 63, g = t >> 6;
+        const A *part = static_cast<const A *>(d.part);
+        for (int64_t j0 = (int64_t)blockIdx.y * 64; j0 < d.len; j0 += (int64_t)gridDim.y * 64) {
+            const int64_t j = j0 + c;
+            A s0 = 0, s1 = 0;
+            if (j < d.len) {
+                int64_t q = g;
+                for (; q + 4 < d.T; q += 8) {
+                    s0 += part[q * d.stride + j];
+                    s1 += part[(q + 4) * d.stride + j];
+                }
+                if (q < d.T) s0 += part[q * d.stride + j];
             }
+            cred[g][c] = s0 + s1;
+            __syncthreads();
+            if (g == 0 && j < d.len) {
+                A s = (cred[0][c] + cred[1][c]) + (cred[2][c] + cred[3][c]);
+                for (int q = 0; q < d.nmul; ++q) s *= load_vec<DOM>(d.mul[q], j);
+                static_cast<A *>(d.out)[j] = s;
+                if constexpr (DOM == DOM_INT) {
+                    if (d.mx_out) atomicMax(d.mx_out, (unsigned long long)(s < 0 ? -s : s));
+                }
+            }
+            __syncthreads();
         }
         return;
     }
@@ -1114,25 +1229,36 @@ hipError_t launch_elim1(const Elim1Desc *d, int nprob, int64_t total_tiles, int 
     return hipGetLastError();
 }
 
-hipError_t launch_colred(const ColDesc *d, int nprob, int64_t total_tiles, int nm, int domain,
-                         hipStream_t s) {
-    dim3 grid((unsigned)total_tiles);
-#define USTAT_COLRED(NM_)                                                                   \
-    if (nm == NM_) {                                                                        \
-        if (domain == DOM_FP) hipLaunchKernelGGL((k_colred<DOM_FP, NM_>), grid, dim3(256), 0, s, d, nprob); \
-        else hipLaunchKernelGGL((k_colred<DOM_INT, NM_>), grid, dim3(256), 0, s, d, nprob);  \
-        return hipGetLastError();                                                           \
+template <int DOM, typename T, int NM>
+static void launch_colred_t(const ColDesc *d, int nprob, dim3 grid, int nout, hipStream_t s) {
+    if (nout <= 4) hipLaunchKernelGGL((k_colred<DOM, T, NM, 4>), grid, dim3(256), 0, s, d, nprob);
+    else hipLaunchKernelGGL((k_colred<DOM, T, NM, kColOut>), grid, dim3(256), 0, s, d, nprob);
+}
+
+template <int DOM, typename T>
+static hipError_t launch_colred_nm(const ColDesc *d, int nprob, dim3 grid, int nm, int nout,
+                                   hipStream_t s) {
+    switch (nm) {
+        case 1: launch_colred_t<DOM, T, 1>(d, nprob, grid, nout, s); break;
+        case 2: launch_colred_t<DOM, T, 2>(d, nprob, grid, nout, s); break;
+        case 3: launch_colred_t<DOM, T, 3>(d, nprob, grid, nout, s); break;
+        default: return hipErrorInvalidValue;
     }
-    USTAT_COLRED(1)
-    USTAT_COLRED(2)
-    USTAT_COLRED(3)
-#undef USTAT_COLRED
-    return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_colred(const ColDesc *d, int nprob, int64_t total_tiles, int nm, int max_out,
+                         int elem_dtype, int domain, hipStream_t s) {
+    dim3 grid((unsigned)total_tiles);
+    if (domain == DOM_INT) return launch_colred_nm<DOM_INT, void>(d, nprob, grid, nm, max_out, s);
+    if (elem_dtype == DT_F32) return launch_colred_nm<DOM_FP, float>(d, nprob, grid, nm, max_out, s);
+    if (elem_dtype == DT_F64) return launch_colred_nm<DOM_FP, double>(d, nprob, grid, nm, max_out, s);
+    return launch_colred_nm<DOM_FP, void>(d, nprob, grid, nm, max_out, s);
 }
 
 hipError_t launch_reduce(const ReduceDesc *d, int nprob, int64_t max_len, int domain,
                          hipStream_t s) {
-    dim3 grid((unsigned)nprob, (unsigned)std::max<int64_t>(1, std::min<int64_t>(64, (max_len + 255) / 256)));
+    dim3 grid((unsigned)nprob, (unsigned)std::max<int64_t>(1, std::min<int64_t>(256, (max_len + 63) / 64)));
     if (domain == DOM_FP) hipLaunchKernelGGL(k_reduce<DOM_FP>, grid, dim3(256), 0, s, d, nprob);
     else hipLaunchKernelGGL(k_reduce<DOM_INT>, grid, dim3(256), 0, s, d, nprob);
     return hipGetLastError();

@@ -198,9 +198,11 @@ hipError_t launch_rbf(const double *X, int64_t n, int32_t d, double divisor, voi
 hipError_t launch_diag(const DiagDesc *d, int nprob, int64_t max_n, int domain, hipStream_t s);
 hipError_t launch_elim1(const Elim1Desc *d, int nprob, int64_t total_tiles, int domain,
                         hipStream_t s);
-// nm: the number of distinct matrices of every group in d (1..kColMat)
-hipError_t launch_colred(const ColDesc *d, int nprob, int64_t total_tiles, int nm, int domain,
-                         hipStream_t s);
+// nm: the number of distinct matrices of every group in d (1..kColMat);
+// max_out: the largest output count of a group; elem_dtype: the DType of
+// every matrix of the launch, or -1 when they differ
+hipError_t launch_colred(const ColDesc *d, int nprob, int64_t total_tiles, int nm, int max_out,
+                         int elem_dtype, int domain, hipStream_t s);
 hipError_t launch_reduce(const ReduceDesc *d, int nprob, int64_t max_len, int domain,
                          hipStream_t s);
 hipError_t launch_elim0(const Elim0Desc *d, int nprob, int domain, hipStream_t s);

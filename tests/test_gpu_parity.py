@@ -57,9 +57,13 @@ def nverts(edges):
 
 # ------------------------------------------------------------------ H1
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_rbf_factor_build(U, prec):
+@pytest.mark.parametrize("d", [12, 40])
+def test_rbf_factor_build(U, prec, d):
+    """The device factor against the oracle's direct-difference RBF, at a
+    ragged n spanning several 64-row tiles (and d above one 32-wide chunk):
+    symmetric bit for bit, unit diagonal."""
     import torch
-    n, d, div = 301, 12, 24.0
+    n, div = 301, 2.0 * d
     say(f"rbf n={n} d={d} {prec}")
     X = W.gaussian_samples(n, d, seed=7)
     K = U.ustat_build_rbf(dev(X, torch.float64), div, prec)
@@ -67,8 +71,14 @@ def test_rbf_factor_build(U, prec):
     ref = oracle.rbf_matrix(X, div)
     got = K.double().cpu().numpy()
     assert np.all(np.diag(got) == 1.0)
+    assert np.array_equal(got, got.T)
     if prec == "f64":
-        assert np.max(np.abs(got - ref)) <= 4e-16
+        # summation-order rounding: a = |x_i - x_j|^2 / div carries about
+        # (d + 2) ulp relative on either side, which exp turns into a*(d+2)
+        # ulp of K, plus one ulp from each side's exp
+        a = -np.log(ref)
+        bound = (a * (d + 2) + 4) * 2.0 ** -53 * ref
+        assert np.all(np.abs(got - ref) <= bound)
     else:
         assert np.max(np.abs(got - ref) / ref) <= 2 ** -24
 
