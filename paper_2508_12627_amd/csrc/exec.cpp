@@ -22,7 +22,7 @@ namespace ustat {
 void Runtime::drop_graphs() {
     for (auto &kv : graphs) {
         if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
-        if (kv.second.blob) (void)hipHostFree(kv.second.blob);
+        if (kv.second.blob) (void)hipFree(kv.second.blob);
     }
     graphs.clear();
 }
@@ -193,7 +193,7 @@ struct Schedule {
     // arena layout
     size_t arena_bytes = 0;
     // fixed regions (offsets in arena)
-    size_t off_scal = 0, off_v = 0, off_u = 0, off_s = 0, off_mx = 0, off_limbs = 0,
+    size_t off_scal = 0, off_v = 0, off_mx = 0, off_limbs = 0,
            off_inmx = 0;
     size_t n_scal = 0, n_mx = 0, n_limbs = 0, n_inmx = 0;
     std::vector<DiagDesc> diag;
@@ -909,8 +909,6 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
     S.n_scal = nscal;
     S.n_mx = nmx;
     S.off_scal = A.alloc(nscal * cfg.wide_es + 16);
-    S.off_u = A.alloc((size_t)nd * cfg.wide_es + 16);
-    S.off_s = A.alloc((size_t)nd * 8 + 16);
     S.off_mx = A.alloc(nmx * 8 + 16);
     // input maxima: one slot per (dataset, edge)
     std::map<std::pair<int, const void *>, int> inmx_of;
@@ -1433,7 +1431,7 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
     if (capture) {
         auto git = rt.graphs.find(capture_key);
         if (git != rt.graphs.end() && git->second.nd == (int)data.size()) {
-            // Replay: the graph uploads its own descriptor blob and
+            // Replay: the graph reads its own device descriptor blob and
             // recomputes everything in the workspace from the inputs.
             HIPCHK(hipGraphLaunch(git->second.exec, stream));
             HIPCHK(hipStreamSynchronize(stream));
@@ -1515,9 +1513,12 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
     // before any asynchronous copy reads the pinned buffer)
     HIPCHK(rt.reserve_desc(up(S.blob_bytes, 64) + S.n_inmx * 8 + 1024));
     const int nd = (int)data.size();
-    const size_t nres = (size_t)S.nprog_total * cfg.wide_es + (size_t)nd * cfg.wide_es + nd * 8;
+    // results buffer [V per program | U per dataset | S per dataset], read
+    // back with one copy
+    const size_t vbytes0 = (size_t)S.nprog_total * cfg.wide_es, ubytes0 = (size_t)nd * cfg.wide_es;
+    const size_t nres = vbytes0 + ubytes0 + (size_t)nd * 8;
     HIPCHK(rt.reserve_hres(nres + 64));
-    if (range.first) HIPCHK(rt.reserve_vacc((size_t)S.nprog_total * cfg.wide_es + 64));
+    if (range.first) HIPCHK(rt.reserve_vacc(nres + 64));
 
     {
         char *hblob = rt.hdesc;
@@ -1526,24 +1527,33 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
             auto old = rt.graphs.find(capture_key);
             if (old != rt.graphs.end()) {
                 if (old->second.exec) (void)hipGraphExecDestroy(old->second.exec);
-                if (old->second.blob) (void)hipHostFree(old->second.blob);
+                if (old->second.blob) (void)hipFree(old->second.blob);
                 rt.graphs.erase(old);
             }
             if (rt.graphs.size() >= 64) rt.drop_graphs();
-            HIPCHK(hipHostMalloc((void **)&entry.blob, S.blob_bytes + 64, hipHostMallocDefault));
+            // the graph's own descriptors, uploaded once before capture
+            HIPCHK(hipMalloc((void **)&entry.blob, S.blob_bytes + 64));
             entry.blob_bytes = S.blob_bytes + 64;
-            hblob = entry.blob;
         }
         std::memcpy(hblob, S.blob.h.data(), S.blob_bytes);
+        char *dd = capture ? entry.blob : rt.ddesc;
+        {
+            hipError_t ue = hipMemcpyAsync(dd, hblob, S.blob_bytes, hipMemcpyHostToDevice, stream);
+            if (ue != hipSuccess) {
+                if (entry.blob) (void)hipFree(entry.blob);
+                *status = 4;
+                return std::string("descriptor upload: ") + hipGetErrorString(ue);
+            }
+        }
         hipGraph_t g = nullptr;
         if (capture) HIPCHK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-        char *dd = rt.ddesc;
         auto fail = [&](hipError_t e, const char *what) -> std::string {
             if (capture) {
                 hipGraph_t junk = nullptr;
                 (void)hipStreamEndCapture(stream, &junk);
                 if (junk) (void)hipGraphDestroy(junk);
-                if (entry.blob) (void)hipHostFree(entry.blob);
+                (void)hipStreamSynchronize(stream);
+                if (entry.blob) (void)hipFree(entry.blob);
                 entry.blob = nullptr;
             }
             *status = 4;
@@ -1554,8 +1564,6 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
             e = pre(stream);
             if (e != hipSuccess) return fail(e, "factor build");
         }
-        e = hipMemcpyAsync(dd, hblob, S.blob_bytes, hipMemcpyHostToDevice, stream);
-        if (e != hipSuccess) return fail(e, "descriptor upload");
         // zero running maxima (a fill kernel, safe under graph capture)
         if (cfg.domain == DOM_INT && S.n_mx) {
             hipLaunchKernelGGL(k_fill_zero, dim3(64), dim3(256), 0, stream,
@@ -1635,30 +1643,26 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
                            reinterpret_cast<int32_t *>(dd + S.off_scnt),
                            reinterpret_cast<int32_t *>(dd + S.off_sidx),
                            reinterpret_cast<int64_t *>(dd + S.off_mu), rt.arena + S.off_scal,
-                           rt.vacc, range.first ? 1 : 0, range.last ? 1 : 0, rt.arena + S.off_u,
-                           reinterpret_cast<double *>(rt.arena + S.off_s), cfg.domain, stream);
+                           rt.vacc, range.first ? 1 : 0, range.last ? 1 : 0, rt.vacc + vbytes0,
+                           reinterpret_cast<double *>(rt.vacc + vbytes0 + ubytes0), cfg.domain,
+                           stream);
         if (e != hipSuccess) return fail(e, "combine");
-        // results: V (all), U (per dataset), S (per dataset)
-        size_t vbytes = (size_t)S.nprog_total * cfg.wide_es, ubytes = (size_t)nd * cfg.wide_es;
-        e = hipMemcpyAsync(rt.hres, rt.vacc, vbytes, hipMemcpyDeviceToHost, stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(rt.hres + vbytes, rt.arena + S.off_u, ubytes, hipMemcpyDeviceToHost,
-                               stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(rt.hres + vbytes + ubytes, rt.arena + S.off_s, (size_t)nd * 8,
-                               hipMemcpyDeviceToHost, stream);
+        // results: V (all), U (per dataset), S (per dataset) in one copy
+        e = hipMemcpyAsync(rt.hres, rt.vacc, nres, hipMemcpyDeviceToHost, stream);
         if (e != hipSuccess) return fail(e, "result copy");
         if (capture) {
             e = hipStreamEndCapture(stream, &g);
             if (e != hipSuccess) {
-                (void)hipHostFree(entry.blob);
+                (void)hipStreamSynchronize(stream);
+                (void)hipFree(entry.blob);
                 *status = 4;
                 return std::string("end capture: ") + hipGetErrorString(e);
             }
             hipError_t ie = hipGraphInstantiate(&entry.exec, g, nullptr, nullptr, 0);
             (void)hipGraphDestroy(g);
             if (ie != hipSuccess) {
-                (void)hipHostFree(entry.blob);
+                (void)hipStreamSynchronize(stream);
+                (void)hipFree(entry.blob);
                 *status = 4;
                 return std::string("graph instantiate: ") + hipGetErrorString(ie);
             }

@@ -46,7 +46,7 @@ struct Runtime {
     // them all.
     struct GraphEntry {
         hipGraphExec_t exec = nullptr;
-        char *blob = nullptr;
+        char *blob = nullptr;   // device descriptor blob read by the graph
         size_t blob_bytes = 0;
         int nd = 0, nprog = 0;
     };

@@ -111,9 +111,28 @@ __device__ __forceinline__ float bf16_to_f32(uint16_t h) {
 // (j, i), so K is symmetric bit for bit and its diagonal is exactly 1.
 // Squared distances are summed over coordinates in increasing order, in
 // fp64, from direct differences.  Tile 64 x 64, each thread 4 x 4.
+template <typename OT>
+__device__ __forceinline__ void store4(OT *p, const double (&v)[4], bool vec, int64_t col,
+                                       int64_t lim) {
+    if (vec) {
+        if constexpr (sizeof(OT) == 4) {
+            typedef float f4 __attribute__((ext_vector_type(4)));
+            *reinterpret_cast<f4 *>(p) = f4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
+        } else {
+            typedef double d2 __attribute__((ext_vector_type(2)));
+            reinterpret_cast<d2 *>(p)[0] = d2{v[0], v[1]};
+            reinterpret_cast<d2 *>(p)[1] = d2{v[2], v[3]};
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            if (col + c < lim) p[c] = (OT)v[c];
+    }
+}
+
+template <typename OT>
 __global__ __launch_bounds__(256) void k_rbf(const double *__restrict__ X, int64_t n, int32_t d,
-                                             double inv_div, void *__restrict__ out,
-                                             int32_t dtype) {
+                                             double inv_div, OT *__restrict__ out) {
     if (blockIdx.y > blockIdx.x) return;  // lower-triangle tiles come from the mirror
     __shared__ double sm[2 * 64 * 33];  // x rows of the tile's i and j ranges
     double(*xi)[33] = reinterpret_cast<double(*)[33]>(sm);
@@ -156,22 +175,20 @@ __global__ __launch_bounds__(256) void k_rbf(const double *__restrict__ X, int64
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int c = 0; c < 4; ++c) val[a][c] = exp(-acc[a][c] * inv_div);
-    // direct tile: rows i0 + 4 ty + a, columns j0 + 4 tx + c
+    // direct tile: rows i0 + 4 ty + a, columns j0 + 4 tx + c (16-byte
+    // stores when the row pitch keeps them aligned)
+    const bool aligned = n % 4 == 0;
+    {
+        const int64_t j = j0 + tx * 4;
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        const int64_t i = i0 + ty * 4 + a;
-        if (i >= n) continue;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int64_t j = j0 + tx * 4 + c;
-            if (j >= n) continue;
-            if (dtype == DT_F64) static_cast<double *>(out)[i * n + j] = val[a][c];
-            else static_cast<float *>(out)[i * n + j] = (float)val[a][c];
+        for (int a = 0; a < 4; ++a) {
+            const int64_t i = i0 + ty * 4 + a;
+            if (i < n && j < n) store4<OT>(out + i * n + j, val[a], aligned && j + 3 < n, j, n);
         }
     }
     if (blockIdx.x == blockIdx.y) return;  // the diagonal tile is its own mirror
-    // mirror tile: stage transposed in LDS (reusing xi/xj), then write rows
-    // j0 + r, columns i0 + 4 tx' + c' with whole-row coalescing
+    // mirror tile: stage transposed in LDS, then write rows j0 + r, columns
+    // i0 + 4 q .. i0 + 4 q + 3
     double *st = sm;  // 64 x 65 doubles
     static_assert(sizeof(sm) >= 64 * 65 * sizeof(double), "staging space");
 #pragma unroll
@@ -179,13 +196,14 @@ __global__ __launch_bounds__(256) void k_rbf(const double *__restrict__ X, int64
 #pragma unroll
         for (int c = 0; c < 4; ++c) st[(tx * 4 + c) * 65 + ty * 4 + a] = val[a][c];
     __syncthreads();
-    for (int e = t; e < 64 * 64; e += 256) {
-        const int r = e >> 6, cc = e & 63;  // mirror row j0 + r, column i0 + cc
-        const int64_t j = j0 + r, i = i0 + cc;
+#pragma unroll
+    for (int e = t; e < 64 * 16; e += 256) {
+        const int r = e >> 4, q = e & 15;
+        const int64_t j = j0 + r, i = i0 + 4 * q;
         if (j >= n || i >= n) continue;
-        const double v = st[r * 65 + cc];
-        if (dtype == DT_F64) static_cast<double *>(out)[j * n + i] = v;
-        else static_cast<float *>(out)[j * n + i] = (float)v;
+        const double v4[4] = {st[r * 65 + 4 * q], st[r * 65 + 4 * q + 1], st[r * 65 + 4 * q + 2],
+                              st[r * 65 + 4 * q + 3]};
+        store4<OT>(out + j * n + i, v4, aligned && i + 3 < n, i, n);
     }
 }
 
@@ -1210,7 +1228,12 @@ __global__ __launch_bounds__(256) void k_slicesrc(const SliceDesc *D, int nprob)
 hipError_t launch_rbf(const double *X, int64_t n, int32_t d, double divisor, void *out,
                       int32_t dtype, hipStream_t s) {
     dim3 grid((unsigned)((n + 63) / 64), (unsigned)((n + 63) / 64));
-    hipLaunchKernelGGL(k_rbf, grid, dim3(256), 0, s, X, n, d, 1.0 / divisor, out, dtype);
+    if (dtype == DT_F64)
+        hipLaunchKernelGGL(k_rbf<double>, grid, dim3(256), 0, s, X, n, d, 1.0 / divisor,
+                           static_cast<double *>(out));
+    else
+        hipLaunchKernelGGL(k_rbf<float>, grid, dim3(256), 0, s, X, n, d, 1.0 / divisor,
+                           static_cast<float *>(out));
     return hipGetLastError();
 }
 
