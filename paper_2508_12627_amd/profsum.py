@@ -44,6 +44,25 @@ def kernel_stats(db: str):
     return [(n, int(c), float(t), float(a), float(p)) for n, c, t, a, p in rows]
 
 
+def dispatch_resources(db: str):
+    """[(name, grid, workgroup, lds, vgpr, agpr, scratch)] for the first
+    dispatch of each kernel."""
+    con = sqlite3.connect(db)
+    try:
+        rows = con.execute("select name, grid_x, workgroup_x, lds_size, vgpr_count, "
+                           "accum_vgpr_count, scratch_size from kernels order by start").fetchall()
+    except sqlite3.Error:
+        rows = []
+    con.close()
+    seen, out = set(), []
+    for r in rows:
+        if r[0] in seen:
+            continue
+        seen.add(r[0])
+        out.append(r)
+    return out
+
+
 def counter_per_dispatch(db: str, counter: str):
     """{kernel name: [value per dispatch]} for one counter."""
     con = sqlite3.connect(db)
@@ -92,6 +111,10 @@ def main(argv=None):
     sub = ap.add_subparsers(dest="cmd", required=True)
     k = sub.add_parser("kernels")
     k.add_argument("db")
+    k.add_argument("--md", default=None, help="also write a markdown summary here")
+    k.add_argument("--title", default="kernel trace")
+    k.add_argument("--command", default="", help="the rocprofv3 command that made the trace")
+    k.add_argument("--note", default="")
     t = sub.add_parser("traffic")
     for a in ("--fetch", "--write", "--cal-fetch", "--cal-write"):
         t.add_argument(a, required=True)
@@ -102,9 +125,29 @@ def main(argv=None):
                    help="extra fields of the record (workload, precision, command)")
     args = ap.parse_args(argv)
     if args.cmd == "kernels":
+        stats = kernel_stats(args.db)
         print(f"{'kernel':<70} {'calls':>6} {'total_us':>11} {'avg_us':>9} {'pct':>6}")
-        for n, c, tot, avg, pct in kernel_stats(args.db):
+        for n, c, tot, avg, pct in stats:
             print(f"{n[:70]:<70} {c:>6} {tot:>11.1f} {avg:>9.2f} {pct:>6.2f}")
+        if args.md:
+            with open(args.md, "w") as f:
+                f.write(f"# {args.title}\n\n")
+                if args.command:
+                    f.write("Command (from the repository root on the GPU box):\n\n")
+                    f.write(f"    {args.command}\n\n")
+                if args.note:
+                    f.write(args.note + "\n\n")
+                f.write("Durations in microseconds (rocprofv3 kernel trace).\n\n")
+                f.write("| kernel | calls | total_us | avg_us | pct |\n|---|---|---|---|---|\n")
+                for n, c, tot, avg, pct in stats:
+                    f.write(f"| `{n.split('(')[0]}` | {c} | {tot:.1f} | {avg:.2f} | {pct:.2f} |\n")
+                res = dispatch_resources(args.db)
+                if res:
+                    f.write("\nPer-dispatch resources (first dispatch of each kernel):\n\n")
+                    f.write("| kernel | grid | workgroup | lds | vgpr | agpr | scratch |\n"
+                            "|---|---|---|---|---|---|---|\n")
+                    for r in res:
+                        f.write("| `" + r[0].split("(")[0] + "` | " + " | ".join(str(x) for x in r[1:]) + " |\n")
         return 0
     rec = traffic(args.fetch, args.write, args.cal_fetch, args.cal_write, args.cal_bytes,
                   args.kernel)
