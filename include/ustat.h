@@ -258,10 +258,12 @@ ustat_status ustat_profile_read(int32_t kind, double *ms, int64_t *launches, dou
  * vertex to condition on (order lists the other len = J - 1 vertices).
  * feat (host float array of at least USTAT_NUM_FEATURES entries) receives
  * step-kind counts, operand and transposition counts, dependency depth,
- * width (conditioning counts one) and log-size terms.  USTAT_E_UNSUPPORTED
+ * width (conditioning counts one), log-size terms, the log of the
+ * program's algorithmic flops and bytes at n, and the number of GEMM steps
+ * repeated per slice of a conditioned program.  USTAT_E_UNSUPPORTED
  * if the order needs a step of degree above 2.
  */
-#define USTAT_NUM_FEATURES 15
+#define USTAT_NUM_FEATURES 18
 ustat_status ustat_order_features(ustat_plan plan, const int32_t *block_of, const int32_t *order,
                                   int32_t len, int32_t slice_var, int64_t n, float *feat);
 

@@ -4,7 +4,7 @@ For random kernel graphs, a sample of each partition's executable orders
 (plain, or conditioned on one vertex when the quotient has treewidth 3) is
 evaluated with ``vstat_eval_ordered`` and timed end to end (host scheduling
 plus device work, best of a few calls).  Each sample is (features of the
-lowered order, log seconds).  The MLP (15 -> H1 -> H2 -> 1) is then trained
+lowered order, log seconds).  The MLP (18 -> H1 -> H2 -> 1) is then trained
 on the GPU by the engine's own forward/backward/Adam kernels and written as
 a cost-model file for ``order="learned"`` plans.  The paper notes, after
 its complexity proposition for V-statistics (section "The Algorithm of
@@ -74,7 +74,7 @@ def wall_seconds(U, h, block_of, order, slice_var, n, fs, repeats: int) -> float
 def harvest(graphs, ns_plain, ns_sliced, partitions_per_graph: int, orders_per_partition: int,
             seed: int, precision: str = "bf16x3", repeats: int = 2, log=print,
             sliced_per_graph: int = 8):
-    """Returns X (samples x 15 float32), y (log seconds, float32) and the
+    """Returns X (samples x NUM_FEATURES float32), y (log seconds, float32) and the
     sample records (graph, partition, candidate, n, seconds)."""
     import torch
     from paper_2508_12627_amd import ustat as U, workloads as W
@@ -222,7 +222,7 @@ def main():
     ap.add_argument("--out", required=True)
     ap.add_argument("--graphs", type=int, default=16)
     ap.add_argument("--sizes", default="1024,2048,4096")
-    ap.add_argument("--sliced-sizes", default="512,1024,1536")
+    ap.add_argument("--sliced-sizes", default="512,1024,2048")
     ap.add_argument("--sliced-partitions", type=int, default=8)
     ap.add_argument("--partitions", type=int, default=12)
     ap.add_argument("--orders", type=int, default=6)

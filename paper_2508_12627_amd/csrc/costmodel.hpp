@@ -30,7 +30,14 @@ void set_last_error(const std::string &msg);
 
 class CostModel : public OrderScorer {
 public:
-    std::string load(const std::string &path) { return load_mlp(path, w_); }
+    // Loads weights; a model for another feature count is rejected.
+    std::string load(const std::string &path) {
+        std::string e = load_mlp(path, w_);
+        if (e.empty() && w_.F != kOrderFeatures)
+            e = "cost model has " + std::to_string(w_.F) + " inputs; the order features number " +
+                std::to_string(kOrderFeatures);
+        return e;
+    }
     double score(const std::vector<float> &feat) const override;
     const MLPWeights &weights() const { return w_; }
 

@@ -156,8 +156,13 @@ struct LevelWork {
     int64_t prep_tiles = 0;
     std::vector<GemmDesc> gemm;
     int64_t gemm_tiles = 0;
-    int gemm_tile = 128;  // block tile side of the level's GEMM launch
     double gemm_flops = 0;
+    // problems of the level on 256-wide tiles, in a launch of their own
+    std::vector<GemmDesc> gemm_big;
+    int64_t gemm_big_tiles = 0;
+    double gemm_big_flops = 0;
+    bool big = false;  // the level's eligible GEMMs take 256-wide tiles
+    size_t off_gemm_big = 0;
     std::vector<Elim1Desc> e1;  // column reductions over more than kColMat matrices
     int64_t e1_tiles = 0;
     std::vector<ColDesc> col[kColMat];  // grouped column reductions, by matrix count
@@ -1036,20 +1041,19 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
     S.levels.assign(G.max_level + 1, LevelWork());
     for (int L = 1; L <= G.max_level; ++L) {
         LevelWork &W = S.levels[L];
-        // 256-wide tiles for the level's GEMM launch when every problem's
-        // padded size is a multiple of 256 and they still give at least one
-        // tile per compute unit (fp32 and split-bf16 only)
+        // 256-wide tiles (fp32 and split-bf16 only) for the level's GEMMs
+        // whose padded size is a multiple of 256, in a launch of their own,
+        // when together they give at least one tile per compute unit; the
+        // other GEMMs of the level keep 128-wide tiles
         {
             int64_t t256 = 0;
-            bool ok = cfg.prec == 1 || cfg.prec == 2;
             for (int id : by_level[L]) {
                 const Node &q = G.nodes[id];
                 if (q.kind != NK::GemmStore && q.kind != NK::GemmFinal) continue;
                 const int64_t np_ = up64(q.n, 128);
-                ok = ok && np_ % 256 == 0;
-                t256 += (np_ / 256) * (np_ / 256);
+                if (np_ % 256 == 0) t256 += (np_ / 256) * (np_ / 256);
             }
-            W.gemm_tile = (ok && t256 >= gemm_big_tiles_min()) ? 256 : 128;
+            W.big = (cfg.prec == 1 || cfg.prec == 2) && t256 > 0 && t256 >= gemm_big_tiles_min();
         }
         std::vector<std::pair<size_t, size_t>> scratch;
         std::vector<ColPending> e1recs;  // this level's column reductions
@@ -1214,6 +1218,11 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
                     int cla = 1, clb = 1;
                     g.A = make_prep(nd_.A, nd_.sv, pA * pS, &lap, &cla);
                     g.B = make_prep(nd_.B, {}, pB, &lbp, &clb);
+                    // the GEMM addresses its operands with 32-bit offsets
+                    if ((double)prep_bytes(cfg, npad, std::max(cla, clb)) >= 4294967296.0) {
+                        *status = 2;
+                        return "a GEMM operand of this size exceeds the 4 GiB the kernels address";
+                    }
                     g.n = n;
                     g.npad = npad;
                     g.ld = npad;
@@ -1222,10 +1231,12 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
                     g.lb = clb;
                     g.la_p = is_int ? lap : nullptr;
                     g.lb_p = is_int ? lbp : nullptr;
-                    g.tiles = (int)(npad / W.gemm_tile);
-                    g.tile_start = W.gemm_tiles;
-                    W.gemm_tiles += (int64_t)g.tiles * g.tiles;
-                    W.gemm_flops += 2.0 * (double)n * n * n;
+                    const bool big = W.big && npad % 256 == 0;
+                    g.tiles = (int)(npad / (big ? 256 : 128));
+                    int64_t &tcount = big ? W.gemm_big_tiles : W.gemm_tiles;
+                    g.tile_start = tcount;
+                    tcount += (int64_t)g.tiles * g.tiles;
+                    (big ? W.gemm_big_flops : W.gemm_flops) += 2.0 * (double)n * n * n;
                     const double cb = n * pA * pS * pB;
                     if (is_int) {
                         if (cb > kOverflow) {
@@ -1269,7 +1280,7 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
                         W.red.push_back(r);
                         nd_.bound = (double)n * n * cb * pZ * paw * pbx;
                     }
-                    W.gemm.push_back(g);
+                    (big ? W.gemm_big : W.gemm).push_back(g);
                     break;
                 }
             }
@@ -1342,6 +1353,7 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
         W.off_tr = S.blob.put(W.tr);
         W.off_prep = S.blob.put(W.prep);
         W.off_gemm = S.blob.put(W.gemm);
+        W.off_gemm_big = S.blob.put(W.gemm_big);
         W.off_e1 = S.blob.put(W.e1);
         for (int k = 0; k < kColMat; ++k) W.off_col[k] = S.blob.put(W.col[k]);
         W.off_e0 = S.blob.put(W.e0);
@@ -1604,10 +1616,16 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
                                 W.prep_tiles, cfg.domain, stream);
                 if (e != hipSuccess) return fail(e, "prep");
             }
+            if (!W.gemm_big.empty()) {
+                ProfScope ps(prof, KIND_GEMM, stream, W.gemm_big_flops);
+                e = launch_gemm(reinterpret_cast<GemmDesc *>(dd + W.off_gemm_big),
+                                (int)W.gemm_big.size(), W.gemm_big_tiles, cfg.prec, 256, stream);
+                if (e != hipSuccess) return fail(e, "gemm");
+            }
             if (!W.gemm.empty()) {
                 ProfScope ps(prof, KIND_GEMM, stream, W.gemm_flops);
                 e = launch_gemm(reinterpret_cast<GemmDesc *>(dd + W.off_gemm), (int)W.gemm.size(),
-                                W.gemm_tiles, cfg.prec, W.gemm_tile, stream);
+                                W.gemm_tiles, cfg.prec, 128, stream);
                 if (e != hipSuccess) return fail(e, "gemm");
             }
             for (int k = 0; k < kColMat; ++k) {

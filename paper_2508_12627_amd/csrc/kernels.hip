@@ -288,7 +288,7 @@ __global__ __launch_bounds__(256) void k_elim1(const Elim1Desc *D, int nprob) {
     typedef typename Dom<DOM>::acc A;
     __shared__ A red[4][256];
     const int64_t b = blockIdx.x;
-    const int p = find_problem(D, nprob, b);
+    const int p = __builtin_amdgcn_readfirstlane(find_problem(D, nprob, b));  // uniform
     const Elim1Desc &d = D[p];
     const int64_t local = b - d.tile_start;
     const int64_t tv = local / d.tiles_w, tw = local % d.tiles_w;
@@ -386,7 +386,7 @@ __global__ __launch_bounds__(256) void k_elim1(const Elim1Desc *D, int nprob) {
 __global__ __launch_bounds__(256) void k_transpose(const TransDesc *D, int nprob) {
     __shared__ long long tile[64][65];
     const int64_t b = blockIdx.x;
-    const int p = find_problem(D, nprob, b);
+    const int p = __builtin_amdgcn_readfirstlane(find_problem(D, nprob, b));  // uniform
     const TransDesc &d = D[p];
     const int64_t local = b - d.tile_start;
     const int64_t ta = local / d.tiles, tb = local % d.tiles;
@@ -650,7 +650,7 @@ template <int DOM>
 __global__ __launch_bounds__(256) void k_prep(const PrepDesc *D, int nprob) {
     typedef typename Dom<DOM>::acc A;
     const int64_t b = blockIdx.x;
-    const int p = find_problem(D, nprob, b);
+    const int p = __builtin_amdgcn_readfirstlane(find_problem(D, nprob, b));  // uniform
     const PrepDesc &d = D[p];
     const int64_t local = b - d.tile_start;
     const int64_t tcol = d.npad / 128;
@@ -853,9 +853,11 @@ struct TileIO {
             int pl = u / (R * UPR);
             int uu = u % (R * UPR);
             int row = uu / UPR, cu = uu % UPR;
-            const char *g = base + pl * planeb + (row0 + row) * ldb + k0b + cu * 16;
-            // global address space: these loads only count against vmcnt, so
-            // waiting for LDS fragment reads never waits for the prefetch
+            const char *g = base + (uint32_t)(pl * planeb + (row0 + row) * ldb + k0b + cu * 16);
+            // a 32-bit offset from the uniform base (every operand buffer is
+            // below 4 GiB, checked when the schedule is built); global address space:
+            // these loads only count against vmcnt, so waiting for LDS
+            // fragment reads never waits for the prefetch
             r[i] = *(const __attribute__((address_space(1))) u32x4 *)(g);
         }
     }
@@ -1012,7 +1014,7 @@ void k_gemm(const GemmDesc *D, int nprob) {
     static_assert(PREC == 1 || PREC == 2 || SH::BM == 128, "large tiles: fp32 accumulators only");
     extern __shared__ __align__(16) char lds[];
     const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
-    const int p = find_problem(D, nprob, b);
+    const int p = __builtin_amdgcn_readfirstlane(find_problem(D, nprob, b));  // uniform
     const GemmDesc &d = D[p];
     const int64_t local = b - d.tile_start;
     // grouped tile order: 8 tile-rows per group, column-major inside it
@@ -1193,7 +1195,7 @@ __global__ __launch_bounds__(256) void k_slicesrc(const SliceDesc *D, int nprob)
     typedef typename Dom<DOM>::acc A;
     __shared__ A tile[64][65];
     const int64_t b = blockIdx.x;
-    const int p = find_problem(D, nprob, b);
+    const int p = __builtin_amdgcn_readfirstlane(find_problem(D, nprob, b));  // uniform
     const SliceDesc &d = D[p];
     const int64_t local = b - d.tile_start;
     const int64_t ti = local / d.tiles, tu = local % d.tiles;

@@ -323,30 +323,52 @@ std::string lower_order(const std::vector<Edge> &edges, const std::vector<int> &
     return "";
 }
 
+std::vector<char> slice_dependent_steps(const VProgram &p) {
+    std::vector<char> vdep(p.vals.size(), 0), sdep(p.steps.size(), 0);
+    if (p.slice_var < 0) return sdep;
+    for (size_t v = 0; v < p.vals.size(); ++v) vdep[v] = p.vals[v].kind == ValKind::SliceVec;
+    for (size_t i = 0; i < p.steps.size(); ++i) {
+        const Step &s = p.steps[i];
+        bool d = false;
+        for (auto *g : {&s.A, &s.B, &s.Z})
+            for (auto &o : *g) d = d || vdep[o.val];
+        for (auto *g : {&s.sv, &s.aw, &s.bx})
+            for (int q : *g) d = d || vdep[q];
+        sdep[i] = d;
+        if (s.out >= 0) vdep[s.out] = d;
+    }
+    return sdep;
+}
+
+// Algorithmic work of one evaluation at size n.  In a conditioned program
+// the steps that depend on the conditioned vertex run once per slice (n
+// times); the others run once, since the executor shares them across slices.
 void program_cost(const VProgram &p, double n, double elem_bytes, double *flops, double *bytes) {
     double f = 0, b = 0;
-    const double slices = p.slice_var >= 0 ? n : 1.0;
-    for (const Step &s : p.steps) {
+    const std::vector<char> dep = slice_dependent_steps(p);
+    for (size_t i = 0; i < p.steps.size(); ++i) {
+        const Step &s = p.steps[i];
+        const double rep = dep[i] ? n : 1.0;
         switch (s.kind) {
             case StepKind::Elim0:
-                f += 2 * n * std::max<size_t>(1, s.sv.size());
-                b += 8 * n * s.sv.size();
+                f += rep * 2 * n * std::max<size_t>(1, s.sv.size());
+                b += rep * 8 * n * s.sv.size();
                 break;
             case StepKind::Elim1:
             case StepKind::Final1:
-                f += 2 * n * n * s.A.size();
-                b += elem_bytes * n * n * s.A.size();
+                f += rep * 2 * n * n * s.A.size();
+                b += rep * elem_bytes * n * n * s.A.size();
                 break;
             case StepKind::Elim2:
             case StepKind::Final2:
-                f += 2 * n * n * n;
-                b += elem_bytes * n * n * (s.A.size() + s.B.size() + s.Z.size() +
-                                           (s.kind == StepKind::Elim2 ? 1 : 0));
+                f += rep * 2 * n * n * n;
+                b += rep * elem_bytes * n * n *
+                     (s.A.size() + s.B.size() + s.Z.size() + (s.kind == StepKind::Elim2 ? 1 : 0));
                 break;
         }
     }
-    if (flops) *flops = f * slices;
-    if (bytes) *bytes = b * slices;
+    if (flops) *flops = f;
+    if (bytes) *bytes = b;
 }
 
 std::vector<float> program_features(const VProgram &p, double n) {
@@ -368,9 +390,19 @@ std::vector<float> program_features(const VProgram &p, double n) {
         }
     }
     float ln = (float)std::log(n);
+    // the work model behind the exhaustive policy, as log flops and bytes,
+    // and the GEMM steps repeated per slice of a conditioned program
+    double fl, by;
+    program_cost(p, n, 4.0, &fl, &by);
+    const std::vector<char> dep = slice_dependent_steps(p);
+    float dep_gemm = 0;
+    for (size_t i = 0; i < p.steps.size(); ++i)
+        if (dep[i] && (p.steps[i].kind == StepKind::Elim2 || p.steps[i].kind == StepKind::Final2))
+            dep_gemm += 1;
     std::vector<float> f = {c[0], c[1], c[2], c[3], c[4], nA, nTransA, nZ, nVec, nPrep,
                             (float)p.depth, (float)p.width, ln, ln * (c[3] + c[4]),
-                            ln * (c[1] + c[2])};
+                            ln * (c[1] + c[2]), (float)std::log(std::max(fl, 1.0)),
+                            (float)std::log(std::max(by, 1.0)), dep_gemm};
     return f;
 }
 
@@ -414,8 +446,7 @@ std::string build_program(const std::vector<Edge> &edges, int m, const std::vect
         if (opts.order == 2 && scorer) return scorer->score(program_features(p, nref));
         double f, b;
         program_cost(p, nref, 4.0, &f, &b);
-        const double slices = p.slice_var >= 0 ? nref : 1.0;
-        return f / 100e12 + b / 5e12 + slices * p.depth * 8e-6 + 1e-9 * sharing_penalty(p);
+        return f / 100e12 + b / 5e12 + p.depth * 8e-6 + 1e-9 * sharing_penalty(p);
     };
     auto keep_program = [&](VProgram &p) {
         p.block_of = out.block_of;

@@ -136,7 +136,14 @@ std::string lower_order(const std::vector<Edge> &edges, const std::vector<int> &
 void program_cost(const VProgram &p, double n, double elem_bytes, double *flops, double *bytes);
 
 // Features of a lowered program, for the learned cost model.
+// Features of a lowered program at sample size n for the order cost model
+// (kOrderFeatures of them).
+constexpr int kOrderFeatures = 18;
 std::vector<float> program_features(const VProgram &p, double n);
+
+// Per step: does it depend on the conditioned (sliced) vertex?  All false
+// for a program that is not conditioned.
+std::vector<char> slice_dependent_steps(const VProgram &p);
 
 std::string make_plan(int m, const std::vector<Edge> &edges, const PlanOptions &opts,
                       const OrderScorer *scorer, Plan &out);

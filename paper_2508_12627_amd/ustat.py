@@ -73,7 +73,7 @@ EXPORTS = ["ustat_plan_opts_default", "ustat_plan_create", "ustat_plan_destroy",
            "ustat_order_features", "vstat_eval_ordered", "ustat_mlp_num_params",
            "ustat_mlp_predict", "ustat_mlp_loss_grad", "ustat_mlp_train", "ustat_mlp_save",
            "ustat_status_string", "ustat_last_error"]
-NUM_FEATURES = 15
+NUM_FEATURES = 18
 
 
 def load_library(path: str = LIB_PATH):

@@ -266,11 +266,12 @@ def test_large_tiles_ragged(U, prec):
 
 def test_large_tiles_batched_level(U):
     """Four n = 2048 datasets put 4 x 64 tiles of 256 in each GEMM level, so
-    the batched launch takes 256-wide tiles while a single dataset (64 such
-    tiles) takes 128-wide ones: both agree to rounding and match the f64
-    path."""
+    their GEMMs run in a 256-wide launch, while the two sizes whose padding
+    is not a multiple of 256 (1900, 333) share the level in a 128-wide one,
+    and a single dataset (64 such tiles) takes 128-wide tiles: all agree to
+    rounding and match the f64 path."""
     import torch
-    ns = [2048] * 4
+    ns = [2048] * 4 + [1900, 333]
     Xs = [dev(W.gaussian_samples(n, 16, seed=80 + i), torch.float64) for i, n in enumerate(ns)]
     P = U.Plan(4, W.CYCLE4, precision="bf16x3")
     say("large tiles batched 4 x 2048 bf16x3")
