@@ -990,7 +990,14 @@ __device__ __forceinline__ void gemm_pass(typename AccT<PREC>::T (&acc)[SH::FM][
         const int64_t kn = (kt + 1 < nk) ? kt + 1 : kt;
         IOA::load(ra, Ab, ldb, planeb, w0, kn * KB);
         IOB::load(rb, Bb, ldb, planeb, x0, kn * KB);
+        // Keep the prefetch at the top of the step and its staging after
+        // the MFMAs: left to itself the scheduler sinks the loads below the
+        // MFMAs (or waits for them in the middle), exposing their latency.
+        // fp64 and int8 keep the free schedule (their register budget is
+        // already full).
+        if constexpr (PREC == 1 || PREC == 2) __builtin_amdgcn_sched_barrier(0);
         mma_tile<PREC, SH::FM, SH::FN, SH::BM, SH::BN>(acc, As, Bs, ra0, rb0, lane);
+        if constexpr (PREC == 1 || PREC == 2) __builtin_amdgcn_sched_barrier(0);
         char *An = lds + (1 - cur) * PAIR;
         IOA::store(ra, An);
         IOB::store(rb, An + IOA::STAGE);
