@@ -279,6 +279,8 @@ def main():
                     help="learned-order workload: graphs lo:hi of the 64")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many plain steps (for external profilers)")
+    ap.add_argument("--tuning", default=None, metavar="GEMM_BIG_MIN,COLRED_BLOCKS",
+                    help="use these launch-shape settings instead of autotuning")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-mebibyte device buffer 4 times (the reference "
                          "kernel for scaling hardware byte counters)")
@@ -313,8 +315,21 @@ def main():
     Xh = W.gaussian_samples(n, d, seed=WORKLOAD["seed"])
     X = torch.tensor(Xh, dtype=torch.float64, device="cuda")
     stream = torch.cuda.Stream()
-    plans = {p: U.Plan(m, edges, precision=p, order=args.order) for p in ("bf16x3", "f32", "f64")}
+    # symmetric: the same DAG as eval_samples builds for its RBF factor, so
+    # that tuning on the factor matrix applies to the samples path
+    plans = {p: U.Plan(m, edges, precision=p, order=args.order, symmetric=True)
+             for p in ("bf16x3", "f32", "f64")}
     main_plan = plans[args.precision]
+    if args.tuning:
+        gb, cb = (int(v) for v in args.tuning.split(","))
+        main_plan.set_tuning(gb, cb)
+        tune_ms = None
+    else:
+        # autotuned launch shapes (outside the timed region)
+        K = U.ustat_build_rbf(X, div, args.precision if args.precision != "bf16x3" else "f32")
+        torch.cuda.synchronize()
+        tune_ms = main_plan.autotune([K] * len(edges), stream=stream, reps=3)
+        del K
 
     if args.profile_steps:
         for _ in range(args.profile_steps):
@@ -334,7 +349,8 @@ def main():
            "config": {"workload": "4-cycle RBF U-statistic, m=4, n=4096, d=16, divisor 32, "
                                   "15 restricted V-statistics", "n": n, "d": d, "m": m,
                       "order": args.order, "precision": args.precision, "cse": True,
-                      "num_vstats": r.num_vstats}}
+                      "num_vstats": r.num_vstats, "tuning": main_plan.tuning(),
+                      "autotuned": tune_ms is not None}}
     dom, kr = kernel_rooflines(U, main_plan, X, div, stream, args.precision)
     out["roofline"] = dict(kr[dom])
     out["roofline"]["dominant_kind"] = dom

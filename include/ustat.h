@@ -164,6 +164,33 @@ ustat_status ustat_plan_workspace(ustat_plan plan, int32_t batch, const int64_t 
                                   int32_t shared_factor, uint64_t *bytes);
 
 /*
+ * Launch-shape tuning of a plan (how the engine cuts work into launches;
+ * results change at most by rounding, exact results not at all).
+ *   gemm_big_min:  a GEMM level takes 256 x 256 tiles for its fp32 and
+ *                  split-bf16 problems whose padded size is a multiple of
+ *                  256 once they give at least this many such tiles
+ *                  (default 256, one per compute unit; 0: whenever
+ *                  eligible; 2^62: never);
+ *   colred_blocks: column-reduction strips are cut so that a level has at
+ *                  least this many blocks (default 1024; 1..2^20).
+ * Setting a tuning drops the plan's cached graphs.
+ */
+ustat_status ustat_plan_tuning(ustat_plan plan, int64_t *gemm_big_min, int64_t *colred_blocks);
+ustat_status ustat_plan_set_tuning(ustat_plan plan, int64_t gemm_big_min, int64_t colred_blocks);
+
+/*
+ * Autotune the plan's launch shapes for sample size n on the given device
+ * factors (as for ustat_eval): every candidate tuning (gemm_big_min in
+ * {256, 0, never} for fp32 and split-bf16, colred_blocks in {256, 1024,
+ * 4096}) evaluates U once to warm up and then reps times (1..100) on
+ * stream (a temporary stream when NULL); the candidate with the least
+ * time per evaluation is kept.  *ms (may be NULL) receives that time.
+ * On error the previous tuning is restored.
+ */
+ustat_status ustat_plan_autotune(ustat_plan plan, int64_t n, const void *const *factors,
+                                 ustat_stream stream, int32_t reps, double *ms);
+
+/*
  * Partition idx (0 <= idx < num_vstats) in restricted-growth form:
  * block_of (host int32 [m]) gives each vertex's block, blocks numbered in
  * order of first appearance; *mu its Moebius coefficient; *tw the exact

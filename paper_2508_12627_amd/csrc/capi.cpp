@@ -4,9 +4,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <functional>
+#include <limits>
 #include <map>
 #include <memory>
 #include <new>
@@ -306,6 +308,82 @@ static ustat_status check_eval(ustat_plan plan, int64_t n) {
         return fail(USTAT_E_UNSUPPORTED, "plan needs a step kind the engine lacks: " +
                                              plan->plan.lower_error);
     return USTAT_OK;
+}
+
+ustat_status ustat_plan_tuning(ustat_plan plan, int64_t *gemm_big_min, int64_t *colred_blocks) {
+    if (!plan) return fail(USTAT_E_INVALID, "plan is NULL");
+    if (gemm_big_min) *gemm_big_min = plan->plan.tuning.gemm_big_min;
+    if (colred_blocks) *colred_blocks = plan->plan.tuning.colred_blocks;
+    return ok();
+}
+
+ustat_status ustat_plan_set_tuning(ustat_plan plan, int64_t gemm_big_min, int64_t colred_blocks) {
+    if (!plan) return fail(USTAT_E_INVALID, "plan is NULL");
+    if (colred_blocks < 1 || colred_blocks > (1 << 20))
+        return fail(USTAT_E_INVALID, "colred_blocks must be in 1..2^20");
+    plan->plan.tuning.gemm_big_min = gemm_big_min < 0 ? 0 : gemm_big_min;
+    plan->plan.tuning.colred_blocks = colred_blocks;
+    plan->rt.drop_graphs();
+    return ok();
+}
+
+ustat_status ustat_plan_autotune(ustat_plan plan, int64_t n, const void *const *factors,
+                                 ustat_stream stream, int32_t reps, double *ms) {
+    ustat_status c = check_eval(plan, n);
+    if (c != USTAT_OK) return c;
+    if (!factors) return fail(USTAT_E_INVALID, "factors is NULL");
+    if (reps < 1 || reps > 100) return fail(USTAT_E_INVALID, "reps must be in 1..100");
+    std::vector<Dataset> data(1);
+    data[0].n = n;
+    data[0].symmetric = plan->plan.opts.symmetric;
+    for (size_t k = 0; k < plan->plan.edges.size(); ++k) {
+        if (!factors[k]) return fail(USTAT_E_INVALID, "a factor pointer is NULL");
+        data[0].factors.push_back(factors[k]);
+    }
+    hipStream_t s = (hipStream_t)stream;
+    bool own = false;
+    if (!s) {
+        if (hipStreamCreate(&s) != hipSuccess) return fail(USTAT_E_HIP, "stream creation failed");
+        own = true;
+    }
+    const int prec = plan->plan.opts.precision;
+    std::vector<int64_t> gbs = {256};
+    if (prec == USTAT_F32 || prec == USTAT_BF16X3) gbs = {256, 0, int64_t(1) << 62};
+    const int64_t cbs[3] = {256, 1024, 4096};
+    const Tuning keep = plan->plan.tuning;
+    Tuning best = keep;
+    double best_s = std::numeric_limits<double>::infinity();
+    ustat_status st = USTAT_OK;
+    // each candidate: one captured (or eager) warm-up evaluation, then the
+    // best of reps timed evaluations, each ending in a stream synchronisation
+    for (int64_t gb : gbs)
+        for (int64_t cb : cbs) {
+            plan->plan.tuning.gemm_big_min = gb;
+            plan->plan.tuning.colred_blocks = cb;
+            plan->rt.drop_graphs();
+            std::string key = "tune:" + std::to_string(n);
+            for (auto f : data[0].factors) key += ":" + std::to_string((uintptr_t)f);
+            std::vector<DatasetResult> res;
+            st = run(plan, plan->all, data, s, res, nullptr, nullptr, key);
+            if (st != USTAT_OK) break;
+            double t = std::numeric_limits<double>::infinity();
+            for (int r = 0; r < reps && st == USTAT_OK; ++r) {
+                auto t0 = std::chrono::steady_clock::now();
+                st = run(plan, plan->all, data, s, res, nullptr, nullptr, key);
+                t = std::min(t, std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+            }
+            if (st != USTAT_OK) break;
+            if (t < best_s) {
+                best_s = t;
+                best = plan->plan.tuning;
+            }
+        }
+    plan->plan.tuning = st == USTAT_OK ? best : keep;
+    plan->rt.drop_graphs();
+    if (own) (void)hipStreamDestroy(s);
+    if (st != USTAT_OK) return st;
+    if (ms) *ms = best_s * 1e3;
+    return ok();
 }
 
 ustat_status ustat_eval(ustat_plan plan, int64_t n, const void *const *factors, ustat_stream stream,

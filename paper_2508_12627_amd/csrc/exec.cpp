@@ -91,17 +91,6 @@ constexpr size_t kAlign = 256;
 inline size_t up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 inline int64_t up64(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
-// Smallest number of 256-wide tiles for which a GEMM level uses them: one
-// per compute unit by default; USTAT_GEMM_BIG_MIN overrides it (a tuning
-// knob: 0 always takes 256-wide tiles where allowed, a huge value never).
-int64_t gemm_big_tiles_min() {
-    static const int64_t v = [] {
-        const char *e = getenv("USTAT_GEMM_BIG_MIN");
-        return e ? (int64_t)atoll(e) : (int64_t)256;
-    }();
-    return v;
-}
-
 // First-fit offset allocator with coalescing (host-side bookkeeping of the
 // device arena; offsets only).
 struct Arena {
@@ -730,12 +719,13 @@ struct ColPending {
 // group of its size n whose matrices together with its own stay within
 // kColMat and that has an output slot left; the rest keep one launch entry
 // each.  The strip height is then chosen for the whole level: the largest
-// of 512, 256, ..., 32 rows that still gives at least 1024 blocks, so that a
-// lone problem fills the chip while batched levels keep few partial rows.
+// of 512, 256, ..., 32 rows that still gives at least min_blocks blocks, so
+// that a lone problem fills the chip while batched levels keep few partial
+// rows.
 // alloc_part(bytes) returns a scratch partial buffer of the level; each
 // output gets a fixed-order reduction of its partials into its result.
 template <class Alloc>
-void layout_column_reductions(const std::vector<ColPending> &recs, LevelWork &W,
+void layout_column_reductions(const std::vector<ColPending> &recs, LevelWork &W, int64_t min_blocks,
                               Alloc &&alloc_part) {
     struct Out {
         ColOut o;
@@ -804,7 +794,7 @@ void layout_column_reductions(const std::vector<ColPending> &recs, LevelWork &W,
         return b;
     };
     int S = kElimStrip;
-    while (S > 32 && blocks(S) < 1024) S /= 2;
+    while (S > 32 && blocks(S) < min_blocks) S /= 2;
     // partials of one output and the reduction that consumes them
     auto partials = [&](const ColPending &r, int64_t strips) {
         const int64_t n = r.e.n;
@@ -1053,7 +1043,7 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
                 const int64_t np_ = up64(q.n, 128);
                 if (np_ % 256 == 0) t256 += (np_ / 256) * (np_ / 256);
             }
-            W.big = (cfg.prec == 1 || cfg.prec == 2) && t256 > 0 && t256 >= gemm_big_tiles_min();
+            W.big = (cfg.prec == 1 || cfg.prec == 2) && t256 > 0 && t256 >= plan.tuning.gemm_big_min;
         }
         std::vector<std::pair<size_t, size_t>> scratch;
         std::vector<ColPending> e1recs;  // this level's column reductions
@@ -1289,7 +1279,7 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
                 return "a V-statistic may exceed the 127-bit range";
             }
         }
-        layout_column_reductions(e1recs, W, [&](size_t bytes) {
+        layout_column_reductions(e1recs, W, plan.tuning.colred_blocks, [&](size_t bytes) {
             const size_t off = A.alloc(bytes);
             scratch.push_back({off, bytes});
             return P(off);

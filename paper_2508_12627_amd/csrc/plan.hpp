@@ -96,10 +96,21 @@ struct OrderScorer {
     virtual double score(const std::vector<float> &feat) const = 0;
 };
 
+// Launch-shape choices of the executor, set by the autotuner or the caller.
+struct Tuning {
+    // a GEMM level uses 256-wide tiles for its eligible problems once they
+    // give at least this many such tiles (2^62: never)
+    int64_t gemm_big_min = 256;
+    // column-reduction strips are cut so that a level has at least this
+    // many blocks (strips of 512 down to 32 rows)
+    int64_t colred_blocks = 1024;
+};
+
 struct Plan {
     int m = 0;
     std::vector<Edge> edges;
     PlanOptions opts;
+    Tuning tuning;
     std::vector<VProgram> progs;
     int M = 0;
     int max_width = 0;

@@ -72,6 +72,7 @@ EXPORTS = ["ustat_plan_opts_default", "ustat_plan_create", "ustat_plan_destroy",
            "ustat_build_rbf", "ustat_profile_enable", "ustat_profile_reset", "ustat_profile_read",
            "ustat_order_features", "vstat_eval_ordered", "ustat_mlp_num_params",
            "ustat_mlp_predict", "ustat_mlp_loss_grad", "ustat_mlp_train", "ustat_mlp_save",
+           "ustat_plan_tuning", "ustat_plan_set_tuning", "ustat_plan_autotune",
            "ustat_status_string", "ustat_last_error"]
 NUM_FEATURES = 18
 
@@ -114,6 +115,9 @@ def load_library(path: str = LIB_PATH):
     L.ustat_mlp_loss_grad.argtypes = [i32, i32, i32, pf32, pf32, pf32, i64, pdbl, pf32]
     L.ustat_mlp_train.argtypes = [i32, i32, i32, pf32, pf32, pf32, i64, i32, ctypes.c_float, pdbl]
     L.ustat_mlp_save.argtypes = [ctypes.c_char_p, i32, i32, i32, pf32]
+    L.ustat_plan_tuning.argtypes = [P, pi64, pi64]
+    L.ustat_plan_set_tuning.argtypes = [P, i64, i64]
+    L.ustat_plan_autotune.argtypes = [P, i64, ctypes.POINTER(P), P, i32, pdbl]
     L.ustat_status_string.argtypes = [i32]
     L.ustat_status_string.restype = ctypes.c_char_p
     L.ustat_last_error.argtypes = []
@@ -208,6 +212,27 @@ def ustat_plan_order(h, idx: int, m: int):
     sv = ctypes.c_int32()
     _check(load_library().ustat_plan_order(h, int(idx), buf, ctypes.byref(ln), ctypes.byref(sv)))
     return list(buf)[: ln.value], sv.value
+
+
+GEMM_BIG_NEVER = 1 << 62
+
+
+def ustat_plan_tuning(h) -> dict:
+    gb, cb = ctypes.c_int64(), ctypes.c_int64()
+    _check(load_library().ustat_plan_tuning(h, ctypes.byref(gb), ctypes.byref(cb)))
+    return {"gemm_big_min": gb.value, "colred_blocks": cb.value}
+
+
+def ustat_plan_set_tuning(h, gemm_big_min: int, colred_blocks: int):
+    _check(load_library().ustat_plan_set_tuning(h, int(gemm_big_min), int(colred_blocks)))
+
+
+def ustat_plan_autotune(h, n: int, factors, stream=None, reps: int = 3) -> float:
+    """Tunes the plan's launch shapes on these factors; returns ms per eval."""
+    ms = ctypes.c_double()
+    _check(load_library().ustat_plan_autotune(h, int(n), _factor_ptrs(factors),
+                                              _stream_handle(stream), int(reps), ctypes.byref(ms)))
+    return ms.value
 
 
 def ustat_graph_treewidth(m: int, edges) -> int:
@@ -388,6 +413,16 @@ class Plan:
 
     def order(self, idx: int) -> List[int]:
         return ustat_plan_order(self.h, idx, self.m)[0]
+
+    def tuning(self) -> dict:
+        return ustat_plan_tuning(self.h)
+
+    def set_tuning(self, gemm_big_min: int, colred_blocks: int):
+        ustat_plan_set_tuning(self.h, gemm_big_min, colred_blocks)
+
+    def autotune(self, factors, stream=None, reps: int = 3) -> float:
+        n = self._check_factors(factors)
+        return ustat_plan_autotune(self.h, n, factors, stream, reps)
 
     def slice_var(self, idx: int) -> int:
         return ustat_plan_order(self.h, idx, self.m)[1]

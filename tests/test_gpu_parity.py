@@ -308,6 +308,33 @@ def test_symmetric_factors_flag(U, name):
     assert ai.exact == bi.exact
 
 
+@pytest.mark.parametrize("prec", ["f32", "bf16x3"])
+def test_autotune_and_forced_tilings_agree(U, prec):
+    """The autotuner keeps one of its candidates, and every forced tiling
+    (256-wide GEMM tiles whenever eligible, or never; coarse or fine column
+    strips) gives U within the precision's tolerance of the f64 path."""
+    import torch
+    n, d = 1000, 16  # pads to 1024: 16 tiles of 256, so only a forced tiling uses them
+    X = W.gaussian_samples(n, d, seed=23)
+    K = U.ustat_build_rbf(dev(X, torch.float64), 32.0, prec)
+    K64 = U.ustat_build_rbf(dev(X, torch.float64), 32.0, "f64")
+    ref = U.Plan(4, W.CYCLE4, precision="f64", symmetric=True).eval([K64] * 4)
+    P = U.Plan(4, W.CYCLE4, precision=prec, symmetric=True)
+    say(f"autotune cycle4 n={n} {prec}")
+    ms = P.autotune([K] * 4, reps=2)
+    t = P.tuning()
+    assert ms > 0 and t["gemm_big_min"] in (256, 0, U.GEMM_BIG_NEVER)
+    assert t["colred_blocks"] in (256, 1024, 4096)
+    r = P.eval([K] * 4)
+    assert abs(r.value - ref.value) <= TOL[prec] * ref.err_scale
+    for gb in (0, U.GEMM_BIG_NEVER):
+        for cb in (1, 4096):
+            say(f"  forced tiling gemm_big_min={gb} colred_blocks={cb}")
+            P.set_tuning(gb, cb)
+            r = P.eval([K] * 4)
+            assert abs(r.value - ref.value) <= TOL[prec] * ref.err_scale
+
+
 def test_cycle5_er_full_size_exact(U):
     """Exact 5-cycle count of G(8192, 0.01) on the int8 path."""
     import torch

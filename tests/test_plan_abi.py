@@ -302,3 +302,16 @@ def test_shipped_cost_model_ranks_orders(U):
     pred, _ = mlp_ref.forward(params, F, H1, H2, X.astype(np.float64))
     assert np.all(np.isfinite(pred)) and np.all(np.diff(pred) > 0)
 
+
+def test_tuning_defaults_and_validation(U):
+    """Launch-shape tuning: defaults, setting, and rejected values (host only)."""
+    P = U.Plan(4, W.CYCLE4, precision="bf16x3")
+    assert P.tuning() == {"gemm_big_min": 256, "colred_blocks": 1024}
+    P.set_tuning(0, 256)
+    assert P.tuning() == {"gemm_big_min": 0, "colred_blocks": 256}
+    P.set_tuning(-7, 4096)
+    assert P.tuning()["gemm_big_min"] == 0
+    for bad in (0, -1, (1 << 20) + 1):
+        with pytest.raises(U.UstatError):
+            P.set_tuning(256, bad)
+
