@@ -437,13 +437,11 @@ std::string build_program(const std::vector<Edge> &edges, int m, const std::vect
     for (const Edge &e : edges)
         if (block_of[e.u] == block_of[e.v]) hasvec[block_of[e.u]] = 1;
     const double nref = opts.n_hint;
-    // Ranking key of a lowered program: the learned model's predicted
-    // log-time, else a time proxy (MFMA work plus memory traffic plus a
+    // Time proxy of a lowered program: MFMA work plus memory traffic plus a
     // per-level launch latency, in seconds at nominal rates; among equal
     // proxies, contractions of input factors without diagonal scaling are
-    // preferred, since they can be shared across partitions).
-    auto rank_key = [&](const VProgram &p) {
-        if (opts.order == 2 && scorer) return scorer->score(program_features(p, nref));
+    // preferred, since they can be shared across partitions.
+    auto proxy_key = [&](const VProgram &p) {
         double f, b;
         program_cost(p, nref, 4.0, &f, &b);
         return f / 100e12 + b / 5e12 + p.depth * 8e-6 + 1e-9 * sharing_penalty(p);
@@ -457,21 +455,13 @@ std::string build_program(const std::vector<Edge> &edges, int m, const std::vect
         p.lower_error.clear();
         out = std::move(p);
     };
-    // Plain orders first.  Min-fill takes its own order; exhaustive and
-    // learned policies enumerate every order (J <= 8) and keep the best key
-    // among the orders of smallest width (the width sets the power of n in
-    // the work, so ranking is only among equal-width orders).
     std::vector<int> mf = minfill_order(J, adj, hasvec);
-    const bool search = opts.order != 0 && J > 1 && J <= 8;
     std::string first_err;
-    {
-        VProgram best_p;
-        double best = std::numeric_limits<double>::infinity();
-        int best_w = std::numeric_limits<int>::max();
-        std::vector<int> perm(J);
-        std::iota(perm.begin(), perm.end(), 0);
-        const std::vector<int> &start = search ? perm : mf;
-        std::vector<int> cur = start;
+    // Candidate programs: every plain order (J <= 8), or, when none stays
+    // within degree 2, every (conditioned vertex c, order of the others).
+    auto plain_candidates = [&](auto &&cb) {
+        std::vector<int> cur(J);
+        std::iota(cur.begin(), cur.end(), 0);
         do {
             VProgram tmp;
             std::string err = lower_order(edges, block_of, J, cur, tmp);
@@ -479,27 +469,91 @@ std::string build_program(const std::vector<Edge> &edges, int m, const std::vect
                 if (first_err.empty()) first_err = err;
                 continue;
             }
-            if (tmp.width > best_w) continue;
-            double key = search ? rank_key(tmp) : 0.0;
-            if (tmp.width < best_w || key < best - 1e-15) {
-                best_w = tmp.width;
-                best = key;
-                best_p = std::move(tmp);
-            }
-        } while (search && std::next_permutation(cur.begin(), cur.end()));
-        if (std::isfinite(best)) {
-            keep_program(best_p);
-            return "";
+            cb(tmp);
+        } while (std::next_permutation(cur.begin(), cur.end()));
+    };
+    auto conditioned_candidates = [&](auto &&cb) {
+        for (int c = 0; c < J; ++c) {
+            std::vector<int> rest;
+            for (int q = 0; q < J; ++q)
+                if (q != c) rest.push_back(q);
+            do {
+                VProgram cand;
+                if (lower_order(edges, block_of, J, rest, cand, c).empty()) cb(cand);
+            } while (std::next_permutation(rest.begin(), rest.end()));
         }
-    }
-    // No order stays within degree 2: condition on one vertex c (sum over
-    // its n values outside the program) and eliminate the rest.  Min-fill
-    // tries min-fill orders of the graph without c for every c and keeps the
-    // smallest work; the search policies rank every (c, order) pair.
-    {
+    };
+    // Search policies rank only among the candidates of smallest width (the
+    // width sets the power of n in the work).  Exhaustive keeps the smallest
+    // proxy.  Learned lets the model choose among the candidates whose
+    // modelled work is close to the least and that share steps across
+    // partitions at least as well (the model, trained on partitions timed
+    // alone, sees neither sharing nor work gaps outside its training range):
+    // the smallest predicted log-time wins, predictions within kLearnedTie of
+    // it (about the model's error) count as ties, and the proxy breaks ties.
+    const bool learned = opts.order == 2 && scorer;
+    constexpr double kLearnedTie = 0.1, kLearnedGate = 0.25;
+    auto search_select = [&](auto &&candidates) {
+        int wmin = std::numeric_limits<int>::max(), share_at_min = 0;
+        double kmin = std::numeric_limits<double>::infinity();
+        candidates([&](VProgram &c) {
+            if (c.width < wmin) {
+                wmin = c.width;
+                kmin = std::numeric_limits<double>::infinity();
+            }
+            if (c.width == wmin) {
+                const double k = proxy_key(c);
+                if (k < kmin) {
+                    kmin = k;
+                    share_at_min = sharing_penalty(c);
+                }
+            }
+        });
+        if (wmin == std::numeric_limits<int>::max()) return false;
+        // learned: the model chooses among the candidates whose modelled
+        // work is within kLearnedGate of the least and that are at least as
+        // shareable as the proxy's choice (which always qualifies)
+        auto gated = [&](const VProgram &c) {
+            if (c.width != wmin) return false;
+            if (!learned) return true;
+            return proxy_key(c) <= kmin * (1.0 + kLearnedGate) && sharing_penalty(c) <= share_at_min;
+        };
+        double pmin = std::numeric_limits<double>::infinity();
+        if (learned)
+            candidates([&](VProgram &c) {
+                if (gated(c)) pmin = std::min(pmin, scorer->score(program_features(c, nref)));
+            });
         VProgram best_p;
         double best = std::numeric_limits<double>::infinity();
-        int best_w = std::numeric_limits<int>::max();
+        candidates([&](VProgram &c) {
+            if (!gated(c)) return;
+            if (learned && scorer->score(program_features(c, nref)) > pmin + kLearnedTie) return;
+            const double k = proxy_key(c);
+            if (k < best - 1e-15) {
+                best = k;
+                best_p = std::move(c);
+            }
+        });
+        keep_program(best_p);
+        return true;
+    };
+    const bool search = opts.order != 0 && J > 1 && J <= 8;
+    if (search) {
+        if (search_select(plain_candidates)) return "";
+        if (search_select(conditioned_candidates)) return "";
+    } else {
+        // Min-fill: its own order; failing that, for every conditioned
+        // vertex c the min-fill order of the graph without c, keeping the
+        // smallest work.
+        VProgram tmp;
+        std::string err = lower_order(edges, block_of, J, mf, tmp);
+        if (err.empty()) {
+            keep_program(tmp);
+            return "";
+        }
+        first_err = err;
+        VProgram best_p;
+        double best = std::numeric_limits<double>::infinity();
         for (int c = 0; c < J; ++c) {
             std::vector<uint32_t> a2 = adj;
             for (int q = 0; q < J; ++q) a2[q] &= ~(1u << c);
@@ -508,31 +562,16 @@ std::string build_program(const std::vector<Edge> &edges, int m, const std::vect
             for (int q = 0; q < J; ++q)
                 if (adj[c] & (1u << q)) hv[q] = 1;
             std::vector<int> rest;
-            if (search) {
-                for (int q = 0; q < J; ++q)
-                    if (q != c) rest.push_back(q);
-            } else {
-                for (int v : minfill_order(J, a2, hv))
-                    if (v != c) rest.push_back(v);
+            for (int v : minfill_order(J, a2, hv))
+                if (v != c) rest.push_back(v);
+            VProgram cand;
+            if (!lower_order(edges, block_of, J, rest, cand, c).empty()) continue;
+            double f, b;
+            program_cost(cand, nref, 4.0, &f, &b);
+            if (f < best) {
+                best = f;
+                best_p = std::move(cand);
             }
-            do {
-                VProgram cand;
-                if (!lower_order(edges, block_of, J, rest, cand, c).empty()) continue;
-                if (cand.width > best_w) continue;
-                double key;
-                if (search) {
-                    key = rank_key(cand);
-                } else {
-                    double f, b;
-                    program_cost(cand, nref, 4.0, &f, &b);
-                    key = f;
-                }
-                if (cand.width < best_w || key < best - 1e-15) {
-                    best_w = cand.width;
-                    best = key;
-                    best_p = std::move(cand);
-                }
-            } while (search && std::next_permutation(rest.begin(), rest.end()));
         }
         if (std::isfinite(best)) {
             keep_program(best_p);

@@ -316,7 +316,7 @@ def test_autotune_and_forced_tilings_agree(U, prec):
     import torch
     n, d = 1000, 16  # pads to 1024: 16 tiles of 256, so only a forced tiling uses them
     X = W.gaussian_samples(n, d, seed=23)
-    K = U.ustat_build_rbf(dev(X, torch.float64), 32.0, prec)
+    K = U.ustat_build_rbf(dev(X, torch.float64), 32.0, "f32")  # split-bf16 reads fp32 factors
     K64 = U.ustat_build_rbf(dev(X, torch.float64), 32.0, "f64")
     ref = U.Plan(4, W.CYCLE4, precision="f64", symmetric=True).eval([K64] * 4)
     P = U.Plan(4, W.CYCLE4, precision=prec, symmetric=True)
