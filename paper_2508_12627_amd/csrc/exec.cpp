@@ -154,12 +154,16 @@ struct LevelWork {
     size_t off_gemm_big = 0;
     std::vector<Elim1Desc> e1;  // column reductions over more than kColMat matrices
     int64_t e1_tiles = 0;
-    std::vector<ColDesc> col[kColMat];  // grouped column reductions, by matrix count
-    int64_t col_tiles[kColMat] = {0, 0, 0};
-    double col_bytes[kColMat] = {0, 0, 0};  // algorithmic HBM bytes per launch
-    int col_maxout[kColMat] = {0, 0, 0};     // largest output count of a group
-    int col_dtype[kColMat] = {-2, -2, -2};  // DType of every matrix, -1 if mixed, -2 none yet
-    size_t off_col[kColMat] = {0, 0, 0};
+    // grouped column reductions, one launch per slot: slot nm - 1 in column
+    // mode, kColMat + nm - 1 in row mode (nm distinct matrices)
+    static constexpr int kColSlots = 2 * kColMat;
+    std::vector<ColDesc> col[kColSlots];
+    int64_t col_tiles[kColSlots] = {0, 0, 0, 0, 0, 0};
+    double col_bytes[kColSlots] = {0, 0, 0, 0, 0, 0};  // algorithmic HBM bytes per launch
+    int col_maxout[kColSlots] = {0, 0, 0, 0, 0, 0};     // largest output count of a group
+    // DType of every matrix, -1 if mixed, -2 none yet
+    int col_dtype[kColSlots] = {-2, -2, -2, -2, -2, -2};
+    size_t off_col[kColSlots] = {0, 0, 0, 0, 0, 0};
     double e1_bytes = 0, prep_bytes = 0, tr_bytes = 0;  // algorithmic HBM bytes
     std::vector<TransDesc> tr;
     int64_t tr_tiles = 0;
@@ -265,6 +269,9 @@ struct Node {
     std::vector<MOp> A, B, Z;
     std::vector<VOp> sv, aw, bx;
     int level = 0, last_use = 0;
+    // a stored matrix equal to its transpose: a product sum_v A(w,v) s(v)
+    // A(x,v) whose two operand groups are the same
+    bool sym = false;
     // storage
     size_t off = 0, bytes = 0;
     int scal = -1, mx = -1;
@@ -337,6 +344,7 @@ int add_node(Dag &G, Node nd, const std::string &key, bool cse);
 MOp direct(Dag &G, const MOp &o, bool want_trans, int d, int64_t n, bool cse, bool sym) {
     if (o.trans == want_trans) return o;
     if (sym && o.node < 0) return MOp{o.node, o.p, want_trans};  // symmetric input
+    if (o.node >= 0 && G.nodes[o.node].sym) return MOp{o.node, o.p, want_trans};
     Node t;
     t.kind = NK::Transpose;
     t.d = d;
@@ -534,6 +542,7 @@ std::string build_dag(const Plan &plan, const std::vector<const VProgram *> &pro
             auto mop = [&](const MatOp &o) {
                 const Ref &r = ref[o.val];
                 if (sym && r.node < 0) return MOp{r.node, r.p, false};
+                if (r.node >= 0 && G.nodes[r.node].sym) return MOp{r.node, r.p, false};
                 return MOp{r.node, r.p, (bool)(o.trans ^ r.flip)};
             };
             auto vop = [&](int v) { return VOp{ref[v].node, ref[v].p, ref[v].off}; };
@@ -592,6 +601,7 @@ std::string build_dag(const Plan &plan, const std::vector<const VProgram *> &pro
                         nd_.A = sw ? B : A;
                         nd_.B = sw ? A : B;
                         nd_.sv = sv;
+                        nd_.sym = group_sig(A, mop_sig) == group_sig(B, mop_sig);
                         int id = add_node(G, nd_, k, cse);
                         ref[st.out].node = id;
                         ref[st.out].flip = sw;
@@ -642,6 +652,7 @@ std::string build_dag(const Plan &plan, const std::vector<const VProgram *> &pro
             g.A = A;
             g.B = B;
             g.sv = pd.sv;
+            g.sym = group_sig(A, mop_sig) == group_sig(B, mop_sig);
             int gid = add_node(G, g, pd.gkey, cse);
             // consumer: y(x') = sum_w' R(w',x') prod Z(w',x') prod aw(w'), an
             // Elim1 over v := w' (R is stored with rows over w'), then a dot
@@ -712,6 +723,7 @@ struct ColPending {
     Elim1Desc e;
     void *out;
     unsigned long long *mx;
+    bool rows = false;  // every matrix symmetric: reduce along rows
 };
 
 // Lays out a level's column reductions.  Those reading few distinct
@@ -733,6 +745,7 @@ void layout_column_reductions(const std::vector<ColPending> &recs, LevelWork &W,
     };
     struct Grp {
         int64_t n;
+        bool rows;
         std::vector<MatRef> M;
         std::vector<Out> outs;
     };
@@ -757,7 +770,7 @@ void layout_column_reductions(const std::vector<ColPending> &recs, LevelWork &W,
         }
         Grp *home = nullptr;
         for (Grp &g : groups) {
-            if (g.n != e.n || (int)g.outs.size() >= kColOut) continue;
+            if (g.n != e.n || g.rows != recs[ri].rows || (int)g.outs.size() >= kColOut) continue;
             std::vector<MatRef> un = g.M;
             for (const MatRef &m : dm) {
                 bool have = false;
@@ -770,7 +783,7 @@ void layout_column_reductions(const std::vector<ColPending> &recs, LevelWork &W,
             break;
         }
         if (!home) {
-            groups.push_back(Grp{e.n, dm, {}});
+            groups.push_back(Grp{e.n, recs[ri].rows, dm, {}});
             home = &groups.back();
         }
         Out o;
@@ -787,9 +800,12 @@ void layout_column_reductions(const std::vector<ColPending> &recs, LevelWork &W,
         home->outs.push_back(o);
     }
     auto wstrips = [](int64_t n) { return (n + 255) / 256; };
+    auto row_blocks = [](int64_t n) { return (n + kRowBlock - 1) / kRowBlock; };
     auto blocks = [&](int S) {
         int64_t b = 0;
-        for (const Grp &g : groups) b += ((g.n + S - 1) / S) * wstrips(g.n);
+        for (const Grp &g : groups)
+            b += g.rows ? row_blocks(g.n) * ((g.n + row_segment(g.n) - 1) / row_segment(g.n))
+                        : ((g.n + S - 1) / S) * wstrips(g.n);
         for (int ri : single) b += ((recs[ri].e.n + S - 1) / S) * wstrips(recs[ri].e.n);
         return b;
     };
@@ -833,14 +849,15 @@ void layout_column_reductions(const std::vector<ColPending> &recs, LevelWork &W,
             c.M[k] = g.M[k];
             c.M[k].zdiag = 0;  // applied per output
         }
-        c.strip = S;
-        c.tiles_v = (int)((g.n + S - 1) / S);
-        c.tiles_w = (int)wstrips(g.n);
+        c.rows = g.rows ? 1 : 0;
+        c.strip = g.rows ? row_segment(g.n) : S;
+        c.tiles_v = (int)((g.n + c.strip - 1) / c.strip);
+        c.tiles_w = g.rows ? (int)row_blocks(g.n) : (int)wstrips(g.n);
         for (int o = 0; o < c.nout; ++o) {
             c.o[o] = g.outs[o].o;
             c.o[o].part = partials(recs[g.outs[o].rec], c.tiles_v);
         }
-        const int b = c.nm - 1;
+        const int b = (g.rows ? kColMat : 0) + c.nm - 1;
         W.col_maxout[b] = std::max(W.col_maxout[b], c.nout);
         for (int k = 0; k < c.nm; ++k) {
             int &cd = W.col_dtype[b];
@@ -1113,6 +1130,9 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
                     }
                     cp.out = P(nd_.off);
                     cp.mx = (is_int && mxbase) ? mxbase + nd_.mx : nullptr;
+                    cp.rows = true;
+                    for (auto &o : nd_.A)
+                        cp.rows = cp.rows && (o.node < 0 ? data[d].symmetric : G.nodes[o.node].sym);
                     e1recs.push_back(cp);
                     break;
                 }
@@ -1345,7 +1365,7 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
         W.off_gemm = S.blob.put(W.gemm);
         W.off_gemm_big = S.blob.put(W.gemm_big);
         W.off_e1 = S.blob.put(W.e1);
-        for (int k = 0; k < kColMat; ++k) W.off_col[k] = S.blob.put(W.col[k]);
+        for (int k = 0; k < LevelWork::kColSlots; ++k) W.off_col[k] = S.blob.put(W.col[k]);
         W.off_e0 = S.blob.put(W.e0);
         W.off_red = S.blob.put(W.red);
     }
@@ -1618,12 +1638,12 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
                                 W.gemm_tiles, cfg.prec, 128, stream);
                 if (e != hipSuccess) return fail(e, "gemm");
             }
-            for (int k = 0; k < kColMat; ++k) {
+            for (int k = 0; k < LevelWork::kColSlots; ++k) {
                 if (W.col[k].empty()) continue;
                 ProfScope ps(prof, KIND_ELIM1, stream, 0, W.col_bytes[k]);
                 e = launch_colred(reinterpret_cast<ColDesc *>(dd + W.off_col[k]), (int)W.col[k].size(),
-                                  W.col_tiles[k], k + 1, W.col_maxout[k], W.col_dtype[k],
-                                  cfg.domain, stream);
+                                  W.col_tiles[k], k % kColMat + 1, W.col_maxout[k], W.col_dtype[k],
+                                  cfg.domain, k >= kColMat, stream);
                 if (e != hipSuccess) return fail(e, "column reduction");
             }
             if (!W.e1.empty()) {

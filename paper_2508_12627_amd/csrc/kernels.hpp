@@ -77,6 +77,10 @@ struct ColDesc {
     int64_t tile_start;
     int32_t tiles_v, tiles_w;
     int32_t strip;  // rows per block (a multiple of 32)
+    // 1: every matrix is symmetric and the reduction runs along rows w:
+    // blocks of kRowBlock rows by `strip` columns (256, 512 or 1024),
+    // tiles_v column segments (one partial each) times tiles_w row blocks
+    int32_t rows;
 };
 
 // out[j] = (sum_{t < T} part[t * stride + j]) * prod_q mul_q[j], j < len,
@@ -181,6 +185,13 @@ struct SliceDesc {
 constexpr int kGemmTile = 128;
 constexpr int kTile = 64;
 constexpr int kElimStrip = 512;  // largest rows per column-reduction block
+constexpr int kRowBlock = 32;  // rows per row-mode reduction block (four waves)
+// Columns per row-mode block for size n: 256 columns per 64 lanes of
+// float4 loads, up to four groups.
+inline int row_segment(int64_t n) {
+    const int64_t g = (n + 255) / 256;
+    return g >= 4 ? 1024 : g >= 2 ? 512 : 256;
+}
 
 // Rows per column-reduction block for size n: about 1024 blocks per
 // problem (so that even a single problem fills the chip), in multiples of
@@ -200,9 +211,10 @@ hipError_t launch_elim1(const Elim1Desc *d, int nprob, int64_t total_tiles, int 
                         hipStream_t s);
 // nm: the number of distinct matrices of every group in d (1..kColMat);
 // max_out: the largest output count of a group; elem_dtype: the DType of
-// every matrix of the launch, or -1 when they differ
+// every matrix of the launch, or -1 when they differ; rows: every group is
+// in row mode (ColDesc::rows), else none is
 hipError_t launch_colred(const ColDesc *d, int nprob, int64_t total_tiles, int nm, int max_out,
-                         int elem_dtype, int domain, hipStream_t s);
+                         int elem_dtype, int domain, bool rows, hipStream_t s);
 hipError_t launch_reduce(const ReduceDesc *d, int nprob, int64_t max_len, int domain,
                          hipStream_t s);
 hipError_t launch_elim0(const Elim0Desc *d, int nprob, int domain, hipStream_t s);
