@@ -763,12 +763,29 @@ __global__ __launch_bounds__(256) void k_reduce(const ReduceDesc *D, int nprob) 
         // scalar (wide) partials: thread t sums q = t, t+256, ... in order
         for (int64_t q = t; q < d.T; q += 256) acc += static_cast<const Wd *>(d.part)[q * d.stride];
     } else {
-        for (int64_t j = t; j < d.len; j += 256) {
-            A s = 0;
-            for (int64_t q = 0; q < d.T; ++q) s += static_cast<const A *>(d.part)[q * d.stride + j];
-            Wd w = (Wd)s;
-            for (int q = 0; q < d.nmul; ++q) w *= (Wd)load_vec<DOM>(d.mul[q], j);
-            acc += w;
+        // four elements per thread per round (j, j + 256, ...), their loads
+        // issued together from clamped indices; summed in that fixed order
+        constexpr int U = 4;
+        for (int64_t j0 = t; j0 < d.len; j0 += 256 * U) {
+            A s[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) s[u] = 0;
+            for (int64_t q = 0; q < d.T; ++q)
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int64_t j = min(j0 + 256 * u, d.len - 1);
+                    s[u] += static_cast<const A *>(d.part)[q * d.stride + j];
+                }
+            Wd w[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) w[u] = (Wd)s[u];
+            for (int q = 0; q < d.nmul; ++q)
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    w[u] *= (Wd)load_vec<DOM>(d.mul[q], min(j0 + 256 * u, d.len - 1));
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (j0 + 256 * u < d.len) acc += w[u];
         }
     }
     red[t] = acc;
@@ -790,10 +807,19 @@ __global__ __launch_bounds__(256) void k_elim0(const Elim0Desc *D, int nprob) {
     const Elim0Desc &d = D[blockIdx.x];
     const int t = threadIdx.x;
     Wd acc = 0;
-    for (int64_t v = t; v < d.n; v += 256) {
-        Wd x = 1;
-        for (int j = 0; j < d.nS; ++j) x *= (Wd)load_vec<DOM>(d.s[j], v);
-        acc += x;
+    // four elements per thread per round (v, v + 256, ...), their loads
+    // issued together from clamped indices; summed in that fixed order
+    constexpr int U = 4;
+    for (int64_t v0 = t; v0 < d.n; v0 += 256 * U) {
+        Wd x[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) x[u] = 1;
+        for (int j = 0; j < d.nS; ++j)
+#pragma unroll
+            for (int u = 0; u < U; ++u) x[u] *= (Wd)load_vec<DOM>(d.s[j], min(v0 + 256 * u, d.n - 1));
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (v0 + 256 * u < d.n) acc += x[u];
     }
     red[t] = acc;
     __syncthreads();
