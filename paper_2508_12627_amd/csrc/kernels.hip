@@ -145,12 +145,19 @@ __global__ __launch_bounds__(256) void k_rbf(const double *__restrict__ X, int64
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[a][c] = 0.0;
     for (int k0 = 0; k0 < d; k0 += 32) {
-        for (int e = t; e < 64 * 32; e += 256) {
+        // clamped loads, all in flight together; entries outside the
+        // samples or coordinates are zeroed afterwards
+#pragma unroll
+        for (int it = 0; it < 64 * 32 / 256; ++it) {
+            const int e = t + 256 * it;
             const int rr = e >> 5, kk = e & 31;
             const int64_t gi = i0 + rr, gj = j0 + rr;
             const int gk = k0 + kk;
-            xi[rr][kk] = (gi < n && gk < d) ? X[gi * d + gk] : 0.0;
-            xj[rr][kk] = (gj < n && gk < d) ? X[gj * d + gk] : 0.0;
+            const int gkc = min(gk, d - 1);
+            const double a = X[min(gi, n - 1) * d + gkc];
+            const double c = X[min(gj, n - 1) * d + gkc];
+            xi[rr][kk] = (gi < n && gk < d) ? a : 0.0;
+            xj[rr][kk] = (gj < n && gk < d) ? c : 0.0;
         }
         __syncthreads();
         const int kmax = min(32, d - k0);
@@ -837,7 +844,7 @@ __global__ __launch_bounds__(256) void k_elim0(const Elim0Desc *D, int nprob) {
 // (w, v), so rows are read and written in order, four consecutive v per
 // lane.  Thread t owns columns v0 + 4 (t%32) .. +3 and rows w0 + t/32 + 8i.
 template <int DOM>
-__global__ __launch_bounds__(256) void k_prep(const PrepDesc *D, int nprob) {
+__global__ __launch_bounds__(256) void k_prep(const PrepDesc *__restrict__ D, int nprob) {
     typedef typename Dom<DOM>::acc A;
     const int64_t b = blockIdx.x;
     const int p = __builtin_amdgcn_readfirstlane(find_problem(D, nprob, b));  // uniform
@@ -865,12 +872,10 @@ __global__ __launch_bounds__(256) void k_prep(const PrepDesc *D, int nprob) {
     }
     A sv[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        A x = (v + j < n) ? (A)1 : (A)0;
-        if (v + j < n)
-            for (int q = 0; q < d.nS; ++q) x *= load_vec<DOM>(d.s[q], v + j);
-        sv[j] = x;
-    }
+    for (int j = 0; j < 4; ++j) sv[j] = (v + j < n) ? (A)1 : (A)0;
+    for (int q = 0; q < d.nS; ++q)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) sv[j] *= load_vec<DOM>(d.s[q], min(v + j, n - 1));
     A pr[8][4];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
@@ -883,13 +888,25 @@ __global__ __launch_bounds__(256) void k_prep(const PrepDesc *D, int nprob) {
         with_dtype(m.dtype, [&](auto tag) {
             typedef decltype(tag) T;
             const T *mp = static_cast<const T *>(m.p);
-            const bool vec = (v + 3 < n) && (m.ld % 4 == 0);
+            // Rows and columns are clamped into range instead of branched
+            // on (pr is already 0 outside it), so the eight rows' loads are
+            // in flight together; 16-byte loads when n and the row pitch
+            // are multiples of 4 (uniform over the block).
             A x[8][4];
+            if (n % 4 == 0 && m.ld % 4 == 0) {
+                const int64_t vc = min(v, n - 4);
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                int64_t w = w0 + rg + 8 * i;
-                if (w < n && v < n) load4<T, A>(mp, w * m.ld + v, vec, v, n, x[i]);
-                else x[i][0] = x[i][1] = x[i][2] = x[i][3] = 0;
+                for (int i = 0; i < 8; ++i) {
+                    const int64_t w = min(w0 + rg + 8 * i, n - 1);
+                    load4<T, A>(mp, w * m.ld + vc, true, vc, n, x[i]);
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int64_t w = min(w0 + rg + 8 * i, n - 1);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) x[i][j] = (A)mp[w * m.ld + min(v + j, n - 1)];
+                }
             }
 #pragma unroll
             for (int i = 0; i < 8; ++i)
@@ -901,20 +918,25 @@ __global__ __launch_bounds__(256) void k_prep(const PrepDesc *D, int nprob) {
                 }
         });
     }
+    // output fields read once (the stores below would otherwise force
+    // their reloads, each waiting for every store in flight)
+    const int64_t npad = d.npad, ldo = d.ldo, plane = d.plane;
+    void *const out = d.out;
+    const int format = d.format;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
         int64_t w = w0 + rg + 8 * i;
-        if (w >= d.npad) continue;
-        int64_t o = w * d.ldo + v;
-        switch (d.format) {
+        if (w >= npad) continue;
+        int64_t o = w * ldo + v;
+        switch (format) {
             case PF_F64: {
                 typedef double v2 __attribute__((ext_vector_type(2)));
-                *reinterpret_cast<v2 *>(static_cast<double *>(d.out) + o) = v2{(double)pr[i][0], (double)pr[i][1]};
-                *reinterpret_cast<v2 *>(static_cast<double *>(d.out) + o + 2) = v2{(double)pr[i][2], (double)pr[i][3]};
+                *reinterpret_cast<v2 *>(static_cast<double *>(out) + o) = v2{(double)pr[i][0], (double)pr[i][1]};
+                *reinterpret_cast<v2 *>(static_cast<double *>(out) + o + 2) = v2{(double)pr[i][2], (double)pr[i][3]};
                 break;
             }
             case PF_F32: {
-                *reinterpret_cast<f32x4 *>(static_cast<float *>(d.out) + o) =
+                *reinterpret_cast<f32x4 *>(static_cast<float *>(out) + o) =
                     f32x4{(float)pr[i][0], (float)pr[i][1], (float)pr[i][2], (float)pr[i][3]};
                 break;
             }
@@ -928,8 +950,8 @@ __global__ __launch_bounds__(256) void k_prep(const PrepDesc *D, int nprob) {
                     hi[j] = h;
                     lo[j] = f32_to_bf16_rne((float)(xd - (double)bf16_to_f32(h)));
                 }
-                *reinterpret_cast<u16x4 *>(static_cast<uint16_t *>(d.out) + o) = hi;
-                *reinterpret_cast<u16x4 *>(static_cast<uint16_t *>(d.out) + o + d.plane) = lo;
+                *reinterpret_cast<u16x4 *>(static_cast<uint16_t *>(out) + o) = hi;
+                *reinterpret_cast<u16x4 *>(static_cast<uint16_t *>(out) + o + plane) = lo;
                 break;
             }
             default: {
@@ -938,10 +960,10 @@ __global__ __launch_bounds__(256) void k_prep(const PrepDesc *D, int nprob) {
                     long long xi = (long long)pr[i][j];
                     for (int l = 0; l + 1 < limbs; ++l) {
                         long long md = ((xi % 128) + 128 + 64) % 128 - 64;  // balanced digit
-                        static_cast<int8_t *>(d.out)[o + j + l * d.plane] = (int8_t)md;
+                        static_cast<int8_t *>(out)[o + j + l * plane] = (int8_t)md;
                         xi = (xi - md) / 128;
                     }
-                    static_cast<int8_t *>(d.out)[o + j + (int64_t)(limbs - 1) * d.plane] = (int8_t)xi;
+                    static_cast<int8_t *>(out)[o + j + (int64_t)(limbs - 1) * plane] = (int8_t)xi;
                 }
                 break;
             }
@@ -1205,7 +1227,7 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t G) {
 
 template <int PREC, class SH>
 __global__ __launch_bounds__(SH::NT) __attribute__((amdgpu_waves_per_eu(2)))
-void k_gemm(const GemmDesc *D, int nprob) {
+void k_gemm(const GemmDesc *__restrict__ D, int nprob) {
     typedef typename AccT<PREC>::T AT;
     constexpr int FM = SH::FM, FN = SH::FN;
     static_assert(PREC == 1 || PREC == 2 || SH::BM == 128, "large tiles: fp32 accumulators only");
@@ -1286,6 +1308,11 @@ void k_gemm(const GemmDesc *D, int nprob) {
                 atomicMax(d.mx_out, mloc);
             }
         }
+        // output fields read once: a reload after each store would wait for
+        // every store in flight
+        void *const C = d.C;
+        const int64_t ldc = d.ldc;
+        const bool c64 = d.dtype_c == DT_F64;
 #pragma clang loop unroll(full)
         for (int ib = 0; ib < FM; ib += 4)
 #pragma unroll
@@ -1297,10 +1324,10 @@ void k_gemm(const GemmDesc *D, int nprob) {
                     int64_t w = wr0 + i * 16 + mfma_row<PREC>(lane, r);
                     int64_t x = xc0 + j * 16 + (lane & 15);
                     if (w < n && x < n) {
-                        int64_t o = w * d.ldc + x;
-                        if constexpr (PREC == 3) static_cast<long long *>(d.C)[o] = value(i, j, r);
-                        else if (d.dtype_c == DT_F64) static_cast<double *>(d.C)[o] = value(i, j, r);
-                        else static_cast<float *>(d.C)[o] = (float)value(i, j, r);
+                        int64_t o = w * ldc + x;
+                        if constexpr (PREC == 3) static_cast<long long *>(C)[o] = value(i, j, r);
+                        else if (c64) static_cast<double *>(C)[o] = value(i, j, r);
+                        else static_cast<float *>(C)[o] = (float)value(i, j, r);
                     }
                 }
         return;
