@@ -217,7 +217,7 @@ __global__ __launch_bounds__(256) void k_rbf(const double *__restrict__ X, int64
 // ----------------------------------------------------------------- diag
 
 template <int DOM>
-__global__ void k_diag(const DiagDesc *D, int nprob) {
+__global__ void k_diag(const DiagDesc *__restrict__ D, int nprob) {
     const DiagDesc &d = D[blockIdx.y];
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < d.n;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -291,7 +291,7 @@ __device__ __forceinline__ void load4(const T *p, int64_t i, bool vec, int64_t c
 // t owns columns w0 + 4 (t%64) .. +3 and rows v0 + t/64 + 4i of each 32-row
 // chunk.
 template <int DOM>
-__global__ __launch_bounds__(256) void k_elim1(const Elim1Desc *D, int nprob) {
+__global__ __launch_bounds__(256) void k_elim1(const Elim1Desc *__restrict__ D, int nprob) {
     typedef typename Dom<DOM>::acc A;
     __shared__ A red[4][256];
     const int64_t b = blockIdx.x;
@@ -390,7 +390,7 @@ __global__ __launch_bounds__(256) void k_elim1(const Elim1Desc *D, int nprob) {
 
 // Transpose: out[b * n + a] = in[a * ld + b] for a, b < n (64 x 64 tiles
 // through LDS, both sides coalesced).
-__global__ __launch_bounds__(256) void k_transpose(const TransDesc *D, int nprob) {
+__global__ __launch_bounds__(256) void k_transpose(const TransDesc *__restrict__ D, int nprob) {
     __shared__ long long tile[64][65];
     const int64_t b = blockIdx.x;
     const int p = __builtin_amdgcn_readfirstlane(find_problem(D, nprob, b));  // uniform
@@ -623,7 +623,7 @@ __global__ __launch_bounds__(256) void k_rowred(const ColDesc *__restrict__ D, i
 }
 
 template <int DOM, typename T, int NM, int NOUT>
-__global__ __launch_bounds__(256) void k_colred(const ColDesc *D, int nprob) {
+__global__ __launch_bounds__(256) void k_colred(const ColDesc *__restrict__ D, int nprob) {
     typedef typename Dom<DOM>::acc A;
     typedef typename std::conditional<std::is_void<T>::value, A, T>::type XT;
     constexpr int ROWS = 4;
@@ -726,7 +726,7 @@ __global__ __launch_bounds__(256) void k_colred(const ColDesc *D, int nprob) {
 // type).  Dot: a single block sums those values over j into out[0] (wide
 // type); `part` elements are wide when len == 1 (GEMM tile partials).
 template <int DOM>
-__global__ __launch_bounds__(256) void k_reduce(const ReduceDesc *D, int nprob) {
+__global__ __launch_bounds__(256) void k_reduce(const ReduceDesc *__restrict__ D, int nprob) {
     typedef typename Dom<DOM>::acc A;
     typedef typename Dom<DOM>::wide Wd;
     const ReduceDesc &d = D[blockIdx.x];
@@ -808,7 +808,7 @@ __global__ __launch_bounds__(256) void k_reduce(const ReduceDesc *D, int nprob) 
 // ----------------------------------------------------------------- elim0
 
 template <int DOM>
-__global__ __launch_bounds__(256) void k_elim0(const Elim0Desc *D, int nprob) {
+__global__ __launch_bounds__(256) void k_elim0(const Elim0Desc *__restrict__ D, int nprob) {
     typedef typename Dom<DOM>::wide Wd;
     __shared__ Wd red[256];
     const Elim0Desc &d = D[blockIdx.x];
@@ -1381,10 +1381,12 @@ void k_gemm(const GemmDesc *__restrict__ D, int nprob) {
 // ----------------------------------------------------------------- combine
 
 template <int DOM>
-__global__ void k_combine(const CombineDesc *D, int ndata, const int32_t *term_off,
-                          const int32_t *term_cnt, const int32_t *off, const int32_t *cnt,
-                          const int32_t *idx, const int64_t *mu, const void *scal, void *accv,
-                          int first, int last, void *uout, double *sout) {
+__global__ void k_combine(const CombineDesc *__restrict__ D, int ndata,
+                          const int32_t *__restrict__ term_off, const int32_t *__restrict__ term_cnt,
+                          const int32_t *__restrict__ off, const int32_t *__restrict__ cnt,
+                          const int32_t *__restrict__ idx, const int64_t *__restrict__ mu,
+                          const void *__restrict__ scal, void *__restrict__ accv, int first,
+                          int last, void *__restrict__ uout, double *__restrict__ sout) {
     typedef typename Dom<DOM>::wide Wd;
     int ds = blockIdx.x * blockDim.x + threadIdx.x;
     if (ds >= ndata) return;
@@ -1415,7 +1417,7 @@ __global__ void k_combine(const CombineDesc *D, int ndata, const int32_t *term_o
 // Slice sources, 64 x 64 tiles through LDS so that both orientations read
 // and write whole rows.
 template <int DOM>
-__global__ __launch_bounds__(256) void k_slicesrc(const SliceDesc *D, int nprob) {
+__global__ __launch_bounds__(256) void k_slicesrc(const SliceDesc *__restrict__ D, int nprob) {
     typedef typename Dom<DOM>::acc A;
     __shared__ A tile[64][65];
     const int64_t b = blockIdx.x;
