@@ -39,7 +39,7 @@ def timed_evals(plan, X, div, steps, warmup, stream):
 
 
 HBM_PEAK = 8.0e12  # bytes/s
-KERNELS = {"gemm": "k_gemm", "elim1": "k_colred/k_elim1", "prep": "k_prep/k_transpose",
+KERNELS = {"gemm": "k_gemm", "elim1": "k_rowred/k_colred/k_elim1", "prep": "k_prep/k_transpose",
            "reduce": "k_reduce", "rbf": "k_rbf"}
 PREC_INDEX = {"f64": 0, "f32": 1, "bf16x3": 2}
 # HBM bytes per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs
@@ -266,8 +266,8 @@ def bench_learned_order(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--precision", default="bf16x3", choices=["bf16x3", "f32", "f64"])
     ap.add_argument("--order", default="exhaustive", choices=["minfill", "exhaustive"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
