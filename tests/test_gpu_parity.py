@@ -308,6 +308,39 @@ def test_symmetric_factors_flag(U, name):
     assert ai.exact == bi.exact
 
 
+@pytest.mark.parametrize("name", ["cycle4", "c5chord", "bowtie"])
+def test_row_reductions_span_segments(U, name):
+    """Reductions over symmetric matrices run along rows in blocks of 32 rows
+    by segments of up to 1024 columns.  At n = 1500 (two segments, 16-byte
+    loads) and n = 1027 (two segments, element loads, a 3-column tail) the
+    symmetric plan agrees with the column-strip plan on the same matrix in
+    fp64 and bit for bit on the exact path; at a small size both match the
+    oracle."""
+    import torch
+    edges = GRAPHS[name]
+    m = nverts(edges)
+    for n in (1500, 1027):
+        (M,) = W.random_matrices(1, n, seed=41 + n, lo=0.0, hi=1.0)
+        M = 0.5 * (M + M.T)
+        Kd = dev(M, torch.float64)
+        say(f"row reductions {name} n={n} f64")
+        a = U.Plan(m, edges, precision="f64", symmetric=True).eval([Kd] * len(edges))
+        b = U.Plan(m, edges, precision="f64").eval([Kd] * len(edges))
+        assert abs(a.value - b.value) <= 1e-12 * b.err_scale
+        A = W.erdos_renyi(n, 0.02, seed=n)
+        Ad = dev(A, torch.int8)
+        say(f"row reductions {name} n={n} i8")
+        ai = U.Plan(m, edges, precision="i8", symmetric=True).eval([Ad] * len(edges))
+        bi = U.Plan(m, edges, precision="i8").eval([Ad] * len(edges))
+        assert ai.exact == bi.exact
+    n = 37
+    (M,) = W.random_matrices(1, n, seed=43, lo=0.0, hi=1.0)
+    M = 0.5 * (M + M.T)
+    ref = oracle.ustat_bruteforce(edges, [M] * len(edges))
+    a = U.Plan(m, edges, precision="f64", symmetric=True).eval([dev(M, torch.float64)] * len(edges))
+    assert abs(a.value - ref) <= 1e-12 * a.err_scale
+
+
 @pytest.mark.parametrize("prec", ["f32", "bf16x3"])
 def test_autotune_and_forced_tilings_agree(U, prec):
     """The autotuner keeps one of its candidates, and every forced tiling
