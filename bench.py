@@ -62,12 +62,14 @@ def measured_traffic(kind, prec):
     frags = KERNELS[kind].split("/")
     if kind == "gemm":
         frags = [f"k_gemm<{PREC_INDEX[prec]}"]
-    tot, hit = 0.0, False
+    # mean over the matching kernels' launches (a kind may span several
+    # kernels, e.g. the row reductions over one and over two matrices)
+    tot, cnt = 0.0, 0
     for name, k in rec.get("kernels", {}).items():
         if any(fr in name for fr in frags) and k.get("bytes_per_launch") is not None:
-            tot += k["bytes_per_launch"]
-            hit = True
-    return tot if hit else None
+            tot += k["bytes_per_launch"] * k["launches"]
+            cnt += k["launches"]
+    return tot / cnt if cnt else None
 
 
 def kernel_rooflines(U, plan, X, div, stream, prec, reps=5):

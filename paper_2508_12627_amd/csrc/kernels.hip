@@ -1380,35 +1380,53 @@ void k_gemm(const GemmDesc *__restrict__ D, int nprob) {
 
 // ----------------------------------------------------------------- combine
 
+// One block per dataset: thread t forms V_p and mu_p * a_p of program
+// p = p0 + t (the chains of index and scalar loads of different programs
+// overlap), then thread 0 adds the terms to U and S in program order, the
+// same order as a serial loop.
 template <int DOM>
-__global__ void k_combine(const CombineDesc *__restrict__ D, int ndata,
-                          const int32_t *__restrict__ term_off, const int32_t *__restrict__ term_cnt,
-                          const int32_t *__restrict__ off, const int32_t *__restrict__ cnt,
-                          const int32_t *__restrict__ idx, const int64_t *__restrict__ mu,
-                          const void *__restrict__ scal, void *__restrict__ accv, int first,
-                          int last, void *__restrict__ uout, double *__restrict__ sout) {
+__global__ __launch_bounds__(256) void k_combine(
+    const CombineDesc *__restrict__ D, int ndata, const int32_t *__restrict__ term_off,
+    const int32_t *__restrict__ term_cnt, const int32_t *__restrict__ off,
+    const int32_t *__restrict__ cnt, const int32_t *__restrict__ idx,
+    const int64_t *__restrict__ mu, const void *__restrict__ scal, void *__restrict__ accv,
+    int first, int last, void *__restrict__ uout, double *__restrict__ sout) {
     typedef typename Dom<DOM>::wide Wd;
-    int ds = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ Wd tvs[256];
+    const int ds = blockIdx.x, t = threadIdx.x;
     if (ds >= ndata) return;
     const Wd *sc = static_cast<const Wd *>(scal);
     Wd *acc = static_cast<Wd *>(accv);
+    const int pb = D[ds].p_begin, pe = D[ds].p_end;
     Wd U = 0;
     double S = 0;
-    for (int p = D[ds].p_begin; p < D[ds].p_end; ++p) {
-        Wd V = 0;
-        for (int t = term_off[p]; t < term_off[p] + term_cnt[p]; ++t) {
-            Wd prod = 1;
-            for (int q = 0; q < cnt[t]; ++q) prod *= sc[idx[off[t] + q]];
-            V += prod;
+    for (int p0 = pb; p0 < pe; p0 += 256) {
+        const int p = p0 + t;
+        Wd tv = 0;
+        if (p < pe) {
+            Wd V = 0;
+            for (int k = term_off[p]; k < term_off[p] + term_cnt[p]; ++k) {
+                Wd prod = 1;
+                for (int q = 0; q < cnt[k]; ++q) prod *= sc[idx[off[k] + q]];
+                V += prod;
+            }
+            const Wd a = first ? V : acc[p] + V;
+            acc[p] = a;
+            tv = (Wd)mu[p] * a;
         }
-        Wd a = first ? V : acc[p] + V;
-        acc[p] = a;
-        Wd tv = (Wd)mu[p] * a;
-        U += tv;
-        double td = (double)tv;
-        S += td < 0 ? -td : td;
+        tvs[t] = tv;
+        __syncthreads();
+        if (t == 0) {
+            const int cntp = min(256, pe - p0);
+            for (int q = 0; q < cntp; ++q) {
+                U += tvs[q];
+                const double td = (double)tvs[q];
+                S += td < 0 ? -td : td;
+            }
+        }
+        __syncthreads();
     }
-    if (last) {
+    if (last && t == 0) {
         static_cast<Wd *>(uout)[ds] = U;
         sout[ds] = S;
     }
@@ -1595,12 +1613,13 @@ hipError_t launch_combine(const CombineDesc *d, int ndata, const int32_t *term_o
                           const int32_t *scal_cnt, const int32_t *scal_idx, const int64_t *mu,
                           const void *scal, void *acc, int first, int last, void *uout,
                           double *sout, int domain, hipStream_t s) {
-    dim3 grid((unsigned)((ndata + 63) / 64));
+    if (ndata <= 0) return hipSuccess;
+    dim3 grid((unsigned)ndata);
     if (domain == DOM_FP)
-        hipLaunchKernelGGL(k_combine<DOM_FP>, grid, dim3(64), 0, s, d, ndata, term_off, term_cnt,
+        hipLaunchKernelGGL(k_combine<DOM_FP>, grid, dim3(256), 0, s, d, ndata, term_off, term_cnt,
                            scal_off, scal_cnt, scal_idx, mu, scal, acc, first, last, uout, sout);
     else
-        hipLaunchKernelGGL(k_combine<DOM_INT>, grid, dim3(64), 0, s, d, ndata, term_off, term_cnt,
+        hipLaunchKernelGGL(k_combine<DOM_INT>, grid, dim3(256), 0, s, d, ndata, term_off, term_cnt,
                            scal_off, scal_cnt, scal_idx, mu, scal, acc, first, last, uout, sout);
     return hipGetLastError();
 }
