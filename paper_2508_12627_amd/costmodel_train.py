@@ -136,9 +136,9 @@ def init_params(F: int, H1: int, H2: int, X, seed: int):
     return p
 
 
-def judge(graphs, n_for, model_path, precision: str = "bf16x3", max_candidates: int = 32,
+def compare_policies(graphs, n_for, model_path, precision: str = "bf16x3", max_candidates: int = 32,
           repeats: int = 2, seed: int = 0, log=print):
-    """Brute-force judge of the order policies.  For every partition of every
+    """Brute-force comparison of the order policies.  For every partition of every
     graph with at least two executable candidates, times a sample of at most
     max_candidates candidates plus the picks of the min-fill, exhaustive
     (cost proxy) and learned policies, all at n = n_for(M) for the graph's
@@ -179,12 +179,12 @@ def judge(graphs, n_for, model_path, precision: str = "bf16x3", max_candidates: 
             for name, c in picks.items():
                 rec[name] = times[c]
             recs.append(rec)
-        log(f"judge graph {gi + 1}/{len(graphs)}: {len(recs)} partitions", flush=True)
+        log(f"policies graph {gi + 1}/{len(graphs)}: {len(recs)} partitions", flush=True)
     return recs
 
 
-def judge_summary(recs, margin: float = 0.05) -> dict:
-    """Totals over all judged partitions and over those where the best
+def policies_summary(recs, margin: float = 0.05) -> dict:
+    """Totals over all compared partitions and over those where the best
     measured order beats min-fill by more than margin."""
     out = {}
     for name, sel in (("all", recs),
@@ -229,22 +229,22 @@ def main():
     ap.add_argument("--steps", type=int, default=3000)
     ap.add_argument("--seed", type=int, default=11)
     ap.add_argument("--data-out", default=None)
-    ap.add_argument("--judge", default=None, metavar="LO:HI",
-                    help="judge the policies on graphs LO:HI of the learned-order workload "
+    ap.add_argument("--compare-policies", default=None, metavar="LO:HI",
+                    help="compare the policies on graphs LO:HI of the learned-order workload "
                          "(64 random 6-vertex graphs, seed 5) with the model --out, at "
                          "n = 2048 (M <= 2) / 512 (M = 3), instead of training")
-    ap.add_argument("--judge-candidates", type=int, default=16)
+    ap.add_argument("--compare-candidates", type=int, default=16)
     args = ap.parse_args()
     import torch
     from paper_2508_12627_amd import ustat as U, workloads as W
     torch.cuda.set_device(0)
-    if args.judge:
-        lo, hi = (int(x) for x in args.judge.split(":"))
+    if args.compare_policies:
+        lo, hi = (int(x) for x in args.compare_policies.split(":"))
         graphs = [e for e in W.random_kernel_graphs(64, 6, 6, 10, seed=5)[lo:hi]
                   if U.Plan(6, e).info()["M"] <= 3]
-        recs = judge(graphs, lambda M: 2048 if M <= 2 else 512, args.out,
-                     max_candidates=args.judge_candidates, repeats=3)
-        summary = judge_summary(recs)
+        recs = compare_policies(graphs, lambda M: 2048 if M <= 2 else 512, args.out,
+                     max_candidates=args.compare_candidates, repeats=3)
+        summary = policies_summary(recs)
         summary.update({"graphs": f"{lo}:{hi}", "model": os.path.basename(args.out)})
         if args.data_out:
             with open(args.data_out, "w") as f:

@@ -1,5 +1,5 @@
 """Order policies on the GPU: the chosen order changes speed, never the
-result, and the learned cost model's picks are judged against brute-force
+result, and the learned cost model's picks are compared against brute-force
 timing of the candidates (the paper leaves order search to heuristics, in its
 remark after the V-statistic complexity proposition)."""
 import json
@@ -71,17 +71,17 @@ def test_int8_counts_identical_across_policies(U):
 
 
 def test_learned_order_gain(U):
-    """Brute-force judge on graphs the model was not trained on: summed over
+    """Brute-force policy comparison on graphs the model was not trained on: summed over
     the partitions where some measured order beats min-fill's by more than
     5%, the learned picks take no more time than min-fill's (5% allowance for
-    timing noise), and the learned picks' total over all judged partitions
+    timing noise), and the learned picks' total over all compared partitions
     is within 5% of min-fill's."""
-    from paper_2508_12627_amd.costmodel_train import judge, judge_summary
+    from paper_2508_12627_amd.costmodel_train import compare_policies, policies_summary
     graphs = [e for e in W.random_kernel_graphs(12, 6, 6, 10, seed=5)
               if U.Plan(6, e).info()["M"] <= 3][:4]
-    recs = judge(graphs, lambda M: 2048 if M <= 2 else 512, U.DEFAULT_COST_MODEL,
+    recs = compare_policies(graphs, lambda M: 2048 if M <= 2 else 512, U.DEFAULT_COST_MODEL,
                  max_candidates=8, repeats=3, log=say)
-    s = judge_summary(recs)
+    s = policies_summary(recs)
     say(json.dumps(s))
     imp = s["improvable"]
     if imp["partitions"]:
