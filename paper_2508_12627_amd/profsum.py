@@ -133,7 +133,7 @@ def main(argv=None):
             with open(args.md, "w") as f:
                 f.write(f"# {args.title}\n\n")
                 if args.command:
-                    f.write("Command (from the repository root on the GPU box):\n\n")
+                    f.write("Command (from the repository root on the MI355X host):\n\n")
                     f.write(f"    {args.command}\n\n")
                 if args.note:
                     f.write(args.note + "\n\n")
