@@ -12,8 +12,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libustat.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["plan.cpp", "costmodel.cpp", "profile.cpp", "exec.cpp", "capi.cpp", "kernels.hip",
-           "mlp.hip"]
+SOURCES = ["k_rowred_mixed.hip", "k_rowred_int.hip", "k_colred_mixed.hip", "k_colred_int.hip",
+           "k_rowred_f64.hip", "k_colred_fp.hip", "k_rowred_f32.hip", "k_gemm.hip", "k_reduce.hip",
+           "kernels.hip", "mlp.hip", "exec.cpp", "capi.cpp", "plan.cpp", "costmodel.cpp", "profile.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",
                 "-packed-fp32-ops"]

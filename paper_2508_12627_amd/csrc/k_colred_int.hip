@@ -1,0 +1,9 @@
+// Instantiations of the column-mode grouped reductions for (DOM_INT, void) (a translation unit of
+// its own, so that the instantiations compile in parallel).
+#include "colred_impl.hpp"
+
+namespace ustat {
+
+template hipError_t launch_colred_dt<DOM_INT, void>(const ColDesc *, int, dim3, int, int, hipStream_t);
+
+}  // namespace ustat

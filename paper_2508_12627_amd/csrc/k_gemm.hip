@@ -1,0 +1,442 @@
+// GEMM steps on MFMA (gfx950): operand tiles staged through LDS, fp64,
+// fp32, split-bf16 and int8-limb products, stored or fused with their
+// consumer.
+
+#include "kdev.hpp"
+
+namespace ustat {
+
+// ----------------------------------------------------------------- GEMM
+//
+// Block tile 128 x 128, four waves in a 2 x 2 arrangement, each wave a
+// 64 x 64 region of 4 x 4 MFMA blocks of 16 x 16.  Operands live in LDS as
+// [row][k] with padding; every 16x16 MFMA family used here (f64 16x16x4,
+// f32 16x16x4, bf16 16x16x32, i8 16x16x64) reads lane l's A fragment from
+// row l%16 and B fragment from column l%16 at k-slot group l/16.  Result
+// item r of lane l sits in column l%16 and row 4*(l/16)+r, except for the
+// f64 instruction, whose rows are interleaved: row l/16 + 4*r.
+
+template <int PREC>
+struct GemmCfg;
+template <>
+struct GemmCfg<0> {  // fp64
+    typedef double E;
+    static constexpr int BK = 16, PLANES = 1;
+};
+template <>
+struct GemmCfg<1> {  // fp32
+    typedef float E;
+    static constexpr int BK = 16, PLANES = 1;
+};
+template <>
+struct GemmCfg<2> {  // bf16 hi/lo
+    typedef uint16_t E;
+    static constexpr int BK = 32, PLANES = 2;
+};
+template <>
+struct GemmCfg<3> {  // int8 limb (one plane per pass)
+    typedef int8_t E;
+    static constexpr int BK = 64, PLANES = 1;
+};
+
+// Row within a 16x16 MFMA result block of item r held by `lane`.
+template <int PREC>
+__device__ __forceinline__ int mfma_row(int lane, int r) {
+    if constexpr (PREC == 0) return (lane >> 4) + 4 * r;
+    else return 4 * (lane >> 4) + r;
+}
+
+template <int PREC>
+struct AccT {
+    typedef f32x4 T;
+};
+template <>
+struct AccT<0> {
+    typedef f64x4 T;
+};
+template <>
+struct AccT<3> {
+    typedef i32x4 T;
+};
+
+// Block-tile shapes.  S128: 128 x 128, four waves (2 x 2) of 64 x 64.
+// S256: 256 x 256, eight waves (2 x 4) of 128 x 64; it halves the operand
+// re-reads per flop, for large problems whose tile count still fills the
+// chip (fp32 and split-bf16 accumulators only: 128 registers per lane).
+struct S128 {
+    static constexpr int BM = 128, BN = 128, WN = 2, NT = 256, FM = 4, FN = 4;
+};
+struct S256 {
+    static constexpr int BM = 256, BN = 256, WN = 4, NT = 512, FM = 8, FN = 4;
+};
+
+// Global <-> LDS staging of one R x BK tile (all planes) of an operand by
+// NT threads.  fp64 rows are padded to 144 bytes.  The 64-byte rows of the
+// other formats are XOR-swizzled in 16-byte chunks, chunk ^ s(row) with
+// s(row) = ((row >> 1) & 3) ^ ((row >> 3) & 1): a 16-byte fragment read by
+// lanes on consecutive rows then touches distinct banks whether the LDS
+// serves 8 lanes over 32 banks or 16 lanes over 64 banks per cycle.
+template <int PREC, int R, int NT>
+struct TileIO {
+    typedef GemmCfg<PREC> C;
+    static constexpr int ROWB = C::BK * (int)sizeof(typename C::E);  // bytes per row
+    static constexpr int UPR = ROWB / 16;                            // 16B units per row
+    static constexpr int UNITS = R * UPR * C::PLANES;
+    static constexpr int PER = UNITS / NT;
+    static_assert(UNITS % NT == 0, "tile units must divide over the threads");
+    static constexpr int LROW = (PREC == 0) ? ROWB + 16 : ROWB;
+    static constexpr int PLANEB = R * LROW;
+    static constexpr int STAGE = PLANEB * C::PLANES;
+
+    __device__ static __forceinline__ int off(int row, int chunk) {
+        if constexpr (PREC == 0) return row * LROW + chunk * 16;
+        else return row * LROW + ((chunk ^ ((row >> 1) & 3) ^ ((row >> 3) & 1)) << 4);
+    }
+    __device__ static void load(u32x4 (&r)[PER], const char *base, int64_t ldb, int64_t planeb,
+                                int64_t row0, int64_t k0b) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            int u = threadIdx.x + NT * i;
+            int pl = u / (R * UPR);
+            int uu = u % (R * UPR);
+            int row = uu / UPR, cu = uu % UPR;
+            const char *g = base + (uint32_t)(pl * planeb + (row0 + row) * ldb + k0b + cu * 16);
+            // a 32-bit offset from the uniform base (every operand buffer is
+            // below 4 GiB, checked when the schedule is built); global address space:
+            // these loads only count against vmcnt, so waiting for LDS
+            // fragment reads never waits for the prefetch
+            r[i] = *(const __attribute__((address_space(1))) u32x4 *)(g);
+        }
+    }
+    __device__ static void store(const u32x4 (&r)[PER], char *lds) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            int u = threadIdx.x + NT * i;
+            int pl = u / (R * UPR);
+            int uu = u % (R * UPR);
+            int row = uu / UPR, cu = uu % UPR;
+            *reinterpret_cast<u32x4 *>(lds + pl * PLANEB + off(row, cu)) = r[i];
+        }
+    }
+};
+
+// One BK step of a wave's FM x FN blocks: A rows from ra0, B rows from rb0
+// (tile-local), fragments read from LDS with the staging layout of R-row
+// tiles (the layout does not depend on R).
+template <int PREC, int FM, int FN, int RA, int RB>
+__device__ __forceinline__ void mma_tile(typename AccT<PREC>::T (&acc)[FM][FN], const char *As,
+                                         const char *Bs, int ra0, int rb0, int lane) {
+    typedef TileIO<PREC, RA, 64> IOA;
+    typedef TileIO<PREC, RB, 64> IOB;
+    const int lr = lane & 15, lg = lane >> 4;
+    if constexpr (PREC == 0) {
+#pragma unroll
+        for (int kk = 0; kk < 16; kk += 4) {
+            double a[FM], b[FN];
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+                a[i] = *reinterpret_cast<const double *>(As + (ra0 + i * 16 + lr) * IOA::LROW +
+                                                         (kk + lg) * 8);
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+                b[j] = *reinterpret_cast<const double *>(Bs + (rb0 + j * 16 + lr) * IOB::LROW +
+                                                         (kk + lg) * 8);
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+    } else if constexpr (PREC == 1) {
+#pragma unroll
+        for (int kk = 0; kk < 16; kk += 4) {
+            float a[FM], b[FN];
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+                a[i] = *reinterpret_cast<const float *>(As + IOA::off(ra0 + i * 16 + lr, kk >> 2) +
+                                                        lg * 4);
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+                b[j] = *reinterpret_cast<const float *>(Bs + IOB::off(rb0 + j * 16 + lr, kk >> 2) +
+                                                        lg * 4);
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+    } else if constexpr (PREC == 2) {
+        bf16x8 bh[FN], bl[FN];
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            const int rb = IOB::off(rb0 + j * 16 + lr, lg);
+            bh[j] = *reinterpret_cast<const bf16x8 *>(Bs + rb);
+            bl[j] = *reinterpret_cast<const bf16x8 *>(Bs + IOB::PLANEB + rb);
+        }
+#pragma unroll
+        for (int i = 0; i < FM; ++i) {
+            const int ra = IOA::off(ra0 + i * 16 + lr, lg);
+            const bf16x8 ah = *reinterpret_cast<const bf16x8 *>(As + ra);
+            const bf16x8 al = *reinterpret_cast<const bf16x8 *>(As + IOA::PLANEB + ra);
+            // small cross terms first, then the leading hi*hi term
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
+            }
+        }
+    } else {
+        i32x4 a[FM], b[FN];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+            a[i] = *reinterpret_cast<const i32x4 *>(As + IOA::off(ra0 + i * 16 + lr, lg));
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+            b[j] = *reinterpret_cast<const i32x4 *>(Bs + IOB::off(rb0 + j * 16 + lr, lg));
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+}
+
+// LDS bytes of one double-buffered (A, B) stage pair for a shape.
+template <int PREC, class SH>
+constexpr int gemm_stage_bytes() {
+    return TileIO<PREC, SH::BM, SH::NT>::STAGE + TileIO<PREC, SH::BN, SH::NT>::STAGE;
+}
+
+// K loop of one (A plane set, B plane set) pass with register prefetch and
+// double-buffered LDS (one barrier per K step).
+template <int PREC, class SH>
+__device__ __forceinline__ void gemm_pass(typename AccT<PREC>::T (&acc)[SH::FM][SH::FN],
+                                          const char *Ab, const char *Bb, int64_t ldb,
+                                          int64_t planeb, int64_t w0, int64_t x0, int64_t npad,
+                                          char *lds) {
+    typedef TileIO<PREC, SH::BM, SH::NT> IOA;
+    typedef TileIO<PREC, SH::BN, SH::NT> IOB;
+    constexpr int PAIR = IOA::STAGE + IOB::STAGE;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int ra0 = (wv / SH::WN) * SH::FM * 16, rb0 = (wv % SH::WN) * SH::FN * 16;
+    constexpr int KB = GemmCfg<PREC>::BK * (int)sizeof(typename GemmCfg<PREC>::E);
+    const int64_t nk = npad / GemmCfg<PREC>::BK;
+    u32x4 ra[IOA::PER], rb[IOB::PER];
+    IOA::load(ra, Ab, ldb, planeb, w0, 0);
+    IOB::load(rb, Bb, ldb, planeb, x0, 0);
+    IOA::store(ra, lds);
+    IOB::store(rb, lds + IOA::STAGE);
+    __syncthreads();
+    for (int64_t kt = 0; kt < nk; ++kt) {
+        const int cur = (int)(kt & 1);
+        char *As = lds + cur * PAIR;
+        char *Bs = As + IOA::STAGE;
+        // Prefetch the next K tile (the last step re-reads its own tile into
+        // the idle buffer, which keeps the loop free of branches).
+        const int64_t kn = (kt + 1 < nk) ? kt + 1 : kt;
+        IOA::load(ra, Ab, ldb, planeb, w0, kn * KB);
+        IOB::load(rb, Bb, ldb, planeb, x0, kn * KB);
+        // Keep the prefetch at the top of the step and its staging after
+        // the MFMAs: left to itself the scheduler sinks the loads below the
+        // MFMAs (or waits for them in the middle), exposing their latency.
+        // fp64 and int8 keep the free schedule (their register budget is
+        // already full).
+        if constexpr (PREC == 1 || PREC == 2) __builtin_amdgcn_sched_barrier(0);
+        mma_tile<PREC, SH::FM, SH::FN, SH::BM, SH::BN>(acc, As, Bs, ra0, rb0, lane);
+        if constexpr (PREC == 1 || PREC == 2) __builtin_amdgcn_sched_barrier(0);
+        char *An = lds + (1 - cur) * PAIR;
+        IOA::store(ra, An);
+        IOB::store(rb, An + IOA::STAGE);
+        __syncthreads();
+    }
+}
+
+
+
+template <int PREC, class SH>
+__global__ __launch_bounds__(SH::NT) __attribute__((amdgpu_waves_per_eu(2)))
+void k_gemm(const GemmDesc *__restrict__ D, int nprob) {
+    typedef typename AccT<PREC>::T AT;
+    constexpr int FM = SH::FM, FN = SH::FN;
+    static_assert(PREC == 1 || PREC == 2 || SH::BM == 128, "large tiles: fp32 accumulators only");
+    extern __shared__ __align__(16) char lds[];
+    const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
+    const int p = __builtin_amdgcn_readfirstlane(find_problem(D, nprob, b));  // uniform
+    const GemmDesc &d = D[p];
+    const int64_t local = b - d.tile_start;
+    // grouped tile order: 8 tile-rows per group, column-major inside it
+    const int64_t T = d.tiles, GM = 8;
+    const int64_t first = (local / (GM * T)) * GM;
+    const int64_t gsz = (T - first) < GM ? (T - first) : GM;
+    const int64_t lg = local - first * T;
+    const int64_t tm = first + lg % gsz, tn = lg / gsz;
+    const int64_t w0 = tm * SH::BM, x0 = tn * SH::BN;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t wr0 = w0 + (wv / SH::WN) * FM * 16, xc0 = x0 + (wv % SH::WN) * FN * 16;
+    constexpr int ES = (int)sizeof(typename GemmCfg<PREC>::E);
+    const int64_t ldb = d.ld * ES, planeb = d.plane * ES;
+
+    AT acc[FM][FN];
+    long long resi[PREC == 3 ? FM : 1][PREC == 3 ? FN : 1][4];
+    (void)resi;
+    if constexpr (PREC == 3) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) resi[i][j][r] = 0;
+        const int nla = d.la_p ? *d.la_p : d.la, nlb = d.lb_p ? *d.lb_p : d.lb;
+        for (int la = 0; la < nla; ++la)
+            for (int lb = 0; lb < nlb; ++lb) {
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j) acc[i][j] = AT{0, 0, 0, 0};
+                gemm_pass<PREC, SH>(acc, static_cast<const char *>(d.A) + la * planeb,
+                                    static_cast<const char *>(d.B) + lb * planeb, ldb, planeb, w0,
+                                    x0, d.npad, lds);
+                const long long wgt = 1ll << (7 * (la + lb));
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) resi[i][j][r] += wgt * (long long)acc[i][j][r];
+            }
+    } else {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) acc[i][j] = AT{0, 0, 0, 0};
+        gemm_pass<PREC, SH>(acc, static_cast<const char *>(d.A), static_cast<const char *>(d.B),
+                            ldb, planeb, w0, x0, d.npad, lds);
+    }
+    // value(i, j, r) of row wr0+i*16+mfma_row(lane,r), column xc0+j*16+lane%16
+    auto value = [&](int i, int j, int r) {
+        if constexpr (PREC == 3) return resi[i][j][r];
+        else return (double)acc[i][j][r];
+    };
+
+    const int64_t n = d.n;
+    if (!d.final_) {
+        if constexpr (PREC == 3) {
+            if (d.mx_out) {
+                unsigned long long mloc = 0;
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            long long v = resi[i][j][r];
+                            unsigned long long a = (unsigned long long)(v < 0 ? -v : v);
+                            mloc = a > mloc ? a : mloc;
+                        }
+                atomicMax(d.mx_out, mloc);
+            }
+        }
+        // output fields read once: a reload after each store would wait for
+        // every store in flight
+        void *const C = d.C;
+        const int64_t ldc = d.ldc;
+        const bool c64 = d.dtype_c == DT_F64;
+#pragma clang loop unroll(full)
+        for (int ib = 0; ib < FM; ib += 4)
+#pragma unroll
+        for (int i = ib; i < ib + 4; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    int64_t w = wr0 + i * 16 + mfma_row<PREC>(lane, r);
+                    int64_t x = xc0 + j * 16 + (lane & 15);
+                    if (w < n && x < n) {
+                        int64_t o = w * ldc + x;
+                        if constexpr (PREC == 3) static_cast<long long *>(C)[o] = value(i, j, r);
+                        else if (c64) static_cast<double *>(C)[o] = value(i, j, r);
+                        else static_cast<float *>(C)[o] = (float)value(i, j, r);
+                    }
+                }
+        return;
+    }
+    // Fused consumer: sum_{w,x} C(w,x) prod Z(w,x) prod aw(w) prod bx(x).
+    typedef typename std::conditional<PREC == 3, i128, double>::type Wd;
+    Wd part = 0;
+#pragma clang loop unroll(full)
+    for (int ib = 0; ib < FM; ib += 4)
+#pragma unroll
+    for (int i = ib; i < ib + 4; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                int64_t w = wr0 + i * 16 + mfma_row<PREC>(lane, r);
+                int64_t x = xc0 + j * 16 + (lane & 15);
+                if (w >= n || x >= n) continue;
+                Wd val = (Wd)value(i, j, r);
+                for (int k = 0; k < d.nZ; ++k) {
+                    const MatRef &z = d.Z[k];
+                    int64_t idx = z.trans ? (x * z.ld + w) : (w * z.ld + x);
+                    Wd zv;
+                    if constexpr (PREC == 3) zv = (Wd)load_int(z.p, z.dtype, idx);
+                    else zv = load_fp(z.p, z.dtype, idx);
+                    if (z.zdiag && w == x) zv = 0;
+                    val *= zv;
+                }
+                for (int q = 0; q < d.naw; ++q) {
+                    if constexpr (PREC == 3) val *= (Wd) static_cast<const long long *>(d.aw[q])[w];
+                    else val *= static_cast<const double *>(d.aw[q])[w];
+                }
+                for (int q = 0; q < d.nbx; ++q) {
+                    if constexpr (PREC == 3) val *= (Wd) static_cast<const long long *>(d.bx[q])[x];
+                    else val *= static_cast<const double *>(d.bx[q])[x];
+                }
+                part += val;
+            }
+    __syncthreads();  // LDS reuse
+    Wd *red = reinterpret_cast<Wd *>(lds);
+    red[threadIdx.x] = part;
+    __syncthreads();
+    // fixed-order tree over the NT partial sums
+    for (int s = SH::NT / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) static_cast<Wd *>(d.part)[local] = red[0];
+}
+
+template <int PREC, class SH>
+static hipError_t launch_gemm_t(const GemmDesc *d, int nprob, int64_t total_tiles, hipStream_t s) {
+    size_t lds = (size_t)2 * gemm_stage_bytes<PREC, SH>();
+    size_t red = (size_t)SH::NT * 16;
+    if (lds < red) lds = red;
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_gemm<PREC, SH>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_gemm<PREC, SH>), dim3((unsigned)total_tiles), dim3(SH::NT), lds, s, d,
+                       nprob);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm(const GemmDesc *d, int nprob, int64_t total_tiles, int precision,
+                       int tile, hipStream_t s) {
+    if (tile == 256) {
+        if (precision == 1) return launch_gemm_t<1, S256>(d, nprob, total_tiles, s);
+        if (precision == 2) return launch_gemm_t<2, S256>(d, nprob, total_tiles, s);
+        return hipErrorInvalidValue;
+    }
+    switch (precision) {
+        case 0: return launch_gemm_t<0, S128>(d, nprob, total_tiles, s);
+        case 1: return launch_gemm_t<1, S128>(d, nprob, total_tiles, s);
+        case 2: return launch_gemm_t<2, S128>(d, nprob, total_tiles, s);
+        default: return launch_gemm_t<3, S128>(d, nprob, total_tiles, s);
+    }
+}
+
+}  // namespace ustat
