@@ -255,6 +255,27 @@ ustat_status ustat_eval_batched(ustat_plan plan, int32_t batch, const int64_t *n
                                 ustat_result *out);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture elsewhere in the program, tight serving loops, harnesses that
+ * forbid hipMalloc): ustat_eval with every device buffer it needs (the
+ * workspace of intermediates, the launch descriptors and the per-program
+ * accumulators) taken from a fixed array of USTAT_NOALLOC_MAX_BYTES bytes
+ * that the library holds on each device it runs on, from the first kernel
+ * launch there until the process ends.  Arguments, results and errors are
+ * those of ustat_eval, plus USTAT_E_INFEASIBLE when the evaluation needs
+ * more than the array (ustat_plan_cost's workspace tells ahead; programs
+ * conditioned on a vertex run in slice chunks that fit).  The call makes no
+ * device or pinned-host allocation and captures no graph; results come back
+ * through ordinary host memory after a synchronisation of the stream.
+ * All calls on one device share its array, which keeps the last call's
+ * contents: calls that overlap in time on one device (from several host
+ * threads or streams) race and must be serialised by the caller.
+ */
+#define USTAT_NOALLOC_MAX_BYTES ((uint64_t)128 << 20)
+ustat_status ustat_eval_noalloc(ustat_plan plan, int64_t n, const void *const *factors,
+                                ustat_stream stream, ustat_result *out);
+
+/*
  * Build the RBF factor matrix alone (Algorithm 1 for the RBF kernel):
  * out (device, n x n) receives exp(-||X_i - X_j||^2 / rbf_divisor) with the
  * squared distance formed in fp64 from direct differences; precision

@@ -11,6 +11,7 @@
 #include <limits>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -281,17 +282,17 @@ ustat_status ustat_graph_treewidth(int32_t m, int32_t num_edges, const int32_t *
 static ustat_status run(ustat_plan plan, const std::vector<const VProgram *> &progs,
                         std::vector<Dataset> &data, hipStream_t s, std::vector<DatasetResult> &res,
                         std::vector<double> *vout, const std::function<hipError_t(hipStream_t)> &pre,
-                        const std::string &key) {
+                        const std::string &key, const ExtMem *ext = nullptr) {
     int st = 0;
     // Launch sequences are captured into a HIP graph and replayed when the
     // stream is not the null stream; profiled runs launch kernel by kernel so
     // that every launch can be timed with events.
     bool capture = (s != nullptr) && plan->plan.opts.precision != USTAT_I8 && !key.empty() &&
-                   !Profiler::enabled();
+                   !Profiler::enabled() && !ext;
     std::string err;
     try {
         if (capture) Profiler::suspend(true);
-        err = execute_all(plan->plan, progs, data, s, plan->rt, res, vout, &st, capture, key, pre);
+        err = execute_all(plan->plan, progs, data, s, plan->rt, res, vout, &st, capture, key, pre, ext);
         if (capture) Profiler::suspend(false);
     } catch (const std::bad_alloc &) {
         Profiler::suspend(false);
@@ -405,6 +406,73 @@ ustat_status ustat_eval(ustat_plan plan, int64_t n, const void *const *factors, 
     if (st != USTAT_OK) return st;
     fill_result(out, res[0], plan->plan, n, (int)plan->all.size());
     return ok();
+}
+
+}  // extern "C"
+
+// Fixed device buffer of ustat_eval_noalloc: every evaluation through that
+// entry point takes its workspace, descriptors and accumulators from here.
+// Each device the library runs on holds its own copy from the moment the
+// code object is loaded there until the process ends.
+static __device__ __align__(256) char scratch[USTAT_NOALLOC_MAX_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_dev[kMaxDevices] = {};
+
+// Device address of the current device's copy of `scratch`.  Host code
+// never uses the array's own name (a host-side stand-in): the address is
+// looked up once per device, with that device current, and kept.
+hipError_t scratch_address(char **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_dev[dev] = static_cast<char *>(p);
+    }
+    *out = g_scratch_dev[dev];
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+ustat_status ustat_eval_noalloc(ustat_plan plan, int64_t n, const void *const *factors,
+                                ustat_stream stream, ustat_result *out) {
+    ustat_status c = check_eval(plan, n);
+    if (c != USTAT_OK) return c;
+    if (!factors || !out) return fail(USTAT_E_INVALID, "factors and out must be non-NULL");
+    try {
+        std::vector<Dataset> data(1);
+        data[0].n = n;
+        data[0].symmetric = plan->plan.opts.symmetric;
+        for (size_t k = 0; k < plan->plan.edges.size(); ++k) {
+            if (!factors[k]) return fail(USTAT_E_INVALID, "a factor pointer is NULL");
+            data[0].factors.push_back(factors[k]);
+        }
+        ExtMem ext;
+        hipError_t e = scratch_address(&ext.base);
+        if (e != hipSuccess)
+            return fail(USTAT_E_HIP, std::string("fixed device buffer: ") + hipGetErrorString(e));
+        ext.bytes = USTAT_NOALLOC_MAX_BYTES;
+        std::vector<DatasetResult> res;
+        ustat_status st = run(plan, plan->all, data, (hipStream_t)stream, res, nullptr, nullptr, "", &ext);
+        if (st != USTAT_OK) return st;
+        fill_result(out, res[0], plan->plan, n, (int)plan->all.size());
+        return ok();
+    } catch (const std::bad_alloc &) {
+        return fail(USTAT_E_NOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(USTAT_E_INVALID, "unexpected host exception");
+    }
 }
 
 ustat_status ustat_build_rbf(int64_t n, int32_t d, const double *X, double rbf_divisor,

@@ -1447,9 +1447,14 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
                     const std::vector<Dataset> &data, hipStream_t stream, Runtime &rt,
                     std::vector<DatasetResult> &out, std::vector<double> *vout, int *status,
                     bool capture, const std::string &capture_key,
-                    const std::function<hipError_t(hipStream_t)> &pre, const SliceRange &range) {
+                    const std::function<hipError_t(hipStream_t)> &pre, const SliceRange &range,
+                    const ExtMem *ext) {
     *status = 0;
     const Cfg cfg = make_cfg(plan.opts.precision);
+    if (ext) capture = false;
+    // host staging of the external-memory mode (ordinary host memory; every
+    // copy through it completes before this function returns)
+    std::vector<char> hstage_ext, hres_ext;
     if (capture) {
         auto git = rt.graphs.find(capture_key);
         if (git != rt.graphs.end() && git->second.nd == (int)data.size()) {
@@ -1487,22 +1492,39 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
             }
         size_t cnt = srcs.size();
         size_t bytes = cnt * (8 + 8 + 8);
-        HIPCHK(rt.reserve_desc(bytes + 1024));
-        HIPCHK(rt.reserve_hres(cnt * 8 + 64));
-        std::memcpy(rt.hdesc, srcs.data(), cnt * 8);
-        std::memcpy(rt.hdesc + cnt * 8, ns.data(), cnt * 8);
-        HIPCHK(hipMemcpyAsync(rt.ddesc, rt.hdesc, cnt * 16, hipMemcpyHostToDevice, stream));
-        unsigned long long *dmx = reinterpret_cast<unsigned long long *>(rt.ddesc + cnt * 16);
+        char *dpre, *hpre, *hmx;
+        if (ext) {
+            // the start of the external region; done with before the
+            // evaluation's own layout is written there
+            if (bytes + 256 > ext->bytes) {
+                *status = 6;
+                return "the input maxima pass needs more than the external workspace";
+            }
+            hstage_ext.assign(cnt * 24, 0);
+            dpre = ext->base;
+            hpre = hstage_ext.data();
+            hmx = hstage_ext.data() + cnt * 16;
+        } else {
+            HIPCHK(rt.reserve_desc(bytes + 1024));
+            HIPCHK(rt.reserve_hres(cnt * 8 + 64));
+            dpre = rt.ddesc;
+            hpre = rt.hdesc;
+            hmx = rt.hres;
+        }
+        std::memcpy(hpre, srcs.data(), cnt * 8);
+        std::memcpy(hpre + cnt * 8, ns.data(), cnt * 8);
+        HIPCHK(hipMemcpyAsync(dpre, hpre, cnt * 16, hipMemcpyHostToDevice, stream));
+        unsigned long long *dmx = reinterpret_cast<unsigned long long *>(dpre + cnt * 16);
         hipLaunchKernelGGL(k_fill_zero, dim3(1), dim3(256), 0, stream, dmx, cnt);
         HIPCHK(hipGetLastError());
-        HIPCHK(launch_absmax_i8(reinterpret_cast<const int8_t *const *>(rt.ddesc),
-                                reinterpret_cast<const int64_t *>(rt.ddesc + cnt * 8), (int)cnt,
+        HIPCHK(launch_absmax_i8(reinterpret_cast<const int8_t *const *>(dpre),
+                                reinterpret_cast<const int64_t *>(dpre + cnt * 8), (int)cnt,
                                 dmx, stream));
-        HIPCHK(hipMemcpyAsync(rt.hres, dmx, cnt * 8, hipMemcpyDeviceToHost, stream));
+        HIPCHK(hipMemcpyAsync(hmx, dmx, cnt * 8, hipMemcpyDeviceToHost, stream));
         HIPCHK(hipStreamSynchronize(stream));
         in_bound.resize(cnt);
         for (size_t i = 0; i < cnt; ++i)
-            in_bound[i] = (double)reinterpret_cast<unsigned long long *>(rt.hres)[i];
+            in_bound[i] = (double)reinterpret_cast<unsigned long long *>(hmx)[i];
     }
     // The layout is deterministic: build once against the arena already
     // held and keep the result when it fits; otherwise size it, grow the
@@ -1510,7 +1532,28 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
     Schedule S;
     std::string err;
     bool built = false;
-    if (rt.arena) {
+    // the arena, blob and accumulators used below
+    char *arena = rt.arena, *vacc = rt.vacc, *hres = rt.hres, *hdesc = rt.hdesc;
+    const int nd = (int)data.size();
+    if (ext) {
+        err = build_schedule(plan, progs, data, cfg, in_bound, ext->base, S, status, range);
+        if (!err.empty()) return err;
+        const size_t nres_ext = (size_t)S.nprog_total * cfg.wide_es + (size_t)nd * cfg.wide_es + (size_t)nd * 8;
+        const size_t need = up(S.arena_bytes, kAlign) + up(S.blob_bytes, kAlign) + S.n_inmx * 8 +
+                            up(nres_ext + 64, kAlign);
+        if (need > ext->bytes) {
+            *status = 6;
+            return "the evaluation needs " + std::to_string(need) + " bytes of workspace, above the " +
+                   std::to_string(ext->bytes) + " bytes of the fixed device buffer";
+        }
+        arena = ext->base;
+        vacc = ext->base + ext->bytes - up(nres_ext + 64, kAlign);
+        hres_ext.assign(nres_ext + 64, 0);
+        hres = hres_ext.data();
+        hstage_ext.assign(up(S.blob_bytes, 64) + S.n_inmx * 8 + 64, 0);
+        hdesc = hstage_ext.data();
+        built = true;
+    } else if (rt.arena) {
         err = build_schedule(plan, progs, data, cfg, in_bound, rt.arena, S, status, range);
         if (!err.empty()) return err;
         built = S.arena_bytes <= rt.arena_bytes;
@@ -1530,20 +1573,25 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
         }
         err = build_schedule(plan, progs, data, cfg, in_bound, rt.arena, S, status, range);
         if (!err.empty()) return err;
+        arena = rt.arena;
     }
-    // room for the blob and, behind it, the staged input maxima (reserved
-    // before any asynchronous copy reads the pinned buffer)
-    HIPCHK(rt.reserve_desc(up(S.blob_bytes, 64) + S.n_inmx * 8 + 1024));
-    const int nd = (int)data.size();
     // results buffer [V per program | U per dataset | S per dataset], read
     // back with one copy
     const size_t vbytes0 = (size_t)S.nprog_total * cfg.wide_es, ubytes0 = (size_t)nd * cfg.wide_es;
     const size_t nres = vbytes0 + ubytes0 + (size_t)nd * 8;
-    HIPCHK(rt.reserve_hres(nres + 64));
-    if (range.first) HIPCHK(rt.reserve_vacc(nres + 64));
+    if (!ext) {
+        // room for the blob and, behind it, the staged input maxima (reserved
+        // before any asynchronous copy reads the pinned buffer)
+        HIPCHK(rt.reserve_desc(up(S.blob_bytes, 64) + S.n_inmx * 8 + 1024));
+        HIPCHK(rt.reserve_hres(nres + 64));
+        if (range.first) HIPCHK(rt.reserve_vacc(nres + 64));
+        vacc = rt.vacc;
+        hres = rt.hres;
+        hdesc = rt.hdesc;
+    }
 
     {
-        char *hblob = rt.hdesc;
+        char *hblob = hdesc;
         Runtime::GraphEntry entry;
         if (capture) {
             auto old = rt.graphs.find(capture_key);
@@ -1558,7 +1606,7 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
             entry.blob_bytes = S.blob_bytes + 64;
         }
         std::memcpy(hblob, S.blob.h.data(), S.blob_bytes);
-        char *dd = capture ? entry.blob : rt.ddesc;
+        char *dd = capture ? entry.blob : ext ? arena + up(S.arena_bytes, kAlign) : rt.ddesc;
         {
             hipError_t ue = hipMemcpyAsync(dd, hblob, S.blob_bytes, hipMemcpyHostToDevice, stream);
             if (ue != hipSuccess) {
@@ -1589,7 +1637,7 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
         // zero running maxima (a fill kernel, safe under graph capture)
         if (cfg.domain == DOM_INT && S.n_mx) {
             hipLaunchKernelGGL(k_fill_zero, dim3(64), dim3(256), 0, stream,
-                               reinterpret_cast<unsigned long long *>(rt.arena + S.off_mx), S.n_mx);
+                               reinterpret_cast<unsigned long long *>(arena + S.off_mx), S.n_mx);
             if ((e = hipGetLastError()) != hipSuccess) return fail(e, "fill");
         }
         if (cfg.domain == DOM_INT) {
@@ -1598,8 +1646,8 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
             for (size_t i = 0; i < S.n_inmx; ++i) im[i] = (unsigned long long)in_bound[i];
             // stage behind the blob in the pinned buffer
             size_t off = up(S.blob_bytes, 64);
-            std::memcpy(rt.hdesc + off, im.data(), im.size() * 8);
-            e = hipMemcpyAsync(rt.arena + S.off_inmx, rt.hdesc + off, im.size() * 8,
+            std::memcpy(hdesc + off, im.data(), im.size() * 8);
+            e = hipMemcpyAsync(arena + S.off_inmx, hdesc + off, im.size() * 8,
                                hipMemcpyHostToDevice, stream);
             if (e != hipSuccess) return fail(e, "input maxima upload");
         }
@@ -1670,13 +1718,13 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
                            reinterpret_cast<int32_t *>(dd + S.off_soff),
                            reinterpret_cast<int32_t *>(dd + S.off_scnt),
                            reinterpret_cast<int32_t *>(dd + S.off_sidx),
-                           reinterpret_cast<int64_t *>(dd + S.off_mu), rt.arena + S.off_scal,
-                           rt.vacc, range.first ? 1 : 0, range.last ? 1 : 0, rt.vacc + vbytes0,
-                           reinterpret_cast<double *>(rt.vacc + vbytes0 + ubytes0), cfg.domain,
+                           reinterpret_cast<int64_t *>(dd + S.off_mu), arena + S.off_scal,
+                           vacc, range.first ? 1 : 0, range.last ? 1 : 0, vacc + vbytes0,
+                           reinterpret_cast<double *>(vacc + vbytes0 + ubytes0), cfg.domain,
                            stream);
         if (e != hipSuccess) return fail(e, "combine");
         // results: V (all), U (per dataset), S (per dataset) in one copy
-        e = hipMemcpyAsync(rt.hres, rt.vacc, nres, hipMemcpyDeviceToHost, stream);
+        e = hipMemcpyAsync(hres, vacc, nres, hipMemcpyDeviceToHost, stream);
         if (e != hipSuccess) return fail(e, "result copy");
         if (capture) {
             e = hipStreamEndCapture(stream, &g);
@@ -1705,7 +1753,7 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
     // unpack
     out.assign(nd, DatasetResult());
     size_t vbytes = (size_t)S.nprog_total * cfg.wide_es, ubytes = (size_t)nd * cfg.wide_es;
-    const char *h = rt.hres;
+    const char *h = hres;
     if (vout) vout->assign(S.nprog_total, 0.0);
     for (int i = 0; i < S.nprog_total && vout; ++i) {
         if (cfg.domain == DOM_FP) (*vout)[i] = reinterpret_cast<const double *>(h)[i];
@@ -1729,16 +1777,22 @@ std::string execute_all(const Plan &plan, const std::vector<const VProgram *> &p
                         const std::vector<Dataset> &data, hipStream_t stream, Runtime &rt,
                         std::vector<DatasetResult> &out, std::vector<double> *vout, int *status,
                         bool capture, const std::string &capture_key,
-                        const std::function<hipError_t(hipStream_t)> &pre) {
+                        const std::function<hipError_t(hipStream_t)> &pre, const ExtMem *ext) {
     bool sliced = false;
     for (const VProgram *p : progs) sliced = sliced || p->slice_var >= 0;
-    if (!sliced) return execute(plan, progs, data, stream, rt, out, vout, status, capture, capture_key, pre);
+    if (!sliced)
+        return execute(plan, progs, data, stream, rt, out, vout, status, capture, capture_key, pre,
+                       SliceRange(), ext);
     // Slice chunks sized to the budget: opts.workspace_limit, else half of
-    // the free device memory (plus what this runtime already holds).
+    // the free device memory (plus what this runtime already holds), or the
+    // external buffer less its accumulators and descriptors.
     int64_t nmax = 0;
     for (auto &d : data) nmax = std::max(nmax, d.n);
     size_t budget = plan.opts.workspace_limit;
-    if (!budget) {
+    if (ext) {
+        const size_t keep = ext->bytes / 8;
+        budget = budget ? std::min(budget, ext->bytes - keep) : ext->bytes - keep;
+    } else if (!budget) {
         size_t fr = 0, tot = 0;
         if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
             *status = 4;
@@ -1762,7 +1816,7 @@ std::string execute_all(const Plan &plan, const std::vector<const VProgram *> &p
         rg.first = lo == 0;
         rg.last = rg.hi >= nmax;
         std::string err = execute(plan, progs, data, stream, rt, out, vout, status, false, "",
-                                  lo == 0 ? pre : nullptr, rg);
+                                  lo == 0 ? pre : nullptr, rg, ext);
         if (!err.empty()) return err;
     }
     return "";

@@ -80,12 +80,24 @@ struct SliceRange {
     bool include_unsliced = true, first = true, last = true;
 };
 
+// Device memory an evaluation may use instead of the runtime's own buffers
+// (the entry point that allocates nothing).  With it, the workspace, the
+// descriptor blob and the per-program accumulators are carved out of
+// [base, base + bytes): the accumulators at the end (they persist across
+// slice chunks), the rest from the start; nothing is captured as a graph and
+// results come back through ordinary host memory.  An evaluation that does
+// not fit fails with status 6 before any launch.
+struct ExtMem {
+    char *base = nullptr;
+    size_t bytes = 0;
+};
+
 std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs,
                     const std::vector<Dataset> &data, hipStream_t stream, Runtime &rt,
                     std::vector<DatasetResult> &out, std::vector<double> *vout, int *status,
                     bool capture = false, const std::string &capture_key = "",
                     const std::function<hipError_t(hipStream_t)> &pre = nullptr,
-                    const SliceRange &range = SliceRange());
+                    const SliceRange &range = SliceRange(), const ExtMem *ext = nullptr);
 
 // Whole evaluation: programs conditioned on a vertex run in slice chunks
 // sized to the workspace budget (no graph capture); otherwise one pass.
@@ -93,7 +105,8 @@ std::string execute_all(const Plan &plan, const std::vector<const VProgram *> &p
                         const std::vector<Dataset> &data, hipStream_t stream, Runtime &rt,
                         std::vector<DatasetResult> &out, std::vector<double> *vout, int *status,
                         bool capture, const std::string &capture_key,
-                        const std::function<hipError_t(hipStream_t)> &pre);
+                        const std::function<hipError_t(hipStream_t)> &pre,
+                        const ExtMem *ext = nullptr);
 
 // Sizes an evaluation of `data` needs: arena, descriptor blob, pinned
 // result bytes (a dry schedule; pointers only fix the sharing pattern).

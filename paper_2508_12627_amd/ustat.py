@@ -73,7 +73,7 @@ EXPORTS = ["ustat_plan_opts_default", "ustat_plan_create", "ustat_plan_destroy",
            "ustat_order_features", "vstat_eval_ordered", "ustat_mlp_num_params",
            "ustat_mlp_predict", "ustat_mlp_loss_grad", "ustat_mlp_train", "ustat_mlp_save",
            "ustat_plan_tuning", "ustat_plan_set_tuning", "ustat_plan_autotune",
-           "ustat_status_string", "ustat_last_error"]
+           "ustat_eval_noalloc", "ustat_status_string", "ustat_last_error"]
 NUM_FEATURES = 18
 
 
@@ -97,6 +97,7 @@ def load_library(path: str = LIB_PATH):
     L.ustat_plan_order.argtypes = [P, i32, pi32, pi32, pi32]
     L.ustat_graph_treewidth.argtypes = [i32, i32, pi32, pi32]
     L.ustat_eval.argtypes = [P, i64, ctypes.POINTER(P), P, ctypes.POINTER(Result)]
+    L.ustat_eval_noalloc.argtypes = [P, i64, ctypes.POINTER(P), P, ctypes.POINTER(Result)]
     L.ustat_eval_samples.argtypes = [P, i64, i32, P, dbl, P, ctypes.POINTER(Result)]
     L.vstat_eval.argtypes = [P, pi32, i64, ctypes.POINTER(P), P, ctypes.POINTER(Result)]
     L.ustat_eval_batched.argtypes = [P, i32, pi64, i32, ctypes.POINTER(P), dbl, P,
@@ -250,6 +251,13 @@ def ustat_eval(h, n: int, factors, stream=None) -> Result:
     r = Result()
     _check(load_library().ustat_eval(h, int(n), _factor_ptrs(factors), _stream_handle(stream),
                                      ctypes.byref(r)))
+    return r
+
+
+def ustat_eval_noalloc(h, n: int, factors, stream=None) -> Result:
+    r = Result()
+    _check(load_library().ustat_eval_noalloc(h, int(n), _factor_ptrs(factors), _stream_handle(stream),
+                                             ctypes.byref(r)))
     return r
 
 
@@ -441,6 +449,10 @@ class Plan:
     def eval(self, factors, stream=None) -> Result:
         n = self._check_factors(factors)
         return ustat_eval(self.h, n, factors, stream)
+
+    def eval_noalloc(self, factors, stream=None) -> Result:
+        n = self._check_factors(factors)
+        return ustat_eval_noalloc(self.h, n, factors, stream)
 
     def eval_samples(self, X, divisor: float, stream=None) -> Result:
         return ustat_eval_samples(self.h, X, divisor, stream)
