@@ -63,7 +63,8 @@ typedef enum {
 typedef enum {
     USTAT_F64 = 0,    /* fp64 MFMA contractions, fp64 everywhere            */
     USTAT_F32 = 1,    /* fp32 MFMA contractions, fp64 reductions/combine    */
-    USTAT_BF16X3 = 2, /* split-bf16 (hi*hi + hi*lo + lo*hi) MFMA, fp32
+    USTAT_BF16X3 = 2, /* split-bf16 MFMA (hi*hi + hi*lo + lo*hi, or six
+                         products of a three-plane split, see below), fp32
                          accumulation, fp64 reductions/combine              */
     USTAT_I8 = 3      /* exact: int8 MFMA on 7-bit limbs, int32 tiles,
                          int64 matrices, 128-bit totals                     */
@@ -110,10 +111,29 @@ typedef struct {
     int64_t exact_hi;   /* USTAT_I8: exact value = exact_hi*2^64 + exact_lo */
     uint64_t exact_lo;
     double err_scale;   /* S = sum_pi |mu_pi V_pi| (|V_pi| for vstat_eval)  */
-    double err_est;     /* a-priori bound on |error| / S for this precision */
+    double err_est;     /* estimate of |value - exact| / S, see below       */
     int32_t num_vstats; /* restricted V-statistics evaluated                */
     int32_t reserved;
 } ustat_result;
+/*
+ * err_est is an estimate, not a worst-case bound: the typical relative
+ * error (about two standard deviations) under the probabilistic model of
+ * rounding errors (independent, mean zero), from the unit roundoff and
+ * inner length of the contraction instructions, the sample size n and the
+ * number of dependency levels of the evaluation; 0 for USTAT_I8.  It does
+ * not credit the averaging of independent element errors in the final
+ * sums, so at large n it usually overstates the error; inputs built to
+ * align rounding errors can exceed it.
+ *
+ * USTAT_BF16X3 contracts operands split into bf16 planes: two planes
+ * (hi + lo, three products per pair) when every contracted value is known
+ * to be non-negative and n >= 1024, otherwise three planes (hi + mid + lo,
+ * six products, every term down to 2^-18), which keeps fp32-level accuracy
+ * when signs cancel.  ustat_eval, vstat_eval and their variants scan the
+ * factor matrices for negative entries on the device first (one read of
+ * each matrix and one small read-back per call); the RBF factors that the
+ * sample entry points build are known to be positive.
+ */
 
 /* Fill *opts with defaults: USTAT_F64, min-fill, no sparsification. */
 ustat_status ustat_plan_opts_default(ustat_plan_opts *opts);

@@ -70,22 +70,6 @@ ustat_status from_exec(int st, const std::string &msg) {
     }
 }
 
-// rough a-priori relative error estimate for the result (root-n model):
-// unit roundoff of the contraction precision times sqrt(n) times the number
-// of rounding stages (elimination depth + 2).
-double err_estimate(const Plan &p, int64_t n) {
-    double u;
-    switch (p.opts.precision) {
-        case USTAT_F64: u = std::ldexp(1.0, -53); break;
-        case USTAT_F32: u = std::ldexp(1.0, -24); break;
-        case USTAT_BF16X3: u = 3.0 * std::ldexp(1.0, -18); break;
-        default: return 0.0;
-    }
-    int depth = 0;
-    for (auto &pr : p.progs) depth = std::max(depth, pr.depth);
-    return u * std::sqrt((double)n) * (depth + 2);
-}
-
 bool canonical_rgs(const int32_t *block_of, int m, std::vector<int> &out) {
     out.assign(m, 0);
     std::vector<int> map;
@@ -121,7 +105,7 @@ void fill_result(ustat_result *out, const DatasetResult &r, const Plan &p, int64
     out->exact_hi = r.exact_hi;
     out->exact_lo = r.exact_lo;
     out->err_scale = r.scale;
-    out->err_est = err_estimate(p, n);
+    out->err_est = r.err_est;
     out->num_vstats = nv;
 }
 
@@ -504,6 +488,7 @@ ustat_status ustat_eval_samples(ustat_plan plan, int64_t n, int32_t d, const dou
     std::vector<Dataset> data(1);
     data[0].n = n;
     data[0].symmetric = true;  // the RBF factor is symmetric bit for bit
+    data[0].nonneg = true;     // and positive
     for (size_t k = 0; k < plan->plan.edges.size(); ++k) data[0].factors.push_back(plan->factors);
     char *fb = plan->factors;
     auto pre = [=](hipStream_t s) -> hipError_t {
@@ -685,7 +670,8 @@ ustat_status ustat_eval_batched(ustat_plan plan, int32_t batch, const int64_t *n
         for (int b = chunks[c].first, i = 0; b < chunks[c].second; ++b, ++i) {
             Dataset ds;
             ds.n = n[b];
-            ds.symmetric = true;  // RBF factors
+            ds.symmetric = true;  // RBF factors: symmetric and positive
+            ds.nonneg = true;
             for (size_t k = 0; k < plan->plan.edges.size(); ++k)
                 ds.factors.push_back(plan->factors + coff[c][i]);
             cdata[c].push_back(ds);

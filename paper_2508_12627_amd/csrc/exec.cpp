@@ -152,6 +152,11 @@ struct LevelWork {
     double gemm_big_flops = 0;
     bool big = false;  // the level's eligible GEMMs take 256-wide tiles
     size_t off_gemm_big = 0;
+    // split-bf16 problems on three-plane operands (six products per pair)
+    std::vector<GemmDesc> gemm6;
+    int64_t gemm6_tiles = 0;
+    double gemm6_flops = 0;
+    size_t off_gemm6 = 0;
     std::vector<Elim1Desc> e1;  // column reductions over more than kColMat matrices
     int64_t e1_tiles = 0;
     // grouped column reductions, one launch per slot: slot nm - 1 in column
@@ -206,6 +211,8 @@ struct Schedule {
     Blob blob;
     int nprog_total = 0;
     size_t n_nodes = 0;
+    int depth = 0;                 // dependency levels of the DAG
+    std::vector<char> two_plane;   // per dataset: a GEMM took two-plane split-bf16
 };
 
 struct Cfg {
@@ -230,15 +237,21 @@ Cfg make_cfg(int prec) {
     return c;
 }
 
-size_t prep_bytes(const Cfg &c, int64_t npad, int limbs) {
+size_t prep_bytes(int pformat, int64_t npad, int limbs) {
     size_t plane = (size_t)npad * (size_t)npad;
-    switch (c.pformat) {
+    switch (pformat) {
         case PF_F64: return plane * 8;
         case PF_F32: return plane * 4;
         case PF_BF16X2: return plane * 4;
+        case PF_BF16X3: return plane * 6;
         default: return plane * (size_t)limbs;
     }
 }
+
+// Split-bf16 GEMMs below this size always take the three-plane scheme: the
+// two-plane scheme's per-product residual (up to about 3 * 2^-18 relative)
+// is only averaged down to fp32 level by long sums of same-sign terms.
+constexpr int64_t kSplit6Below = 1024;
 
 // ---------------------------------------------------------------------------
 // Node DAG.  Every step of every (dataset, V-statistic) program becomes a
@@ -276,6 +289,7 @@ struct Node {
     size_t off = 0, bytes = 0;
     int scal = -1, mx = -1;
     double bound = 0;
+    bool neg = false;  // may hold negative entries (split-bf16 scheme choice)
     // Transpose: source (node or input pointer) in A[0]
 };
 
@@ -879,6 +893,7 @@ void layout_column_reductions(const std::vector<ColPending> &recs, LevelWork &W,
 std::string build_schedule(const Plan &plan, const std::vector<const VProgram *> &progs,
                            const std::vector<Dataset> &data, const Cfg &cfg,
                            const std::vector<double> &in_bound,  // per dataset*edge (INT)
+                           const std::vector<char> &in_signed,   // per dataset*edge, empty: none
                            char *base, Schedule &S, int *status,
                            const SliceRange &range = SliceRange()) {
     S = Schedule();
@@ -895,6 +910,8 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
         return err;
     }
     S.n_nodes = G.nodes.size();
+    S.depth = G.max_level;
+    S.two_plane.assign(nd, 0);
     const bool is_int = cfg.domain == DOM_INT;
     if ((base || getenv("USTAT_DEBUG_DAG_DRY")) && getenv("USTAT_DEBUG_DAG")) {
         int cnt[6] = {0, 0, 0, 0, 0, 0};
@@ -939,6 +956,15 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
     auto in_b = [&](int d, const void *ptr) {
         if (in_bound.empty()) return 127.0;
         return in_bound[inmx_of[std::make_pair(d, ptr)]];
+    };
+    // inputs that may hold negative entries: one flag per (dataset, edge),
+    // looked up by pointer (the first edge carrying it)
+    std::map<std::pair<int, const void *>, int> in_index;
+    for (int d = 0; d < nd; ++d)
+        for (int k = 0; k < ne; ++k) in_index.emplace(std::make_pair(d, data[d].factors[k]), d * ne + k);
+    auto in_neg = [&](int d, const void *ptr) -> bool {
+        if (in_signed.empty()) return false;
+        return in_signed[in_index[std::make_pair(d, ptr)]] != 0;
     };
     // diagonals (prologue)
     std::vector<size_t> diag_off(G.diag_index.size());
@@ -990,6 +1016,11 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
         const MOp s0 = src_of(o);
         return s0.node >= 0 ? G.nodes[s0.node].bound : in_b(d, s0.p);
     };
+    auto mneg = [&](int d, const MOp &o) {
+        const MOp s0 = src_of(o);
+        return s0.node >= 0 ? G.nodes[s0.node].neg : in_neg(d, s0.p);
+    };
+    auto vneg = [&](int d, const VOp &v) { return v.node >= 0 ? G.nodes[v.node].neg : in_neg(d, v.p); };
     auto mmx = [&](int d, const MOp &o) -> const unsigned long long * {
         if (!inmxbase) return nullptr;
         const MOp s0 = src_of(o);
@@ -1019,8 +1050,9 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
 
     // last GEMM level of every operand prep built only from inputs, so that
     // it can be released after that level
-    auto prep_key = [&](int d, int64_t n, const std::vector<MOp> &ops, const std::vector<VOp> &sv) {
-        std::string key = std::to_string(d) + "|" + std::to_string(n) + "|";
+    auto prep_key = [&](int d, int64_t n, const std::vector<MOp> &ops, const std::vector<VOp> &sv,
+                        int format) {
+        std::string key = std::to_string(d) + "|" + std::to_string(n) + "|" + std::to_string(format) + "|";
         bool pers = true;
         for (auto &o : ops) {
             pers = pers && (o.node < 0);
@@ -1033,11 +1065,37 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
         }
         return std::make_pair(key, pers);
     };
+    // Sign of every node (nodes come in topological order): a value may be
+    // negative only when one of its operands may be.
+    for (auto &nd_ : G.nodes) {
+        bool ng = false;
+        const int d = nd_.d;
+        if (nd_.kind == NK::SliceSrc || nd_.kind == NK::Transpose) {
+            ng = mneg(d, nd_.A[0]);
+        } else {
+            for (auto *g : {&nd_.A, &nd_.B, &nd_.Z})
+                for (auto &o : *g) ng = ng || mneg(d, o);
+        }
+        for (auto *g : {&nd_.sv, &nd_.aw, &nd_.bx})
+            for (auto &v : *g) ng = ng || vneg(d, v);
+        nd_.neg = ng;
+    }
+    // operand format of a GEMM node: split-bf16 takes three planes when a
+    // contracted operand may be negative or the size is small
+    auto gemm_format = [&](const Node &q) {
+        if (cfg.pformat != PF_BF16X2) return cfg.pformat;
+        bool ng = q.n < kSplit6Below;
+        for (auto &o : q.A) ng = ng || mneg(q.d, o);
+        for (auto &o : q.B) ng = ng || mneg(q.d, o);
+        for (auto &v : q.sv) ng = ng || vneg(q.d, v);
+        return ng ? (int)PF_BF16X3 : (int)PF_BF16X2;
+    };
     std::map<std::string, int> prep_last;
     for (auto &nd_ : G.nodes)
         if (nd_.kind == NK::GemmStore || nd_.kind == NK::GemmFinal) {
-            auto ka = prep_key(nd_.d, nd_.n, nd_.A, nd_.sv);
-            auto kb = prep_key(nd_.d, nd_.n, nd_.B, {});
+            const int fm = gemm_format(nd_);
+            auto ka = prep_key(nd_.d, nd_.n, nd_.A, nd_.sv, fm);
+            auto kb = prep_key(nd_.d, nd_.n, nd_.B, {}, fm);
             prep_last[ka.first] = std::max(prep_last[ka.first], nd_.level);
             prep_last[kb.first] = std::max(prep_last[kb.first], nd_.level);
         }
@@ -1057,6 +1115,7 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
             for (int id : by_level[L]) {
                 const Node &q = G.nodes[id];
                 if (q.kind != NK::GemmStore && q.kind != NK::GemmFinal) continue;
+                if (gemm_format(q) == PF_BF16X3) continue;
                 const int64_t np_ = up64(q.n, 128);
                 if (np_ % 256 == 0) t256 += (np_ / 256) * (np_ / 256);
             }
@@ -1175,9 +1234,10 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
                 }
                 case NK::GemmStore:
                 case NK::GemmFinal: {
+                    const int fmt = gemm_format(nd_);
                     auto make_prep = [&](const std::vector<MOp> &ops, const std::vector<VOp> &sv,
                                          double bound, const int32_t **limbs_p, int *max_limbs) {
-                        auto kp = prep_key(d, n, ops, sv);
+                        auto kp = prep_key(d, n, ops, sv, fmt);
                         const std::string &key = kp.first;
                         const bool pers = kp.second;
                         int cap = cfg.pformat == PF_I8LIMBS ? limbs_for(bound, 9) : 1;
@@ -1186,7 +1246,7 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
                         if (it == tab.end()) {
                             PrepRec rec;
                             rec.limbs = cap;
-                            rec.bytes = prep_bytes(cfg, npad, cap);
+                            rec.bytes = prep_bytes(fmt, npad, cap);
                             rec.off = A.alloc(rec.bytes);
                             rec.limb_slot = (int)limb_next++;
                             if (!pers) scratch.push_back({rec.off, rec.bytes});
@@ -1201,7 +1261,7 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
                             for (int q = 0; q < pd.nA; ++q) pd.A[q] = mref(d, ops[q]);
                             for (int q = 0; q < pd.nS; ++q) pd.s[q] = vptr(d, sv[q]);
                             pd.out = P(rec.off);
-                            pd.format = cfg.pformat;
+                            pd.format = fmt;
                             pd.limbs = cap;
                             pd.tiles = (int)(npad / 64);
                             pd.tile_start = W.prep_tiles;
@@ -1229,7 +1289,7 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
                     g.A = make_prep(nd_.A, nd_.sv, pA * pS, &lap, &cla);
                     g.B = make_prep(nd_.B, {}, pB, &lbp, &clb);
                     // the GEMM addresses its operands with 32-bit offsets
-                    if ((double)prep_bytes(cfg, npad, std::max(cla, clb)) >= 4294967296.0) {
+                    if ((double)prep_bytes(fmt, npad, std::max(cla, clb)) >= 4294967296.0) {
                         *status = 2;
                         return "a GEMM operand of this size exceeds the 4 GiB the kernels address";
                     }
@@ -1241,12 +1301,14 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
                     g.lb = clb;
                     g.la_p = is_int ? lap : nullptr;
                     g.lb_p = is_int ? lbp : nullptr;
-                    const bool big = W.big && npad % 256 == 0;
+                    const bool six = fmt == PF_BF16X3;
+                    if (fmt == PF_BF16X2) S.two_plane[d] = 1;
+                    const bool big = W.big && npad % 256 == 0 && !six;
                     g.tiles = (int)(npad / (big ? 256 : 128));
-                    int64_t &tcount = big ? W.gemm_big_tiles : W.gemm_tiles;
+                    int64_t &tcount = six ? W.gemm6_tiles : big ? W.gemm_big_tiles : W.gemm_tiles;
                     g.tile_start = tcount;
                     tcount += (int64_t)g.tiles * g.tiles;
-                    (big ? W.gemm_big_flops : W.gemm_flops) += 2.0 * (double)n * n * n;
+                    (six ? W.gemm6_flops : big ? W.gemm_big_flops : W.gemm_flops) += 2.0 * (double)n * n * n;
                     const double cb = n * pA * pS * pB;
                     if (is_int) {
                         if (cb > kOverflow) {
@@ -1290,7 +1352,7 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
                         W.red.push_back(r);
                         nd_.bound = (double)n * n * cb * pZ * paw * pbx;
                     }
-                    (big ? W.gemm_big : W.gemm).push_back(g);
+                    (six ? W.gemm6 : big ? W.gemm_big : W.gemm).push_back(g);
                     break;
                 }
             }
@@ -1364,6 +1426,7 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
         W.off_prep = S.blob.put(W.prep);
         W.off_gemm = S.blob.put(W.gemm);
         W.off_gemm_big = S.blob.put(W.gemm_big);
+        W.off_gemm6 = S.blob.put(W.gemm6);
         W.off_e1 = S.blob.put(W.e1);
         for (int k = 0; k < LevelWork::kColSlots; ++k) W.off_col[k] = S.blob.put(W.col[k]);
         W.off_e0 = S.blob.put(W.e0);
@@ -1380,10 +1443,56 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
     return "";
 }
 
+}  // namespace
+
+// The estimate follows the probabilistic model of rounding errors of Higham
+// and Mary (2019): errors independent with mean zero, so that a sequential
+// sum of k terms of unit roundoff u carries a relative error of order
+// sqrt(k) u rather than k u.  Every dependency level (plus the diagonal
+// prologue and the combination) is a stage; stages add in quadrature.  A
+// stage's contraction accumulates n / k_c MFMA results in sequence (k_c the
+// instruction's inner length: 4 for fp64 and fp32, 32 for bf16) in unit
+// roundoff u_c, and its fp64 reductions and the combination add up to n
+// terms in sequence.  The two-plane split-bf16 scheme leaves a residual of
+// up to about 3 * 2^-18 per product, of random sign, averaged over the n
+// products of a contraction.  The factor 2 covers about two standard
+// deviations.  This is an estimate of the typical error, not a worst-case
+// bound: it does not credit the further averaging of independent element
+// errors in the final sums (so it usually overstates the error at large n),
+// and data built to align the errors can exceed it.
+double error_estimate(int precision, int64_t n, int depth, bool two_plane) {
+    double uc, kc;
+    switch (precision) {
+        case 0: uc = std::ldexp(1.0, -53); kc = 4; break;
+        case 1: uc = std::ldexp(1.0, -24); kc = 4; break;
+        case 2: uc = std::ldexp(1.0, -24); kc = 32; break;
+        default: return 0.0;  // exact
+    }
+    const double D = depth + 2.0, nn = (double)std::max<int64_t>(n, 1);
+    const double ur = std::ldexp(1.0, -53);
+    double e = 2.0 * std::sqrt(D) * (uc * std::sqrt(std::max(1.0, nn / kc)) + ur * std::sqrt(nn));
+    if (two_plane) e += 2.0 * std::sqrt(D) * 3.0 * std::ldexp(1.0, -18) / std::sqrt(nn);
+    return e;
+}
+
+namespace {
+
 __global__ void k_fill_zero(unsigned long long *p, size_t n) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (size_t)gridDim.x * blockDim.x)
         p[i] = 0;
+}
+
+// Sign flags for sizing a schedule before the inputs are scanned: every
+// input not known to be non-negative may be negative (three-plane operands
+// are the larger ones).
+std::vector<char> worst_signs(const Cfg &cfg, const std::vector<Dataset> &data) {
+    std::vector<char> f;
+    if (cfg.pformat != PF_BF16X2 || data.empty()) return f;
+    const size_t ne = data[0].factors.size();
+    for (const Dataset &d : data)
+        for (size_t k = 0; k < ne; ++k) f.push_back(d.nonneg ? 0 : 1);
+    return f;
 }
 
 }  // namespace
@@ -1394,7 +1503,7 @@ ScheduleSizes schedule_sizes(const Plan &plan, const std::vector<const VProgram 
     int st = 0;
     const Cfg cfg = make_cfg(plan.opts.precision);
     ScheduleSizes z;
-    std::string err = build_schedule(plan, progs, data, cfg, {}, nullptr, S, &st, range);
+    std::string err = build_schedule(plan, progs, data, cfg, {}, worst_signs(cfg, data), nullptr, S, &st, range);
     if (!err.empty()) return z;
     z.arena = S.arena_bytes;
     z.blob = S.blob_bytes;
@@ -1411,6 +1520,7 @@ size_t workspace_bytes(const Plan &plan, const std::vector<const VProgram *> &pr
         Dataset d;
         d.n = n;
         d.symmetric = plan.opts.symmetric;
+        d.nonneg = shared_factor;  // the sample entry points' RBF factors
         // distinct placeholder pointers per dataset (and per edge unless shared)
         for (size_t k = 0; k < plan.edges.size(); ++k) {
             d.factors.push_back(&fake[slot % sizeof fake]);
@@ -1425,7 +1535,8 @@ size_t workspace_bytes(const Plan &plan, const std::vector<const VProgram *> &pr
         if (p->slice_var >= 0) rg.hi = 1;
     Schedule S;
     int st = 0;
-    std::string err = build_schedule(plan, progs, data, make_cfg(plan.opts.precision), {}, nullptr, S,
+    const Cfg cfg = make_cfg(plan.opts.precision);
+    std::string err = build_schedule(plan, progs, data, cfg, {}, worst_signs(cfg, data), nullptr, S,
                                      &st, rg);
     if (!err.empty()) {
         if (getenv("USTAT_DEBUG_DAG")) fprintf(stderr, "workspace: %s\n", err.c_str());
@@ -1455,8 +1566,71 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
     // host staging of the external-memory mode (ordinary host memory; every
     // copy through it completes before this function returns)
     std::vector<char> hstage_ext, hres_ext;
+    const int ne = (int)plan.edges.size();
+    // Split-bf16: which inputs may hold negative entries (one device scan of
+    // the factors not known to be non-negative, read back once); the choice
+    // of contraction scheme depends on it, so it is part of the graph key.
+    std::vector<char> in_signed;
+    std::string key = capture_key;
+    if (cfg.pformat == PF_BF16X2) {
+        std::vector<const void *> srcs;
+        std::vector<int64_t> ns;
+        std::vector<int> slot;
+        in_signed.assign((size_t)data.size() * ne, 0);
+        for (size_t d = 0; d < data.size(); ++d) {
+            if (data[d].nonneg) continue;
+            for (int k = 0; k < ne; ++k) {
+                int dup = -1;
+                for (int q = 0; q < k; ++q)
+                    if (data[d].factors[q] == data[d].factors[k]) dup = q;
+                if (dup >= 0) continue;
+                srcs.push_back(data[d].factors[k]);
+                ns.push_back(data[d].n);
+                slot.push_back((int)(d * ne + k));
+            }
+        }
+        if (!srcs.empty()) {
+            const size_t cnt = srcs.size();
+            char *dpre, *hpre;
+            if (ext) {
+                if (cnt * 20 + 256 > ext->bytes) {
+                    *status = 6;
+                    return "the sign scan needs more than the external workspace";
+                }
+                hstage_ext.assign(cnt * 20 + 64, 0);
+                dpre = ext->base;
+                hpre = hstage_ext.data();
+            } else {
+                HIPCHK(rt.reserve_desc(cnt * 20 + 1024));
+                dpre = rt.ddesc;
+                hpre = rt.hdesc;
+            }
+            std::memcpy(hpre, srcs.data(), cnt * 8);
+            std::memcpy(hpre + cnt * 8, ns.data(), cnt * 8);
+            HIPCHK(hipMemcpyAsync(dpre, hpre, cnt * 16, hipMemcpyHostToDevice, stream));
+            unsigned int *dfl = reinterpret_cast<unsigned int *>(dpre + cnt * 16);
+            HIPCHK(hipMemsetAsync(dfl, 0, cnt * 4, stream));
+            HIPCHK(launch_signscan(reinterpret_cast<const void *const *>(dpre),
+                                   reinterpret_cast<const int64_t *>(dpre + cnt * 8), (int)cnt,
+                                   cfg.in_dt == DT_F32, dfl, stream));
+            std::vector<unsigned int> fl(cnt);
+            HIPCHK(hipMemcpyAsync(fl.data(), dfl, cnt * 4, hipMemcpyDeviceToHost, stream));
+            HIPCHK(hipStreamSynchronize(stream));
+            for (size_t i = 0; i < cnt; ++i) in_signed[slot[i]] = fl[i] ? 1 : 0;
+            // repeated pointers share their first edge's flag
+            for (size_t d = 0; d < data.size(); ++d)
+                for (int k = 0; k < ne; ++k)
+                    for (int q = 0; q < k; ++q)
+                        if (data[d].factors[q] == data[d].factors[k]) {
+                            in_signed[d * ne + k] = in_signed[d * ne + q];
+                            break;
+                        }
+            key += "|sign:";
+            for (char c : in_signed) key += c ? '1' : '0';
+        }
+    }
     if (capture) {
-        auto git = rt.graphs.find(capture_key);
+        auto git = rt.graphs.find(key);
         if (git != rt.graphs.end() && git->second.nd == (int)data.size()) {
             // Replay: the graph reads its own device descriptor blob and
             // recomputes everything in the workspace from the inputs.
@@ -1473,11 +1647,11 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
             for (int d = 0; d < nd; ++d) {
                 out[d].value = reinterpret_cast<const double *>(h + vbytes)[d];
                 out[d].scale = reinterpret_cast<const double *>(h + vbytes + ubytes)[d];
+                out[d].err_est = git->second.err_est[d];
             }
             return "";
         }
     }
-    const int ne = (int)plan.edges.size();
     std::vector<double> in_bound;
     Profiler *prof = Profiler::active();
     if (cfg.domain == DOM_INT) {
@@ -1536,7 +1710,7 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
     char *arena = rt.arena, *vacc = rt.vacc, *hres = rt.hres, *hdesc = rt.hdesc;
     const int nd = (int)data.size();
     if (ext) {
-        err = build_schedule(plan, progs, data, cfg, in_bound, ext->base, S, status, range);
+        err = build_schedule(plan, progs, data, cfg, in_bound, in_signed, ext->base, S, status, range);
         if (!err.empty()) return err;
         const size_t nres_ext = (size_t)S.nprog_total * cfg.wide_es + (size_t)nd * cfg.wide_es + (size_t)nd * 8;
         const size_t need = up(S.arena_bytes, kAlign) + up(S.blob_bytes, kAlign) + S.n_inmx * 8 +
@@ -1554,11 +1728,11 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
         hdesc = hstage_ext.data();
         built = true;
     } else if (rt.arena) {
-        err = build_schedule(plan, progs, data, cfg, in_bound, rt.arena, S, status, range);
+        err = build_schedule(plan, progs, data, cfg, in_bound, in_signed, rt.arena, S, status, range);
         if (!err.empty()) return err;
         built = S.arena_bytes <= rt.arena_bytes;
     } else {
-        err = build_schedule(plan, progs, data, cfg, in_bound, nullptr, S, status, range);
+        err = build_schedule(plan, progs, data, cfg, in_bound, in_signed, nullptr, S, status, range);
         if (!err.empty()) return err;
     }
     if (plan.opts.workspace_limit && S.arena_bytes > plan.opts.workspace_limit) {
@@ -1571,7 +1745,7 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
             *status = 3;
             return std::string("device workspace allocation failed: ") + hipGetErrorString(e);
         }
-        err = build_schedule(plan, progs, data, cfg, in_bound, rt.arena, S, status, range);
+        err = build_schedule(plan, progs, data, cfg, in_bound, in_signed, rt.arena, S, status, range);
         if (!err.empty()) return err;
         arena = rt.arena;
     }
@@ -1594,7 +1768,7 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
         char *hblob = hdesc;
         Runtime::GraphEntry entry;
         if (capture) {
-            auto old = rt.graphs.find(capture_key);
+            auto old = rt.graphs.find(key);
             if (old != rt.graphs.end()) {
                 if (old->second.exec) (void)hipGraphExecDestroy(old->second.exec);
                 if (old->second.blob) (void)hipFree(old->second.blob);
@@ -1680,6 +1854,12 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
                                 (int)W.gemm_big.size(), W.gemm_big_tiles, cfg.prec, 256, stream);
                 if (e != hipSuccess) return fail(e, "gemm");
             }
+            if (!W.gemm6.empty()) {
+                ProfScope ps(prof, KIND_GEMM, stream, W.gemm6_flops);
+                e = launch_gemm(reinterpret_cast<GemmDesc *>(dd + W.off_gemm6), (int)W.gemm6.size(),
+                                W.gemm6_tiles, kGemmBf16x6, 128, stream);
+                if (e != hipSuccess) return fail(e, "gemm");
+            }
             if (!W.gemm.empty()) {
                 ProfScope ps(prof, KIND_GEMM, stream, W.gemm_flops);
                 e = launch_gemm(reinterpret_cast<GemmDesc *>(dd + W.off_gemm), (int)W.gemm.size(),
@@ -1744,7 +1924,9 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
             }
             entry.nd = nd;
             entry.nprog = S.nprog_total;
-            rt.graphs[capture_key] = entry;
+            for (int d = 0; d < nd; ++d)
+                entry.err_est.push_back(error_estimate(cfg.prec, data[d].n, S.depth, S.two_plane[d] != 0));
+            rt.graphs[key] = entry;
             HIPCHK(hipGraphLaunch(entry.exec, stream));
         }
     }
@@ -1769,6 +1951,7 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
             out[d].exact_lo = (uint64_t)u;
         }
         out[d].scale = reinterpret_cast<const double *>(h + vbytes + ubytes)[d];
+        out[d].err_est = error_estimate(cfg.prec, data[d].n, S.depth, S.two_plane[d] != 0);
     }
     return "";
 }
@@ -1808,6 +1991,7 @@ std::string execute_all(const Plan &plan, const std::vector<const VProgram *> &p
     const size_t per = a2 > a1 ? a2 - a1 : 1;
     int64_t chunk = a1 >= budget ? 1 : (int64_t)((budget - a1) / per) + 1;
     chunk = std::max<int64_t>(1, std::min<int64_t>(chunk, nmax));
+    std::vector<double> est;  // largest estimate over the chunks, per dataset
     for (int64_t lo = 0; lo < nmax; lo += chunk) {
         SliceRange rg;
         rg.lo = lo;
@@ -1818,7 +2002,10 @@ std::string execute_all(const Plan &plan, const std::vector<const VProgram *> &p
         std::string err = execute(plan, progs, data, stream, rt, out, vout, status, false, "",
                                   lo == 0 ? pre : nullptr, rg, ext);
         if (!err.empty()) return err;
+        est.resize(out.size(), 0.0);
+        for (size_t d = 0; d < out.size(); ++d) est[d] = std::max(est[d], out[d].err_est);
     }
+    for (size_t d = 0; d < out.size(); ++d) out[d].err_est = est[d];
     return "";
 }
 

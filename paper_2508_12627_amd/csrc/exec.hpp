@@ -19,13 +19,22 @@ struct Dataset {
     int64_t n = 0;
     std::vector<const void *> factors;  // one device pointer per edge
     bool symmetric = false;             // every factor matrix is symmetric
+    // every factor entry is known to be >= 0 (the RBF factors the engine
+    // builds); otherwise split-bf16 plans scan the factors for signs
+    bool nonneg = false;
 };
 
 struct DatasetResult {
     double value = 0, scale = 0;
     int64_t exact_hi = 0;
     uint64_t exact_lo = 0;
+    double err_est = 0;  // estimate of |value - exact| / scale (0 when exact)
 };
+
+// Estimate of |U - U_exact| / S for an evaluation at size n whose deepest
+// program has `depth` dependency levels, under the probabilistic model of
+// rounding errors (independent with mean zero): see exec.cpp.
+double error_estimate(int precision, int64_t n, int depth, bool two_plane);
 
 // Device and pinned-host memory owned by a plan, grown on demand and reused
 // across evaluations.
@@ -49,6 +58,7 @@ struct Runtime {
         char *blob = nullptr;   // device descriptor blob read by the graph
         size_t blob_bytes = 0;
         int nd = 0, nprog = 0;
+        std::vector<double> err_est;  // per dataset
     };
     std::map<std::string, GraphEntry> graphs;
     void drop_graphs();

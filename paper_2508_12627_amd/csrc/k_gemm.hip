@@ -38,6 +38,11 @@ struct GemmCfg<3> {  // int8 limb (one plane per pass)
     typedef int8_t E;
     static constexpr int BK = 64, PLANES = 1;
 };
+template <>
+struct GemmCfg<kGemmBf16x6> {  // bf16 hi/mid/lo
+    typedef uint16_t E;
+    static constexpr int BK = 32, PLANES = 3;
+};
 
 // Row within a 16x16 MFMA result block of item r held by `lane`.
 template <int PREC>
@@ -186,6 +191,34 @@ __device__ __forceinline__ void mma_tile(typename AccT<PREC>::T (&acc)[FM][FN], 
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
             }
         }
+    } else if constexpr (PREC == kGemmBf16x6) {
+        // the six products of order 1, 2^-9 and 2^-18 of a three-plane
+        // split (a0 + a1 + a2)(b0 + b1 + b2), smallest first; the three
+        // dropped ones are of order 2^-27 and below
+        bf16x8 b0[FN], b1[FN], b2[FN];
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            const int rb = IOB::off(rb0 + j * 16 + lr, lg);
+            b0[j] = *reinterpret_cast<const bf16x8 *>(Bs + rb);
+            b1[j] = *reinterpret_cast<const bf16x8 *>(Bs + IOB::PLANEB + rb);
+            b2[j] = *reinterpret_cast<const bf16x8 *>(Bs + 2 * IOB::PLANEB + rb);
+        }
+#pragma unroll
+        for (int i = 0; i < FM; ++i) {
+            const int ra = IOA::off(ra0 + i * 16 + lr, lg);
+            const bf16x8 a0 = *reinterpret_cast<const bf16x8 *>(As + ra);
+            const bf16x8 a1 = *reinterpret_cast<const bf16x8 *>(As + IOA::PLANEB + ra);
+            const bf16x8 a2 = *reinterpret_cast<const bf16x8 *>(As + 2 * IOA::PLANEB + ra);
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, b0[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b2[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0[j], acc[i][j], 0, 0, 0);
+            }
+        }
     } else {
         i32x4 a[FM], b[FN];
 #pragma unroll
@@ -242,9 +275,9 @@ __device__ __forceinline__ void gemm_pass(typename AccT<PREC>::T (&acc)[SH::FM][
         // MFMAs (or waits for them in the middle), exposing their latency.
         // fp64 and int8 keep the free schedule (their register budget is
         // already full).
-        if constexpr (PREC == 1 || PREC == 2) __builtin_amdgcn_sched_barrier(0);
+        if constexpr (PREC == 1 || PREC == 2 || PREC == kGemmBf16x6) __builtin_amdgcn_sched_barrier(0);
         mma_tile<PREC, SH::FM, SH::FN, SH::BM, SH::BN>(acc, As, Bs, ra0, rb0, lane);
-        if constexpr (PREC == 1 || PREC == 2) __builtin_amdgcn_sched_barrier(0);
+        if constexpr (PREC == 1 || PREC == 2 || PREC == kGemmBf16x6) __builtin_amdgcn_sched_barrier(0);
         char *An = lds + (1 - cur) * PAIR;
         IOA::store(ra, An);
         IOB::store(rb, An + IOA::STAGE);
@@ -435,7 +468,9 @@ hipError_t launch_gemm(const GemmDesc *d, int nprob, int64_t total_tiles, int pr
         case 0: return launch_gemm_t<0, S128>(d, nprob, total_tiles, s);
         case 1: return launch_gemm_t<1, S128>(d, nprob, total_tiles, s);
         case 2: return launch_gemm_t<2, S128>(d, nprob, total_tiles, s);
-        default: return launch_gemm_t<3, S128>(d, nprob, total_tiles, s);
+        case 3: return launch_gemm_t<3, S128>(d, nprob, total_tiles, s);
+        case kGemmBf16x6: return launch_gemm_t<kGemmBf16x6, S128>(d, nprob, total_tiles, s);
+        default: return hipErrorInvalidValue;
     }
 }
 

@@ -137,6 +137,27 @@ __global__ void k_diag(const DiagDesc *__restrict__ D, int nprob) {
     }
 }
 
+// Sign scan of fp32 or fp64 matrices: flag[p] is set when matrix p holds a
+// negative entry (or a NaN, for which no sign can be relied on).  Loads are
+// issued from clamped indices, four per thread per round.
+template <typename T>
+__global__ __launch_bounds__(256) void k_signscan(const void *const *src, const int64_t *n,
+                                                  int nprob, unsigned int *flag) {
+    const int p = blockIdx.y;
+    const T *a = static_cast<const T *>(src[p]);
+    const int64_t cnt = n[p] * n[p];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    bool neg = false;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += 4 * stride) {
+        T v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = a[min(i + u * stride, cnt - 1)];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) neg = neg || !(v[u] >= (T)0);
+    }
+    if (__any(neg) && (threadIdx.x & 63) == 0) atomicOr(&flag[p], 1u);
+}
+
 // Largest |entry| of int8 matrices (one running max per problem).
 __global__ void k_absmax_i8(const int8_t *const *src, const int64_t *n, int nprob,
                             unsigned long long *mx) {
@@ -309,6 +330,27 @@ __global__ __launch_bounds__(256) void k_prep(const PrepDesc *__restrict__ D, in
                 *reinterpret_cast<u16x4 *>(static_cast<uint16_t *>(out) + o + plane) = lo;
                 break;
             }
+            case PF_BF16X3: {
+                // x = hi + mid + lo + r with |r| below about 2^-26 |x|: each
+                // plane rounds what the previous ones leave (in fp64, exact)
+                typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
+                u16x4 hi, mid, lo;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    double xd = (double)pr[i][j];
+                    const uint16_t h = f32_to_bf16_rne((float)xd);
+                    xd -= (double)bf16_to_f32(h);
+                    const uint16_t md = f32_to_bf16_rne((float)xd);
+                    xd -= (double)bf16_to_f32(md);
+                    hi[j] = h;
+                    mid[j] = md;
+                    lo[j] = f32_to_bf16_rne((float)xd);
+                }
+                *reinterpret_cast<u16x4 *>(static_cast<uint16_t *>(out) + o) = hi;
+                *reinterpret_cast<u16x4 *>(static_cast<uint16_t *>(out) + o + plane) = mid;
+                *reinterpret_cast<u16x4 *>(static_cast<uint16_t *>(out) + o + 2 * plane) = lo;
+                break;
+            }
             default: {
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
@@ -449,6 +491,15 @@ hipError_t launch_prep(const PrepDesc *d, int nprob, int64_t total_tiles, int do
     dim3 grid((unsigned)total_tiles);
     if (domain == DOM_FP) hipLaunchKernelGGL(k_prep<DOM_FP>, grid, dim3(256), 0, s, d, nprob);
     else hipLaunchKernelGGL(k_prep<DOM_INT>, grid, dim3(256), 0, s, d, nprob);
+    return hipGetLastError();
+}
+
+hipError_t launch_signscan(const void *const *src, const int64_t *n, int nprob, int f32,
+                           unsigned int *flag, hipStream_t s) {
+    if (f32)
+        hipLaunchKernelGGL(k_signscan<float>, dim3(256, (unsigned)nprob), dim3(256), 0, s, src, n, nprob, flag);
+    else
+        hipLaunchKernelGGL(k_signscan<double>, dim3(256, (unsigned)nprob), dim3(256), 0, s, src, n, nprob, flag);
     return hipGetLastError();
 }
 

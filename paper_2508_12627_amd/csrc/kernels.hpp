@@ -113,13 +113,14 @@ struct Elim0Desc {
     void *out;
 };
 
-enum PrepFormat : int32_t { PF_F64 = 0, PF_F32 = 1, PF_BF16X2 = 2, PF_I8LIMBS = 3 };
+enum PrepFormat : int32_t { PF_F64 = 0, PF_F32 = 1, PF_BF16X2 = 2, PF_I8LIMBS = 3, PF_BF16X3 = 4 };
 
 // GEMM operand: out[w * ldo + v] = prod_j s_j(v) prod_k A_k(v, w) for
 // w, v < n and 0 in the padding up to npad, every operand stored (w, v)
 // (trans == 1); tiles of 64 rows x 128 columns, (npad/64) * (npad/128) per
 // problem; ldo a multiple of 4.  PF_BF16X2 writes hi at out and
-// lo at out + plane (elements); PF_I8LIMBS writes `limbs` planes of 7-bit
+// lo at out + plane (elements); PF_BF16X3 writes hi, mid and lo planes
+// (x - hi - mid rounded); PF_I8LIMBS writes `limbs` planes of 7-bit
 // digits (balanced for all but the top one).
 struct PrepDesc {
     int64_t n, npad, ldo, plane;
@@ -221,10 +222,18 @@ hipError_t launch_elim0(const Elim0Desc *d, int nprob, int domain, hipStream_t s
 hipError_t launch_transpose(const TransDesc *d, int nprob, int64_t total_tiles, hipStream_t s);
 hipError_t launch_prep(const PrepDesc *d, int nprob, int64_t total_tiles, int domain,
                        hipStream_t s);
-// tile: 128 (any precision) or 256 (fp32 and split-bf16; npad % 256 == 0,
-// GemmDesc::tiles counted in 256-row tiles)
+// precision: a ustat_precision, or kGemmBf16x6 for split-bf16 operands
+// prepared in three planes (PF_BF16X3) whose products take the six terms
+// of order up to 2^-18 (128-wide tiles only).
+// tile: 128 (any precision) or 256 (fp32 and two-plane split-bf16;
+// npad % 256 == 0, GemmDesc::tiles counted in 256-row tiles)
+constexpr int kGemmBf16x6 = 4;
 hipError_t launch_gemm(const GemmDesc *d, int nprob, int64_t total_tiles, int precision,
                        int tile, hipStream_t s);
+// flag[p] = 1 when matrix p (n[p] x n[p], fp32 when f32 else fp64) holds a
+// negative (or NaN) entry, else 0; the flags must be zero on entry.
+hipError_t launch_signscan(const void *const *src, const int64_t *n, int nprob, int f32,
+                           unsigned int *flag, hipStream_t s);
 hipError_t launch_absmax_i8(const int8_t *const *src, const int64_t *n, int nprob,
                             unsigned long long *mx, hipStream_t s);
 hipError_t launch_slicesrc(const SliceDesc *d, int nprob, int64_t total_tiles, int domain,
