@@ -483,7 +483,10 @@ ustat_status ustat_eval_samples(ustat_plan plan, int64_t n, int32_t d, const dou
         return fail(USTAT_E_INVALID, "samples with an RBF kernel need a floating-point precision");
     const int dt = plan->plan.opts.precision == USTAT_F64 ? DT_F64 : DT_F32;
     const size_t es = dt == DT_F64 ? 8 : 4;
-    hipError_t e = grow(&plan->factors, &plan->factors_bytes, (size_t)n * n * es, &plan->rt);
+    // the factor and, when a GEMM reads it alone, its operand form behind it
+    const int opf = factor_operand_format(plan->plan, n, true);
+    const size_t kb = ((size_t)n * n * es + 255) / 256 * 256;
+    hipError_t e = grow(&plan->factors, &plan->factors_bytes, kb + factor_operand_bytes(opf, n), &plan->rt);
     if (e != hipSuccess) return fail(USTAT_E_NOMEM, hipGetErrorString(e));
     std::vector<Dataset> data(1);
     data[0].n = n;
@@ -491,9 +494,12 @@ ustat_status ustat_eval_samples(ustat_plan plan, int64_t n, int32_t d, const dou
     data[0].nonneg = true;     // and positive
     for (size_t k = 0; k < plan->plan.edges.size(); ++k) data[0].factors.push_back(plan->factors);
     char *fb = plan->factors;
+    char *ob = opf >= 0 ? plan->factors + kb : nullptr;
+    data[0].operand = ob;
+    data[0].operand_format = opf;
     auto pre = [=](hipStream_t s) -> hipError_t {
         ProfScope ps(Profiler::active(), KIND_RBF, s, 0);
-        return launch_rbf(X, n, d, rbf_divisor, fb, dt, s);
+        return launch_rbf(X, n, d, rbf_divisor, fb, dt, s, ob, opf);
     };
     std::string key = "samples:" + std::to_string(n) + ":" + std::to_string(d) + ":" +
                       std::to_string((uintptr_t)X) + ":" + std::to_string(rbf_divisor) + ":" +
@@ -618,7 +624,13 @@ ustat_status ustat_eval_batched(ustat_plan plan, int32_t batch, const int64_t *n
     }
     const int dt = plan->plan.opts.precision == USTAT_F64 ? DT_F64 : DT_F32;
     const size_t es = dt == DT_F64 ? 8 : 4;
-    auto fbytes = [&](int64_t nn) { return ((size_t)nn * nn * es + 255) / 256 * 256; };
+    // per dataset: the factor and, when a GEMM reads it alone, its operand
+    // form behind it
+    auto kbytes = [&](int64_t nn) { return ((size_t)nn * nn * es + 255) / 256 * 256; };
+    auto opfmt = [&](int64_t nn) { return factor_operand_format(plan->plan, nn, true); };
+    auto fbytes = [&](int64_t nn) {
+        return kbytes(nn) + (factor_operand_bytes(opfmt(nn), nn) + 255) / 256 * 256;
+    };
     // Split the batch into chunks whose factor matrices and workspace fit
     // the budget: opts.workspace_limit, else half of the free device memory
     // (counting the buffers this plan already holds as free).
@@ -674,6 +686,8 @@ ustat_status ustat_eval_batched(ustat_plan plan, int32_t batch, const int64_t *n
             ds.nonneg = true;
             for (size_t k = 0; k < plan->plan.edges.size(); ++k)
                 ds.factors.push_back(plan->factors + coff[c][i]);
+            ds.operand_format = opfmt(n[b]);
+            ds.operand = ds.operand_format >= 0 ? plan->factors + coff[c][i] + kbytes(n[b]) : nullptr;
             cdata[c].push_back(ds);
         }
         ScheduleSizes z = schedule_sizes(plan->plan, plan->all, cdata[c]);
@@ -694,10 +708,16 @@ ustat_status ustat_eval_batched(ustat_plan plan, int32_t batch, const int64_t *n
         std::vector<const double *> xs(X + b0, X + b1);
         std::vector<int64_t> ns(n + b0, n + b1);
         std::vector<char *> fps;
-        for (size_t i = 0; i < ns.size(); ++i) fps.push_back(plan->factors + coff[c][i]);
+        std::vector<void *> ops;
+        std::vector<int> opfs;
+        for (size_t i = 0; i < ns.size(); ++i) {
+            fps.push_back(plan->factors + coff[c][i]);
+            ops.push_back(const_cast<void *>(cdata[c][i].operand));
+            opfs.push_back(cdata[c][i].operand_format);
+        }
         auto pre = [=](hipStream_t s) -> hipError_t {
             for (size_t i = 0; i < xs.size(); ++i) {
-                hipError_t e2 = launch_rbf(xs[i], ns[i], d, rbf_divisor, fps[i], dt, s);
+                hipError_t e2 = launch_rbf(xs[i], ns[i], d, rbf_divisor, fps[i], dt, s, ops[i], opfs[i]);
                 if (e2 != hipSuccess) return e2;
             }
             return hipSuccess;

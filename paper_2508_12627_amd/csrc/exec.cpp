@@ -1237,6 +1237,14 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
                     const int fmt = gemm_format(nd_);
                     auto make_prep = [&](const std::vector<MOp> &ops, const std::vector<VOp> &sv,
                                          double bound, const int32_t **limbs_p, int *max_limbs) {
+                        // the factor's operand form, written with the factor
+                        if (data[d].operand && fmt == data[d].operand_format && !sparsify &&
+                            data[d].symmetric && ops.size() == 1 && sv.empty() && ops[0].node < 0 &&
+                            ops[0].p == data[d].factors[0]) {
+                            *limbs_p = nullptr;
+                            *max_limbs = 1;
+                            return data[d].operand;
+                        }
                         auto kp = prep_key(d, n, ops, sv, fmt);
                         const std::string &key = kp.first;
                         const bool pers = kp.second;
@@ -1496,6 +1504,27 @@ std::vector<char> worst_signs(const Cfg &cfg, const std::vector<Dataset> &data) 
 }
 
 }  // namespace
+
+int factor_operand_format(const Plan &plan, int64_t n, bool nonneg) {
+    const Cfg cfg = make_cfg(plan.opts.precision);
+    if (cfg.domain != DOM_FP || plan.opts.sparsify) return -1;
+    int fmt = cfg.pformat;
+    if (fmt == PF_BF16X2 && (!nonneg || n < kSplit6Below)) fmt = PF_BF16X3;
+    if (fmt == PF_BF16X3) return -1;  // the three-plane form is not written with the factor
+    for (const VProgram &p : plan.progs)
+        for (const Step &st : p.steps) {
+            if (st.kind != StepKind::Elim2 && st.kind != StepKind::Final2) continue;
+            const bool a = st.A.size() == 1 && st.sv.empty() && p.vals[st.A[0].val].kind == ValKind::InputMat;
+            const bool b = st.B.size() == 1 && p.vals[st.B[0].val].kind == ValKind::InputMat;
+            if (a || b) return fmt;
+        }
+    return -1;
+}
+
+size_t factor_operand_bytes(int format, int64_t n) {
+    if (format < 0) return 0;
+    return prep_bytes(format, up64(n, 128), 1);
+}
 
 ScheduleSizes schedule_sizes(const Plan &plan, const std::vector<const VProgram *> &progs,
                              const std::vector<Dataset> &data, const SliceRange &range) {

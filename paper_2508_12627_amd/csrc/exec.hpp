@@ -22,7 +22,19 @@ struct Dataset {
     // every factor entry is known to be >= 0 (the RBF factors the engine
     // builds); otherwise split-bf16 plans scan the factors for signs
     bool nonneg = false;
+    // the GEMM-operand form of factors[0] (every edge's factor, in the
+    // sample entry points) in prep format operand_format, written with the
+    // factor; GEMM operands that are that factor alone then need no prep
+    const void *operand = nullptr;
+    int operand_format = -1;
 };
+
+// Prep format in which a GEMM of the plan reads the shared factor of a
+// dataset of size n on its own (no vectors, no other matrices), or -1 when
+// none does; the sample entry points then write that form with the factor.
+int factor_operand_format(const Plan &plan, int64_t n, bool nonneg);
+// Bytes of that operand form at size n.
+size_t factor_operand_bytes(int format, int64_t n);
 
 struct DatasetResult {
     double value = 0, scale = 0;

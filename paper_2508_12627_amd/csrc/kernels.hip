@@ -12,114 +12,160 @@ namespace ustat {
 // ----------------------------------------------------------------- RBF
 
 // RBF factor K(i,j) = exp(-||x_i - x_j||^2 / divisor) (Algorithm 1 with the
-// kernel on an edge as the factor).  Only tiles on or above the diagonal
-// are computed; each is written at (i, j) and, staged through LDS, at
-// (j, i), so K is symmetric bit for bit and its diagonal is exactly 1.
-// Squared distances are summed over coordinates in increasing order, in
-// fp64, from direct differences.  Tile 64 x 64, each thread 4 x 4.
-template <typename OT>
-__device__ __forceinline__ void store4(OT *p, const double (&v)[4], bool vec, int64_t col,
-                                       int64_t lim) {
-    if (vec) {
-        if constexpr (sizeof(OT) == 4) {
-            typedef float f4 __attribute__((ext_vector_type(4)));
-            *reinterpret_cast<f4 *>(p) = f4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
-        } else {
-            typedef double d2 __attribute__((ext_vector_type(2)));
-            reinterpret_cast<d2 *>(p)[0] = d2{v[0], v[1]};
-            reinterpret_cast<d2 *>(p)[1] = d2{v[2], v[3]};
-        }
-    } else {
+// kernel on an edge as the factor).  The squared distance comes from the
+// Gram matrix on fp64 MFMA (16x16x4): ||x_i||^2 + ||x_j||^2 - 2 x_i.x_j,
+// clamped at 0, with the norms summed over the coordinates in increasing
+// order; K(i,i) = 1 exactly.  Only 64 x 64 tiles on or above the diagonal
+// are computed; each value is written at (i, j) and, staged through LDS, at
+// (j, i), so K is symmetric bit for bit.  With OPF >= 0 the same values are
+// also written in the GEMM-operand form of that prep format (npad x npad,
+// zero padded: fp64, fp32, or bf16 hi and lo planes), so that no separate
+// operand preparation of the factor is needed.
+template <typename KT, int OPF>
+__device__ __forceinline__ void rbf_store16(KT *__restrict__ K, void *__restrict__ op, int64_t n,
+                                            int64_t npad, int64_t g, int64_t c0, const double (&v)[16]) {
+    if (g < n) {
+        KT *row = K + g * n;
+        if (n % 4 == 0 && c0 + 15 < n) {
+            if constexpr (sizeof(KT) == 4) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
-            if (col + c < lim) p[c] = (OT)v[c];
+                for (int q = 0; q < 4; ++q)
+                    *reinterpret_cast<f32x4 *>(row + c0 + 4 * q) =
+                        f32x4{(float)v[4 * q], (float)v[4 * q + 1], (float)v[4 * q + 2], (float)v[4 * q + 3]};
+            } else {
+                typedef double d2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+                for (int q = 0; q < 8; ++q) *reinterpret_cast<d2 *>(row + c0 + 2 * q) = d2{v[2 * q], v[2 * q + 1]};
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 16; ++e)
+                if (c0 + e < n) row[c0 + e] = (KT)v[e];
+        }
+    }
+    if constexpr (OPF == PF_F64) {
+        typedef double d2 __attribute__((ext_vector_type(2)));
+        double *o = static_cast<double *>(op) + g * npad + c0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) *reinterpret_cast<d2 *>(o + 2 * q) = d2{v[2 * q], v[2 * q + 1]};
+    } else if constexpr (OPF == PF_F32) {
+        float *o = static_cast<float *>(op) + g * npad + c0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            *reinterpret_cast<f32x4 *>(o + 4 * q) =
+                f32x4{(float)v[4 * q], (float)v[4 * q + 1], (float)v[4 * q + 2], (float)v[4 * q + 3]};
+    } else if constexpr (OPF == PF_BF16X2) {
+        // the split of the fp32 factor value, as the operand preparation
+        // forms it: hi = bf16(x), lo = bf16(x - hi)
+        typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+        u16x8 hi[2], lo[2];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const double xd = (double)(float)v[e];
+            const uint16_t h = f32_to_bf16_rne((float)xd);
+            hi[e >> 3][e & 7] = h;
+            lo[e >> 3][e & 7] = f32_to_bf16_rne((float)(xd - (double)bf16_to_f32(h)));
+        }
+        uint16_t *o = static_cast<uint16_t *>(op) + g * npad + c0;
+        *reinterpret_cast<u16x8 *>(o) = hi[0];
+        *reinterpret_cast<u16x8 *>(o + 8) = hi[1];
+        *reinterpret_cast<u16x8 *>(o + npad * npad) = lo[0];
+        *reinterpret_cast<u16x8 *>(o + npad * npad + 8) = lo[1];
     }
 }
 
-template <typename OT>
+template <typename KT, int OPF>
 __global__ __launch_bounds__(256) void k_rbf(const double *__restrict__ X, int64_t n, int32_t d,
-                                             double inv_div, OT *__restrict__ out) {
+                                             double inv_div, KT *__restrict__ K,
+                                             void *__restrict__ op, int64_t npad) {
     if (blockIdx.y > blockIdx.x) return;  // lower-triangle tiles come from the mirror
-    __shared__ double sm[2 * 64 * 33];  // x rows of the tile's i and j ranges
-    double(*xi)[33] = reinterpret_cast<double(*)[33]>(sm);
-    double(*xj)[33] = reinterpret_cast<double(*)[33]>(sm + 64 * 33);
-    const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
+    // coordinates of the tile's i and j samples, 16 at a time; values staged
+    // in the factor's element type (what is written anyway): about 35 KB for
+    // fp32 factors, so that four blocks share a compute unit
+    __shared__ double xs[2][64][17];
+    __shared__ double nrm[2][64];
+    __shared__ KT val[64][65];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int qi = wv >> 1, qj = wv & 1;  // the wave's 32 x 32 quadrant
     const int64_t i0 = (int64_t)blockIdx.y * 64, j0 = (int64_t)blockIdx.x * 64;
-    double acc[4][4];
+    f64x4 acc[2][2];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[a][c] = 0.0;
-    for (int k0 = 0; k0 < d; k0 += 32) {
-        // clamped loads, all in flight together; entries outside the
-        // samples or coordinates are zeroed afterwards
+        for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+    double nacc = 0.0;  // threads < 128: squared norm of one sample
+    for (int k0 = 0; k0 < d; k0 += 16) {
+        // clamped loads, all in flight together; entries outside the samples
+        // or coordinates are zeroed afterwards
+        double v[8];
 #pragma unroll
-        for (int it = 0; it < 64 * 32 / 256; ++it) {
-            const int e = t + 256 * it;
-            const int rr = e >> 5, kk = e & 31;
-            const int64_t gi = i0 + rr, gj = j0 + rr;
-            const int gk = k0 + kk;
-            const int gkc = min(gk, d - 1);
-            const double a = X[min(gi, n - 1) * d + gkc];
-            const double c = X[min(gj, n - 1) * d + gkc];
-            xi[rr][kk] = (gi < n && gk < d) ? a : 0.0;
-            xj[rr][kk] = (gj < n && gk < d) ? c : 0.0;
+        for (int it = 0; it < 8; ++it) {
+            const int e = t + 256 * it, side = e >> 10, rr = (e >> 4) & 63, kk = e & 15;
+            const int64_t g = (side ? j0 : i0) + rr;
+            v[it] = X[min(g, n - 1) * d + min(k0 + kk, d - 1)];
+        }
+        if (k0 > 0) __syncthreads();  // the previous chunk's reads are done
+#pragma unroll
+        for (int it = 0; it < 8; ++it) {
+            const int e = t + 256 * it, side = e >> 10, rr = (e >> 4) & 63, kk = e & 15;
+            const int64_t g = (side ? j0 : i0) + rr;
+            xs[side][rr][kk] = (g < n && k0 + kk < d) ? v[it] : 0.0;
         }
         __syncthreads();
-        const int kmax = min(32, d - k0);
-        for (int kk = 0; kk < kmax; ++kk) {
-            double av[4], bv[4];
-#pragma unroll
-            for (int a = 0; a < 4; ++a) av[a] = xi[ty * 4 + a][kk];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) bv[c] = xj[tx * 4 + c][kk];
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    const double diff = av[a] - bv[c];
-                    acc[a][c] = fma(diff, diff, acc[a][c]);
-                }
+        if (t < 128) {
+            const int side = t >> 6, rr = t & 63;
+            for (int kk = 0; kk < 16; ++kk) nacc = fma(xs[side][rr][kk], xs[side][rr][kk], nacc);
         }
-        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 16; kk += 4) {
+            double av[2], bv[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) av[a] = xs[0][qi * 32 + a * 16 + (lane & 15)][kk + (lane >> 4)];
+#pragma unroll
+            for (int b = 0; b < 2; ++b) bv[b] = xs[1][qj * 32 + b * 16 + (lane & 15)][kk + (lane >> 4)];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+        }
     }
-    double val[4][4];
+    if (t < 128) nrm[t >> 6][t & 63] = nacc;
+    __syncthreads();
+    // item r of lane l in a 16 x 16 block of the fp64 MFMA: row l/16 + 4 r,
+    // column l % 16
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) val[a][c] = exp(-acc[a][c] * inv_div);
-    // direct tile: rows i0 + 4 ty + a, columns j0 + 4 tx + c (16-byte
-    // stores when the row pitch keeps them aligned)
-    const bool aligned = n % 4 == 0;
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = qi * 32 + a * 16 + (lane >> 4) + 4 * r;
+                const int col = qj * 32 + b * 16 + (lane & 15);
+                const int64_t gi = i0 + row, gj = j0 + col;
+                double sq = nrm[0][row] + nrm[1][col] - 2.0 * acc[a][b][r];
+                sq = sq > 0.0 ? sq : 0.0;
+                const double k = gi == gj ? 1.0 : exp(-sq * inv_div);
+                val[row][col] = (KT)((gi < n && gj < n) ? k : 0.0);
+            }
+    __syncthreads();
+    // direct tile: row r, 16 consecutive columns per thread
     {
-        const int64_t j = j0 + tx * 4;
+        const int r = t >> 2, c = (t & 3) * 16;
+        double v[16];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            const int64_t i = i0 + ty * 4 + a;
-            if (i < n && j < n) store4<OT>(out + i * n + j, val[a], aligned && j + 3 < n, j, n);
-        }
+        for (int e = 0; e < 16; ++e) v[e] = (double)val[r][c + e];
+        rbf_store16<KT, OPF>(K, op, n, npad, i0 + r, j0 + c, v);
     }
     if (blockIdx.x == blockIdx.y) return;  // the diagonal tile is its own mirror
-    // mirror tile: stage transposed in LDS, then write rows j0 + r, columns
-    // i0 + 4 q .. i0 + 4 q + 3
-    double *st = sm;  // 64 x 65 doubles
-    static_assert(sizeof(sm) >= 64 * 65 * sizeof(double), "staging space");
+    {
+        const int r = t >> 2, c = (t & 3) * 16;
+        double v[16];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) st[(tx * 4 + c) * 65 + ty * 4 + a] = val[a][c];
-    __syncthreads();
-#pragma unroll
-    for (int e = t; e < 64 * 16; e += 256) {
-        const int r = e >> 4, q = e & 15;
-        const int64_t j = j0 + r, i = i0 + 4 * q;
-        if (j >= n || i >= n) continue;
-        const double v4[4] = {st[r * 65 + 4 * q], st[r * 65 + 4 * q + 1], st[r * 65 + 4 * q + 2],
-                              st[r * 65 + 4 * q + 3]};
-        store4<OT>(out + j * n + i, v4, aligned && i + 3 < n, i, n);
+        for (int e = 0; e < 16; ++e) v[e] = (double)val[c + e][r];
+        rbf_store16<KT, OPF>(K, op, n, npad, j0 + r, i0 + c, v);
     }
 }
-
 
 // ----------------------------------------------------------------- diag
 
@@ -462,14 +508,33 @@ __global__ __launch_bounds__(256) void k_slicesrc(const SliceDesc *__restrict__ 
 // ----------------------------------------------------------------- launchers
 
 hipError_t launch_rbf(const double *X, int64_t n, int32_t d, double divisor, void *out,
-                      int32_t dtype, hipStream_t s) {
-    dim3 grid((unsigned)((n + 63) / 64), (unsigned)((n + 63) / 64));
-    if (dtype == DT_F64)
-        hipLaunchKernelGGL(k_rbf<double>, grid, dim3(256), 0, s, X, n, d, 1.0 / divisor,
-                           static_cast<double *>(out));
-    else
-        hipLaunchKernelGGL(k_rbf<float>, grid, dim3(256), 0, s, X, n, d, 1.0 / divisor,
-                           static_cast<float *>(out));
+                      int32_t dtype, hipStream_t s, void *op, int32_t op_format) {
+    const int64_t npad = (n + 127) / 128 * 128;
+    const unsigned T = (unsigned)(op ? npad / 64 : (n + 63) / 64);
+    dim3 grid(T, T);
+    const double inv = 1.0 / divisor;
+    if (dtype == DT_F64) {
+        if (op && op_format == PF_F64)
+            hipLaunchKernelGGL((k_rbf<double, PF_F64>), grid, dim3(256), 0, s, X, n, d, inv,
+                               static_cast<double *>(out), op, npad);
+        else if (!op)
+            hipLaunchKernelGGL((k_rbf<double, -1>), grid, dim3(256), 0, s, X, n, d, inv,
+                               static_cast<double *>(out), op, npad);
+        else
+            return hipErrorInvalidValue;
+    } else {
+        if (op && op_format == PF_F32)
+            hipLaunchKernelGGL((k_rbf<float, PF_F32>), grid, dim3(256), 0, s, X, n, d, inv,
+                               static_cast<float *>(out), op, npad);
+        else if (op && op_format == PF_BF16X2)
+            hipLaunchKernelGGL((k_rbf<float, PF_BF16X2>), grid, dim3(256), 0, s, X, n, d, inv,
+                               static_cast<float *>(out), op, npad);
+        else if (!op)
+            hipLaunchKernelGGL((k_rbf<float, -1>), grid, dim3(256), 0, s, X, n, d, inv,
+                               static_cast<float *>(out), op, npad);
+        else
+            return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

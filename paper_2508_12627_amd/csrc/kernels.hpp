@@ -205,8 +205,11 @@ inline int elim_strip_rows(int64_t n) {
     return (int)s;
 }
 
+// RBF factor (n x n, dtype DT_F64 or DT_F32) and, when op is non-null, its
+// GEMM-operand form in prep format op_format (PF_F64 with DT_F64; PF_F32 or
+// PF_BF16X2 with DT_F32), npad = ceil(n / 128) * 128, zero padded.
 hipError_t launch_rbf(const double *X, int64_t n, int32_t d, double divisor, void *out,
-                      int32_t dtype, hipStream_t s);
+                      int32_t dtype, hipStream_t s, void *op = nullptr, int32_t op_format = -1);
 hipError_t launch_diag(const DiagDesc *d, int nprob, int64_t max_n, int domain, hipStream_t s);
 hipError_t launch_elim1(const Elim1Desc *d, int nprob, int64_t total_tiles, int domain,
                         hipStream_t s);

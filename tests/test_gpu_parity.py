@@ -86,15 +86,20 @@ def test_rbf_factor_build(U, prec, d):
     got = K.double().cpu().numpy()
     assert np.all(np.diag(got) == 1.0)
     assert np.array_equal(got, got.T)
+    # The device forms |x_i - x_j|^2 as |x_i|^2 + |x_j|^2 - 2 x_i.x_j (Gram
+    # on fp64 MFMA, sums of d terms): its rounding error is at most about
+    # (d + 3) u (|x_i|^2 + |x_j|^2 + 2 |x_i| |x_j|); the oracle's direct
+    # differences carry a (d + 2) u relative in a = |x_i - x_j|^2 / div;
+    # exp adds an ulp on each side.
+    u = 2.0 ** -53
+    a = -np.log(ref)
+    nr = np.sqrt(np.sum(X * X, axis=1))
+    scale = (nr[:, None] + nr[None, :]) ** 2
+    bound = ((d + 3) * scale / div + a * (d + 3) + 6) * u * ref
     if prec == "f64":
-        # summation-order rounding: a = |x_i - x_j|^2 / div carries about
-        # (d + 2) ulp relative on either side, which exp turns into a*(d+2)
-        # ulp of K, plus one ulp from each side's exp
-        a = -np.log(ref)
-        bound = (a * (d + 2) + 4) * 2.0 ** -53 * ref
         assert np.all(np.abs(got - ref) <= bound)
     else:
-        assert np.max(np.abs(got - ref) / ref) <= 2 ** -24
+        assert np.all(np.abs(got - ref) <= 2.0 ** -24 * ref + bound)
 
 
 # ------------------------------------------------------------------ small n, every path

@@ -200,3 +200,25 @@ def test_edge_graphs_exact(U, name, edges):
     say(f"exact {name} n={n}")
     r = U.Plan(m, edges, precision="i8").eval([dev(M, torch.int8) for M in mats])
     assert r.exact == ref
+
+
+# ------------------------------------------------------------------ factor operand form
+@pytest.mark.parametrize("prec,n", [("bf16x3", 1500), ("bf16x3", 700), ("f32", 1100), ("f64", 530)])
+def test_factor_operand_form_matches_prep(U, prec, n):
+    """The sample entry point writes the GEMM-operand form of the RBF factor
+    together with the factor (no separate operand preparation); evaluating
+    the same factor through ustat_eval, whose GEMMs prepare it, gives the
+    same U bit for bit (n = 700 in split-bf16 takes three-plane operands,
+    which are still prepared)."""
+    import torch
+    d = 16
+    X = dev(W.gaussian_samples(n, d, seed=800 + n), torch.float64)
+    for name, edges in (("cycle4", W.CYCLE4), ("c5chord", W.CYCLE5_CHORD)):
+        m = nverts(edges)
+        P = U.Plan(m, edges, precision=prec)
+        Q = U.Plan(m, edges, precision=prec, symmetric=True)
+        say(f"operand form {name} {prec} n={n}")
+        a = P.eval_samples(X, 2.0 * d)
+        K = U.ustat_build_rbf(X, 2.0 * d, "f64" if prec == "f64" else "f32")
+        b = Q.eval([K] * len(edges))
+        assert a.value == b.value and a.err_scale == b.err_scale
