@@ -81,6 +81,13 @@ struct S256 {
 // s(row) = ((row >> 1) & 3) ^ ((row >> 3) & 1): a 16-byte fragment read by
 // lanes on consecutive rows then touches distinct banks whether the LDS
 // serves 8 lanes over 32 banks or 16 lanes over 64 banks per cycle.
+//
+// Split-bf16 (two planes) interleaves the planes instead: a 128-byte LDS row
+// holds the row's hi chunks 0..3 and lo chunks 4..7, XOR-swizzled as
+// chunk ^ (row & 7).  Measured on gfx950 (rocprofv3 SQ_LDS_BANK_CONFLICT),
+// 16-byte fragment reads of 16 rows x 4 chunks conflict whatever the
+// permutation inside 64-byte rows, and not at all over 128-byte rows
+// swizzled this way.
 template <int PREC, int R, int NT>
 struct TileIO {
     typedef GemmCfg<PREC> C;
@@ -89,22 +96,42 @@ struct TileIO {
     static constexpr int UNITS = R * UPR * C::PLANES;
     static constexpr int PER = UNITS / NT;
     static_assert(UNITS % NT == 0, "tile units must divide over the threads");
-    static constexpr int LROW = (PREC == 0) ? ROWB + 16 : ROWB;
-    static constexpr int PLANEB = R * LROW;
-    static constexpr int STAGE = PLANEB * C::PLANES;
+    static constexpr bool ILV = PREC == 2;  // planes interleaved in 128-byte rows
+    static constexpr int LROW = (PREC == 0) ? ROWB + 16 : ILV ? 2 * ROWB : ROWB;
+    static constexpr int PLANEB = ILV ? 4 * 16 : R * LROW;  // plane offset: in chunks*16 when ILV
+    static constexpr int STAGE = ILV ? R * LROW : PLANEB * C::PLANES;
 
     __device__ static __forceinline__ int off(int row, int chunk) {
         if constexpr (PREC == 0) return row * LROW + chunk * 16;
+        else if constexpr (ILV) return row * LROW + ((chunk ^ (row & 7)) << 4);
         else return row * LROW + ((chunk ^ ((row >> 1) & 3) ^ ((row >> 3) & 1)) << 4);
+    }
+    // The 16-byte unit a thread moves: plane-major in general; row-major
+    // with the planes of a row adjacent when they are interleaved, so that
+    // consecutive lanes fill whole 128-byte LDS rows.
+    __device__ static __forceinline__ void unit(int u, int &pl, int &row, int &cu) {
+        if constexpr (ILV) {
+            row = u / (C::PLANES * UPR);
+            pl = (u / UPR) % C::PLANES;
+            cu = u % UPR;
+        } else {
+            pl = u / (R * UPR);
+            const int uu = u % (R * UPR);
+            row = uu / UPR;
+            cu = uu % UPR;
+        }
+    }
+    // LDS offset of 16-byte chunk `chunk` of plane `pl` in row `row`
+    __device__ static __forceinline__ int poff(int pl, int row, int chunk) {
+        if constexpr (ILV) return off(row, pl * UPR + chunk);
+        else return pl * PLANEB + off(row, chunk);
     }
     __device__ static void load(u32x4 (&r)[PER], const char *base, int64_t ldb, int64_t planeb,
                                 int64_t row0, int64_t k0b) {
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
-            int u = threadIdx.x + NT * i;
-            int pl = u / (R * UPR);
-            int uu = u % (R * UPR);
-            int row = uu / UPR, cu = uu % UPR;
+            int pl, row, cu;
+            unit(threadIdx.x + NT * i, pl, row, cu);
             const char *g = base + (uint32_t)(pl * planeb + (row0 + row) * ldb + k0b + cu * 16);
             // a 32-bit offset from the uniform base (every operand buffer is
             // below 4 GiB, checked when the schedule is built); global address space:
@@ -113,14 +140,35 @@ struct TileIO {
             r[i] = *(const __attribute__((address_space(1))) u32x4 *)(g);
         }
     }
+    // Direct-to-LDS staging of the interleaved layout (global_load_lds,
+    // 16 bytes per lane): a wave instruction fills 8 consecutive 128-byte
+    // LDS rows, lane l landing at slot l (row l / 8, position l % 8); the
+    // lane loads the plane and chunk that the swizzle puts at that position.
+    // Wave wv issues instructions wv, wv + NW, ... of the tile.
+    static constexpr int DMA_PER = R / 8 / (NT / 64);
+    __device__ static void dma(const char *base, int64_t ldb, int64_t planeb, int64_t row0,
+                               int64_t k0b, char *lds) {
+        static_assert(ILV && R % (8 * (NT / 64)) == 0, "direct staging: interleaved rows");
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        const int pos = lane & 7;
+#pragma unroll
+        for (int q = 0; q < DMA_PER; ++q) {
+            const int r0 = (wv + (NT / 64) * q) * 8;
+            const int row = r0 + (lane >> 3);
+            const int c8 = pos ^ (row & 7);
+            const int pl = c8 / UPR, cu = c8 % UPR;
+            const char *g = base + (uint32_t)(pl * planeb + (row0 + row) * ldb + k0b + cu * 16);
+            __builtin_amdgcn_global_load_lds((const void *)g,
+                                             (__attribute__((address_space(3))) void *)(lds + r0 * LROW),
+                                             16, 0, 0);
+        }
+    }
     __device__ static void store(const u32x4 (&r)[PER], char *lds) {
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
-            int u = threadIdx.x + NT * i;
-            int pl = u / (R * UPR);
-            int uu = u % (R * UPR);
-            int row = uu / UPR, cu = uu % UPR;
-            *reinterpret_cast<u32x4 *>(lds + pl * PLANEB + off(row, cu)) = r[i];
+            int pl, row, cu;
+            unit(threadIdx.x + NT * i, pl, row, cu);
+            *reinterpret_cast<u32x4 *>(lds + poff(pl, row, cu)) = r[i];
         }
     }
 };
@@ -174,15 +222,13 @@ __device__ __forceinline__ void mma_tile(typename AccT<PREC>::T (&acc)[FM][FN], 
         bf16x8 bh[FN], bl[FN];
 #pragma unroll
         for (int j = 0; j < FN; ++j) {
-            const int rb = IOB::off(rb0 + j * 16 + lr, lg);
-            bh[j] = *reinterpret_cast<const bf16x8 *>(Bs + rb);
-            bl[j] = *reinterpret_cast<const bf16x8 *>(Bs + IOB::PLANEB + rb);
+            bh[j] = *reinterpret_cast<const bf16x8 *>(Bs + IOB::poff(0, rb0 + j * 16 + lr, lg));
+            bl[j] = *reinterpret_cast<const bf16x8 *>(Bs + IOB::poff(1, rb0 + j * 16 + lr, lg));
         }
 #pragma unroll
         for (int i = 0; i < FM; ++i) {
-            const int ra = IOA::off(ra0 + i * 16 + lr, lg);
-            const bf16x8 ah = *reinterpret_cast<const bf16x8 *>(As + ra);
-            const bf16x8 al = *reinterpret_cast<const bf16x8 *>(As + IOA::PLANEB + ra);
+            const bf16x8 ah = *reinterpret_cast<const bf16x8 *>(As + IOA::poff(0, ra0 + i * 16 + lr, lg));
+            const bf16x8 al = *reinterpret_cast<const bf16x8 *>(As + IOA::poff(1, ra0 + i * 16 + lr, lg));
             // small cross terms first, then the leading hi*hi term
 #pragma unroll
             for (int j = 0; j < FN; ++j) {
@@ -239,6 +285,44 @@ __device__ __forceinline__ void mma_tile(typename AccT<PREC>::T (&acc)[FM][FN], 
 template <int PREC, class SH>
 constexpr int gemm_stage_bytes() {
     return TileIO<PREC, SH::BM, SH::NT>::STAGE + TileIO<PREC, SH::BN, SH::NT>::STAGE;
+}
+
+// K loop of the interleaved split-bf16 layout: the next K tile goes from
+// global memory straight into the idle LDS buffer (no register staging, no
+// LDS stores), issued at the top of the step; its completion and one
+// barrier end the step.
+template <int PREC, class SH>
+__device__ __forceinline__ void gemm_pass_dma(typename AccT<PREC>::T (&acc)[SH::FM][SH::FN],
+                                              const char *Ab, const char *Bb, int64_t ldb,
+                                              int64_t planeb, int64_t w0, int64_t x0, int64_t npad,
+                                              char *lds) {
+    typedef TileIO<PREC, SH::BM, SH::NT> IOA;
+    typedef TileIO<PREC, SH::BN, SH::NT> IOB;
+    constexpr int PAIR = IOA::STAGE + IOB::STAGE;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int ra0 = (wv / SH::WN) * SH::FM * 16, rb0 = (wv % SH::WN) * SH::FN * 16;
+    constexpr int KB = GemmCfg<PREC>::BK * (int)sizeof(typename GemmCfg<PREC>::E);
+    const int64_t nk = npad / GemmCfg<PREC>::BK;
+    IOA::dma(Ab, ldb, planeb, w0, 0, lds);
+    IOB::dma(Bb, ldb, planeb, x0, 0, lds + IOA::STAGE);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    for (int64_t kt = 0; kt < nk; ++kt) {
+        const int cur = (int)(kt & 1);
+        char *As = lds + cur * PAIR;
+        char *Bs = As + IOA::STAGE;
+        char *An = lds + (1 - cur) * PAIR;
+        // the last step re-reads its own tile into the idle buffer, which
+        // keeps the loop free of branches
+        const int64_t kn = (kt + 1 < nk) ? kt + 1 : kt;
+        IOA::dma(Ab, ldb, planeb, w0, kn * KB, An);
+        IOB::dma(Bb, ldb, planeb, x0, kn * KB, An + IOA::STAGE);
+        __builtin_amdgcn_sched_barrier(0);
+        mma_tile<PREC, SH::FM, SH::FN, SH::BM, SH::BN>(acc, As, Bs, ra0, rb0, lane);
+        __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+    }
 }
 
 // K loop of one (A plane set, B plane set) pass with register prefetch and
@@ -343,8 +427,12 @@ void k_gemm(const GemmDesc *__restrict__ D, int nprob) {
         for (int i = 0; i < FM; ++i)
 #pragma unroll
             for (int j = 0; j < FN; ++j) acc[i][j] = AT{0, 0, 0, 0};
-        gemm_pass<PREC, SH>(acc, static_cast<const char *>(d.A), static_cast<const char *>(d.B),
-                            ldb, planeb, w0, x0, d.npad, lds);
+        if constexpr (TileIO<PREC, SH::BM, SH::NT>::ILV)
+            gemm_pass_dma<PREC, SH>(acc, static_cast<const char *>(d.A), static_cast<const char *>(d.B),
+                                    ldb, planeb, w0, x0, d.npad, lds);
+        else
+            gemm_pass<PREC, SH>(acc, static_cast<const char *>(d.A), static_cast<const char *>(d.B),
+                                ldb, planeb, w0, x0, d.npad, lds);
     }
     // value(i, j, r) of row wr0+i*16+mfma_row(lane,r), column xc0+j*16+lane%16
     auto value = [&](int i, int j, int r) {
