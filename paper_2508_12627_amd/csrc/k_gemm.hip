@@ -219,7 +219,13 @@ __device__ __forceinline__ void mma_tile(typename AccT<PREC>::T (&acc)[FM][FN], 
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
         }
     } else if constexpr (PREC == 2) {
-        bf16x8 bh[FN], bl[FN];
+        // Row-block major: the B fragments and row block 0's A fragments
+        // first, then per row block its 3 FN products while the next row
+        // block's A fragments are read (the scheduling groups below keep
+        // that interleave, so LDS latency hides behind MFMAs).  For each
+        // (i, j) the small cross terms come first, then hi*hi; the products
+        // of one accumulator are FN instructions apart.
+        bf16x8 bh[FN], bl[FN], ah[FM], al[FM];
 #pragma unroll
         for (int j = 0; j < FN; ++j) {
             bh[j] = *reinterpret_cast<const bf16x8 *>(Bs + IOB::poff(0, rb0 + j * 16 + lr, lg));
@@ -227,15 +233,28 @@ __device__ __forceinline__ void mma_tile(typename AccT<PREC>::T (&acc)[FM][FN], 
         }
 #pragma unroll
         for (int i = 0; i < FM; ++i) {
-            const bf16x8 ah = *reinterpret_cast<const bf16x8 *>(As + IOA::poff(0, ra0 + i * 16 + lr, lg));
-            const bf16x8 al = *reinterpret_cast<const bf16x8 *>(As + IOA::poff(1, ra0 + i * 16 + lr, lg));
-            // small cross terms first, then the leading hi*hi term
+            ah[i] = *reinterpret_cast<const bf16x8 *>(As + IOA::poff(0, ra0 + i * 16 + lr, lg));
+            al[i] = *reinterpret_cast<const bf16x8 *>(As + IOA::poff(1, ra0 + i * 16 + lr, lg));
+        }
 #pragma unroll
-            for (int j = 0; j < FN; ++j) {
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
-            }
+        for (int i = 0; i < FM; ++i) {
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+        }
+        // scheduling groups: DS reads of B and row block 0, then for each
+        // row block its MFMAs with the next row block's two reads
+        __builtin_amdgcn_sched_group_barrier(0x100, 2 * FN + 2, 0);
+#pragma unroll
+        for (int i = 0; i < FM; ++i) {
+            if (i + 1 < FM) __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, 3 * FN, 0);
         }
     } else if constexpr (PREC == kGemmBf16x6) {
         // the six products of order 1, 2^-9 and 2^-18 of a three-plane
