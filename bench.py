@@ -128,10 +128,35 @@ def cpu_baseline(X, div, budget_s=15.0):
         t += time.perf_counter() - t1
         items += more
     frac = items / float(n * n)
-    return {"value": frac / t, "unit": "evals/s", "cores": oracle.num_threads(), "kind": "oracle",
+    cores = oracle.num_threads()
+    # the same oracle on one core, over a smaller prefix sample
+    oracle.set_num_threads(1)
+    try:
+        items1 = max(2, items // max(1, cores))
+        t1 = time.perf_counter()
+        oracle.ustat_bruteforce(edges, [K] * 4, items=(0, items1))
+        t1 = time.perf_counter() - t1
+    finally:
+        oracle.set_num_threads(cores)
+    return {"value": frac / t, "unit": "evals/s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "single_thread_value": items1 / float(n * n) / t1,
             "sample": f"brute-force sum over distinct ordered 4-tuples restricted to the first "
-                      f"{items} (i0, i1) prefixes of {n * n} at n={n} ({t:.1f} s), scaled by "
-                      f"the prefix fraction"}
+                      f"{items} (i0, i1) prefixes of {n * n} at n={n} ({t:.1f} s on {cores} "
+                      f"threads), scaled by the prefix fraction; single thread: the first "
+                      f"{items1} prefixes ({t1:.1f} s)"}
+
+
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def bench_batched(args):

@@ -169,7 +169,9 @@ ustat_status ustat_plan_info(ustat_plan plan, int32_t *num_vstats, int32_t *M,
  * flops counts 2 per multiply-add of every contraction step (fp64-equivalent
  * products; a split-bf16 step executes three times as many MFMA flops), and
  * bytes the minimum HBM traffic of the steps.  workspace: device bytes the
- * evaluation needs.
+ * evaluation needs.  Errors: USTAT_E_OVERFLOW (workspace requested, exact
+ * plan) when an intermediate may overflow for factors of magnitude up to
+ * 127 (evaluation bounds with the factors' true maxima instead).
  */
 ustat_status ustat_plan_cost(ustat_plan plan, int64_t n, double *flops, double *bytes,
                              uint64_t *workspace);
@@ -367,6 +369,19 @@ ustat_status ustat_mlp_train(int32_t F, int32_t H1, int32_t H2, float *params, c
 /* Write params as a cost-model file readable through opts.cost_model_path. */
 ustat_status ustat_mlp_save(const char *path, int32_t F, int32_t H1, int32_t H2,
                             const float *params);
+
+/*
+ * For tests of the error paths (not for production callers): arm a
+ * one-shot failure.  kind 0: the (countdown + 1)-th host allocation point
+ * of the planner or executor fails (the call returns USTAT_E_NOMEM);
+ * kind 1: the (countdown + 1)-th device or pinned-host allocation reports
+ * out of memory (USTAT_E_NOMEM); kind 2: the (countdown + 1)-th evaluation
+ * fails at its first launch, after any graph capture has begun
+ * (USTAT_E_HIP; the capture is ended and the stream left usable).
+ * countdown < 0 disarms the kind.  Process-wide, not thread-safe with
+ * concurrent calls.  Errors: USTAT_E_INVALID for an unknown kind.
+ */
+ustat_status ustat_debug_inject(int32_t kind, int64_t countdown);
 
 const char *ustat_status_string(ustat_status s);
 const char *ustat_last_error(void);

@@ -303,3 +303,8 @@ int oracle_cycle_walks(long n, const int64_t *rowptr, const int32_t *col, int64_
 }
 
 int oracle_num_threads(void) { return omp_get_max_threads(); }
+
+/* Threads used by later calls (timing the oracle on one core). */
+void oracle_set_num_threads(int t) {
+    if (t >= 1) omp_set_num_threads(t);
+}

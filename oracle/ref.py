@@ -62,6 +62,11 @@ def num_threads() -> int:
     return int(_lib().oracle_num_threads())
 
 
+def set_num_threads(t: int) -> None:
+    """Threads the C routines use from now on."""
+    _lib().oracle_set_num_threads(int(t))
+
+
 def _edge_arrays(edges: Edges):
     ne = len(edges)
     eu = (ctypes.c_int * ne)(*[int(u) for u, _ in edges])

@@ -18,6 +18,8 @@
 
 #include "../../include/ustat.h"
 #include "costmodel.hpp"
+#include "guard.hpp"
+#include "inject.hpp"
 #include "exec.hpp"
 #include "kernels.hpp"
 #include "plan.hpp"
@@ -89,6 +91,7 @@ bool canonical_rgs(const int32_t *block_of, int m, std::vector<int> &out) {
 }
 
 hipError_t grow(char **p, size_t *have, size_t need, Runtime *rt = nullptr) {
+    if (inject_fire(INJ_DEVICE_ALLOC)) return hipErrorOutOfMemory;
     if (*p && *have >= need) return hipSuccess;
     if (rt) rt->drop_graphs();  // captured graphs reference the old buffer
     if (*p) (void)hipFree(*p);
@@ -114,15 +117,18 @@ void fill_result(ustat_result *out, const DatasetResult &r, const Plan &p, int64
 extern "C" {
 
 ustat_status ustat_plan_opts_default(ustat_plan_opts *opts) {
+    USTAT_GUARD_BEGIN
     if (!opts) return fail(USTAT_E_INVALID, "opts is NULL");
     std::memset(opts, 0, sizeof *opts);
     opts->precision = USTAT_F64;
     opts->order = USTAT_ORDER_MINFILL;
     return ok();
+    USTAT_GUARD_END
 }
 
 ustat_status ustat_plan_create(int32_t m, int32_t num_edges, const int32_t *edges,
                                const ustat_plan_opts *opts, ustat_plan *out) {
+    USTAT_GUARD_BEGIN
     if (!out) return fail(USTAT_E_INVALID, "out is NULL");
     *out = nullptr;
     if (!edges || num_edges < 1) return fail(USTAT_E_INVALID, "need at least one edge");
@@ -168,15 +174,19 @@ ustat_status ustat_plan_create(int32_t m, int32_t num_edges, const int32_t *edge
     } catch (const std::exception &ex) {
         return fail(USTAT_E_INVALID, ex.what());
     }
+    USTAT_GUARD_END
 }
 
 ustat_status ustat_plan_destroy(ustat_plan plan) {
+    USTAT_GUARD_BEGIN
     delete plan;
     return ok();
+    USTAT_GUARD_END
 }
 
 ustat_status ustat_plan_info(ustat_plan plan, int32_t *num_vstats, int32_t *M, int64_t *N_l,
                              int32_t *max_width) {
+    USTAT_GUARD_BEGIN
     if (!plan) return fail(USTAT_E_INVALID, "plan is NULL");
     if (num_vstats) *num_vstats = (int32_t)plan->plan.progs.size();
     if (M) *M = plan->plan.M;
@@ -184,10 +194,12 @@ ustat_status ustat_plan_info(ustat_plan plan, int32_t *num_vstats, int32_t *M, i
         for (int l = 0; l <= plan->plan.m; ++l) N_l[l] = plan->plan.N_l[l];
     if (max_width) *max_width = plan->plan.max_width;
     return ok();
+    USTAT_GUARD_END
 }
 
 ustat_status ustat_plan_cost(ustat_plan plan, int64_t n, double *flops, double *bytes,
                              uint64_t *workspace) {
+    USTAT_GUARD_BEGIN
     if (!plan) return fail(USTAT_E_INVALID, "plan is NULL");
     if (n < 1) return fail(USTAT_E_INVALID, "n must be positive");
     double f = 0, b = 0;
@@ -201,14 +213,25 @@ ustat_status ustat_plan_cost(ustat_plan plan, int64_t n, double *flops, double *
     if (flops) *flops = f;
     if (bytes) *bytes = b;
     if (workspace) {
-        if (!plan->plan.executable) *workspace = 0;
-        else *workspace = workspace_bytes(plan->plan, plan->all, {n}, false);
+        if (!plan->plan.executable) {
+            *workspace = 0;
+        } else {
+            int st = 0;
+            const size_t w = workspace_bytes(plan->plan, plan->all, {n}, false, &st);
+            if (st == 5)
+                return fail(USTAT_E_OVERFLOW,
+                            "an exact intermediate may overflow for inputs of magnitude up to 127");
+            if (st == 2) return fail(USTAT_E_UNSUPPORTED, "this size is outside what the engine runs");
+            *workspace = w;
+        }
     }
     return ok();
+    USTAT_GUARD_END
 }
 
 ustat_status ustat_plan_workspace(ustat_plan plan, int32_t batch, const int64_t *n,
                                   int32_t shared_factor, uint64_t *bytes) {
+    USTAT_GUARD_BEGIN
     if (!plan || batch < 1 || !n || !bytes) return fail(USTAT_E_INVALID, "bad arguments");
     if (!plan->plan.executable) return fail(USTAT_E_UNSUPPORTED, plan->plan.lower_error);
     for (int b = 0; b < batch; ++b)
@@ -216,10 +239,12 @@ ustat_status ustat_plan_workspace(ustat_plan plan, int32_t batch, const int64_t 
     std::vector<int64_t> ns(n, n + batch);
     *bytes = workspace_bytes(plan->plan, plan->all, ns, shared_factor != 0);
     return ok();
+    USTAT_GUARD_END
 }
 
 ustat_status ustat_plan_partition(ustat_plan plan, int32_t idx, int32_t *block_of, int64_t *mu,
                                   int32_t *tw, int32_t *width) {
+    USTAT_GUARD_BEGIN
     if (!plan) return fail(USTAT_E_INVALID, "plan is NULL");
     if (idx < 0 || idx >= (int32_t)plan->plan.progs.size())
         return fail(USTAT_E_INVALID, "partition index out of range");
@@ -230,10 +255,12 @@ ustat_status ustat_plan_partition(ustat_plan plan, int32_t idx, int32_t *block_o
     if (tw) *tw = p.tw;
     if (width) *width = p.width;
     return ok();
+    USTAT_GUARD_END
 }
 
 ustat_status ustat_plan_order(ustat_plan plan, int32_t idx, int32_t *order, int32_t *len,
                               int32_t *slice_var) {
+    USTAT_GUARD_BEGIN
     if (!plan) return fail(USTAT_E_INVALID, "plan is NULL");
     if (idx < 0 || idx >= (int32_t)plan->plan.progs.size())
         return fail(USTAT_E_INVALID, "partition index out of range");
@@ -243,10 +270,12 @@ ustat_status ustat_plan_order(ustat_plan plan, int32_t idx, int32_t *order, int3
     if (len) *len = (int32_t)p.order.size();
     if (slice_var) *slice_var = p.slice_var;
     return ok();
+    USTAT_GUARD_END
 }
 
 ustat_status ustat_graph_treewidth(int32_t m, int32_t num_edges, const int32_t *edges,
                                    int32_t *tw) {
+    USTAT_GUARD_BEGIN
     if (m < 1 || m > 16) return fail(USTAT_E_INVALID, "m must be in 1..16");
     if (num_edges < 0 || (num_edges > 0 && !edges) || !tw)
         return fail(USTAT_E_INVALID, "bad arguments");
@@ -261,6 +290,7 @@ ustat_status ustat_graph_treewidth(int32_t m, int32_t num_edges, const int32_t *
     }
     *tw = exact_treewidth(m, adj);
     return ok();
+    USTAT_GUARD_END
 }
 
 static ustat_status run(ustat_plan plan, const std::vector<const VProgram *> &progs,
@@ -296,13 +326,16 @@ static ustat_status check_eval(ustat_plan plan, int64_t n) {
 }
 
 ustat_status ustat_plan_tuning(ustat_plan plan, int64_t *gemm_big_min, int64_t *colred_blocks) {
+    USTAT_GUARD_BEGIN
     if (!plan) return fail(USTAT_E_INVALID, "plan is NULL");
     if (gemm_big_min) *gemm_big_min = plan->plan.tuning.gemm_big_min;
     if (colred_blocks) *colred_blocks = plan->plan.tuning.colred_blocks;
     return ok();
+    USTAT_GUARD_END
 }
 
 ustat_status ustat_plan_set_tuning(ustat_plan plan, int64_t gemm_big_min, int64_t colred_blocks) {
+    USTAT_GUARD_BEGIN
     if (!plan) return fail(USTAT_E_INVALID, "plan is NULL");
     if (colred_blocks < 1 || colred_blocks > (1 << 20))
         return fail(USTAT_E_INVALID, "colred_blocks must be in 1..2^20");
@@ -310,10 +343,12 @@ ustat_status ustat_plan_set_tuning(ustat_plan plan, int64_t gemm_big_min, int64_
     plan->plan.tuning.colred_blocks = colred_blocks;
     plan->rt.drop_graphs();
     return ok();
+    USTAT_GUARD_END
 }
 
 ustat_status ustat_plan_autotune(ustat_plan plan, int64_t n, const void *const *factors,
                                  ustat_stream stream, int32_t reps, double *ms) {
+    USTAT_GUARD_BEGIN
     ustat_status c = check_eval(plan, n);
     if (c != USTAT_OK) return c;
     if (!factors) return fail(USTAT_E_INVALID, "factors is NULL");
@@ -369,10 +404,12 @@ ustat_status ustat_plan_autotune(ustat_plan plan, int64_t n, const void *const *
     if (st != USTAT_OK) return st;
     if (ms) *ms = best_s * 1e3;
     return ok();
+    USTAT_GUARD_END
 }
 
 ustat_status ustat_eval(ustat_plan plan, int64_t n, const void *const *factors, ustat_stream stream,
                         ustat_result *out) {
+    USTAT_GUARD_BEGIN
     ustat_status c = check_eval(plan, n);
     if (c != USTAT_OK) return c;
     if (!factors || !out) return fail(USTAT_E_INVALID, "factors and out must be non-NULL");
@@ -390,6 +427,7 @@ ustat_status ustat_eval(ustat_plan plan, int64_t n, const void *const *factors, 
     if (st != USTAT_OK) return st;
     fill_result(out, res[0], plan->plan, n, (int)plan->all.size());
     return ok();
+    USTAT_GUARD_END
 }
 
 }  // extern "C"
@@ -431,6 +469,7 @@ extern "C" {
 
 ustat_status ustat_eval_noalloc(ustat_plan plan, int64_t n, const void *const *factors,
                                 ustat_stream stream, ustat_result *out) {
+    USTAT_GUARD_BEGIN
     ustat_status c = check_eval(plan, n);
     if (c != USTAT_OK) return c;
     if (!factors || !out) return fail(USTAT_E_INVALID, "factors and out must be non-NULL");
@@ -457,10 +496,12 @@ ustat_status ustat_eval_noalloc(ustat_plan plan, int64_t n, const void *const *f
     } catch (...) {
         return fail(USTAT_E_INVALID, "unexpected host exception");
     }
+    USTAT_GUARD_END
 }
 
 ustat_status ustat_build_rbf(int64_t n, int32_t d, const double *X, double rbf_divisor,
                              int32_t precision, void *out, ustat_stream stream) {
+    USTAT_GUARD_BEGIN
     if (n < 1 || d < 1 || d > 256 || !X || !out) return fail(USTAT_E_INVALID, "bad arguments");
     if (!(rbf_divisor > 0) || !std::isfinite(rbf_divisor))
         return fail(USTAT_E_INVALID, "rbf_divisor must be positive");
@@ -470,10 +511,12 @@ ustat_status ustat_build_rbf(int64_t n, int32_t d, const double *X, double rbf_d
                               (hipStream_t)stream);
     if (e != hipSuccess) return fail(USTAT_E_HIP, hipGetErrorString(e));
     return ok();
+    USTAT_GUARD_END
 }
 
 ustat_status ustat_eval_samples(ustat_plan plan, int64_t n, int32_t d, const double *X,
                                 double rbf_divisor, ustat_stream stream, ustat_result *out) {
+    USTAT_GUARD_BEGIN
     ustat_status c = check_eval(plan, n);
     if (c != USTAT_OK) return c;
     if (d < 1 || d > 256 || !X || !out) return fail(USTAT_E_INVALID, "bad arguments");
@@ -509,10 +552,12 @@ ustat_status ustat_eval_samples(ustat_plan plan, int64_t n, int32_t d, const dou
     if (st != USTAT_OK) return st;
     fill_result(out, res[0], plan->plan, n, (int)plan->all.size());
     return ok();
+    USTAT_GUARD_END
 }
 
 ustat_status vstat_eval(ustat_plan plan, const int32_t *block_of, int64_t n,
                         const void *const *factors, ustat_stream stream, ustat_result *out) {
+    USTAT_GUARD_BEGIN
     if (!plan) return fail(USTAT_E_INVALID, "plan is NULL");
     if (!block_of || !factors || !out) return fail(USTAT_E_INVALID, "NULL argument");
     if (n < 1 || n > (1ll << 20)) return fail(USTAT_E_INVALID, "n out of range");
@@ -544,6 +589,7 @@ ustat_status vstat_eval(ustat_plan plan, const int32_t *block_of, int64_t n,
     fill_result(out, res[0], plan->plan, n, 1);
     out->err_scale = std::fabs(res[0].value);
     return ok();
+    USTAT_GUARD_END
 }
 
 static ustat_status lower_given(ustat_plan plan, const int32_t *block_of, const int32_t *order,
@@ -572,6 +618,7 @@ static ustat_status lower_given(ustat_plan plan, const int32_t *block_of, const 
 
 ustat_status ustat_order_features(ustat_plan plan, const int32_t *block_of, const int32_t *order,
                                   int32_t len, int32_t slice_var, int64_t n, float *feat) {
+    USTAT_GUARD_BEGIN
     if (!feat || n < 1) return fail(USTAT_E_INVALID, "bad arguments");
     VProgram prog;
     ustat_status st = lower_given(plan, block_of, order, len, slice_var, prog);
@@ -580,12 +627,14 @@ ustat_status ustat_order_features(ustat_plan plan, const int32_t *block_of, cons
     if ((int)f.size() != USTAT_NUM_FEATURES) return fail(USTAT_E_INVALID, "feature size mismatch");
     std::copy(f.begin(), f.end(), feat);
     return ok();
+    USTAT_GUARD_END
 }
 
 ustat_status vstat_eval_ordered(ustat_plan plan, const int32_t *block_of, const int32_t *order,
                                 int32_t len, int32_t slice_var, int64_t n,
                                 const void *const *factors, ustat_stream stream,
                                 ustat_result *out) {
+    USTAT_GUARD_BEGIN
     if (!factors || !out) return fail(USTAT_E_INVALID, "NULL argument");
     if (n < 1 || n > (1ll << 20)) return fail(USTAT_E_INVALID, "n out of range");
     VProgram prog;
@@ -605,11 +654,13 @@ ustat_status vstat_eval_ordered(ustat_plan plan, const int32_t *block_of, const 
     fill_result(out, res[0], plan->plan, n, 1);
     out->err_scale = std::fabs(res[0].value);
     return ok();
+    USTAT_GUARD_END
 }
 
 ustat_status ustat_eval_batched(ustat_plan plan, int32_t batch, const int64_t *n, int32_t d,
                                 const double *const *X, double rbf_divisor, ustat_stream stream,
                                 ustat_result *out) {
+    USTAT_GUARD_BEGIN
     if (!plan) return fail(USTAT_E_INVALID, "plan is NULL");
     if (batch < 1 || !n || !X || !out || d < 1 || d > 256)
         return fail(USTAT_E_INVALID, "bad arguments");
@@ -729,21 +780,27 @@ ustat_status ustat_eval_batched(ustat_plan plan, int32_t batch, const int64_t *n
             fill_result(&out[b], res[b - b0], plan->plan, n[b], (int)plan->all.size());
     }
     return ok();
+    USTAT_GUARD_END
 }
 
 ustat_status ustat_profile_enable(int32_t on) {
+    USTAT_GUARD_BEGIN
     Profiler::enable(on != 0);
     return ok();
+    USTAT_GUARD_END
 }
 
 ustat_status ustat_profile_reset(void) {
+    USTAT_GUARD_BEGIN
     Profiler::enable(true);
     if (Profiler::active()) Profiler::active()->reset();
     return ok();
+    USTAT_GUARD_END
 }
 
 ustat_status ustat_profile_read(int32_t kind, double *ms, int64_t *launches, double *flops,
                                 double *bytes) {
+    USTAT_GUARD_BEGIN
     if (kind < 0 || kind >= KIND_COUNT) return fail(USTAT_E_INVALID, "unknown kind");
     Profiler *p = Profiler::active();
     if (!p) return fail(USTAT_E_INVALID, "profiling is not enabled");
@@ -751,6 +808,13 @@ ustat_status ustat_profile_read(int32_t kind, double *ms, int64_t *launches, dou
     if (launches) *launches = p->launches[kind];
     if (flops) *flops = p->flops[kind];
     if (bytes) *bytes = p->bytes[kind];
+    return ok();
+    USTAT_GUARD_END
+}
+
+ustat_status ustat_debug_inject(int32_t kind, int64_t countdown) {
+    if (kind < 0 || kind >= INJ_KINDS) return fail(USTAT_E_INVALID, "unknown failure kind");
+    inject_arm(kind, countdown);
     return ok();
 }
 

@@ -14,6 +14,7 @@
 #include <map>
 #include <unordered_map>
 
+#include "inject.hpp"
 #include "kernels.hpp"
 #include "profile.hpp"
 
@@ -37,6 +38,7 @@ Runtime::~Runtime() {
 }
 
 hipError_t Runtime::reserve_arena(size_t bytes) {
+    if (inject_fire(INJ_DEVICE_ALLOC)) return hipErrorOutOfMemory;
     if (bytes <= arena_bytes && arena) return hipSuccess;
     drop_graphs();
     if (arena) (void)hipFree(arena);
@@ -48,6 +50,7 @@ hipError_t Runtime::reserve_arena(size_t bytes) {
 }
 
 hipError_t Runtime::reserve_desc(size_t bytes) {
+    if (inject_fire(INJ_DEVICE_ALLOC)) return hipErrorOutOfMemory;
     if (bytes <= ddesc_bytes && ddesc) return hipSuccess;
     drop_graphs();
     if (ddesc) (void)hipFree(ddesc);
@@ -64,6 +67,7 @@ hipError_t Runtime::reserve_desc(size_t bytes) {
 }
 
 hipError_t Runtime::reserve_vacc(size_t bytes) {
+    if (inject_fire(INJ_DEVICE_ALLOC)) return hipErrorOutOfMemory;
     if (bytes <= vacc_bytes && vacc) return hipSuccess;
     drop_graphs();
     if (vacc) (void)hipFree(vacc);
@@ -75,6 +79,7 @@ hipError_t Runtime::reserve_vacc(size_t bytes) {
 }
 
 hipError_t Runtime::reserve_hres(size_t bytes) {
+    if (inject_fire(INJ_DEVICE_ALLOC)) return hipErrorOutOfMemory;
     if (bytes <= hres_bytes && hres) return hipSuccess;
     drop_graphs();
     if (hres) (void)hipHostFree(hres);
@@ -516,6 +521,7 @@ std::string build_dag(const Plan &plan, const std::vector<const VProgram *> &pro
         }
     };
     for (int d = 0; d < nd; ++d) {
+        inject_host_alloc();
         const int64_t n = data[d].n;
         const bool sym = data[d].symmetric;
         for (int p = 0; p < np; ++p) {
@@ -1105,6 +1111,7 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
     for (size_t i = 0; i < G.nodes.size(); ++i) by_level[G.nodes[i].level].push_back((int)i);
     S.levels.assign(G.max_level + 1, LevelWork());
     for (int L = 1; L <= G.max_level; ++L) {
+        inject_host_alloc();
         LevelWork &W = S.levels[L];
         // 256-wide tiles (fp32 and split-bf16 only) for the level's GEMMs
         // whose padded size is a multiple of 256, in a launch of their own,
@@ -1541,7 +1548,7 @@ ScheduleSizes schedule_sizes(const Plan &plan, const std::vector<const VProgram 
 }
 
 size_t workspace_bytes(const Plan &plan, const std::vector<const VProgram *> &progs,
-                       const std::vector<int64_t> &ns, bool shared_factor) {
+                       const std::vector<int64_t> &ns, bool shared_factor, int *status) {
     std::vector<Dataset> data;
     static char fake[1 << 16];
     size_t slot = 0;
@@ -1567,12 +1574,23 @@ size_t workspace_bytes(const Plan &plan, const std::vector<const VProgram *> &pr
     const Cfg cfg = make_cfg(plan.opts.precision);
     std::string err = build_schedule(plan, progs, data, cfg, {}, worst_signs(cfg, data), nullptr, S,
                                      &st, rg);
+    if (status) *status = st;
     if (!err.empty()) {
         if (getenv("USTAT_DEBUG_DAG")) fprintf(stderr, "workspace: %s\n", err.c_str());
         return 0;
     }
     return S.arena_bytes;
 }
+
+// a device or pinned-host allocation: failure is USTAT_E_NOMEM
+#define ALLOCCHK(x)                                                            \
+    do {                                                                       \
+        hipError_t e_ = (x);                                                   \
+        if (e_ != hipSuccess) {                                                \
+            *status = 3;                                                       \
+            return std::string(#x) + ": " + hipGetErrorString(e_);             \
+        }                                                                      \
+    } while (0)
 
 #define HIPCHK(x)                                                              \
     do {                                                                       \
@@ -1630,7 +1648,7 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
                 dpre = ext->base;
                 hpre = hstage_ext.data();
             } else {
-                HIPCHK(rt.reserve_desc(cnt * 20 + 1024));
+                ALLOCCHK(rt.reserve_desc(cnt * 20 + 1024));
                 dpre = rt.ddesc;
                 hpre = rt.hdesc;
             }
@@ -1708,8 +1726,8 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
             hpre = hstage_ext.data();
             hmx = hstage_ext.data() + cnt * 16;
         } else {
-            HIPCHK(rt.reserve_desc(bytes + 1024));
-            HIPCHK(rt.reserve_hres(cnt * 8 + 64));
+            ALLOCCHK(rt.reserve_desc(bytes + 1024));
+            ALLOCCHK(rt.reserve_hres(cnt * 8 + 64));
             dpre = rt.ddesc;
             hpre = rt.hdesc;
             hmx = rt.hres;
@@ -1785,9 +1803,9 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
     if (!ext) {
         // room for the blob and, behind it, the staged input maxima (reserved
         // before any asynchronous copy reads the pinned buffer)
-        HIPCHK(rt.reserve_desc(up(S.blob_bytes, 64) + S.n_inmx * 8 + 1024));
-        HIPCHK(rt.reserve_hres(nres + 64));
-        if (range.first) HIPCHK(rt.reserve_vacc(nres + 64));
+        ALLOCCHK(rt.reserve_desc(up(S.blob_bytes, 64) + S.n_inmx * 8 + 1024));
+        ALLOCCHK(rt.reserve_hres(nres + 64));
+        if (range.first) ALLOCCHK(rt.reserve_vacc(nres + 64));
         vacc = rt.vacc;
         hres = rt.hres;
         hdesc = rt.hdesc;
@@ -1805,7 +1823,7 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
             }
             if (rt.graphs.size() >= 64) rt.drop_graphs();
             // the graph's own descriptors, uploaded once before capture
-            HIPCHK(hipMalloc((void **)&entry.blob, S.blob_bytes + 64));
+            ALLOCCHK(hipMalloc((void **)&entry.blob, S.blob_bytes + 64));
             entry.blob_bytes = S.blob_bytes + 64;
         }
         std::memcpy(hblob, S.blob.h.data(), S.blob_bytes);
@@ -1819,8 +1837,28 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
             }
         }
         hipGraph_t g = nullptr;
-        if (capture) HIPCHK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+        // Ends a capture left open when a host exception unwinds through the
+        // launch sequence (the error paths below end it themselves).
+        struct CaptureGuard {
+            hipStream_t s;
+            char **blob;
+            bool active = false;
+            ~CaptureGuard() {
+                if (!active) return;
+                hipGraph_t junk = nullptr;
+                (void)hipStreamEndCapture(s, &junk);
+                if (junk) (void)hipGraphDestroy(junk);
+                (void)hipStreamSynchronize(s);
+                if (*blob) (void)hipFree(*blob);
+                *blob = nullptr;
+            }
+        } cguard{stream, &entry.blob};
+        if (capture) {
+            HIPCHK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+            cguard.active = true;
+        }
         auto fail = [&](hipError_t e, const char *what) -> std::string {
+            cguard.active = false;
             if (capture) {
                 hipGraph_t junk = nullptr;
                 (void)hipStreamEndCapture(stream, &junk);
@@ -1833,6 +1871,7 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
             return std::string(what) + ": " + hipGetErrorString(e);
         };
         hipError_t e = hipSuccess;
+        if (inject_fire(INJ_HIP)) return fail(hipErrorLaunchFailure, "injected launch failure");
         if (pre) {
             e = pre(stream);
             if (e != hipSuccess) return fail(e, "factor build");
@@ -1937,6 +1976,7 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
         if (e != hipSuccess) return fail(e, "result copy");
         if (capture) {
             e = hipStreamEndCapture(stream, &g);
+            cguard.active = false;
             if (e != hipSuccess) {
                 (void)hipStreamSynchronize(stream);
                 (void)hipFree(entry.blob);

@@ -139,7 +139,10 @@ ScheduleSizes schedule_sizes(const Plan &plan, const std::vector<const VProgram 
                              const std::vector<Dataset> &data, const SliceRange &range = SliceRange());
 
 // Upper bound of the workspace bytes an evaluation at size n needs.
+// *status (may be null) receives the dry schedule's ustat_status code: 0,
+// or e.g. 5 when an exact intermediate's a-priori bound (from inputs of
+// magnitude up to 127) may overflow; the bytes are 0 then.
 size_t workspace_bytes(const Plan &plan, const std::vector<const VProgram *> &progs,
-                       const std::vector<int64_t> &ns, bool shared_factor);
+                       const std::vector<int64_t> &ns, bool shared_factor, int *status = nullptr);
 
 }  // namespace ustat

@@ -20,6 +20,7 @@
 
 #include "../../include/ustat.h"
 #include "costmodel.hpp"
+#include "guard.hpp"
 
 namespace ustat {
 namespace {
@@ -259,6 +260,7 @@ size_t ustat_mlp_num_params(int32_t F, int32_t H1, int32_t H2) {
 
 ustat_status ustat_mlp_predict(int32_t F, int32_t H1, int32_t H2, const float *params,
                                const float *X, int64_t N, float *out) {
+    USTAT_GUARD_BEGIN
     if (bad_sizes(F, H1, H2, N) || !params || !X || !out) {
         set_last_error("bad MLP arguments");
         return USTAT_E_INVALID;
@@ -270,11 +272,13 @@ ustat_status ustat_mlp_predict(int32_t F, int32_t H1, int32_t H2, const float *p
     if (hipMemcpy(out, D.yhat, sizeof(float) * N, hipMemcpyDeviceToHost) != hipSuccess)
         return mlp_fail("copy failed");
     return USTAT_OK;
+    USTAT_GUARD_END
 }
 
 ustat_status ustat_mlp_loss_grad(int32_t F, int32_t H1, int32_t H2, const float *params,
                                  const float *X, const float *y, int64_t N, double *loss,
                                  float *grad) {
+    USTAT_GUARD_BEGIN
     if (bad_sizes(F, H1, H2, N) || !params || !X || !y || !loss || !grad) {
         set_last_error("bad MLP arguments");
         return USTAT_E_INVALID;
@@ -287,10 +291,12 @@ ustat_status ustat_mlp_loss_grad(int32_t F, int32_t H1, int32_t H2, const float 
     if (hipMemcpy(grad, D.grad, sizeof(float) * L.total, hipMemcpyDeviceToHost) != hipSuccess)
         return mlp_fail("copy failed");
     return USTAT_OK;
+    USTAT_GUARD_END
 }
 
 ustat_status ustat_mlp_train(int32_t F, int32_t H1, int32_t H2, float *params, const float *X,
                              const float *y, int64_t N, int32_t steps, float lr, double *losses) {
+    USTAT_GUARD_BEGIN
     if (bad_sizes(F, H1, H2, N) || !params || !X || !y || steps < 1 || !(lr > 0)) {
         set_last_error("bad MLP arguments");
         return USTAT_E_INVALID;
@@ -316,9 +322,11 @@ ustat_status ustat_mlp_train(int32_t F, int32_t H1, int32_t H2, float *params, c
     if (hipMemcpy(params, D.params, sizeof(float) * L.total, hipMemcpyDeviceToHost) != hipSuccess)
         return mlp_fail("copy failed");
     return USTAT_OK;
+    USTAT_GUARD_END
 }
 
 ustat_status ustat_mlp_save(const char *path, int32_t F, int32_t H1, int32_t H2, const float *params) {
+    USTAT_GUARD_BEGIN
     if (!path || !params || F < 1 || H1 < 1 || H2 < 1) return USTAT_E_INVALID;
     Layout L(F, H1, H2);
     MLPWeights w;
@@ -340,6 +348,7 @@ ustat_status ustat_mlp_save(const char *path, int32_t F, int32_t H1, int32_t H2,
         return USTAT_E_INVALID;
     }
     return USTAT_OK;
+    USTAT_GUARD_END
 }
 
 }  // extern "C"

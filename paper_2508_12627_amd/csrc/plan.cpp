@@ -5,6 +5,8 @@
 // elimination order to kernel steps.
 #include "plan.hpp"
 
+#include "inject.hpp"
+
 #include <algorithm>
 #include <cmath>
 #include <functional>
@@ -425,6 +427,7 @@ static int sharing_penalty(const VProgram &p) {
 
 std::string build_program(const std::vector<Edge> &edges, int m, const std::vector<int> &block_of,
                           const PlanOptions &opts, const OrderScorer *scorer, VProgram &out) {
+    inject_host_alloc();
     int J = 0;
     for (int b : block_of) J = std::max(J, b + 1);
     out.block_of = block_of;
@@ -586,6 +589,7 @@ std::string build_program(const std::vector<Edge> &edges, int m, const std::vect
 
 std::string make_plan(int m, const std::vector<Edge> &edges, const PlanOptions &opts,
                       const OrderScorer *scorer, Plan &out) {
+    inject_host_alloc();
     if (m < 1 || m > kMaxM) return "m must be in 1..10";
     if (edges.empty()) return "the kernel graph needs at least one edge";
     std::vector<char> used(m, 0);

@@ -23,12 +23,18 @@ import sqlite3
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = [os.path.join(HERE, "csrc", "kernels.hip"), os.path.join(HERE, "csrc", "kernels.hpp")]
+def kernel_sources():
+    """Every device-code source of the engine: the kernel translation units
+    and the headers they include."""
+    d = os.path.join(HERE, "csrc")
+    names = sorted(f for f in os.listdir(d)
+                   if f.endswith(".hip") or f in ("kernels.hpp", "kdev.hpp") or f.endswith("_impl.hpp"))
+    return [os.path.join(d, f) for f in names if f != "mlp.hip"]
 
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
+    for p in kernel_sources():
         with open(p, "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]

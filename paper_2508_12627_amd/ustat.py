@@ -73,7 +73,7 @@ EXPORTS = ["ustat_plan_opts_default", "ustat_plan_create", "ustat_plan_destroy",
            "ustat_order_features", "vstat_eval_ordered", "ustat_mlp_num_params",
            "ustat_mlp_predict", "ustat_mlp_loss_grad", "ustat_mlp_train", "ustat_mlp_save",
            "ustat_plan_tuning", "ustat_plan_set_tuning", "ustat_plan_autotune",
-           "ustat_eval_noalloc", "ustat_status_string", "ustat_last_error"]
+           "ustat_eval_noalloc", "ustat_debug_inject", "ustat_status_string", "ustat_last_error"]
 NUM_FEATURES = 18
 
 
@@ -119,6 +119,7 @@ def load_library(path: str = LIB_PATH):
     L.ustat_plan_tuning.argtypes = [P, pi64, pi64]
     L.ustat_plan_set_tuning.argtypes = [P, i64, i64]
     L.ustat_plan_autotune.argtypes = [P, i64, ctypes.POINTER(P), P, i32, pdbl]
+    L.ustat_debug_inject.argtypes = [i32, i64]
     L.ustat_status_string.argtypes = [i32]
     L.ustat_status_string.restype = ctypes.c_char_p
     L.ustat_last_error.argtypes = []
@@ -234,6 +235,14 @@ def ustat_plan_autotune(h, n: int, factors, stream=None, reps: int = 3) -> float
     _check(load_library().ustat_plan_autotune(h, int(n), _factor_ptrs(factors),
                                               _stream_handle(stream), int(reps), ctypes.byref(ms)))
     return ms.value
+
+
+INJECT_HOST_ALLOC, INJECT_DEVICE_ALLOC, INJECT_HIP = 0, 1, 2
+
+
+def ustat_debug_inject(kind: int, countdown: int):
+    """Arm a one-shot failure for tests of the error paths (see ustat.h)."""
+    _check(load_library().ustat_debug_inject(int(kind), int(countdown)))
 
 
 def ustat_graph_treewidth(m: int, edges) -> int:
