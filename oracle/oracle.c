@@ -308,3 +308,179 @@ int oracle_num_threads(void) { return omp_get_max_threads(); }
 void oracle_set_num_threads(int t) {
     if (t >= 1) omp_set_num_threads(t);
 }
+
+/* ------------------------------------------------------------------------
+ * Induced motif counts of a simple graph (the motif application): for
+ * every connected graph on k = 3 or 4 vertices, the number of vertex
+ * subsets of size k whose induced subgraph is isomorphic to it.  Classes
+ * are told apart by edge count and degree sequence:
+ *   k = 3: out[0] two edges (V-shape), out[1] three (triangle);
+ *   k = 4: out[0] three edges, one vertex of degree 3 (3-star);
+ *          out[1] three edges, a path (degrees 2,2,1,1);
+ *          out[2] four edges, a triangle with a tail (a vertex of degree 3);
+ *          out[3] four edges, a 4-cycle (all degrees 2);
+ *          out[4] five edges (diamond); out[5] six edges (K4).
+ * ------------------------------------------------------------------------ */
+
+static int motif_class(int k, const int *deg, int edges) {
+    if (k == 3) return edges == 2 ? 0 : edges == 3 ? 1 : -1;
+    int has3 = 0;
+    for (int a = 0; a < 4; ++a) has3 |= deg[a] == 3;
+    switch (edges) {
+        case 3: return has3 ? 0 : 1;  /* connected with 3 edges: star or path */
+        case 4: return has3 ? 2 : 3;
+        case 5: return 4;
+        case 6: return 5;
+        default: return -1;
+    }
+}
+
+static int connected_small(int k, const int8_t *A, long n, const long *v) {
+    int seen = 1, changed = 1;
+    while (changed) {
+        changed = 0;
+        for (int a = 0; a < k; ++a)
+            if (seen >> a & 1)
+                for (int b = 0; b < k; ++b)
+                    if (!(seen >> b & 1) && A[v[a] * n + v[b]]) {
+                        seen |= 1 << b;
+                        changed = 1;
+                    }
+    }
+    return seen == (1 << k) - 1;
+}
+
+/* Class of the induced subgraph on the k vertices v (or -1 when it is not
+ * connected). */
+static int induced_class(int k, const int8_t *A, long n, const long *v) {
+    int deg[4] = {0, 0, 0, 0}, e = 0;
+    for (int a = 0; a < k; ++a)
+        for (int b = a + 1; b < k; ++b)
+            if (A[v[a] * n + v[b]]) {
+                ++deg[a];
+                ++deg[b];
+                ++e;
+            }
+    if (!connected_small(k, A, n, v)) return -1;
+    return motif_class(k, deg, e);
+}
+
+/* Brute force over all k-subsets i < j < l (< q); O(n^k / k!). */
+int oracle_motifs_bruteforce(long n, const int8_t *A, int k, int64_t *out) {
+    if (n < 1 || !A || !out || (k != 3 && k != 4)) return -1;
+    const int ncls = k == 3 ? 2 : 6;
+    int64_t tot[6] = {0, 0, 0, 0, 0, 0};
+#pragma omp parallel
+    {
+        int64_t loc[6] = {0, 0, 0, 0, 0, 0};
+#pragma omp for schedule(dynamic, 1)
+        for (long i = 0; i < n; ++i)
+            for (long j = i + 1; j < n; ++j)
+                for (long l = j + 1; l < n; ++l) {
+                    if (k == 3) {
+                        const long v[4] = {i, j, l, 0};
+                        int c = induced_class(3, A, n, v);
+                        if (c >= 0) ++loc[c];
+                        continue;
+                    }
+                    for (long q = l + 1; q < n; ++q) {
+                        const long v[4] = {i, j, l, q};
+                        int c = induced_class(4, A, n, v);
+                        if (c >= 0) ++loc[c];
+                    }
+                }
+#pragma omp critical
+        for (int c = 0; c < 6; ++c) tot[c] += loc[c];
+    }
+    for (int c = 0; c < ncls; ++c) out[c] = tot[c];
+    return 0;
+}
+
+/* Enumeration of the connected induced k-subgraphs of a sparse graph (CSR),
+ * each exactly once, by the extension rule of Wernicke's ESU algorithm:
+ * grow a set from its smallest vertex v, adding candidates that are larger
+ * than v and adjacent to the set, where a vertex becomes a candidate only
+ * through the first set member it is adjacent to (its exclusive
+ * neighbourhood). */
+typedef struct {
+    long n;
+    const int64_t *rp;
+    const int32_t *col;
+    int k;
+    int64_t cnt[6];
+} esu_t;
+
+static int adj_csr(const esu_t *g, long a, long b) {
+    long lo = g->rp[a], hi = g->rp[a + 1];
+    while (lo < hi) { /* columns are sorted */
+        long mid = (lo + hi) / 2;
+        if (g->col[mid] < b) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo < g->rp[a + 1] && g->col[lo] == b;
+}
+
+static void esu_extend(esu_t *g, long *sub, int ns, long *ext, int ne, long v) {
+    if (ns == g->k) {
+        int deg[4] = {0, 0, 0, 0}, e = 0;
+        for (int a = 0; a < ns; ++a)
+            for (int b = a + 1; b < ns; ++b)
+                if (adj_csr(g, sub[a], sub[b])) {
+                    ++deg[a];
+                    ++deg[b];
+                    ++e;
+                }
+        int c = motif_class(g->k, deg, e);
+        if (c >= 0) ++g->cnt[c];
+        return;
+    }
+    /* candidates are consumed one at a time, as the rule prescribes */
+    long *cand = malloc(sizeof(long) * (size_t)(ne + 1));
+    int nc = ne;
+    for (int i = 0; i < ne; ++i) cand[i] = ext[i];
+    while (nc > 0) {
+        long w = cand[--nc];
+        /* new extension: the remaining candidates plus w's exclusive
+         * neighbours larger than v */
+        long cap = nc + (g->rp[w + 1] - g->rp[w]);
+        long *next = malloc(sizeof(long) * (size_t)(cap + 1));
+        int nn = 0;
+        for (int i = 0; i < nc; ++i) next[nn++] = cand[i];
+        for (long p = g->rp[w]; p < g->rp[w + 1]; ++p) {
+            long u = g->col[p];
+            if (u <= v) continue;
+            int bad = 0;
+            for (int a = 0; a < ns && !bad; ++a) bad = u == sub[a] || adj_csr(g, u, sub[a]);
+            for (int i = 0; i < nc && !bad; ++i) bad = u == cand[i];
+            if (!bad) next[nn++] = u;
+        }
+        sub[ns] = w;
+        esu_extend(g, sub, ns + 1, next, nn, v);
+        free(next);
+    }
+    free(cand);
+}
+
+int oracle_motifs_esu(long n, const int64_t *rowptr, const int32_t *col, int k, int64_t *out) {
+    if (n < 1 || !rowptr || !col || !out || (k != 3 && k != 4)) return -1;
+    int64_t tot[6] = {0, 0, 0, 0, 0, 0};
+#pragma omp parallel
+    {
+        esu_t g = {n, rowptr, col, k, {0, 0, 0, 0, 0, 0}};
+#pragma omp for schedule(dynamic, 16)
+        for (long v = 0; v < n; ++v) {
+            long sub[4] = {v, 0, 0, 0};
+            long deg = rowptr[v + 1] - rowptr[v];
+            long *ext = malloc(sizeof(long) * (size_t)(deg + 1));
+            int ne = 0;
+            for (long p = rowptr[v]; p < rowptr[v + 1]; ++p)
+                if (col[p] > v) ext[ne++] = col[p];
+            esu_extend(&g, sub, 1, ext, ne, v);
+            free(ext);
+        }
+#pragma omp critical
+        for (int c = 0; c < 6; ++c) tot[c] += g.cnt[c];
+    }
+    for (int c = 0; c < (k == 3 ? 2 : 6); ++c) out[c] = tot[c];
+    return 0;
+}

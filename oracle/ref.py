@@ -366,3 +366,43 @@ def tuple_pattern_sums(edges: Edges, mats) -> dict:
             val = val * mats[k][tup[u], tup[v]]
         out[tuple(lab)] = out.get(tuple(lab), 0) + val
     return out
+
+
+# --------------------------------------------------------------------------
+# Induced motif counts (the motif application), independent of the
+# U-statistic decomposition: brute force over vertex subsets, and an
+# enumeration of connected induced subgraphs for sparse graphs.
+# --------------------------------------------------------------------------
+
+MOTIFS3 = ["v-shape", "triangle"]
+MOTIFS4 = ["3-star", "path", "tailed-triangle", "square", "diamond", "k4"]
+
+
+def motifs_bruteforce(A, k: int) -> list:
+    """Induced counts of the connected k-vertex motifs (k = 3: V-shape,
+    triangle; k = 4: 3-star, path, tailed triangle, square, diamond, K4)
+    by testing every k-subset of vertices."""
+    A = np.ascontiguousarray(np.asarray(A) != 0, dtype=np.int8)
+    n = A.shape[0]
+    out = (ctypes.c_int64 * 6)()
+    lib = _lib()
+    lib.oracle_motifs_bruteforce.argtypes = [ctypes.c_long, ctypes.c_void_p, ctypes.c_int,
+                                             ctypes.POINTER(ctypes.c_int64)]
+    rc = lib.oracle_motifs_bruteforce(n, A.ctypes.data, int(k), out)
+    if rc != 0:
+        raise ValueError("oracle_motifs_bruteforce: bad arguments")
+    return [int(x) for x in list(out)[: (2 if k == 3 else 6)]]
+
+
+def motifs_esu(A, k: int) -> list:
+    """The same counts by enumerating each connected induced k-subgraph
+    once (suited to large sparse graphs)."""
+    n, rowptr, col = _csr(A)
+    out = (ctypes.c_int64 * 6)()
+    lib = _lib()
+    lib.oracle_motifs_esu.argtypes = [ctypes.c_long, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                      ctypes.POINTER(ctypes.c_int64)]
+    rc = lib.oracle_motifs_esu(n, rowptr.ctypes.data, col.ctypes.data, int(k), out)
+    if rc != 0:
+        raise ValueError("oracle_motifs_esu: bad arguments")
+    return [int(x) for x in list(out)[: (2 if k == 3 else 6)]]
