@@ -371,6 +371,30 @@ ustat_status ustat_mlp_save(const char *path, int32_t F, int32_t H1, int32_t H2,
                             const float *params);
 
 /*
+ * Induced motif counts of a simple graph (the motif application of Section
+ * 4.2 and its appendix): for each connected motif r on `size` vertices,
+ * the number of vertex subsets inducing r equals U(h_r) / |Aut(r)|, where
+ * h_r is the kernel over the complete graph on `size` vertices with factor
+ * A on the motif's edges and B = 1 - A on its non-edges.  Every pair is an
+ * edge of that kernel graph, so with Lemma 3 only the finest partition
+ * remains; its quotient for size 4 (K4) has treewidth 3 and is evaluated
+ * by conditioning on one vertex.
+ *
+ * ustat_plan_create_motifs plans the motifs of size 3 (V-shape, triangle)
+ * or 4 (3-star, path, tailed triangle, square, diamond, K4) on the exact
+ * path (the precision and sparsify options are ignored: USTAT_I8, Lemma
+ * 3); the plan queries (ustat_plan_info, ...) describe the first motif.
+ * ustat_motif_counts evaluates every motif of the plan in one pass, steps
+ * equal across motifs (products of A and B) computed once: A is a device
+ * int8 n x n symmetric 0/1 adjacency with a zero diagonal (else
+ * USTAT_E_INVALID, checked on the device), counts a host int64 array of 2
+ * (size 3) or 6 (size 4) entries, in the order above.
+ */
+ustat_status ustat_plan_create_motifs(int32_t size, const ustat_plan_opts *opts, ustat_plan *out);
+ustat_status ustat_motif_counts(ustat_plan plan, int64_t n, const int8_t *A, ustat_stream stream,
+                                int64_t *counts);
+
+/*
  * For tests of the error paths (not for production callers): arm a
  * one-shot failure.  kind 0: the (countdown + 1)-th host allocation point
  * of the planner or executor fails (the call returns USTAT_E_NOMEM);

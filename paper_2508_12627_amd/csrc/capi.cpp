@@ -35,6 +35,11 @@ struct ustat_plan_s {
     // device buffer holding factor matrices built from samples
     char *factors = nullptr;
     size_t factors_bytes = 0;
+    // motif plans (ustat_plan_create_motifs): one kernel per motif, and the
+    // automorphism count that turns its U-statistic into the motif count
+    std::vector<Plan> motifs;
+    std::vector<int64_t> motif_aut;
+    int motif_size = 0;
     ~ustat_plan_s() {
         if (factors) (void)hipFree(factors);
     }
@@ -808,6 +813,115 @@ ustat_status ustat_profile_read(int32_t kind, double *ms, int64_t *launches, dou
     if (launches) *launches = p->launches[kind];
     if (flops) *flops = p->flops[kind];
     if (bytes) *bytes = p->bytes[kind];
+    return ok();
+    USTAT_GUARD_END
+}
+
+}  // extern "C"
+
+namespace {
+
+// The motif kernels of the motif application: the complete graph on 3 or 4
+// vertices, with factor A (an edge of the motif) or B = 1 - A (a non-edge)
+// on every vertex pair, and the motif's automorphism count.  Order: V-shape,
+// triangle; 3-star, path, tailed triangle, square, diamond, K4.
+struct MotifKernel {
+    std::vector<int> on_a;  // per pair: 1 reads A, 0 reads B
+    int64_t aut;
+};
+
+const std::vector<Edge> &motif_pairs(int size) {
+    static const std::vector<Edge> p3 = {{0, 1}, {1, 2}, {2, 0}};
+    static const std::vector<Edge> p4 = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+    return size == 3 ? p3 : p4;
+}
+
+const std::vector<MotifKernel> &motif_kernels(int size) {
+    static const std::vector<MotifKernel> m3 = {{{1, 1, 0}, 2}, {{1, 1, 1}, 6}};
+    static const std::vector<MotifKernel> m4 = {{{1, 1, 1, 0, 0, 0}, 6}, {{1, 0, 0, 1, 0, 1}, 2},
+                                                {{1, 1, 0, 1, 0, 1}, 2}, {{1, 0, 1, 1, 0, 1}, 8},
+                                                {{1, 1, 1, 1, 1, 0}, 4}, {{1, 1, 1, 1, 1, 1}, 24}};
+    return size == 3 ? m3 : m4;
+}
+
+}  // namespace
+
+extern "C" {
+
+ustat_status ustat_plan_create_motifs(int32_t size, const ustat_plan_opts *opts, ustat_plan *out) {
+    USTAT_GUARD_BEGIN
+    if (!out) return fail(USTAT_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (size != 3 && size != 4) return fail(USTAT_E_INVALID, "motif size must be 3 or 4");
+    ustat_plan_opts o;
+    ustat_plan_opts_default(&o);
+    if (opts) o = *opts;
+    if (o.order < 0 || o.order > 1) return fail(USTAT_E_INVALID, "order policy must be min-fill or exhaustive");
+    if (o.flags & ~(USTAT_FLAG_NO_CSE | USTAT_FLAG_SYMMETRIC))
+        return fail(USTAT_E_INVALID, "unknown flag bits");
+    std::unique_ptr<ustat_plan_s> p(new ustat_plan_s());
+    PlanOptions po;
+    po.precision = USTAT_I8;  // exact counts
+    po.order = o.order;
+    po.sparsify = 1;          // Lemma 3: only the finest partition of a complete graph survives
+    po.workspace_limit = o.workspace_limit;
+    if (o.n_hint < 0 || o.n_hint > (1ll << 20)) return fail(USTAT_E_INVALID, "n_hint out of range");
+    if (o.n_hint > 0) po.n_hint = (double)o.n_hint;
+    po.cse = !(o.flags & USTAT_FLAG_NO_CSE);
+    po.symmetric = true;      // A and B are symmetric
+    for (const MotifKernel &mo : motif_kernels(size)) {
+        Plan pl;
+        std::string err = make_plan(size, motif_pairs(size), po, nullptr, pl);
+        if (!err.empty()) return fail(USTAT_E_INVALID, err);
+        p->motifs.push_back(std::move(pl));
+        p->motif_aut.push_back(mo.aut);
+    }
+    p->motif_size = size;
+    p->plan = p->motifs[0];
+    for (auto &pr : p->plan.progs) p->all.push_back(&pr);
+    *out = p.release();
+    return ok();
+    USTAT_GUARD_END
+}
+
+ustat_status ustat_motif_counts(ustat_plan plan, int64_t n, const int8_t *A, ustat_stream stream,
+                                int64_t *counts) {
+    USTAT_GUARD_BEGIN
+    if (!plan || !plan->motif_size) return fail(USTAT_E_INVALID, "not a motif plan");
+    if (!A || !counts) return fail(USTAT_E_INVALID, "A and counts must be non-NULL");
+    if (n < plan->motif_size || n > (1ll << 20)) return fail(USTAT_E_INVALID, "n out of range");
+    const int size = plan->motif_size;
+    hipStream_t s = (hipStream_t)stream;
+    // B = 1 - A off the diagonal (0 on it), and a check that A is a
+    // symmetric 0/1 matrix with a zero diagonal
+    hipError_t e = grow(&plan->factors, &plan->factors_bytes, (size_t)n * n + 256, &plan->rt);
+    if (e != hipSuccess) return fail(USTAT_E_NOMEM, hipGetErrorString(e));
+    int8_t *B = reinterpret_cast<int8_t *>(plan->factors);
+    unsigned int bad = 0;
+    e = launch_motif_complement(A, B, n, reinterpret_cast<unsigned int *>(plan->factors + (size_t)n * n), &bad, s);
+    if (e != hipSuccess) return fail(USTAT_E_HIP, hipGetErrorString(e));
+    if (bad) return fail(USTAT_E_INVALID, "A is not a symmetric 0/1 adjacency with a zero diagonal");
+    // one dataset per motif, all reading A and B: equal steps of different
+    // motifs are computed once
+    const std::vector<MotifKernel> &kern = motif_kernels(size);
+    std::vector<Dataset> data(plan->motifs.size());
+    std::vector<std::vector<const VProgram *>> progs(plan->motifs.size());
+    for (size_t r = 0; r < plan->motifs.size(); ++r) {
+        data[r].n = n;
+        data[r].symmetric = true;
+        data[r].nonneg = true;
+        for (int a : kern[r].on_a) data[r].factors.push_back(a ? (const void *)A : (const void *)B);
+        for (auto &pr : plan->motifs[r].progs) data[r].progs.push_back(&pr);
+    }
+    std::vector<DatasetResult> res;
+    ustat_status st = run(plan, plan->all, data, s, res, nullptr, nullptr, "");
+    if (st != USTAT_OK) return st;
+    for (size_t r = 0; r < res.size(); ++r) {
+        const __int128 u = ((__int128)res[r].exact_hi << 64) | (__int128)res[r].exact_lo;
+        const int64_t aut = plan->motif_aut[r];
+        if (u < 0 || u % aut != 0) return fail(USTAT_E_HIP, "motif sum not divisible by its automorphisms");
+        counts[r] = (int64_t)(u / aut);
+    }
     return ok();
     USTAT_GUARD_END
 }

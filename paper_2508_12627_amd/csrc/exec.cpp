@@ -493,8 +493,11 @@ void clone_slices(Dag &G, const std::vector<Inst> &insts) {
 
 std::string build_dag(const Plan &plan, const std::vector<const VProgram *> &progs,
                       const std::vector<Dataset> &data, bool cse, const SliceRange &range, Dag &G) {
-    const int nd = (int)data.size(), np = (int)progs.size();
-    G.prog_terms.assign((size_t)nd * np, {});
+    const int nd = (int)data.size();
+    // programs of dataset d are numbered poff[d] .. poff[d + 1] - 1
+    std::vector<int> poff(nd + 1, 0);
+    for (int d = 0; d < nd; ++d) poff[d + 1] = poff[d] + (int)progs_of(progs, data[d]).size();
+    G.prog_terms.assign((size_t)poff[nd], {});
     struct Pending {
         int dp, term, pos;
         int64_t n;
@@ -524,13 +527,15 @@ std::string build_dag(const Plan &plan, const std::vector<const VProgram *> &pro
         inject_host_alloc();
         const int64_t n = data[d].n;
         const bool sym = data[d].symmetric;
+        const std::vector<const VProgram *> &dprogs = progs_of(progs, data[d]);
+        const int np = (int)dprogs.size();
         for (int p = 0; p < np; ++p) {
-          const VProgram &pr = *progs[p];
+          const VProgram &pr = *dprogs[p];
           const bool sliced = pr.slice_var >= 0;
           if (!sliced && !range.include_unsliced) continue;
           const int64_t s_lo = sliced ? std::max<int64_t>(0, range.lo) : -1;
           const int64_t s_hi = sliced ? std::min<int64_t>(n, range.hi) : 0;
-          if (sliced && s_hi - s_lo > 1) sliced_insts.push_back({d * np + p, d, s_hi - s_lo - 1});
+          if (sliced && s_hi - s_lo > 1) sliced_insts.push_back({poff[d] + p, d, s_hi - s_lo - 1});
           for (int64_t slice = s_lo; slice < std::min(s_hi, s_lo + 1); ++slice) {
             std::vector<Ref> ref(pr.vals.size());
             for (size_t v = 0; v < pr.vals.size(); ++v) {
@@ -566,7 +571,7 @@ std::string build_dag(const Plan &plan, const std::vector<const VProgram *> &pro
                 return MOp{r.node, r.p, (bool)(o.trans ^ r.flip)};
             };
             auto vop = [&](int v) { return VOp{ref[v].node, ref[v].p, ref[v].off}; };
-            const int dp = d * np + p;
+            const int dp = poff[d] + p;
             std::vector<int> term;
             for (const Step &st : pr.steps) {
                 std::vector<MOp> A, B, Z;
@@ -904,10 +909,11 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
                            const SliceRange &range = SliceRange()) {
     S = Schedule();
     Arena A;
-    const int ne = (int)plan.edges.size();
     const int nd = (int)data.size();
-    const int np = (int)progs.size();
-    S.nprog_total = nd * np;
+    const int ne = nd ? (int)data[0].factors.size() : 0;  // factors per dataset (equal for all)
+    std::vector<int> poff(nd + 1, 0);
+    for (int d = 0; d < nd; ++d) poff[d + 1] = poff[d] + (int)progs_of(progs, data[d]).size();
+    S.nprog_total = poff[nd];
     auto P = [&](size_t off) -> void * { return base ? (void *)(base + off) : nullptr; };
     Dag G;
     std::string err = build_dag(plan, progs, data, plan.opts.cse, range, G);
@@ -1406,11 +1412,13 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
     // combine tables: programs -> terms -> scalar slots
     for (int d = 0; d < nd; ++d) {
         CombineDesc c;
-        c.p_begin = d * np;
-        c.p_end = (d + 1) * np;
+        const std::vector<const VProgram *> &dprogs = progs_of(progs, data[d]);
+        const int np = (int)dprogs.size();
+        c.p_begin = poff[d];
+        c.p_end = poff[d + 1];
         S.comb.push_back(c);
         for (int p = 0; p < np; ++p) {
-            const auto &terms = G.prog_terms[d * np + p];
+            const auto &terms = G.prog_terms[poff[d] + p];
             S.term_off.push_back((int32_t)S.scal_off.size());
             S.term_cnt.push_back((int32_t)terms.size());
             double bsum = 0;
@@ -1424,10 +1432,10 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
                 }
                 bsum += b;
             }
-            if (progs[p]->slice_var >= 0 && !terms.empty())
+            if (dprogs[p]->slice_var >= 0 && !terms.empty())
                 bsum *= (double)data[d].n / (double)terms.size();  // all slices, every chunk
-            S.mu.push_back(progs[p]->mu);
-            if (is_int && bsum * std::fabs((double)progs[p]->mu) * np > kOverflowWide) {
+            S.mu.push_back(dprogs[p]->mu);
+            if (is_int && bsum * std::fabs((double)dprogs[p]->mu) * np > kOverflowWide) {
                 *status = 5;
                 return "the combined U-statistic may exceed the 127-bit range";
             }
@@ -1613,7 +1621,7 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
     // host staging of the external-memory mode (ordinary host memory; every
     // copy through it completes before this function returns)
     std::vector<char> hstage_ext, hres_ext;
-    const int ne = (int)plan.edges.size();
+    const int ne = data.empty() ? 0 : (int)data[0].factors.size();
     // Split-bf16: which inputs may hold negative entries (one device scan of
     // the factors not known to be non-negative, read back once); the choice
     // of contraction scheme depends on it, so it is part of the graph key.
@@ -2032,6 +2040,8 @@ std::string execute_all(const Plan &plan, const std::vector<const VProgram *> &p
                         const std::function<hipError_t(hipStream_t)> &pre, const ExtMem *ext) {
     bool sliced = false;
     for (const VProgram *p : progs) sliced = sliced || p->slice_var >= 0;
+    for (const Dataset &d : data)
+        for (const VProgram *p : d.progs) sliced = sliced || p->slice_var >= 0;
     if (!sliced)
         return execute(plan, progs, data, stream, rt, out, vout, status, capture, capture_key, pre,
                        SliceRange(), ext);

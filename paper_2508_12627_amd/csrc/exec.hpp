@@ -27,7 +27,18 @@ struct Dataset {
     // factor; GEMM operands that are that factor alone then need no prep
     const void *operand = nullptr;
     int operand_format = -1;
+    // programs of this dataset when non-empty (their input values index
+    // `factors`), otherwise the programs the evaluation is called with;
+    // datasets with their own programs let one evaluation serve several
+    // kernels on shared inputs, with equal steps merged across them
+    std::vector<const VProgram *> progs;
 };
+
+// The programs dataset d evaluates.
+inline const std::vector<const VProgram *> &progs_of(const std::vector<const VProgram *> &progs,
+                                                      const Dataset &d) {
+    return d.progs.empty() ? progs : d.progs;
+}
 
 // Prep format in which a GEMM of the plan reads the shared factor of a
 // dataset of size n on its own (no vectors, no other matrices), or -1 when

@@ -204,6 +204,48 @@ __global__ __launch_bounds__(256) void k_signscan(const void *const *src, const 
     if (__any(neg) && (threadIdx.x & 63) == 0) atomicOr(&flag[p], 1u);
 }
 
+// Complement of a simple graph's adjacency for motif kernels: B = 1 - A off
+// the diagonal, 0 on it, in 64 x 64 tiles; the tile and its mirror go
+// through LDS so that *bad is set (once per wave) when A is not a symmetric
+// 0/1 matrix with a zero diagonal.
+__global__ __launch_bounds__(256) void k_motif_complement(const int8_t *__restrict__ A,
+                                                          int8_t *__restrict__ B, int64_t n,
+                                                          unsigned int *bad) {
+    __shared__ int8_t ta[64][65], tb[64][65];
+    const int64_t i0 = (int64_t)blockIdx.y * 64, j0 = (int64_t)blockIdx.x * 64;
+    const int t = threadIdx.x;
+    for (int e = t; e < 4096; e += 256) {
+        const int r = e >> 6, c = e & 63;
+        const int64_t i = i0 + r, j = j0 + c;
+        ta[r][c] = (i < n && j < n) ? A[i * n + j] : (int8_t)0;
+        const int64_t i2 = j0 + r, j2 = i0 + c;  // the mirror tile, row-major
+        tb[r][c] = (i2 < n && j2 < n) ? A[i2 * n + j2] : (int8_t)0;
+    }
+    __syncthreads();
+    bool wrong = false;
+    for (int e = t; e < 4096; e += 256) {
+        const int r = e >> 6, c = e & 63;
+        const int64_t i = i0 + r, j = j0 + c;
+        if (i >= n || j >= n) continue;
+        const int a = ta[r][c], at = tb[c][r];
+        wrong = wrong || (a != 0 && a != 1) || a != at || (i == j && a != 0);
+        B[i * n + j] = (int8_t)(i == j ? 0 : 1 - a);
+    }
+    if (__any(wrong) && (t & 63) == 0) atomicOr(bad, 1u);
+}
+
+hipError_t launch_motif_complement(const int8_t *A, int8_t *B, int64_t n, unsigned int *dbad,
+                                   unsigned int *hbad, hipStream_t s) {
+    hipError_t e = hipMemsetAsync(dbad, 0, sizeof(unsigned int), s);
+    if (e != hipSuccess) return e;
+    const unsigned T = (unsigned)((n + 63) / 64);
+    hipLaunchKernelGGL(k_motif_complement, dim3(T, T), dim3(256), 0, s, A, B, n, dbad);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(hbad, dbad, sizeof(unsigned int), hipMemcpyDeviceToHost, s)) != hipSuccess)
+        return e;
+    return hipStreamSynchronize(s);
+}
+
 // Largest |entry| of int8 matrices (one running max per problem).
 __global__ void k_absmax_i8(const int8_t *const *src, const int64_t *n, int nprob,
                             unsigned long long *mx) {

@@ -237,6 +237,11 @@ hipError_t launch_gemm(const GemmDesc *d, int nprob, int64_t total_tiles, int pr
 // negative (or NaN) entry, else 0; the flags must be zero on entry.
 hipError_t launch_signscan(const void *const *src, const int64_t *n, int nprob, int f32,
                            unsigned int *flag, hipStream_t s);
+// B = 1 - A off the diagonal and 0 on it (n x n int8); *hbad (host)
+// receives nonzero when A is not a symmetric 0/1 matrix with a zero
+// diagonal; dbad is device scratch.  Synchronises s.
+hipError_t launch_motif_complement(const int8_t *A, int8_t *B, int64_t n, unsigned int *dbad,
+                                   unsigned int *hbad, hipStream_t s);
 hipError_t launch_absmax_i8(const int8_t *const *src, const int64_t *n, int nprob,
                             unsigned long long *mx, hipStream_t s);
 hipError_t launch_slicesrc(const SliceDesc *d, int nprob, int64_t total_tiles, int domain,

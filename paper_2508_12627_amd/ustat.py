@@ -73,7 +73,8 @@ EXPORTS = ["ustat_plan_opts_default", "ustat_plan_create", "ustat_plan_destroy",
            "ustat_order_features", "vstat_eval_ordered", "ustat_mlp_num_params",
            "ustat_mlp_predict", "ustat_mlp_loss_grad", "ustat_mlp_train", "ustat_mlp_save",
            "ustat_plan_tuning", "ustat_plan_set_tuning", "ustat_plan_autotune",
-           "ustat_eval_noalloc", "ustat_debug_inject", "ustat_status_string", "ustat_last_error"]
+           "ustat_eval_noalloc", "ustat_debug_inject", "ustat_plan_create_motifs",
+           "ustat_motif_counts", "ustat_status_string", "ustat_last_error"]
 NUM_FEATURES = 18
 
 
@@ -120,6 +121,8 @@ def load_library(path: str = LIB_PATH):
     L.ustat_plan_set_tuning.argtypes = [P, i64, i64]
     L.ustat_plan_autotune.argtypes = [P, i64, ctypes.POINTER(P), P, i32, pdbl]
     L.ustat_debug_inject.argtypes = [i32, i64]
+    L.ustat_plan_create_motifs.argtypes = [i32, ctypes.POINTER(PlanOpts), ctypes.POINTER(P)]
+    L.ustat_motif_counts.argtypes = [P, i64, P, P, pi64]
     L.ustat_status_string.argtypes = [i32]
     L.ustat_status_string.restype = ctypes.c_char_p
     L.ustat_last_error.argtypes = []
@@ -235,6 +238,50 @@ def ustat_plan_autotune(h, n: int, factors, stream=None, reps: int = 3) -> float
     _check(load_library().ustat_plan_autotune(h, int(n), _factor_ptrs(factors),
                                               _stream_handle(stream), int(reps), ctypes.byref(ms)))
     return ms.value
+
+
+MOTIFS = {3: ["v-shape", "triangle"],
+          4: ["3-star", "path", "tailed-triangle", "square", "diamond", "k4"]}
+
+
+def ustat_plan_create_motifs(size: int, order="minfill", cse: bool = True,
+                             workspace_limit: int = 0):
+    L = load_library()
+    o = PlanOpts()
+    _check(L.ustat_plan_opts_default(ctypes.byref(o)))
+    o.order = ORDERS[order] if isinstance(order, str) else int(order)
+    o.flags = 0 if cse else FLAG_NO_CSE
+    o.workspace_limit = int(workspace_limit)
+    h = ctypes.c_void_p()
+    _check(L.ustat_plan_create_motifs(int(size), ctypes.byref(o), ctypes.byref(h)))
+    return h
+
+
+def ustat_motif_counts(h, A: torch.Tensor, size: int, stream=None) -> List[int]:
+    assert A.dtype == torch.int8 and A.is_cuda and A.is_contiguous() and A.dim() == 2
+    k = len(MOTIFS[size])
+    out = (ctypes.c_int64 * k)()
+    _check(load_library().ustat_motif_counts(h, A.shape[0], ctypes.c_void_p(A.data_ptr()),
+                                             _stream_handle(stream), out))
+    return [int(x) for x in out]
+
+
+class MotifPlan:
+    """Owning wrapper of a motif plan (ustat_plan_create_motifs)."""
+
+    def __init__(self, size: int, order="minfill", cse: bool = True, workspace_limit: int = 0):
+        self.size = int(size)
+        self.names = MOTIFS[self.size]
+        self.h = ustat_plan_create_motifs(size, order, cse, workspace_limit)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h and _lib is not None:
+            _lib.ustat_plan_destroy(h)
+            self.h = None
+
+    def counts(self, A, stream=None) -> List[int]:
+        return ustat_motif_counts(self.h, A, self.size, stream)
 
 
 INJECT_HOST_ALLOC, INJECT_DEVICE_ALLOC, INJECT_HIP = 0, 1, 2
