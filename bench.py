@@ -235,6 +235,57 @@ def bench_cycle5_exact(args):
     print(json.dumps(out))
 
 
+def bench_motifs(args):
+    """Induced motif counts of Erdos-Renyi graphs on the exact path at the
+    sizes of the paper's motif tables: all 3-vertex motifs of G(20000, p)
+    and all 4-vertex motifs of G(2000, p), p = 0.01 (seed 3); one
+    evaluation counts every motif of a size (steps shared across motifs).
+    The oracle (enumeration of connected induced subgraphs) is timed on the
+    host cores beside it and must agree exactly."""
+    import torch
+    import oracle
+    from paper_2508_12627_amd import ustat as U, workloads as W
+    out = {"metric": "induced motif counts, seconds per graph (all motifs of a size)",
+           "unit": "s", "higher_is_better": False,
+           "config": {"workload": "G(20000, 0.01) 3-vertex motifs; G(2000, 0.01) 4-vertex motifs; "
+                                  "seed 3; complete-graph kernels with A and 1 - A factors"}}
+    for size, n, p in ((3, 20000, 0.01), (4, 2000, 0.01)):
+        print(f"motifs: size {size}, G({n}, {p})", file=sys.stderr, flush=True)
+        A = W.erdos_renyi(n, p, seed=3)
+        Ad = torch.tensor(A, dtype=torch.int8, device="cuda")
+        plan = U.MotifPlan(size)
+        got = plan.counts(Ad)
+        torch.cuda.synchronize()
+        steps = max(2, args.steps // 40)
+        U.ustat_profile_enable(True)
+        U.ustat_profile_reset()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            got = plan.counts(Ad)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / steps
+        g = U.ustat_profile_read("gemm")
+        U.ustat_profile_enable(False)
+        rec = {"n": n, "p": p, "seconds": el, "counts": dict(zip(plan.names, got)),
+               "gemm": {"ms_per_eval": g["ms"] / steps, "launches_per_eval": g["launches"] / steps,
+                        "int8_tops_algorithmic": g["flops"] / (g["ms"] * 1e-3) / 1e12 if g["ms"] else None}}
+        print(f"  {el:.4f} s per evaluation; oracle...", file=sys.stderr, flush=True)
+        if not args.no_cpu_baseline:
+            t1 = time.perf_counter()
+            if size == 3:
+                ref = oracle.motifs3_closed_form(A)
+                how = "whole graph (degrees and the trace formula for triangles)"
+            else:
+                ref = oracle.motifs_esu(A, size)
+                how = "whole graph (enumeration of connected induced subgraphs)"
+            rec["cpu_baseline"] = {"seconds": time.perf_counter() - t1, "cores": oracle.num_threads(),
+                                   "kind": "oracle", "cpu_model": cpu_model(), "sample": how}
+            rec["exact_match"] = ref == got
+        out[f"size{size}"] = rec
+    out["value"] = out["size4"]["seconds"]
+    print(json.dumps(out))
+
+
 def bench_learned_order(args):
     """Learned order choice, end to end.  64 random kernel graphs on 6
     vertices (6-10 edges, seed 5, draws with an isolated vertex rejected);
@@ -300,7 +351,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--workload", default="cycle4",
-                    choices=["cycle4", "batched", "cycle5-exact", "learned-order"],
+                    choices=["cycle4", "batched", "cycle5-exact", "learned-order", "motifs"],
                     help="cycle4: the headline line; the others print their own line")
     ap.add_argument("--graph-range", default="0:64",
                     help="learned-order workload: graphs lo:hi of the 64")
@@ -337,6 +388,8 @@ def main():
         return bench_cycle5_exact(args)
     if args.workload == "learned-order":
         return bench_learned_order(args)
+    if args.workload == "motifs":
+        return bench_motifs(args)
     m, edges, n, d = WORKLOAD["m"], WORKLOAD["edges"], WORKLOAD["n"], WORKLOAD["d"]
     div = 2.0 * d
     Xh = W.gaussian_samples(n, d, seed=WORKLOAD["seed"])

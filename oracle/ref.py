@@ -406,3 +406,14 @@ def motifs_esu(A, k: int) -> list:
     if rc != 0:
         raise ValueError("oracle_motifs_esu: bad arguments")
     return [int(x) for x in list(out)[: (2 if k == 3 else 6)]]
+
+
+def motifs3_closed_form(A) -> list:
+    """Induced 3-vertex motif counts from degrees and the trace formula:
+    triangles T = tr(A^3) / 6, and V-shapes = sum_i C(deg_i, 2) - 3 T (every
+    path of length two is an induced V-shape unless its ends are adjacent,
+    which happens three times per triangle)."""
+    A = np.asarray(A)
+    deg = np.count_nonzero(A, axis=1).astype(np.int64)
+    T = count_triangles(A)
+    return [int(np.sum(deg * (deg - 1) // 2)) - 3 * T, T]

@@ -81,3 +81,9 @@ def test_bruteforce_and_enumeration_agree(n, p, seed):
 def test_triangles_match_trace_formula():
     A = W.erdos_renyi(200, 0.1, seed=5)
     assert oracle.motifs_bruteforce(A, 3)[1] == oracle.count_triangles(A.astype(np.int64))
+
+
+@pytest.mark.parametrize("n,p,seed", [(60, 0.2, 7), (150, 0.05, 8)])
+def test_closed_form_3_motifs(n, p, seed):
+    A = W.erdos_renyi(n, p, seed=seed)
+    assert oracle.motifs3_closed_form(A) == oracle.motifs_bruteforce(A, 3)
