@@ -8,6 +8,10 @@
         HBM bytes per launch of the kernels whose name contains NAME, from
         FETCH_SIZE and WRITE_SIZE runs, each scaled by what the same counter
         reads for a plain device copy of B bytes (the calibration runs)
+    python -m paper_2508_12627_amd.profsum mfma RESULTS.db [--md OUT.md ...]
+        per-kernel MFMA busy fraction, SQ_VALU_MFMA_BUSY_CYCLES over
+        (GRBM_GUI_ACTIVE / 8 XCDs) x 1024 SIMDs, and the LDS bank-conflict
+        rate SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE (a --pmc run)
 
 The traffic record carries a hash of the kernel sources, so a reader can
 tell whether the counters still describe the current kernels.
@@ -23,13 +27,18 @@ import sqlite3
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
+# Device code outside the dense evaluation path that traffic records cover:
+# the cost-model network and the low-rank path (which has its own records).
+_OTHER_PATHS = ("mlp.hip", "k_lowrank.hip")
+
+
 def kernel_sources():
-    """Every device-code source of the engine: the kernel translation units
-    and the headers they include."""
+    """Every device-code source of the dense evaluation path: the kernel
+    translation units and the headers they include."""
     d = os.path.join(HERE, "csrc")
     names = sorted(f for f in os.listdir(d)
                    if f.endswith(".hip") or f in ("kernels.hpp", "kdev.hpp") or f.endswith("_impl.hpp"))
-    return [os.path.join(d, f) for f in names if f != "mlp.hip"]
+    return [os.path.join(d, f) for f in names if f not in _OTHER_PATHS]
 
 
 def kernel_source_hash() -> str:
@@ -85,6 +94,28 @@ def _mean(v):
     return sum(v) / len(v) if v else 0.0
 
 
+SIMDS = 256 * 4   # MI355X: 256 compute units of 4 SIMDs
+XCDS = 8          # GRBM_GUI_ACTIVE is summed over the 8 XCDs
+
+
+def mfma_busy(db: str):
+    """[(kernel, dispatches, mfma_busy_fraction, active_us, lds_conflict_rate)]
+    from a --pmc run with SQ_VALU_MFMA_BUSY_CYCLES and GRBM_GUI_ACTIVE (and
+    optionally SQ_LDS_BANK_CONFLICT, SQ_LDS_IDX_ACTIVE)."""
+    busy = counter_per_dispatch(db, "SQ_VALU_MFMA_BUSY_CYCLES")
+    gui = counter_per_dispatch(db, "GRBM_GUI_ACTIVE")
+    conf = counter_per_dispatch(db, "SQ_LDS_BANK_CONFLICT")
+    lds = counter_per_dispatch(db, "SQ_LDS_IDX_ACTIVE")
+    out = []
+    for k in sorted(gui):
+        g = _mean(gui[k]) / XCDS
+        b = _mean(busy.get(k, []))
+        act = _mean(lds.get(k, []))
+        rate = _mean(conf.get(k, [])) / act if act else None
+        out.append((k, len(gui[k]), b / (g * SIMDS) if g else 0.0, g / 2.4e3, rate))
+    return out
+
+
 def traffic(fetch_db, write_db, cal_fetch_db, cal_write_db, cal_bytes, kernel):
     """Per-launch HBM bytes of the matching kernels, calibrated on a copy."""
     cf = counter_per_dispatch(cal_fetch_db, "FETCH_SIZE")
@@ -129,7 +160,31 @@ def main(argv=None):
     t.add_argument("--out", default=None)
     t.add_argument("--meta", action="append", default=[], metavar="KEY=VALUE",
                    help="extra fields of the record (workload, precision, command)")
+    mf = sub.add_parser("mfma")
+    mf.add_argument("db")
+    mf.add_argument("--md", default=None)
+    mf.add_argument("--title", default="MFMA busy")
+    mf.add_argument("--command", default="")
+    mf.add_argument("--note", default="")
     args = ap.parse_args(argv)
+    if args.cmd == "mfma":
+        rows = mfma_busy(args.db)
+        lines = ["| kernel | dispatches | MFMA busy | active us (2.4 GHz) | LDS conflict rate |",
+                 "|---|---|---|---|---|"]
+        for k, nd, f, us, rate in rows:
+            r = "-" if rate is None else f"{rate:.4f}"
+            lines.append(f"| `{k.split('(')[0]}` | {nd} | {f:.3f} | {us:.1f} | {r} |")
+        print("\n".join(lines))
+        if args.md:
+            with open(args.md, "w") as f:
+                f.write(f"# {args.title}\n\n")
+                if args.command:
+                    f.write("Command (from the repository root on the MI355X host):\n\n")
+                    f.write(f"    {args.command}\n\n")
+                if args.note:
+                    f.write(args.note + "\n\n")
+                f.write("\n".join(lines) + "\n")
+        return 0
     if args.cmd == "kernels":
         stats = kernel_stats(args.db)
         print(f"{'kernel':<70} {'calls':>6} {'total_us':>11} {'avg_us':>9} {'pct':>6}")
