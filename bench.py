@@ -286,6 +286,130 @@ def bench_motifs(args):
     print(json.dumps(out))
 
 
+# Table tab:HOIF_runtime of the paper, n = 10000, single RTX 5090, dense
+# n x n factors (seconds per U-statistic, by order): context only.
+HOIF_PAPER_GPU_S = {2: 0.04398, 3: 0.08977, 4: 0.17264, 5: 0.41339, 6: 1.66450, 7: 8.58869}
+
+
+def bench_hoif(args):
+    """Influence-function chains of Section 4.1 from low-rank panels: the
+    U-statistics of h_j for orders j = 2..7 (g on the first j - 2 edges of
+    the chain, f on the last) at n = 10000 with a rank-8 dictionary (panels
+    P = A phi(Z), Q = Y phi(Z), seed 11).  One step = the six U-statistics
+    from panels resident in HBM, no n x n matrix formed.  Beside it: the
+    dense path on the materialised n x n factors (the form the paper's
+    table times) in fp64, and the oracle on a bounded sample."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_2508_12627_amd import ustat as U, workloads as W
+    n, k, orders = 10000, 8, list(range(2, 8))
+    P, Q = W.hoif_panels(n, k, seed=11)
+    Pd = torch.tensor(P, dtype=torch.float64, device="cuda")
+    Qd = torch.tensor(Q, dtype=torch.float64, device="cuda")
+    plans = {j: U.Plan(j, W.hoif_chain(j)) for j in orders}
+    FG = {j: ([Pd] * (j - 1), [Pd] * (j - 2) + [Qd]) for j in orders}
+    res = {}
+    for j in orders:  # schedules built and uploaded outside the timed region
+        res[j] = plans[j].eval_lowrank(*FG[j])
+    print("hoif: schedules ready", file=sys.stderr, flush=True)
+    steps = max(3, args.steps // 10)
+    warm = max(1, args.warmup // 10)
+    for _ in range(warm):
+        for j in orders:
+            plans[j].eval_lowrank(*FG[j])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for j in orders:
+            r = plans[j].eval_lowrank(*FG[j])
+            assert r.value == res[j].value  # deterministic
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    per = {}
+    for j in orders:
+        t1 = time.perf_counter()
+        for _ in range(steps):
+            plans[j].eval_lowrank(*FG[j])
+        per[j] = (time.perf_counter() - t1) / steps
+    print(f"hoif: {1e3 * el:.3f} ms per step", file=sys.stderr, flush=True)
+    # live kernel timing with HIP events (one step)
+    U.ustat_profile_enable(True)
+    U.ustat_profile_reset()
+    for j in orders:
+        plans[j].eval_lowrank(*FG[j])
+    st, rd = U.ustat_profile_read("lowrank_step"), U.ustat_profile_read("lowrank_reduce")
+    U.ustat_profile_enable(False)
+    flops, byts, ms = st["flops"], st["bytes"], st["ms"]
+    alu_peak = 78.6e12  # fp64 vector FLOP/s
+    intensity = flops / byts
+    bound = "alu" if intensity > alu_peak / HBM_PEAK else "hbm"
+    achieved = flops / (ms * 1e-3) if bound == "alu" else byts / (ms * 1e-3)
+    peak = alu_peak if bound == "alu" else HBM_PEAK
+    roof = {"kernel": "k_lr_steps", "bound": bound,
+            "achieved": achieved / (1e12 if bound == "alu" else 1e9),
+            "peak": peak / (1e12 if bound == "alu" else 1e9),
+            "unit": "TFLOP/s" if bound == "alu" else "GB/s", "frac": achieved / peak,
+            "traffic": None, "launches_per_step": st["launches"],
+            "avg_launch_ms": ms / max(1, st["launches"]), "ms_per_step": ms,
+            "flops_per_step": flops, "bytes_per_step": byts,
+            "reduce_ms_per_step": rd["ms"], "reduce_launches_per_step": rd["launches"]}
+    info = {j: plans[j].lowrank_info(n, k, [0] * (2 * j - 3) + [1]) for j in orders}
+    out = {"metric": "HOIF chain U-statistics, orders 2..7 at n=10000 from rank-8 panels, "
+                     "steps/s (one step = all six orders)",
+           "value": 1.0 / el, "unit": "steps/s", "n_gpus": 1, "steps": steps, "warmup": warm,
+           "ms_per_step": 1e3 * el, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic: Z ~ U[0,1]^4, A ~ Bernoulli(expit(Z1+Z2-1)), Y = A + sum Z + N(0,1), "
+                   "cosine dictionary of 8 functions, seed 11",
+           "config": {"workload": "influence-function chains g..g f, orders 2-7, n=10000, rank 8, "
+                                  "every partition (Bell(j)), low-rank panels",
+                      "n": n, "rank": k, "orders": orders},
+           "roofline": roof,
+           "per_order": {str(j): {"ms": 1e3 * per[j], "U": res[j].value, "S": res[j].err_scale,
+                                  "err_est": res[j].err_est, "num_vstats": res[j].num_vstats,
+                                  "madds": info[j]["madds"], "steps": info[j]["num_steps"],
+                                  "workspace_bytes": info[j]["workspace_bytes"],
+                                  "paper_rtx5090_dense_s": HOIF_PAPER_GPU_S[j]}
+                         for j in orders}}
+    if not args.no_compare:
+        # the same U-statistics through the dense path on n x n factors in fp64
+        Tg = Pd @ Pd.T
+        Tf = Pd @ Qd.T
+        torch.cuda.synchronize()
+        dense = {}
+        for j in orders:
+            fac = [Tg] * (j - 2) + [Tf]
+            D = U.Plan(j, W.hoif_chain(j), precision="f64", order="exhaustive")
+            D.eval(fac)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            rdn = D.eval(fac)
+            torch.cuda.synchronize()
+            dense[str(j)] = {"ms": 1e3 * (time.perf_counter() - t1),
+                             "diff_vs_lowrank_over_S": abs(rdn.value - res[j].value) / res[j].err_scale}
+            print(f"hoif: dense order {j} {dense[str(j)]['ms']:.1f} ms", file=sys.stderr, flush=True)
+            del D
+        del Tg, Tf
+        out["dense_f64_same_factors"] = dense
+    if not args.no_cpu_baseline:
+        # the oracle's cost is linear in n (one pass over the samples per
+        # rank-index assignment): time it on the first ns rows, scale by n / ns
+        ns = 3000
+        Ps, Qs = np.ascontiguousarray(P[:ns]), np.ascontiguousarray(Q[:ns])
+        t1 = time.perf_counter()
+        for j in orders:
+            F, G = W.hoif_factor_panels(j, Ps, Qs)
+            oracle.ustat_lowrank(W.hoif_chain(j), F, G)
+        t_s = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": 1.0 / (t_s * n / ns), "unit": "steps/s",
+                               "cores": oracle.num_threads(), "kind": "oracle", "cpu_model": cpu_model(),
+                               "sample": f"subset dynamic programme over the first {ns} of {n} samples "
+                                         f"for all six orders ({t_s:.1f} s), scaled by {n}/{ns} "
+                                         "(its cost is linear in n)"}
+    print(json.dumps(out))
+
+
 def bench_learned_order(args):
     """Learned order choice, end to end.  64 random kernel graphs on 6
     vertices (6-10 edges, seed 5, draws with an isolated vertex rejected);
@@ -351,7 +475,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--workload", default="cycle4",
-                    choices=["cycle4", "batched", "cycle5-exact", "learned-order", "motifs"],
+                    choices=["cycle4", "batched", "cycle5-exact", "learned-order", "motifs", "hoif"],
                     help="cycle4: the headline line; the others print their own line")
     ap.add_argument("--graph-range", default="0:64",
                     help="learned-order workload: graphs lo:hi of the 64")
@@ -390,6 +514,8 @@ def main():
         return bench_learned_order(args)
     if args.workload == "motifs":
         return bench_motifs(args)
+    if args.workload == "hoif":
+        return bench_hoif(args)
     m, edges, n, d = WORKLOAD["m"], WORKLOAD["edges"], WORKLOAD["n"], WORKLOAD["d"]
     div = 2.0 * d
     Xh = W.gaussian_samples(n, d, seed=WORKLOAD["seed"])

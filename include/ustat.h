@@ -298,6 +298,57 @@ ustat_status ustat_eval_noalloc(ustat_plan plan, int64_t n, const void *const *f
                                 ustat_stream stream, ustat_result *out);
 
 /*
+ * U(h, X) from low-rank factors, without forming any n x n matrix: factor e
+ * is T_e = F_e G_e^T with F[e], G[e] device pointers to row-major fp64
+ * n x r panels (host arrays of num_edges pointers; the same pointer may
+ * appear several times, as in the chains of the higher-order influence
+ * function estimators of Section 4.1, where g = (A phi)(A phi)^T and
+ * f = (A phi)(Y phi)^T).  Writing T_e(i, j) = sum_a F_e(i, a) G_e(j, a)
+ * adds one rank index per edge to the Einsum of every restricted
+ * V-statistic (Definition "Restricted V-Statistic", Algorithm 3); the engine
+ * sums out sample and rank indices one at a time (the proof of Proposition
+ * 1), in the order of least multiply-adds among those that never give a
+ * value two sample indices, merges equal steps across partitions and forms
+ * the Moebius combination of Lemma 2 over every partition of [m] (the
+ * plan's sparsification is ignored: Lemma 3 needs zero-diagonal factors).
+ * fp64 throughout, whatever the plan's floating-point precision; err_scale
+ * and err_est as for USTAT_F64, num_vstats = Bell(m).  The plan's
+ * workspace limit applies.  n in [m, 2^31], r in 1..4096.
+ * Errors: USTAT_E_INVALID (sizes, NULL pointers, motif plan),
+ * USTAT_E_UNSUPPORTED (USTAT_I8 plan; a step with more than 8 operands or
+ * a value with more than 8 indices; a network of more than 32 indices),
+ * USTAT_E_INFEASIBLE, USTAT_E_NOMEM, USTAT_E_HIP.
+ */
+ustat_status ustat_eval_lowrank(ustat_plan plan, int64_t n, int32_t r, const double *const *F,
+                                const double *const *G, ustat_stream stream, ustat_result *out);
+
+/*
+ * The low-rank schedule of ustat_eval_lowrank, host only (no device call):
+ * panel_ids (host int32 [2 num_edges], the ids of F_0, G_0, F_1, G_1, ...;
+ * equal ids mean the same panel; NULL = all distinct) stand for the
+ * pointers.  madds counts the multiply-adds of the merged steps (the size
+ * of the summed index times the size of the value produced), madds_unmerged
+ * the same over every partition's own steps; workspace_bytes is the device
+ * workspace; num_exact_orders / num_greedy_orders count the partitions
+ * whose order came from the exact search (networks of at most 16 indices)
+ * or from the greedy rule.  Errors as ustat_eval_lowrank, without
+ * USTAT_E_INFEASIBLE, USTAT_E_NOMEM and USTAT_E_HIP.
+ */
+typedef struct {
+    double madds;
+    double madds_unmerged;
+    int64_t workspace_bytes;
+    int32_t num_partitions;
+    int32_t num_steps;
+    int32_t depth;
+    int32_t num_exact_orders;
+    int32_t num_greedy_orders;
+    int32_t reserved;
+} ustat_lowrank_stats;
+ustat_status ustat_lowrank_info(ustat_plan plan, int64_t n, int32_t r, const int32_t *panel_ids,
+                                ustat_lowrank_stats *out);
+
+/*
  * Build the RBF factor matrix alone (Algorithm 1 for the RBF kernel):
  * out (device, n x n) receives exp(-||X_i - X_j||^2 / rbf_divisor) with the
  * squared distance formed in fp64 from direct differences; precision
@@ -310,7 +361,7 @@ ustat_status ustat_build_rbf(int64_t n, int32_t d, const double *X, double rbf_d
  * Kernel timing (HIP events recorded around every grouped launch on the
  * launch stream; off by default, never active inside graph capture).
  * kind: 0 operand prep, 1 GEMM, 2 column reduction, 3 partial reduction,
- * 4 factor build.  ustat_profile_read returns totals since the last reset:
+ * 4 factor build, 5 low-rank summation steps, 6 low-rank chunk sums.  ustat_profile_read returns totals since the last reset:
  * milliseconds, number of launches, algorithmic flops (2 n^3 per GEMM) and
  * algorithmic bytes (every operand element read once plus the outputs
  * written, for the column reduction and operand prep kernels).  Any output

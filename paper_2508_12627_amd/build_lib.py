@@ -14,7 +14,8 @@ LIB = os.path.join(HERE, "libustat.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["k_rowred_mixed.hip", "k_rowred_int.hip", "k_colred_mixed.hip", "k_colred_int.hip",
            "k_rowred_f64.hip", "k_colred_fp.hip", "k_rowred_f32.hip", "k_gemm.hip", "k_reduce.hip",
-           "kernels.hip", "mlp.hip", "exec.cpp", "capi.cpp", "plan.cpp", "costmodel.cpp", "profile.cpp", "inject.cpp"]
+           "kernels.hip", "k_lowrank.hip", "mlp.hip", "exec.cpp", "capi.cpp", "plan.cpp",
+           "lowrank.cpp", "costmodel.cpp", "profile.cpp", "inject.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",
                 "-packed-fp32-ops"]

@@ -22,6 +22,7 @@
 #include "inject.hpp"
 #include "exec.hpp"
 #include "kernels.hpp"
+#include "lowrank.hpp"
 #include "plan.hpp"
 #include "profile.hpp"
 
@@ -40,6 +41,8 @@ struct ustat_plan_s {
     std::vector<Plan> motifs;
     std::vector<int64_t> motif_aut;
     int motif_size = 0;
+    // low-rank schedules by sample size, rank and panel identity
+    std::map<std::string, std::unique_ptr<LrSchedule>> lowrank;
     ~ustat_plan_s() {
         if (factors) (void)hipFree(factors);
     }
@@ -431,6 +434,134 @@ ustat_status ustat_eval(ustat_plan plan, int64_t n, const void *const *factors, 
     ustat_status st = run(plan, plan->all, data, (hipStream_t)stream, res, nullptr, nullptr, key);
     if (st != USTAT_OK) return st;
     fill_result(out, res[0], plan->plan, n, (int)plan->all.size());
+    return ok();
+    USTAT_GUARD_END
+}
+
+}  // extern "C"
+
+namespace {
+
+// Table slot (1-based) of every panel F_0, G_0, F_1, G_1, ...: equal
+// pointers (or equal caller ids) share a slot.
+template <typename T>
+std::vector<int> panel_slots(const std::vector<T> &ids) {
+    std::vector<int> slot(ids.size());
+    std::vector<T> seen;
+    for (size_t k = 0; k < ids.size(); ++k) {
+        auto it = std::find(seen.begin(), seen.end(), ids[k]);
+        if (it == seen.end()) {
+            seen.push_back(ids[k]);
+            slot[k] = (int)seen.size();
+        } else {
+            slot[k] = (int)(it - seen.begin()) + 1;
+        }
+    }
+    return slot;
+}
+
+ustat_status check_lowrank(ustat_plan plan, int64_t n, int32_t r) {
+    if (!plan) return fail(USTAT_E_INVALID, "plan is NULL");
+    if (!plan->motifs.empty()) return fail(USTAT_E_INVALID, "motif plans take adjacency matrices");
+    if (n < plan->plan.m) return fail(USTAT_E_INVALID, "n must be at least m");
+    if (n > (1ll << 31)) return fail(USTAT_E_INVALID, "n above 2^31 is not supported");
+    if (r < 1 || r > 4096) return fail(USTAT_E_INVALID, "r must be in 1..4096");
+    if (plan->plan.opts.precision == USTAT_I8)
+        return fail(USTAT_E_UNSUPPORTED, "the low-rank path is floating point (fp64)");
+    return USTAT_OK;
+}
+
+// The schedule for (n, r, panel identity), built and uploaded on first use.
+ustat_status lowrank_schedule(ustat_plan plan, int64_t n, int32_t r, const std::vector<int> &slots,
+                              bool upload, LrSchedule **out) {
+    std::string key = std::to_string(n) + ":" + std::to_string(r);
+    for (int s : slots) key += ":" + std::to_string(s);
+    auto it = plan->lowrank.find(key);
+    if (it == plan->lowrank.end()) {
+        std::unique_ptr<LrSchedule> s(new LrSchedule());
+        std::string err = build_lowrank(plan->plan, n, r, slots, *s);
+        if (!err.empty()) return fail(USTAT_E_UNSUPPORTED, err);
+        it = plan->lowrank.emplace(key, std::move(s)).first;
+    }
+    LrSchedule &s = *it->second;
+    const uint64_t lim = plan->plan.opts.workspace_limit;
+    if (lim && (uint64_t)s.ws_elems * 8 > lim)
+        return fail(USTAT_E_INFEASIBLE, "low-rank workspace of " + std::to_string(s.ws_elems * 8) +
+                                            " bytes exceeds the workspace limit");
+    if (upload) {
+        hipError_t e = upload_lowrank(s);
+        if (e == hipErrorOutOfMemory) return fail(USTAT_E_NOMEM, "low-rank descriptors: out of memory");
+        if (e != hipSuccess) return fail(USTAT_E_HIP, std::string("low-rank descriptors: ") + hipGetErrorString(e));
+    }
+    *out = &s;
+    return USTAT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ustat_status ustat_eval_lowrank(ustat_plan plan, int64_t n, int32_t r, const double *const *F,
+                                const double *const *G, ustat_stream stream, ustat_result *out) {
+    USTAT_GUARD_BEGIN
+    ustat_status c = check_lowrank(plan, n, r);
+    if (c != USTAT_OK) return c;
+    if (!F || !G || !out) return fail(USTAT_E_INVALID, "F, G and out must be non-NULL");
+    const size_t E = plan->plan.edges.size();
+    std::vector<const double *> ptrs;
+    for (size_t k = 0; k < E; ++k) {
+        if (!F[k] || !G[k]) return fail(USTAT_E_INVALID, "a panel pointer is NULL");
+        ptrs.push_back(F[k]);
+        ptrs.push_back(G[k]);
+    }
+    const std::vector<int> slots = panel_slots(ptrs);
+    LrSchedule *s = nullptr;
+    c = lowrank_schedule(plan, n, r, slots, true, &s);
+    if (c != USTAT_OK) return c;
+    if (plan->rt.reserve_arena((size_t)s->ws_elems * 8 + 256) != hipSuccess ||
+        plan->rt.reserve_hres(64) != hipSuccess)
+        return fail(USTAT_E_NOMEM, "low-rank workspace: out of memory");
+    std::vector<const double *> tab(s->nslots - 1, nullptr);
+    for (size_t k = 0; k < ptrs.size(); ++k) tab[slots[k] - 1] = ptrs[k];
+    double *hres = (double *)plan->rt.hres;
+    hipError_t e = run_lowrank(*s, tab.data(), (double *)plan->rt.arena, (hipStream_t)stream, hres);
+    if (e != hipSuccess) return fail(USTAT_E_HIP, std::string("low-rank evaluation: ") + hipGetErrorString(e));
+    std::memset(out, 0, sizeof *out);
+    out->value = hres[0];
+    out->err_scale = hres[1];
+    out->err_est = error_estimate(0, n, s->depth, false);
+    out->num_vstats = s->nparts;
+    return ok();
+    USTAT_GUARD_END
+}
+
+ustat_status ustat_lowrank_info(ustat_plan plan, int64_t n, int32_t r, const int32_t *panel_ids,
+                                ustat_lowrank_stats *out) {
+    USTAT_GUARD_BEGIN
+    ustat_status c = check_lowrank(plan, n, r);
+    if (c != USTAT_OK) return c;
+    if (!out) return fail(USTAT_E_INVALID, "out is NULL");
+    const size_t E2 = 2 * plan->plan.edges.size();
+    std::vector<int32_t> ids(E2);
+    for (size_t k = 0; k < E2; ++k) ids[k] = panel_ids ? panel_ids[k] : (int32_t)k;
+    LrSchedule *s = nullptr;
+    c = lowrank_schedule(plan, n, r, panel_slots(ids), false, &s);
+    if (c != USTAT_OK && c != USTAT_E_INFEASIBLE) return c;
+    if (!s) {
+        // over the workspace limit: still report the schedule
+        std::string key = std::to_string(n) + ":" + std::to_string(r);
+        for (int q : panel_slots(ids)) key += ":" + std::to_string(q);
+        s = plan->lowrank.at(key).get();
+    }
+    std::memset(out, 0, sizeof *out);
+    out->madds = s->flops;
+    out->madds_unmerged = s->flops_unmerged;
+    out->workspace_bytes = s->ws_elems * 8;
+    out->num_partitions = s->nparts;
+    out->num_steps = (int32_t)s->steps.size();
+    out->depth = s->depth;
+    out->num_exact_orders = s->ndp;
+    out->num_greedy_orders = s->ngreedy;
     return ok();
     USTAT_GUARD_END
 }

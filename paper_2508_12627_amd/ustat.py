@@ -32,7 +32,8 @@ STATUS = {0: "ok", 1: "invalid", 2: "unsupported", 3: "nomem", 4: "hip", 5: "ove
 FLAG_NO_CSE = 1
 FLAG_SYMMETRIC = 2
 FACTOR_DTYPE = {F64: torch.float64, F32: torch.float32, BF16X3: torch.float32, I8: torch.int8}
-PROFILE_KINDS = {"prep": 0, "gemm": 1, "elim1": 2, "reduce": 3, "rbf": 4}
+PROFILE_KINDS = {"prep": 0, "gemm": 1, "elim1": 2, "reduce": 3, "rbf": 4, "lowrank_step": 5,
+                 "lowrank_reduce": 6}
 
 
 class UstatError(RuntimeError):
@@ -74,8 +75,17 @@ EXPORTS = ["ustat_plan_opts_default", "ustat_plan_create", "ustat_plan_destroy",
            "ustat_mlp_predict", "ustat_mlp_loss_grad", "ustat_mlp_train", "ustat_mlp_save",
            "ustat_plan_tuning", "ustat_plan_set_tuning", "ustat_plan_autotune",
            "ustat_eval_noalloc", "ustat_debug_inject", "ustat_plan_create_motifs",
-           "ustat_motif_counts", "ustat_status_string", "ustat_last_error"]
+           "ustat_motif_counts", "ustat_eval_lowrank", "ustat_lowrank_info",
+           "ustat_status_string", "ustat_last_error"]
 NUM_FEATURES = 18
+
+
+class LowrankStats(ctypes.Structure):
+    _fields_ = [("madds", ctypes.c_double), ("madds_unmerged", ctypes.c_double),
+                ("workspace_bytes", ctypes.c_int64), ("num_partitions", ctypes.c_int32),
+                ("num_steps", ctypes.c_int32), ("depth", ctypes.c_int32),
+                ("num_exact_orders", ctypes.c_int32), ("num_greedy_orders", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 def load_library(path: str = LIB_PATH):
@@ -123,6 +133,9 @@ def load_library(path: str = LIB_PATH):
     L.ustat_debug_inject.argtypes = [i32, i64]
     L.ustat_plan_create_motifs.argtypes = [i32, ctypes.POINTER(PlanOpts), ctypes.POINTER(P)]
     L.ustat_motif_counts.argtypes = [P, i64, P, P, pi64]
+    L.ustat_eval_lowrank.argtypes = [P, i64, i32, ctypes.POINTER(P), ctypes.POINTER(P), P,
+                                     ctypes.POINTER(Result)]
+    L.ustat_lowrank_info.argtypes = [P, i64, i32, pi32, ctypes.POINTER(LowrankStats)]
     L.ustat_status_string.argtypes = [i32]
     L.ustat_status_string.restype = ctypes.c_char_p
     L.ustat_last_error.argtypes = []
@@ -315,6 +328,20 @@ def ustat_eval_noalloc(h, n: int, factors, stream=None) -> Result:
     _check(load_library().ustat_eval_noalloc(h, int(n), _factor_ptrs(factors), _stream_handle(stream),
                                              ctypes.byref(r)))
     return r
+
+
+def ustat_eval_lowrank(h, n: int, r: int, F, G, stream=None) -> Result:
+    res = Result()
+    _check(load_library().ustat_eval_lowrank(h, int(n), int(r), _factor_ptrs(F), _factor_ptrs(G),
+                                             _stream_handle(stream), ctypes.byref(res)))
+    return res
+
+
+def ustat_lowrank_info(h, n: int, r: int, panel_ids=None) -> dict:
+    st = LowrankStats()
+    ids = None if panel_ids is None else (ctypes.c_int32 * len(panel_ids))(*[int(i) for i in panel_ids])
+    _check(load_library().ustat_lowrank_info(h, int(n), int(r), ids, ctypes.byref(st)))
+    return {k: getattr(st, k) for k, _ in LowrankStats._fields_ if k != "reserved"}
 
 
 def ustat_eval_samples(h, X: torch.Tensor, divisor: float, stream=None) -> Result:
@@ -512,6 +539,17 @@ class Plan:
 
     def eval_samples(self, X, divisor: float, stream=None) -> Result:
         return ustat_eval_samples(self.h, X, divisor, stream)
+
+    def eval_lowrank(self, F, G, stream=None) -> Result:
+        """U from factors T_e = F[e] G[e]^T (fp64 n x r device panels)."""
+        assert len(F) == len(self.edges) and len(G) == len(self.edges), "two panels per edge"
+        n, r = F[0].shape
+        for t in list(F) + list(G):
+            assert t.is_cuda and t.is_contiguous() and t.dtype == torch.float64 and t.shape == (n, r)
+        return ustat_eval_lowrank(self.h, n, r, F, G, stream)
+
+    def lowrank_info(self, n: int, r: int, panel_ids=None) -> dict:
+        return ustat_lowrank_info(self.h, n, r, panel_ids)
 
     def vstat(self, block_of, factors, stream=None) -> Result:
         n = self._check_factors(factors)

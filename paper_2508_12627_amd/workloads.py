@@ -97,3 +97,37 @@ def lowrank_factors(count: int, n: int, r: int, seed: int, lo=0.1, hi=1.0):
     rng = np.random.default_rng(seed)
     return [(rng.uniform(lo, hi, size=(n, r)), rng.uniform(lo, hi, size=(n, r)))
             for _ in range(count)]
+
+
+def hoif_chain(order: int):
+    """Kernel graph of the order-j chain (Section 4.1): factors g on edges
+    (0,1) .. (j-3, j-2), f on the last edge (j-2, j-1)."""
+    return path(order)
+
+
+def hoif_panels(n: int, k: int, seed: int, d: int = 4):
+    """Panels of the two factors of the influence-function chains of Section
+    4.1, g(X1, X2) = A1 phi(Z1)^T A2 phi(Z2) and f(X1, X2) = A1 phi(Z1)^T
+    phi(Z2) Y2, i.e. g = P P^T and f = P Q^T with P = A phi(Z), Q = Y phi(Z)
+    (n x k each, fp64).  The paper leaves the data-generating process open;
+    this one draws Z iid uniform on [0, 1]^d, treatment A ~ Bernoulli(expit(
+    Z_1 + Z_2 - 1)), outcome Y = A + sum(Z) + N(0, 1), and a cosine
+    dictionary that is orthonormal under the uniform law, phi_l(z) =
+    sqrt(2) cos(pi (1 + l // d) z_{l mod d}) for l < k.  Building the panels
+    is the kernel evaluation step, not part of the method."""
+    rng = np.random.default_rng(seed)
+    Z = rng.uniform(0.0, 1.0, size=(n, d))
+    A = (rng.uniform(size=n) < 1.0 / (1.0 + np.exp(-(Z[:, 0] + Z[:, 1 % d] - 1.0)))).astype(np.float64)
+    Y = A + Z.sum(axis=1) + rng.standard_normal(n)
+    lidx = np.arange(k)
+    phi = np.sqrt(2.0) * np.cos(np.pi * (1 + lidx // d)[None, :] * Z[:, lidx % d])
+    P = A[:, None] * phi
+    Q = Y[:, None] * phi
+    return np.ascontiguousarray(P), np.ascontiguousarray(Q)
+
+
+def hoif_factor_panels(order: int, P, Q):
+    """(F, G) panel lists of the order-j chain: g = P P^T on the first j-2
+    edges, f = P Q^T on the last."""
+    e = order - 1
+    return [P] * e, [P] * (e - 1) + [Q]

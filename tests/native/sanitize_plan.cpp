@@ -73,6 +73,17 @@ static void exercise(int m, const std::vector<std::pair<int, int>> &edges) {
                     EXPECT(ustat_plan_set_tuning(p, 0, 0) == USTAT_E_INVALID);
                     EXPECT(ustat_plan_set_tuning(p, gb, cb) == USTAT_OK);
                     EXPECT(ustat_eval(p, m - 1, nullptr, nullptr, nullptr) == USTAT_E_INVALID);
+                    if (flags == 0 && sp == 0 && order == 0) {
+                        // low-rank schedules: all panels distinct, then all one panel
+                        ustat_lowrank_stats ls;
+                        const ustat_status want = prec == 3 ? USTAT_E_UNSUPPORTED : USTAT_OK;
+                        EXPECT(ustat_lowrank_info(p, 1000, 3, nullptr, &ls) == want);
+                        std::vector<int32_t> same(2 * edges.size(), 0);
+                        EXPECT(ustat_lowrank_info(p, 77, 1, same.data(), &ls) == want);
+                        EXPECT(ustat_lowrank_info(p, 77, 0, nullptr, &ls) == USTAT_E_INVALID);
+                        EXPECT(ustat_eval_lowrank(p, 77, 2, nullptr, nullptr, nullptr, nullptr) ==
+                               (prec == 3 ? USTAT_E_UNSUPPORTED : USTAT_E_INVALID));
+                    }
                     EXPECT(ustat_plan_destroy(p) == USTAT_OK);
                 }
 }

@@ -1,0 +1,148 @@
+"""GPU parity of the low-rank evaluation (factors T_e = F_e G_e^T given as
+n x r panels, no n x n matrix formed) against the oracle's subset dynamic
+programme over the samples, which never forms a V-statistic:
+
+- the influence-function chains of Section 4.1 (orders 2..7, g = P P^T on
+  all edges but the last, f = P Q^T on the last) at the paper's largest
+  sample size n = 10000, with the rank cut so the oracle finishes in
+  seconds, and at the benchmark's rank 8 for order 7 at n = 300;
+- other kernel graphs (cycles, a chord, K4 of treewidth 3, parallel and
+  antiparallel edges) on distinct signed panels,
+  at ragged n that cut the long sums into several chunks with a short tail;
+- n = m, r = 1, and repeated calls (bit-identical).
+
+|U - U_ref| <= 1e-12 S (S = sum_pi |mu_pi V_pi| from the engine) and the
+measured error below the engine's err_est.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2508_12627_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+K4 = [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def U():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2508_12627_amd import ustat
+    ustat.load_library()
+    return ustat
+
+
+def dev(a):
+    import torch
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def nverts(edges):
+    return 1 + max(max(e) for e in edges)
+
+
+def check(tag, r, ref):
+    err = abs(r.value - ref) / r.err_scale
+    say(f"ERRSTAT lowrank {tag} err={err:.3e} est={r.err_est:.3e} U={r.value:.6e}")
+    assert err <= TOL, (err, TOL)
+    assert err <= r.err_est, (err, r.err_est)
+
+
+def run_chain(U, order, n, r, seed):
+    P, Q = W.hoif_panels(n, r, seed)
+    F, G = W.hoif_factor_panels(order, P, Q)
+    ref = oracle.ustat_lowrank(W.hoif_chain(order), F, G)
+    Pd, Qd = dev(P), dev(Q)
+    Fd = [Pd] * (order - 1)
+    Gd = [Pd] * (order - 2) + [Qd]
+    plan = U.Plan(order, W.hoif_chain(order))
+    say(f"hoif chain order={order} n={n} r={r}")
+    res = plan.eval_lowrank(Fd, Gd)
+    assert res.num_vstats == [1, 1, 2, 5, 15, 52, 203, 877][order]
+    check(f"hoif-{order}-{n}-{r}", res, ref)
+    return res
+
+
+@pytest.mark.parametrize("order,r", [(2, 8), (3, 8), (4, 8), (5, 8), (6, 5), (7, 4)])
+def test_hoif_chains_n10000(U, order, r):
+    run_chain(U, order, 10000, r, seed=900 + order)
+
+
+def test_hoif_order7_rank8(U):
+    run_chain(U, 7, 300, 8, seed=907)
+
+
+@pytest.mark.parametrize("name,edges,n,r", [
+    ("triangle", W.TRIANGLE, 1537, 3),
+    ("cycle4", W.CYCLE4, 2049, 3),
+    ("c5chord", W.CYCLE5_CHORD, 777, 2),
+    ("k4", K4, 333, 2),
+    ("antiparallel", [(0, 1), (1, 0), (1, 2)], 4099, 4),
+    ("parallel-same", [(0, 1), (0, 1), (1, 2), (2, 0)], 1025, 3),
+])
+def test_graphs_signed(U, name, edges, n, r):
+    rng = np.random.default_rng(sum(map(ord, name)) + n)
+    F = [rng.uniform(-1, 1, (n, r)) for _ in edges]
+    G = [rng.uniform(-1, 1, (n, r)) for _ in edges]
+    ref = oracle.ustat_lowrank(edges, F, G)
+    plan = U.Plan(nverts(edges), edges)
+    say(f"lowrank {name} n={n} r={r}")
+    res = plan.eval_lowrank([dev(f) for f in F], [dev(g) for g in G])
+    check(name, res, ref)
+
+
+@pytest.mark.parametrize("name,edges", [("m2", [(0, 1)]), ("cycle4", W.CYCLE4),
+                                        ("path5", W.path(5))])
+def test_n_equals_m_and_rank_one(U, name, edges):
+    m = nverts(edges)
+    for n, r in ((m, 2), (m + 1, 1), (257, 1)):
+        rng = np.random.default_rng(7 * n + r)
+        F = [rng.uniform(-1, 1, (n, r)) for _ in edges]
+        G = [rng.uniform(-1, 1, (n, r)) for _ in edges]
+        ref = oracle.ustat_lowrank(edges, F, G)
+        say(f"lowrank {name} n={n} r={r}")
+        res = U.Plan(m, edges).eval_lowrank([dev(f) for f in F], [dev(g) for g in G])
+        if n == m and ref == 0.0:
+            assert res.value == 0.0 or abs(res.value) <= 1e-12 * res.err_scale
+            continue
+        check(f"{name}-{n}-{r}", res, ref)
+
+
+def test_repeat_bit_identical(U):
+    """The cached schedule gives the same bits, and distinct panels with
+    equal contents give the same value as one shared panel."""
+    P, Q = W.hoif_panels(3001, 6, 941)
+    Pd, Qd = dev(P), dev(Q)
+    plan = U.Plan(5, W.hoif_chain(5))
+    a = plan.eval_lowrank([Pd] * 4, [Pd] * 3 + [Qd])
+    b = plan.eval_lowrank([Pd] * 4, [Pd] * 3 + [Qd])
+    assert a.value == b.value and a.err_scale == b.err_scale
+    copies = [Pd.clone() for _ in range(4)]
+    c = plan.eval_lowrank(copies, copies[1:] + [Qd])
+    assert abs(c.value - a.value) <= 1e-13 * a.err_scale
+
+
+def test_errors(U):
+    plan = U.Plan(3, W.path(3), precision="i8")
+    P = dev(np.ones((10, 2)))
+    with pytest.raises(U.UstatError) as e:
+        plan.eval_lowrank([P, P], [P, P])
+    assert e.value.code == 2  # USTAT_E_UNSUPPORTED
+    plan = U.Plan(3, W.path(3))
+    with pytest.raises(U.UstatError) as e:
+        U.ustat_eval_lowrank(plan.h, 2, 2, [P, P], [P, P])  # n < m
+    assert e.value.code == 1
+    with pytest.raises(U.UstatError) as e:
+        U.ustat_eval_lowrank(plan.h, 10, 0, [P, P], [P, P])  # r < 1
+    assert e.value.code == 1

@@ -38,7 +38,8 @@ def test_planner_and_abi_under_sanitizers(tmp_path):
                    if f.endswith(".hip.o")] if os.path.isdir(OBJ) else []
     if not device_objs:
         pytest.skip("engine not built (run build() first)")
-    host = ["plan.cpp", "costmodel.cpp", "profile.cpp", "exec.cpp", "capi.cpp", "inject.cpp"]
+    host = ["plan.cpp", "costmodel.cpp", "profile.cpp", "exec.cpp", "capi.cpp", "inject.cpp",
+            "lowrank.cpp"]
     flags = ["-x", "hip", "--offload-arch=gfx950", "-O1", "-g", "-std=c++17", "-fPIC",
              "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
              "-Xarch_host", "-fno-omit-frame-pointer",
