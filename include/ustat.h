@@ -331,7 +331,10 @@ ustat_status ustat_eval_lowrank(ustat_plan plan, int64_t n, int32_t r, const dou
  * the same over every partition's own steps; workspace_bytes is the device
  * workspace; num_exact_orders / num_greedy_orders count the partitions
  * whose order came from the exact search (networks of at most 16 indices)
- * or from the greedy rule.  Errors as ustat_eval_lowrank, without
+ * or from the greedy rule; num_gemm_steps counts the steps over a sample
+ * index that run as fp64 MFMA GEMMs (their operands split into two groups
+ * with disjoint indices, each side of the output at least 32 long; the
+ * others run on the vector units).  Errors as ustat_eval_lowrank, without
  * USTAT_E_INFEASIBLE, USTAT_E_NOMEM and USTAT_E_HIP.
  */
 typedef struct {
@@ -343,7 +346,7 @@ typedef struct {
     int32_t depth;
     int32_t num_exact_orders;
     int32_t num_greedy_orders;
-    int32_t reserved;
+    int32_t num_gemm_steps;
 } ustat_lowrank_stats;
 ustat_status ustat_lowrank_info(ustat_plan plan, int64_t n, int32_t r, const int32_t *panel_ids,
                                 ustat_lowrank_stats *out);
@@ -361,8 +364,10 @@ ustat_status ustat_build_rbf(int64_t n, int32_t d, const double *X, double rbf_d
  * Kernel timing (HIP events recorded around every grouped launch on the
  * launch stream; off by default, never active inside graph capture).
  * kind: 0 operand prep, 1 GEMM, 2 column reduction, 3 partial reduction,
- * 4 factor build, 5 low-rank summation steps, 6 low-rank chunk sums.  ustat_profile_read returns totals since the last reset:
- * milliseconds, number of launches, algorithmic flops (2 n^3 per GEMM) and
+ * 4 factor build, 5 low-rank summation steps, 6 low-rank chunk sums,
+ * 7 low-rank outer-product (GEMM) steps.  ustat_profile_read returns
+ * totals since the last reset: milliseconds, number of launches,
+ * algorithmic flops (2 n^3 per GEMM, 2 M N n per low-rank GEMM step) and
  * algorithmic bytes (every operand element read once plus the outputs
  * written, for the column reduction and operand prep kernels).  Any output
  * pointer may be NULL.

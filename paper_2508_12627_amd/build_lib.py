@@ -23,11 +23,17 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           "-I" + os.path.join(HERE, "..", "include")]
 
 
+# Per-source code generation options: the low-rank outer-product kernel
+# keeps its fp64 MFMA accumulators in ordinary VGPRs (no copies between
+# accumulation and vector registers around every MFMA group of its loop).
+EXTRA = {"k_lowrank.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
+
+
 def _compile(src: str) -> str:
     path = os.path.join(CSRC, src)
     obj = os.path.join(BUILD, src + ".o")
     lang = ["-x", "hip"]
-    cmd = [HIPCC] + lang + DEVICE_FLAGS + COMMON + ["-c", path, "-o", obj]
+    cmd = [HIPCC] + lang + DEVICE_FLAGS + COMMON + EXTRA.get(src, []) + ["-c", path, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stderr)

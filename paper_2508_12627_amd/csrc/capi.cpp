@@ -558,10 +558,11 @@ ustat_status ustat_lowrank_info(ustat_plan plan, int64_t n, int32_t r, const int
     out->madds_unmerged = s->flops_unmerged;
     out->workspace_bytes = s->ws_elems * 8;
     out->num_partitions = s->nparts;
-    out->num_steps = (int32_t)s->steps.size();
+    out->num_steps = (int32_t)(s->steps.size() + s->krs.size());
     out->depth = s->depth;
     out->num_exact_orders = s->ndp;
     out->num_greedy_orders = s->ngreedy;
+    out->num_gemm_steps = (int32_t)s->krs.size();
     return ok();
     USTAT_GUARD_END
 }

@@ -94,7 +94,15 @@ __global__ __launch_bounds__(kLrThreads) void k_lr_steps(const LrStepDesc *__res
     double acc = 0.0;
     if (o < st.nout) {
         lr_offsets(st, o, off);
-        for (int64_t x = x0 + xl; x < x1; x += st.xlanes) acc += lr_term(p, off, sx, nin, x);
+        // two independent chains so that loads overlap
+        double acc1 = 0.0;
+        int64_t x = x0 + xl;
+        for (; x + st.xlanes < x1; x += 2 * st.xlanes) {
+            acc += lr_term(p, off, sx, nin, x);
+            acc1 += lr_term(p, off, sx, nin, x + st.xlanes);
+        }
+        if (x < x1) acc += lr_term(p, off, sx, nin, x);
+        acc += acc1;
     }
     red[tid] = acc;
     __syncthreads();
@@ -105,16 +113,176 @@ __global__ __launch_bounds__(kLrThreads) void k_lr_steps(const LrStepDesc *__res
     }
 }
 
+// Offset of index i of one side: sum_d digit_d(i) st[d], digits in radix
+// dim[0..nd) with dim[nd-1] fastest (31-bit quantities).
+__device__ inline uint32_t side_offset(uint32_t i, int nd, const int32_t *dim, const int32_t *st) {
+    uint32_t off = 0;
+    for (int d = nd - 1; d >= 0; --d) {
+        const uint32_t dm = (uint32_t)dim[d];
+        const uint32_t q = i / dm;
+        off += (i - q * dm) * (uint32_t)st[d];
+        i = q;
+    }
+    return off;
+}
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+// operands live in device global memory: global (not flat) loads
+typedef const double __attribute__((address_space(1))) *gptr;
+
+// Outer-product steps.  A 64 x 64 output tile per block of four waves, each
+// wave an independent 32 x 32 sub-tile from 2 x 2 fp64 MFMA 16x16x4 blocks.
+// Every lane forms its own MFMA operand values directly: the A value of
+// fragment row (lane & 15) at x = x0 + (lane >> 4) is the product of the NL
+// left operand reads, the B value likewise from the NR right operands; no
+// LDS staging and no block barriers.  Rows and columns past M or N and x
+// past the chunk read clamped (valid) addresses and are multiplied by zero,
+// so no branch guards a load.
+template <int NL, int NR>
+__device__ __forceinline__ void kr_tile(const LrKrDesc &st, const double *const *__restrict__ tab,
+                                        uint32_t c, uint32_t tm, uint32_t tn) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lr = lane & 15, lg = lane >> 4;
+    const uint32_t r0 = tm * kLrKrTile + (wv >> 1) * 32, c0 = tn * kLrKrTile + (wv & 1) * 32;
+    gptr pl[NL > 0 ? NL : 1], pr[NR];
+    uint32_t ol[2][NL > 0 ? NL : 1], orr[2][NR], sl[NL > 0 ? NL : 1], sr[NR];
+    double zl[2], zr[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const uint32_t row = r0 + 16 * i + lr, col = c0 + 16 * i + lr;
+        zl[i] = row < (uint32_t)st.M ? 1.0 : 0.0;
+        zr[i] = col < (uint32_t)st.N ? 1.0 : 0.0;
+        const uint32_t rc = min(row, (uint32_t)st.M - 1), cc = min(col, (uint32_t)st.N - 1);
+#pragma unroll
+        for (int u = 0; u < NL; ++u) ol[i][u] = side_offset(rc, st.ndl, st.dl, st.st[u]);
+#pragma unroll
+        for (int u = 0; u < NR; ++u) orr[i][u] = side_offset(cc, st.ndr, st.dr, st.st[kLrKrSide + u]);
+    }
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {
+        pl[u] = (gptr)(tab[st.slot[u]] + st.base[u]);
+        sl[u] = (uint32_t)st.sx[u];
+    }
+#pragma unroll
+    for (int u = 0; u < NR; ++u) {
+        pr[u] = (gptr)(tab[st.slot[kLrKrSide + u]] + st.base[kLrKrSide + u]);
+        sr[u] = (uint32_t)st.sx[kLrKrSide + u];
+    }
+    const uint32_t x0 = c * (uint32_t)st.xchunk;
+    const uint32_t x1 = min((uint32_t)st.nx, x0 + (uint32_t)st.xchunk);
+    f64x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f64x4{0, 0, 0, 0};
+    // raw operand reads for x = xq + lg (clamped), issued one step ahead of
+    // the products and MFMAs that consume them
+    double ra[2][NL > 0 ? NL : 1], rb[2][NR];
+    auto fetch = [&](uint32_t xq, double (&fa)[2][NL > 0 ? NL : 1], double (&fb)[2][NR]) {
+        const uint32_t xc = min(xq + lg, x1 - 1);
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+#pragma unroll
+            for (int u = 0; u < NL; ++u) fa[i][u] = pl[u][ol[i][u] + xc * sl[u]];
+#pragma unroll
+            for (int u = 0; u < NR; ++u) fb[i][u] = pr[u][orr[i][u] + xc * sr[u]];
+        }
+    };
+    fetch(x0, ra, rb);
+    for (uint32_t xq = x0; xq < x1; xq += 4) {
+        double na[2][NL > 0 ? NL : 1], nb[2][NR];
+        fetch(xq + 4, na, nb);
+        const double z = xq + lg < x1 ? 1.0 : 0.0;
+        double a[2], b[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            double va = zl[i] * z, vb = zr[i];
+#pragma unroll
+            for (int u = 0; u < NL; ++u) va *= ra[i][u];
+#pragma unroll
+            for (int u = 0; u < NR; ++u) vb *= rb[i][u];
+            a[i] = va;
+            b[i] = vb;
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+#pragma unroll
+            for (int u = 0; u < NL; ++u) ra[i][u] = na[i][u];
+#pragma unroll
+            for (int u = 0; u < NR; ++u) rb[i][u] = nb[i][u];
+        }
+    }
+    // accumulator element r of block (i, j): row r0 + 16 i + lg + 4 r,
+    // column c0 + 16 j + lr
+    double *o = const_cast<double *>(tab[0]) + st.out + (int64_t)c * st.nout;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const uint32_t col = c0 + 16 * j + lr;
+        if (col >= (uint32_t)st.N) continue;
+        const uint32_t co = side_offset(col, st.ndr, st.dr, st.orr);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const uint32_t row = r0 + 16 * i + lg + 4 * r;
+                if (row < (uint32_t)st.M) o[side_offset(row, st.ndl, st.dl, st.ol) + co] = acc[i][j][r];
+            }
+    }
+}
+
+__global__ __launch_bounds__(kLrThreads) void k_lr_kr(const LrKrDesc *__restrict__ desc,
+                                                      int64_t nkr,
+                                                      const double *const *__restrict__ tab) {
+    const int64_t b = blockIdx.x;
+    const LrKrDesc &st = desc[find_step(desc, nkr, b)];
+    const uint32_t bi = (uint32_t)(b - st.block0);
+    const uint32_t c = bi / st.tiles, t = bi - c * st.tiles;
+    const uint32_t tm = t / st.tiles_n, tn = t - tm * st.tiles_n;
+    switch (st.nl * 8 + st.nr) {
+#define KR_CASE(L, R) \
+    case L * 8 + R: kr_tile<L, R>(st, tab, c, tm, tn); break;
+        KR_CASE(1, 1) KR_CASE(1, 2) KR_CASE(1, 3) KR_CASE(1, 4)
+        KR_CASE(2, 1) KR_CASE(2, 2) KR_CASE(2, 3) KR_CASE(2, 4)
+        KR_CASE(3, 1) KR_CASE(3, 2) KR_CASE(3, 3) KR_CASE(3, 4)
+        KR_CASE(4, 1) KR_CASE(4, 2) KR_CASE(4, 3) KR_CASE(4, 4)
+#undef KR_CASE
+        default: break;
+    }
+}
+
 __global__ __launch_bounds__(kLrThreads) void k_lr_reduce(const LrReduceDesc *__restrict__ desc,
                                                           int64_t nred, double *__restrict__ ws) {
+    __shared__ double red[kLrThreads];
     const int64_t b = blockIdx.x;
     const LrReduceDesc &rd = desc[find_step(desc, nred, b)];
-    const int64_t o = (b - rd.block0) * kLrThreads + threadIdx.x;
-    if (o >= rd.nout) return;
-    const double *p = ws + rd.part + o;
+    const int tid = threadIdx.x;
+    const int ol = tid % rd.otile, cl = tid / rd.otile;
+    const int64_t o = (b - rd.block0) * rd.otile + ol;
     double s = 0.0;
-    for (int c = 0; c < rd.nchunk; ++c) s += p[c * rd.nout];
-    ws[rd.out + o] = s;
+    if (o < rd.nout) {
+        const double *p = ws + rd.part + o;
+        // two independent sums so that loads overlap
+        double s1 = 0.0;
+        int c = cl;
+        for (; c + rd.clanes < rd.nchunk; c += 2 * rd.clanes) {
+            s += p[(int64_t)c * rd.nout];
+            s1 += p[(int64_t)(c + rd.clanes) * rd.nout];
+        }
+        if (c < rd.nchunk) s += p[(int64_t)c * rd.nout];
+        s += s1;
+    }
+    red[tid] = s;
+    __syncthreads();
+    if (cl == 0 && o < rd.nout) {
+        double t = red[ol];
+        for (int j = 1; j < rd.clanes; ++j) t += red[ol + j * rd.otile];
+        ws[rd.out + o] = t;
+    }
 }
 
 __device__ inline void two_sum_add(double &s, double &c, double x) {
@@ -165,6 +333,12 @@ void launch_lr_steps(const LrStepDesc *d, int64_t nsteps, int64_t blocks,
                      const double *const *tab, hipStream_t s) {
     if (nsteps <= 0 || blocks <= 0) return;
     hipLaunchKernelGGL(k_lr_steps, dim3((unsigned)blocks), dim3(kLrThreads), 0, s, d, nsteps, tab);
+}
+
+void launch_lr_kr(const LrKrDesc *d, int64_t nkr, int64_t blocks, const double *const *tab,
+                  hipStream_t s) {
+    if (nkr <= 0 || blocks <= 0) return;
+    hipLaunchKernelGGL(k_lr_kr, dim3((unsigned)blocks), dim3(kLrThreads), 0, s, d, nkr, tab);
 }
 
 void launch_lr_reduce(const LrReduceDesc *d, int64_t nred, int64_t blocks, double *ws,

@@ -146,6 +146,51 @@ struct Tensor {
     std::vector<int> nodes;  // network node of each index
 };
 
+// Row-major element strides of a value's indices.
+void value_strides(const LrValue &v, int64_t *st) {
+    int64_t s = 1;
+    for (int q = v.nd - 1; q >= 0; --q) {
+        st[q] = s;
+        s *= v.dims[q];
+    }
+}
+
+// Split of a long step's operands into a left and a right group whose
+// output indices are disjoint (operands without output indices go left),
+// with the largest min(M, N) of the two index-space sizes; 0 when no split
+// gives both sides at least kLrKrMin (the generic kernel is used then: a
+// GEMM of a side shorter than 8 wastes most of each 16-wide MFMA block).
+constexpr int64_t kLrKrMin = 8;
+uint32_t kr_split(const LrValue &v, const std::vector<LrValue> &vals) {
+    const int nin = (int)v.ins.size();
+    const int64_t lim = (int64_t)1 << 31;
+    if (v.nx >= lim || v.size >= lim) return 0;
+    for (int t : v.ins)
+        if (vals[t].size >= lim) return 0;
+    std::vector<uint32_t> dm(nin, 0);
+    for (int t = 0; t < nin; ++t)
+        for (int p : v.maps[t])
+            if (p >= 0) dm[t] |= 1u << p;
+    uint32_t best = 0;
+    int64_t best_min = kLrKrMin - 1;
+    for (uint32_t mask = 1; mask + 1 < (1u << nin); ++mask) {
+        if (__builtin_popcount(mask) > kLrKrSide || nin - __builtin_popcount(mask) > kLrKrSide) continue;
+        uint32_t dl = 0, dr = 0;
+        for (int t = 0; t < nin; ++t) (mask >> t & 1 ? dl : dr) |= dm[t];
+        if (dl & dr) continue;
+        bool empty_right = false;
+        for (int t = 0; t < nin; ++t) empty_right |= !(mask >> t & 1) && dm[t] == 0;
+        if (empty_right) continue;
+        int64_t M = 1, N = 1;
+        for (int q = 0; q < v.nd; ++q) (dl >> q & 1 ? M : N) *= v.dims[q];
+        if (std::min(M, N) > best_min) {
+            best_min = std::min(M, N);
+            best = mask;
+        }
+    }
+    return best;
+}
+
 }  // namespace
 
 std::string build_lowrank(const Plan &plan, int64_t n, int r, const std::vector<int> &slot_of,
@@ -334,15 +379,109 @@ std::string build_lowrank(const Plan &plan, int64_t n, int r, const std::vector<
     // descriptors, level by level
     out.steps.clear();
     out.reds.clear();
+    out.krs.clear();
     out.levels.assign(depth, LrLevel());
     int64_t part_max = 0;
     for (int L = 1; L <= depth; ++L) {
         LrLevel &lv = out.levels[L - 1];
         lv.steps_off = (int64_t)out.steps.size();
         lv.red_off = (int64_t)out.reds.size();
-        int64_t part_off = values_end, blocks = 0, rblocks = 0;
+        lv.kr_off = (int64_t)out.krs.size();
+        int64_t part_off = values_end, blocks = 0, rblocks = 0, krblocks = 0;
+        // partial sums of a long step cut into nch chunks: the output goes
+        // to a partial buffer and a reduce descriptor sums it into the value
+        auto partials = [&](const LrValue &v, int64_t nch) -> int64_t {
+            if (nch == 1) return v.off;
+            LrReduceDesc rd;
+            std::memset(&rd, 0, sizeof rd);
+            rd.part = part_off;
+            rd.out = v.off;
+            rd.nout = v.size;
+            rd.nchunk = (int32_t)nch;
+            int64_t ot = 1;
+            while (ot < v.size && ot < kLrThreads) ot <<= 1;
+            while (ot > 16 && kLrThreads / ot * 8 < nch) ot >>= 1;  // at most ~8 chunks a lane
+            rd.otile = (int32_t)ot;
+            rd.clanes = (int32_t)(kLrThreads / ot);
+            rd.block0 = rblocks;
+            rblocks += (v.size + ot - 1) / ot;
+            lv.red_bytes += 8.0 * (double)v.size * (double)(nch + 1);
+            out.reds.push_back(rd);
+            const int64_t at = part_off;
+            part_off += (nch * v.size + 31) & ~int64_t(31);
+            return at;
+        };
         for (auto &v : vals) {
             if (v.kind != 1 || v.level != L) continue;
+            const uint32_t split = v.long_x ? kr_split(v, vals) : 0;
+            if (split) {
+                LrKrDesc k;
+                std::memset(&k, 0, sizeof k);
+                int64_t ost[kLrMaxDim];
+                value_strides(v, ost);
+                uint32_t dlm = 0;
+                for (size_t t = 0; t < v.ins.size(); ++t)
+                    if (split >> t & 1)
+                        for (int p : v.maps[t])
+                            if (p >= 0) dlm |= 1u << p;
+                int posl[kLrMaxDim], posr[kLrMaxDim];
+                k.M = k.N = 1;
+                for (int q = 0; q < v.nd; ++q) {
+                    if (dlm >> q & 1) {
+                        posl[k.ndl] = q;
+                        k.dl[k.ndl] = (int32_t)v.dims[q];
+                        k.ol[k.ndl++] = (int32_t)ost[q];
+                        k.M *= (int32_t)v.dims[q];
+                    } else {
+                        posr[k.ndr] = q;
+                        k.dr[k.ndr] = (int32_t)v.dims[q];
+                        k.orr[k.ndr++] = (int32_t)ost[q];
+                        k.N *= (int32_t)v.dims[q];
+                    }
+                }
+                int cnt[2] = {0, 0};
+                for (int side = 0; side < 2; ++side)
+                    for (size_t t = 0; t < v.ins.size(); ++t) {
+                        if ((split >> t & 1) != (side == 0 ? 1u : 0u)) continue;
+                        const int u = side * kLrKrSide + cnt[side]++;
+                        const LrValue &in = vals[v.ins[t]];
+                        k.slot[u] = in.kind == 0 ? in.slot : 0;
+                        k.base[u] = in.kind == 0 ? 0 : in.off;
+                        int64_t ist[kLrMaxDim];
+                        value_strides(in, ist);
+                        const int nds = side == 0 ? k.ndl : k.ndr;
+                        const int *pos = side == 0 ? posl : posr;
+                        for (int q = 0; q < in.nd; ++q) {
+                            const int p = v.maps[t][q];
+                            if (p < 0) {
+                                k.sx[u] += (int32_t)ist[q];
+                                continue;
+                            }
+                            for (int d = 0; d < nds; ++d)
+                                if (pos[d] == p) k.st[u][d] += (int32_t)ist[q];
+                        }
+                    }
+                k.nl = cnt[0];
+                k.nr = cnt[1];
+                k.nx = (int32_t)v.nx;
+                k.nout = (int32_t)v.size;
+                k.tiles_n = (k.N + kLrKrTile - 1) / kLrKrTile;
+                k.tiles = ((k.M + kLrKrTile - 1) / kLrKrTile) * k.tiles_n;
+                int64_t nch = std::min<int64_t>(32, std::max<int64_t>(1, (2048 + k.tiles - 1) / k.tiles));
+                nch = std::min<int64_t>(nch, std::max<int64_t>(1, k.nx / 256));
+                nch = std::min<int64_t>(nch, std::max<int64_t>(1, (((int64_t)1 << 31) - 1) / v.size));
+                k.xchunk = (int32_t)(((k.nx + nch - 1) / nch + 15) / 16 * 16);
+                nch = (k.nx + k.xchunk - 1) / k.xchunk;
+                k.nchunk = (int32_t)nch;
+                k.out = partials(v, nch);
+                k.block0 = krblocks;
+                krblocks += nch * k.tiles;
+                lv.kr_flops += 2.0 * (double)k.M * (double)k.N * (double)k.nx;
+                lv.kr_bytes += 8.0 * (double)v.size;
+                for (int t : v.ins) lv.kr_bytes += 8.0 * (double)vals[t].size;
+                out.krs.push_back(k);
+                continue;
+            }
             LrStepDesc d;
             std::memset(&d, 0, sizeof d);
             d.nin = (int32_t)v.ins.size();
@@ -381,35 +520,26 @@ std::string build_lowrank(const Plan &plan, int64_t n, int r, const std::vector<
                 d.otile = (int32_t)ot;
                 d.xlanes = (int32_t)(kLrThreads / ot);
                 const int64_t ntile = (d.nout + ot - 1) / ot;
-                int64_t nch = std::max<int64_t>(1, 4096 / ntile);
-                nch = std::min(nch, std::max<int64_t>(1, d.nx / (d.xlanes * 16)));
+                // about 16 values of x per thread for small outputs (short
+                // dependent chains; such steps are latency-bound), 64 for
+                // larger ones (fewer partials); at most 4096 blocks per step
+                const int64_t per = d.nout <= 256 ? 16 : 64;
+                int64_t nch = (d.nx + d.xlanes * per - 1) / (d.xlanes * per);
+                nch = std::max<int64_t>(1, std::min(nch, 4096 / ntile));
                 d.xchunk = (d.nx + nch - 1) / nch;
                 nch = (d.nx + d.xchunk - 1) / d.xchunk;
                 d.nchunk = (int32_t)nch;
-                if (nch == 1) {
-                    d.out = v.off;
-                } else {
-                    d.out = part_off;
-                    LrReduceDesc rd;
-                    std::memset(&rd, 0, sizeof rd);
-                    rd.part = part_off;
-                    rd.out = v.off;
-                    rd.nout = d.nout;
-                    rd.nchunk = (int32_t)nch;
-                    rd.block0 = rblocks;
-                    rblocks += (d.nout + kLrThreads - 1) / kLrThreads;
-                    lv.red_bytes += 8.0 * (double)d.nout * (double)(nch + 1);
-                    out.reds.push_back(rd);
-                    part_off += (nch * d.nout + 31) & ~int64_t(31);
-                }
+                d.out = partials(v, nch);
                 blocks += ntile * nch;
             }
             out.steps.push_back(d);
         }
         lv.nsteps = (int64_t)out.steps.size() - lv.steps_off;
         lv.nred = (int64_t)out.reds.size() - lv.red_off;
+        lv.nkr = (int64_t)out.krs.size() - lv.kr_off;
         lv.blocks = blocks;
         lv.rblocks = rblocks;
+        lv.krblocks = krblocks;
         part_max = std::max(part_max, part_off - values_end);
     }
     out.part_elems = part_max;
@@ -428,6 +558,8 @@ hipError_t upload_lowrank(LrSchedule &s) {
     off = align(off + s.steps.size() * sizeof(LrStepDesc));
     s.off_reds = off;
     off = align(off + s.reds.size() * sizeof(LrReduceDesc));
+    s.off_krs = off;
+    off = align(off + s.krs.size() * sizeof(LrKrDesc));
     s.off_mu = off;
     off = align(off + s.mu.size() * 8);
     s.off_cst = off;
@@ -450,6 +582,7 @@ hipError_t upload_lowrank(LrSchedule &s) {
     std::vector<char> h(off, 0);
     std::memcpy(h.data() + s.off_steps, s.steps.data(), s.steps.size() * sizeof(LrStepDesc));
     std::memcpy(h.data() + s.off_reds, s.reds.data(), s.reds.size() * sizeof(LrReduceDesc));
+    std::memcpy(h.data() + s.off_krs, s.krs.data(), s.krs.size() * sizeof(LrKrDesc));
     std::memcpy(h.data() + s.off_mu, s.mu.data(), s.mu.size() * 8);
     std::memcpy(h.data() + s.off_cst, s.cst.data(), s.cst.size() * 8);
     std::memcpy(h.data() + s.off_first, s.sc_first.data(), s.sc_first.size() * 4);
@@ -469,11 +602,16 @@ hipError_t run_lowrank(LrSchedule &s, const double *const *panels, double *ws, h
     const auto *dtab = (const double *const *)(s.blob + s.off_tab);
     const auto *dsteps = (const LrStepDesc *)(s.blob + s.off_steps);
     const auto *dreds = (const LrReduceDesc *)(s.blob + s.off_reds);
+    const auto *dkrs = (const LrKrDesc *)(s.blob + s.off_krs);
     Profiler *prof = Profiler::active();
     for (const LrLevel &lv : s.levels) {
-        {
+        if (lv.nsteps) {
             ProfScope ps(prof, KIND_LR_STEP, stream, lv.flops, lv.bytes);
             launch_lr_steps(dsteps + lv.steps_off, lv.nsteps, lv.blocks, dtab, stream);
+        }
+        if (lv.nkr) {
+            ProfScope ps(prof, KIND_LR_KR, stream, lv.kr_flops, lv.kr_bytes);
+            launch_lr_kr(dkrs + lv.kr_off, lv.nkr, lv.krblocks, dtab, stream);
         }
         if (lv.nred) {
             ProfScope ps(prof, KIND_LR_REDUCE, stream, 0.0, lv.red_bytes);

@@ -50,15 +50,44 @@ struct LrStepDesc {
     int64_t block0;  // first block of this step in its launch
 };
 
-// Sum of the nchunk partials of a long step, in chunk order.
+// A long step whose operands split into two groups with disjoint indices,
+// out[l, r] = sum_x A(x, l) B(x, r) with A(x, l) the product of the left
+// operands and B(x, r) that of the right ones (a sum of outer products of
+// Khatri-Rao rows): an fp64 MFMA GEMM with inner dimension x whose operand
+// values are formed in registers.  Up to kLrKrSide operands a side:
+// operands 0..nl-1 are the left ones, kLrKrSide..kLrKrSide+nr-1 the right
+// ones.  Operand u is read at slot base[u] + x sx[u] +
+// sum_d digit_d st[u][d] over the digits of l (left, radix dl) or of r
+// (right, radix dr); the output element (l, r) is at out + c nout +
+// sum_d digit_d(l) ol[d] + sum_d digit_d(r) orr[d] (c the chunk of x;
+// partials when nchunk > 1).  Offsets within a value fit 31 bits.
+constexpr int kLrKrTile = 64;
+constexpr int kLrKrSide = 4;
+struct LrKrDesc {
+    int32_t ndl, ndr, nl, nr;  // side indices, side operands (1..kLrKrSide)
+    int32_t slot[2 * kLrKrSide];
+    int64_t base[2 * kLrKrSide];
+    int32_t sx[2 * kLrKrSide];
+    int32_t st[2 * kLrKrSide][kLrMaxDim];
+    int32_t dl[kLrMaxDim], dr[kLrMaxDim];
+    int32_t ol[kLrMaxDim], orr[kLrMaxDim];
+    int32_t M, N, nx, xchunk, nchunk, tiles_n, tiles, nout;
+    int64_t out, block0;
+};
+
+// Sum of the nchunk partials of a long step: a block covers `otile`
+// outputs with `clanes` threads each; lane l sums chunks l, l + clanes, ...
+// and the lanes' sums are added in lane order.
 struct LrReduceDesc {
     int64_t part, out, nout, block0;
-    int32_t nchunk, pad;
+    int32_t nchunk, otile, clanes, pad;
 };
 
 struct LrLevel {
     int64_t steps_off = 0, nsteps = 0, blocks = 0;    // into the step array
     int64_t red_off = 0, nred = 0, rblocks = 0;        // into the reduce array
+    int64_t kr_off = 0, nkr = 0, krblocks = 0;         // into the outer-product array
+    double kr_flops = 0, kr_bytes = 0;
     // algorithmic work of the level's steps: nin flops per term (nin - 1
     // products and one addition), bytes of every operand read once and of
     // every value written once (fp64)
@@ -72,6 +101,7 @@ struct LrSchedule {
     int nslots = 0;            // 1 + distinct panels
     std::vector<LrStepDesc> steps;
     std::vector<LrReduceDesc> reds;
+    std::vector<LrKrDesc> krs;
     std::vector<LrLevel> levels;
     // Moebius combination: partition p has coefficient mu[p], a constant
     // factor cst[p] (n per block without edges) and the product of the
@@ -87,7 +117,7 @@ struct LrSchedule {
     // device copies: steps, reduces, combine arrays (one blob)
     char *blob = nullptr;
     size_t blob_bytes = 0;
-    size_t off_steps = 0, off_reds = 0, off_mu = 0, off_cst = 0, off_first = 0, off_sc = 0,
+    size_t off_steps = 0, off_reds = 0, off_krs = 0, off_mu = 0, off_cst = 0, off_first = 0, off_sc = 0,
            off_tab = 0, off_res = 0;
     int device = -1;
     ~LrSchedule();
@@ -112,6 +142,8 @@ hipError_t run_lowrank(LrSchedule &s, const double *const *panels, double *ws, h
 // Launchers (k_lowrank.hip).
 void launch_lr_steps(const LrStepDesc *d, int64_t nsteps, int64_t blocks,
                      const double *const *tab, hipStream_t s);
+void launch_lr_kr(const LrKrDesc *d, int64_t nkr, int64_t blocks, const double *const *tab,
+                  hipStream_t s);
 void launch_lr_reduce(const LrReduceDesc *d, int64_t nred, int64_t blocks, double *ws,
                       hipStream_t s);
 void launch_lr_combine(const double *mu, const double *cst, const int32_t *first,

@@ -11,7 +11,7 @@
 namespace ustat {
 
 enum ProfKind { KIND_PREP = 0, KIND_GEMM = 1, KIND_ELIM1 = 2, KIND_REDUCE = 3, KIND_RBF = 4,
-                KIND_LR_STEP = 5, KIND_LR_REDUCE = 6, KIND_COUNT = 7 };
+                KIND_LR_STEP = 5, KIND_LR_REDUCE = 6, KIND_LR_KR = 7, KIND_COUNT = 8 };
 
 class Profiler {
 public:

@@ -33,7 +33,7 @@ FLAG_NO_CSE = 1
 FLAG_SYMMETRIC = 2
 FACTOR_DTYPE = {F64: torch.float64, F32: torch.float32, BF16X3: torch.float32, I8: torch.int8}
 PROFILE_KINDS = {"prep": 0, "gemm": 1, "elim1": 2, "reduce": 3, "rbf": 4, "lowrank_step": 5,
-                 "lowrank_reduce": 6}
+                 "lowrank_reduce": 6, "lowrank_outer": 7}
 
 
 class UstatError(RuntimeError):
@@ -85,7 +85,7 @@ class LowrankStats(ctypes.Structure):
                 ("workspace_bytes", ctypes.c_int64), ("num_partitions", ctypes.c_int32),
                 ("num_steps", ctypes.c_int32), ("depth", ctypes.c_int32),
                 ("num_exact_orders", ctypes.c_int32), ("num_greedy_orders", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("num_gemm_steps", ctypes.c_int32)]
 
 
 def load_library(path: str = LIB_PATH):
@@ -341,7 +341,7 @@ def ustat_lowrank_info(h, n: int, r: int, panel_ids=None) -> dict:
     st = LowrankStats()
     ids = None if panel_ids is None else (ctypes.c_int32 * len(panel_ids))(*[int(i) for i in panel_ids])
     _check(load_library().ustat_lowrank_info(h, int(n), int(r), ids, ctypes.byref(st)))
-    return {k: getattr(st, k) for k, _ in LowrankStats._fields_ if k != "reserved"}
+    return {k: getattr(st, k) for k, _ in LowrankStats._fields_}
 
 
 def ustat_eval_samples(h, X: torch.Tensor, divisor: float, stream=None) -> Result:

@@ -9,6 +9,8 @@ programme over the samples, which never forms a V-statistic:
 - other kernel graphs (cycles, a chord, K4 of treewidth 3, parallel and
   antiparallel edges) on distinct signed panels,
   at ragged n that cut the long sums into several chunks with a short tail;
+- the fp64 MFMA path of the steps over a sample index whose operands split
+  into two groups (ragged and full 64-wide tiles);
 - n = m, r = 1, and repeated calls (bit-identical).
 
 |U - U_ref| <= 1e-12 S (S = sum_pi |mu_pi V_pi| from the engine) and the
@@ -81,6 +83,17 @@ def test_hoif_chains_n10000(U, order, r):
 
 def test_hoif_order7_rank8(U):
     run_chain(U, 7, 300, 8, seed=907)
+
+
+@pytest.mark.parametrize("order,n,r", [(5, 10000, 6), (6, 2000, 6), (7, 300, 8)])
+def test_outer_product_steps(U, order, n, r):
+    """Orders whose largest steps over a sample index run as fp64 MFMA
+    GEMMs: rank 6 gives sides of 36 and 216 (ragged against the 64-wide
+    tiles), rank 8 sides of 64 and 512."""
+    plan = U.Plan(order, W.hoif_chain(order))
+    info = plan.lowrank_info(n, r, [0] * (2 * order - 3) + [1])
+    assert info["num_gemm_steps"] > 0
+    run_chain(U, order, n, r, seed=950 + order)
 
 
 @pytest.mark.parametrize("name,edges,n,r", [
