@@ -130,43 +130,40 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 // operands live in device global memory: global (not flat) loads
 typedef const double __attribute__((address_space(1))) *gptr;
 
-// Outer-product steps.  A 64 x 64 output tile per block of four waves, each
-// wave an independent 32 x 32 sub-tile from 2 x 2 fp64 MFMA 16x16x4 blocks.
-// Every lane forms its own MFMA operand values directly: the A value of
-// fragment row (lane & 15) at x = x0 + (lane >> 4) is the product of the NL
-// left operand reads, the B value likewise from the NR right operands; no
-// LDS staging and no block barriers.  Rows and columns past M or N and x
-// past the chunk read clamped (valid) addresses and are multiplied by zero,
-// so no branch guards a load.
+// Outer-product steps.  A 64 x 64 output tile per block of four waves (each
+// wave a 32 x 32 sub-tile from 2 x 2 fp64 MFMA 16x16x4 blocks).  Per 16
+// values of x the block forms the A and B operand tiles in LDS: thread t
+// forms column t % 64 of both at rows t / 64 + 4q, each element the product
+// of its side's operand reads at that x.  The raw reads of the next 16
+// values are issued before the MFMAs of the current ones.  Tiles are
+// k-major with a row pitch of 80 doubles, so the fragment reads of the two
+// half-waves fall in different banks.  Rows and columns past M or N and x
+// past the chunk read clamped (valid) addresses and are multiplied by zero.
+constexpr int kKrBK = 16, kKrPitch = kLrKrTile + 16;
+
 template <int NL, int NR>
 __device__ __forceinline__ void kr_tile(const LrKrDesc &st, const double *const *__restrict__ tab,
-                                        uint32_t c, uint32_t tm, uint32_t tn) {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+                                        uint32_t c, uint32_t tm, uint32_t tn, double *As,
+                                        double *Bs) {
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int lr = lane & 15, lg = lane >> 4;
-    const uint32_t r0 = tm * kLrKrTile + (wv >> 1) * 32, c0 = tn * kLrKrTile + (wv & 1) * 32;
-    gptr pl[NL > 0 ? NL : 1], pr[NR];
-    uint32_t ol[2][NL > 0 ? NL : 1], orr[2][NR], sl[NL > 0 ? NL : 1], sr[NR];
-    double zl[2], zr[2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        const uint32_t row = r0 + 16 * i + lr, col = c0 + 16 * i + lr;
-        zl[i] = row < (uint32_t)st.M ? 1.0 : 0.0;
-        zr[i] = col < (uint32_t)st.N ? 1.0 : 0.0;
-        const uint32_t rc = min(row, (uint32_t)st.M - 1), cc = min(col, (uint32_t)st.N - 1);
-#pragma unroll
-        for (int u = 0; u < NL; ++u) ol[i][u] = side_offset(rc, st.ndl, st.dl, st.st[u]);
-#pragma unroll
-        for (int u = 0; u < NR; ++u) orr[i][u] = side_offset(cc, st.ndr, st.dr, st.st[kLrKrSide + u]);
-    }
+    const int wm = (wv >> 1) * 32, wn = (wv & 1) * 32;
+    const uint32_t il = tm * kLrKrTile + (tid & 63), ir = tn * kLrKrTile + (tid & 63);
+    const double zl = il < (uint32_t)st.M ? 1.0 : 0.0, zr = ir < (uint32_t)st.N ? 1.0 : 0.0;
+    const uint32_t ilc = min(il, (uint32_t)st.M - 1), irc = min(ir, (uint32_t)st.N - 1);
+    gptr pl[NL], pr[NR];
+    uint32_t ol[NL], orr[NR], sl[NL], sr[NR];
 #pragma unroll
     for (int u = 0; u < NL; ++u) {
         pl[u] = (gptr)(tab[st.slot[u]] + st.base[u]);
         sl[u] = (uint32_t)st.sx[u];
+        ol[u] = side_offset(ilc, st.ndl, st.dl, st.st[u]);
     }
 #pragma unroll
     for (int u = 0; u < NR; ++u) {
         pr[u] = (gptr)(tab[st.slot[kLrKrSide + u]] + st.base[kLrKrSide + u]);
         sr[u] = (uint32_t)st.sx[kLrKrSide + u];
+        orr[u] = side_offset(irc, st.ndr, st.dr, st.st[kLrKrSide + u]);
     }
     const uint32_t x0 = c * (uint32_t)st.xchunk;
     const uint32_t x1 = min((uint32_t)st.nx, x0 + (uint32_t)st.xchunk);
@@ -175,61 +172,62 @@ __device__ __forceinline__ void kr_tile(const LrKrDesc &st, const double *const 
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f64x4{0, 0, 0, 0};
-    // raw operand reads for x = xq + lg (clamped), issued one step ahead of
-    // the products and MFMAs that consume them
-    double ra[2][NL > 0 ? NL : 1], rb[2][NR];
-    auto fetch = [&](uint32_t xq, double (&fa)[2][NL > 0 ? NL : 1], double (&fb)[2][NR]) {
-        const uint32_t xc = min(xq + lg, x1 - 1);
+    double ra[kKrBK / 4][NL], rb[kKrBK / 4][NR];
+    auto fetch = [&](uint32_t xb) {
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
+        for (int q = 0; q < kKrBK / 4; ++q) {
+            const uint32_t xc = min(xb + wv + 4 * q, x1 - 1);
 #pragma unroll
-            for (int u = 0; u < NL; ++u) fa[i][u] = pl[u][ol[i][u] + xc * sl[u]];
+            for (int u = 0; u < NL; ++u) ra[q][u] = pl[u][ol[u] + xc * sl[u]];
 #pragma unroll
-            for (int u = 0; u < NR; ++u) fb[i][u] = pr[u][orr[i][u] + xc * sr[u]];
+            for (int u = 0; u < NR; ++u) rb[q][u] = pr[u][orr[u] + xc * sr[u]];
         }
     };
-    fetch(x0, ra, rb);
-    for (uint32_t xq = x0; xq < x1; xq += 4) {
-        double na[2][NL > 0 ? NL : 1], nb[2][NR];
-        fetch(xq + 4, na, nb);
-        const double z = xq + lg < x1 ? 1.0 : 0.0;
-        double a[2], b[2];
+    fetch(x0);
+    for (uint32_t xb = x0; xb < x1; xb += kKrBK) {
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            double va = zl[i] * z, vb = zr[i];
+        for (int q = 0; q < kKrBK / 4; ++q) {
+            double a = xb + wv + 4 * q < x1 ? zl : 0.0, b = zr;
 #pragma unroll
-            for (int u = 0; u < NL; ++u) va *= ra[i][u];
+            for (int u = 0; u < NL; ++u) a *= ra[q][u];
 #pragma unroll
-            for (int u = 0; u < NR; ++u) vb *= rb[i][u];
-            a[i] = va;
-            b[i] = vb;
+            for (int u = 0; u < NR; ++u) b *= rb[q][u];
+            As[(wv + 4 * q) * kKrPitch + (tid & 63)] = a;
+            Bs[(wv + 4 * q) * kKrPitch + (tid & 63)] = b;
         }
+        __syncthreads();
+        fetch(xb + kKrBK);  // past x1: clamped reads, unused
+        // keep those reads above the MFMAs (the scheduler would sink them
+        // to their uses at the top of the next step)
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int kk = 0; kk < kKrBK; kk += 4) {
+            double a[2], b[2];
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+            for (int i = 0; i < 2; ++i) a[i] = As[(kk + lg) * kKrPitch + wm + 16 * i + lr];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
+            for (int j = 0; j < 2; ++j) b[j] = Bs[(kk + lg) * kKrPitch + wn + 16 * j + lr];
 #pragma unroll
-            for (int u = 0; u < NL; ++u) ra[i][u] = na[i][u];
+            for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int u = 0; u < NR; ++u) rb[i][u] = nb[i][u];
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
         }
+        __syncthreads();
     }
-    // accumulator element r of block (i, j): row r0 + 16 i + lg + 4 r,
-    // column c0 + 16 j + lr
+    // accumulator element r of block (i, j): tile row wm + 16 i + lg + 4 r,
+    // tile column wn + 16 j + lr
     double *o = const_cast<double *>(tab[0]) + st.out + (int64_t)c * st.nout;
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-        const uint32_t col = c0 + 16 * j + lr;
+        const uint32_t col = tn * kLrKrTile + wn + 16 * j + lr;
         if (col >= (uint32_t)st.N) continue;
         const uint32_t co = side_offset(col, st.ndr, st.dr, st.orr);
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const uint32_t row = r0 + 16 * i + lg + 4 * r;
+                const uint32_t row = tm * kLrKrTile + wm + 16 * i + lg + 4 * r;
                 if (row < (uint32_t)st.M) o[side_offset(row, st.ndl, st.dl, st.ol) + co] = acc[i][j][r];
             }
     }
@@ -238,6 +236,7 @@ __device__ __forceinline__ void kr_tile(const LrKrDesc &st, const double *const 
 __global__ __launch_bounds__(kLrThreads) void k_lr_kr(const LrKrDesc *__restrict__ desc,
                                                       int64_t nkr,
                                                       const double *const *__restrict__ tab) {
+    __shared__ double As[kKrBK * kKrPitch], Bs[kKrBK * kKrPitch];
     const int64_t b = blockIdx.x;
     const LrKrDesc &st = desc[find_step(desc, nkr, b)];
     const uint32_t bi = (uint32_t)(b - st.block0);
@@ -245,7 +244,7 @@ __global__ __launch_bounds__(kLrThreads) void k_lr_kr(const LrKrDesc *__restrict
     const uint32_t tm = t / st.tiles_n, tn = t - tm * st.tiles_n;
     switch (st.nl * 8 + st.nr) {
 #define KR_CASE(L, R) \
-    case L * 8 + R: kr_tile<L, R>(st, tab, c, tm, tn); break;
+    case L * 8 + R: kr_tile<L, R>(st, tab, c, tm, tn, As, Bs); break;
         KR_CASE(1, 1) KR_CASE(1, 2) KR_CASE(1, 3) KR_CASE(1, 4)
         KR_CASE(2, 1) KR_CASE(2, 2) KR_CASE(2, 3) KR_CASE(2, 4)
         KR_CASE(3, 1) KR_CASE(3, 2) KR_CASE(3, 3) KR_CASE(3, 4)

@@ -49,6 +49,12 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def short_name(name: str) -> str:
+    """Kernel name without its argument list (and without the anonymous
+    namespace qualifier, whose parentheses would cut it short)."""
+    return name.replace("(anonymous namespace)::", "").split("(")[0]
+
+
 def kernel_stats(db: str):
     """[(name, calls, total_us, average_us, percent)] from a kernel trace."""
     con = sqlite3.connect(db)
@@ -173,7 +179,7 @@ def main(argv=None):
                  "|---|---|---|---|---|"]
         for k, nd, f, us, rate in rows:
             r = "-" if rate is None else f"{rate:.4f}"
-            lines.append(f"| `{k.split('(')[0]}` | {nd} | {f:.3f} | {us:.1f} | {r} |")
+            lines.append(f"| `{short_name(k)}` | {nd} | {f:.3f} | {us:.1f} | {r} |")
         print("\n".join(lines))
         if args.md:
             with open(args.md, "w") as f:
@@ -201,14 +207,14 @@ def main(argv=None):
                 f.write("Durations in microseconds (rocprofv3 kernel trace).\n\n")
                 f.write("| kernel | calls | total_us | avg_us | pct |\n|---|---|---|---|---|\n")
                 for n, c, tot, avg, pct in stats:
-                    f.write(f"| `{n.split('(')[0]}` | {c} | {tot:.1f} | {avg:.2f} | {pct:.2f} |\n")
+                    f.write(f"| `{short_name(n)}` | {c} | {tot:.1f} | {avg:.2f} | {pct:.2f} |\n")
                 res = dispatch_resources(args.db)
                 if res:
                     f.write("\nPer-dispatch resources (first dispatch of each kernel):\n\n")
                     f.write("| kernel | grid | workgroup | lds | vgpr | agpr | scratch |\n"
                             "|---|---|---|---|---|---|---|\n")
                     for r in res:
-                        f.write("| `" + r[0].split("(")[0] + "` | " + " | ".join(str(x) for x in r[1:]) + " |\n")
+                        f.write("| `" + short_name(r[0]) + "` | " + " | ".join(str(x) for x in r[1:]) + " |\n")
         return 0
     rec = traffic(args.fetch, args.write, args.cal_fetch, args.cal_write, args.cal_bytes,
                   args.kernel)
