@@ -354,8 +354,10 @@ ustat_status ustat_lowrank_info(ustat_plan plan, int64_t n, int32_t r, const int
 /*
  * Build the RBF factor matrix alone (Algorithm 1 for the RBF kernel):
  * out (device, n x n) receives exp(-||X_i - X_j||^2 / rbf_divisor) with the
- * squared distance formed in fp64 from direct differences; precision
- * USTAT_F64 writes double, USTAT_F32 writes float (rounded once).
+ * squared distance formed in fp64 as ||X_i||^2 + ||X_j||^2 - 2 X_i.X_j (the
+ * Gram term on fp64 MFMA, the result clamped at 0), the diagonal exactly 1
+ * and the matrix exactly symmetric; precision USTAT_F64 writes double,
+ * USTAT_F32 writes float (rounded once).
  */
 ustat_status ustat_build_rbf(int64_t n, int32_t d, const double *X, double rbf_divisor,
                              int32_t precision, void *out, ustat_stream stream);

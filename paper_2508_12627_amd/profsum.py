@@ -4,7 +4,7 @@
         per-kernel calls, total and average duration (kernel trace)
     python -m paper_2508_12627_amd.profsum traffic --fetch F.db --write W.db \\
         --cal-fetch CF.db --cal-write CW.db --cal-bytes B --kernel NAME [--out T.json]
-        [--meta KEY=VALUE ...]
+        [--path dense|lowrank] [--meta KEY=VALUE ...]
         HBM bytes per launch of the kernels whose name contains NAME, from
         FETCH_SIZE and WRITE_SIZE runs, each scaled by what the same counter
         reads for a plain device copy of B bytes (the calibration runs)
@@ -41,9 +41,18 @@ def kernel_sources():
     return [os.path.join(d, f) for f in names if f not in _OTHER_PATHS]
 
 
-def kernel_source_hash() -> str:
+def lowrank_sources():
+    """Device code of the low-rank path: its kernels and the descriptor
+    header they include."""
+    d = os.path.join(HERE, "csrc")
+    return [os.path.join(d, f) for f in ("k_lowrank.hip", "lowrank.hpp")]
+
+
+def kernel_source_hash(path: str = "dense") -> str:
+    """Hash of the device sources of one evaluation path ("dense" or
+    "lowrank")."""
     h = hashlib.sha256()
-    for p in kernel_sources():
+    for p in (lowrank_sources() if path == "lowrank" else kernel_sources()):
         with open(p, "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -122,7 +131,7 @@ def mfma_busy(db: str):
     return out
 
 
-def traffic(fetch_db, write_db, cal_fetch_db, cal_write_db, cal_bytes, kernel):
+def traffic(fetch_db, write_db, cal_fetch_db, cal_write_db, cal_bytes, kernel, path="dense"):
     """Per-launch HBM bytes of the matching kernels, calibrated on a copy."""
     cf = counter_per_dispatch(cal_fetch_db, "FETCH_SIZE")
     cw = counter_per_dispatch(cal_write_db, "WRITE_SIZE")
@@ -135,7 +144,7 @@ def traffic(fetch_db, write_db, cal_fetch_db, cal_write_db, cal_bytes, kernel):
     w = counter_per_dispatch(write_db, "WRITE_SIZE")
     out = {"calibration": {"copy_bytes": cal_bytes, "fetch_kib": cf_kib, "write_kib": cw_kib,
                            "fetch_scale": fs, "write_scale": ws},
-           "source_hash": kernel_source_hash(), "kernels": {}}
+           "source_hash": kernel_source_hash(path), "path": path, "kernels": {}}
     for name in sorted(set(f) | set(w)):
         if kernel not in name:
             continue
@@ -163,6 +172,8 @@ def main(argv=None):
         t.add_argument(a, required=True)
     t.add_argument("--cal-bytes", type=float, required=True)
     t.add_argument("--kernel", required=True)
+    t.add_argument("--path", default="dense", choices=["dense", "lowrank"],
+                   help="whose device sources the record's hash covers")
     t.add_argument("--out", default=None)
     t.add_argument("--meta", action="append", default=[], metavar="KEY=VALUE",
                    help="extra fields of the record (workload, precision, command)")
@@ -217,7 +228,7 @@ def main(argv=None):
                         f.write("| `" + short_name(r[0]) + "` | " + " | ".join(str(x) for x in r[1:]) + " |\n")
         return 0
     rec = traffic(args.fetch, args.write, args.cal_fetch, args.cal_write, args.cal_bytes,
-                  args.kernel)
+                  args.kernel, args.path)
     for kv in args.meta:
         k, _, v = kv.partition("=")
         rec[k] = v
