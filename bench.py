@@ -249,10 +249,28 @@ def bench_cycle5_exact(args):
             r = plan.eval([Ad] * 5)
         torch.cuda.synchronize()
         el = (time.perf_counter() - t0) / steps
-        out["sparsified" if sp else "full"] = {"ms_per_eval": 1e3 * el, "U": str(r.exact),
-                                               "cycles": str(r.exact // 10),
-                                               "num_vstats": r.num_vstats}
-    out["value"] = 1e3 / out["full"]["ms_per_eval"]
+        rec = {"ms_per_eval": 1e3 * el, "U": str(r.exact), "cycles": str(r.exact // 10),
+               "num_vstats": r.num_vstats}
+        # live GEMM timing (HIP events) of one evaluation: algorithmic
+        # 2 n^3 integer multiply-adds per product against the int8 MFMA peak
+        U.ustat_profile_enable(True)
+        U.ustat_profile_reset()
+        plan.eval([Ad] * 5)
+        g = U.ustat_profile_read("gemm")
+        U.ustat_profile_enable(False)
+        if g["ms"] > 0:
+            ach = g["flops"] / (g["ms"] * 1e-3)
+            rec["roofline"] = {"kernel": "k_gemm<i8>", "bound": "mfma", "achieved": ach / 1e12,
+                               "peak": 5000.0, "unit": "TOP/s", "frac": ach / 5.0e15,
+                               "traffic": None, "launches_per_eval": g["launches"],
+                               "avg_launch_ms": g["ms"] / max(1, g["launches"]),
+                               "ops_per_eval": g["flops"]}
+        out["sparsified" if sp else "full"] = rec
+    # the sparsified program (Lemma 3) is the faster one; both are reported
+    best = min(("full", "sparsified"), key=lambda k: out[k]["ms_per_eval"])
+    out["value"] = 1e3 / out[best]["ms_per_eval"]
+    out["value_from"] = best
+    out["roofline"] = out[best].get("roofline")
     print(json.dumps(out))
 
 

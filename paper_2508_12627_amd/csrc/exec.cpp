@@ -492,7 +492,8 @@ void clone_slices(Dag &G, const std::vector<Inst> &insts) {
 }
 
 std::string build_dag(const Plan &plan, const std::vector<const VProgram *> &progs,
-                      const std::vector<Dataset> &data, bool cse, const SliceRange &range, Dag &G) {
+                      const std::vector<Dataset> &data, bool cse, const SliceRange &range, Dag &G,
+                      const std::vector<char> &in_binary = std::vector<char>()) {
     const int nd = (int)data.size();
     // programs of dataset d are numbered poff[d] .. poff[d + 1] - 1
     std::vector<int> poff(nd + 1, 0);
@@ -571,6 +572,25 @@ std::string build_dag(const Plan &plan, const std::vector<const VProgram *> &pro
                 return MOp{r.node, r.p, (bool)(o.trans ^ r.flip)};
             };
             auto vop = [&](int v) { return VOp{ref[v].node, ref[v].p, ref[v].off}; };
+            // A Hadamard group that repeats a 0/1 input (in the same
+            // orientation) keeps one copy: M o M = M entry by entry.
+            auto binary_input = [&](const void *ptr) {
+                if (in_binary.empty()) return false;
+                const int ne_ = (int)data[d].factors.size();
+                for (int k = 0; k < ne_; ++k)
+                    if (data[d].factors[k] == ptr) return in_binary[(size_t)d * ne_ + k] != 0;
+                return false;
+            };
+            auto dedupe = [&](std::vector<MOp> &L) {
+                std::vector<MOp> keep;
+                for (const MOp &o : L) {
+                    bool dup = false;
+                    if (o.node < 0 && binary_input(o.p))
+                        for (const MOp &q : keep) dup = dup || (q.node < 0 && q.p == o.p && q.trans == o.trans);
+                    if (!dup) keep.push_back(o);
+                }
+                L.swap(keep);
+            };
             const int dp = poff[d] + p;
             std::vector<int> term;
             for (const Step &st : pr.steps) {
@@ -579,6 +599,9 @@ std::string build_dag(const Plan &plan, const std::vector<const VProgram *> &pro
                 for (auto &o : st.A) A.push_back(mop(o));
                 for (auto &o : st.B) B.push_back(mop(o));
                 for (auto &o : st.Z) Z.push_back(mop(o));
+                dedupe(A);
+                dedupe(B);
+                dedupe(Z);
                 for (int q : st.sv) sv.push_back(vop(q));
                 for (int q : st.aw) aw.push_back(vop(q));
                 for (int q : st.bx) bx.push_back(vop(q));
@@ -906,7 +929,8 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
                            const std::vector<double> &in_bound,  // per dataset*edge (INT)
                            const std::vector<char> &in_signed,   // per dataset*edge, empty: none
                            char *base, Schedule &S, int *status,
-                           const SliceRange &range = SliceRange()) {
+                           const SliceRange &range = SliceRange(),
+                           const std::vector<char> &in_binary = std::vector<char>()) {
     S = Schedule();
     Arena A;
     const int nd = (int)data.size();
@@ -916,7 +940,7 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
     S.nprog_total = poff[nd];
     auto P = [&](size_t off) -> void * { return base ? (void *)(base + off) : nullptr; };
     Dag G;
-    std::string err = build_dag(plan, progs, data, plan.opts.cse, range, G);
+    std::string err = build_dag(plan, progs, data, plan.opts.cse, range, G, in_binary);
     if (!err.empty()) {
         *status = 1;
         return err;
@@ -1708,6 +1732,7 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
         }
     }
     std::vector<double> in_bound;
+    std::vector<char> in_binary;  // per dataset*edge (INT): all entries 0 or 1
     Profiler *prof = Profiler::active();
     if (cfg.domain == DOM_INT) {
         // Exact path: the a-priori bounds start from the inputs' true
@@ -1720,7 +1745,7 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
                 ns.push_back(d.n);
             }
         size_t cnt = srcs.size();
-        size_t bytes = cnt * (8 + 8 + 8);
+        size_t bytes = cnt * (8 + 8 + 16);
         char *dpre, *hpre, *hmx;
         if (ext) {
             // the start of the external region; done with before the
@@ -1729,13 +1754,13 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
                 *status = 6;
                 return "the input maxima pass needs more than the external workspace";
             }
-            hstage_ext.assign(cnt * 24, 0);
+            hstage_ext.assign(cnt * 32, 0);
             dpre = ext->base;
             hpre = hstage_ext.data();
             hmx = hstage_ext.data() + cnt * 16;
         } else {
             ALLOCCHK(rt.reserve_desc(bytes + 1024));
-            ALLOCCHK(rt.reserve_hres(cnt * 8 + 64));
+            ALLOCCHK(rt.reserve_hres(cnt * 16 + 64));
             dpre = rt.ddesc;
             hpre = rt.hdesc;
             hmx = rt.hres;
@@ -1744,16 +1769,20 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
         std::memcpy(hpre + cnt * 8, ns.data(), cnt * 8);
         HIPCHK(hipMemcpyAsync(dpre, hpre, cnt * 16, hipMemcpyHostToDevice, stream));
         unsigned long long *dmx = reinterpret_cast<unsigned long long *>(dpre + cnt * 16);
-        hipLaunchKernelGGL(k_fill_zero, dim3(1), dim3(256), 0, stream, dmx, cnt);
+        hipLaunchKernelGGL(k_fill_zero, dim3(1), dim3(256), 0, stream, dmx, 2 * cnt);
         HIPCHK(hipGetLastError());
         HIPCHK(launch_absmax_i8(reinterpret_cast<const int8_t *const *>(dpre),
                                 reinterpret_cast<const int64_t *>(dpre + cnt * 8), (int)cnt,
                                 dmx, stream));
-        HIPCHK(hipMemcpyAsync(hmx, dmx, cnt * 8, hipMemcpyDeviceToHost, stream));
+        HIPCHK(hipMemcpyAsync(hmx, dmx, cnt * 16, hipMemcpyDeviceToHost, stream));
         HIPCHK(hipStreamSynchronize(stream));
         in_bound.resize(cnt);
-        for (size_t i = 0; i < cnt; ++i)
-            in_bound[i] = (double)reinterpret_cast<unsigned long long *>(hmx)[i];
+        in_binary.assign(cnt, 0);
+        const unsigned long long *hm = reinterpret_cast<const unsigned long long *>(hmx);
+        for (size_t i = 0; i < cnt; ++i) {
+            in_bound[i] = (double)hm[i];
+            in_binary[i] = hm[i] <= 1 && hm[cnt + i] == 0;  // every entry 0 or 1
+        }
     }
     // The layout is deterministic: build once against the arena already
     // held and keep the result when it fits; otherwise size it, grow the
@@ -1765,7 +1794,8 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
     char *arena = rt.arena, *vacc = rt.vacc, *hres = rt.hres, *hdesc = rt.hdesc;
     const int nd = (int)data.size();
     if (ext) {
-        err = build_schedule(plan, progs, data, cfg, in_bound, in_signed, ext->base, S, status, range);
+        err = build_schedule(plan, progs, data, cfg, in_bound, in_signed, ext->base, S, status, range,
+                             in_binary);
         if (!err.empty()) return err;
         const size_t nres_ext = (size_t)S.nprog_total * cfg.wide_es + (size_t)nd * cfg.wide_es + (size_t)nd * 8;
         const size_t need = up(S.arena_bytes, kAlign) + up(S.blob_bytes, kAlign) + S.n_inmx * 8 +
@@ -1783,11 +1813,13 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
         hdesc = hstage_ext.data();
         built = true;
     } else if (rt.arena) {
-        err = build_schedule(plan, progs, data, cfg, in_bound, in_signed, rt.arena, S, status, range);
+        err = build_schedule(plan, progs, data, cfg, in_bound, in_signed, rt.arena, S, status, range,
+                             in_binary);
         if (!err.empty()) return err;
         built = S.arena_bytes <= rt.arena_bytes;
     } else {
-        err = build_schedule(plan, progs, data, cfg, in_bound, in_signed, nullptr, S, status, range);
+        err = build_schedule(plan, progs, data, cfg, in_bound, in_signed, nullptr, S, status, range,
+                             in_binary);
         if (!err.empty()) return err;
     }
     if (plan.opts.workspace_limit && S.arena_bytes > plan.opts.workspace_limit) {
@@ -1800,7 +1832,8 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
             *status = 3;
             return std::string("device workspace allocation failed: ") + hipGetErrorString(e);
         }
-        err = build_schedule(plan, progs, data, cfg, in_bound, in_signed, rt.arena, S, status, range);
+        err = build_schedule(plan, progs, data, cfg, in_bound, in_signed, rt.arena, S, status, range,
+                             in_binary);
         if (!err.empty()) return err;
         arena = rt.arena;
     }

@@ -252,19 +252,25 @@ __global__ void k_absmax_i8(const int8_t *const *src, const int64_t *n, int npro
     const int p = blockIdx.y;
     const int8_t *a = src[p];
     const int64_t cnt = n[p] * n[p];
-    int best = 0;
+    int best = 0, neg = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
          i += (int64_t)gridDim.x * blockDim.x) {
         int v = a[i];
         best = max(best, v < 0 ? -v : v);
+        neg |= v < 0;
     }
-    __shared__ int red[256];
+    __shared__ int red[256], rneg[256];
     red[threadIdx.x] = best;
+    rneg[threadIdx.x] = neg;
     __syncthreads();
     if (threadIdx.x == 0) {
-        int m = 0;
-        for (int q = 0; q < 256; ++q) m = max(m, red[q]);
+        int m = 0, ng = 0;
+        for (int q = 0; q < 256; ++q) {
+            m = max(m, red[q]);
+            ng |= rneg[q];
+        }
         atomicMax(&mx[p], (unsigned long long)m);
+        if (ng) atomicMax(&mx[nprob + p], 1ull);
     }
 }
 

@@ -242,6 +242,8 @@ hipError_t launch_signscan(const void *const *src, const int64_t *n, int nprob, 
 // diagonal; dbad is device scratch.  Synchronises s.
 hipError_t launch_motif_complement(const int8_t *A, int8_t *B, int64_t n, unsigned int *dbad,
                                    unsigned int *hbad, hipStream_t s);
+// mx[p] = max |entry| of int8 matrix p, mx[nprob + p] = 1 if it has a
+// negative entry (mx zeroed by the caller, 2 nprob words).
 hipError_t launch_absmax_i8(const int8_t *const *src, const int64_t *n, int nprob,
                             unsigned long long *mx, hipStream_t s);
 hipError_t launch_slicesrc(const SliceDesc *d, int nprob, int64_t total_tiles, int domain,
