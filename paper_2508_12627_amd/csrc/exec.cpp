@@ -1737,12 +1737,20 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
     if (cfg.domain == DOM_INT) {
         // Exact path: the a-priori bounds start from the inputs' true
         // maxima (one small device-to-host copy).
+        // one scan per distinct matrix; slot_of maps (dataset, edge) to it
         std::vector<const int8_t *> srcs;
         std::vector<int64_t> ns;
+        std::vector<size_t> slot_of;
         for (auto &d : data)
             for (int k = 0; k < ne; ++k) {
-                srcs.push_back(static_cast<const int8_t *>(d.factors[k]));
-                ns.push_back(d.n);
+                const int8_t *ptr = static_cast<const int8_t *>(d.factors[k]);
+                size_t j = 0;
+                while (j < srcs.size() && !(srcs[j] == ptr && ns[j] == d.n)) ++j;
+                if (j == srcs.size()) {
+                    srcs.push_back(ptr);
+                    ns.push_back(d.n);
+                }
+                slot_of.push_back(j);
             }
         size_t cnt = srcs.size();
         size_t bytes = cnt * (8 + 8 + 16);
@@ -1776,12 +1784,14 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
                                 dmx, stream));
         HIPCHK(hipMemcpyAsync(hmx, dmx, cnt * 16, hipMemcpyDeviceToHost, stream));
         HIPCHK(hipStreamSynchronize(stream));
-        in_bound.resize(cnt);
-        in_binary.assign(cnt, 0);
+        const size_t nin = slot_of.size();
+        in_bound.resize(nin);
+        in_binary.assign(nin, 0);
         const unsigned long long *hm = reinterpret_cast<const unsigned long long *>(hmx);
-        for (size_t i = 0; i < cnt; ++i) {
-            in_bound[i] = (double)hm[i];
-            in_binary[i] = hm[i] <= 1 && hm[cnt + i] == 0;  // every entry 0 or 1
+        for (size_t i = 0; i < nin; ++i) {
+            const size_t j = slot_of[i];
+            in_bound[i] = (double)hm[j];
+            in_binary[i] = hm[j] <= 1 && hm[cnt + j] == 0;  // every entry 0 or 1
         }
     }
     // The layout is deterministic: build once against the arena already

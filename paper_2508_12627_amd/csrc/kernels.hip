@@ -247,17 +247,36 @@ hipError_t launch_motif_complement(const int8_t *A, int8_t *B, int64_t n, unsign
 }
 
 // Largest |entry| of int8 matrices (one running max per problem).
-__global__ void k_absmax_i8(const int8_t *const *src, const int64_t *n, int nprob,
-                            unsigned long long *mx) {
+__global__ __launch_bounds__(256) void k_absmax_i8(const int8_t *const *src, const int64_t *n,
+                                                    int nprob, unsigned long long *mx) {
     const int p = blockIdx.y;
     const int8_t *a = src[p];
     const int64_t cnt = n[p] * n[p];
     int best = 0, neg = 0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        int v = a[i];
-        best = max(best, v < 0 ? -v : v);
-        neg |= v < 0;
+    // 16 entries per load where the matrix allows it (hipMalloc'd buffers
+    // are 256-byte aligned; cnt a multiple of 16), single bytes otherwise
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (((uintptr_t)a & 15) == 0 && (cnt & 15) == 0) {
+        const uint4 *a16 = reinterpret_cast<const uint4 *>(a);
+        for (int64_t i = t0; i < cnt / 16; i += stride) {
+            const uint4 q = a16[i];
+            const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int v = (int8_t)(w[k] >> (8 * b));
+                    best = max(best, v < 0 ? -v : v);
+                    neg |= v < 0;
+                }
+        }
+    } else {
+        for (int64_t i = t0; i < cnt; i += stride) {
+            const int v = a[i];
+            best = max(best, v < 0 ? -v : v);
+            neg |= v < 0;
+        }
     }
     __shared__ int red[256], rneg[256];
     red[threadIdx.x] = best;
@@ -618,7 +637,7 @@ hipError_t launch_signscan(const void *const *src, const int64_t *n, int nprob, 
 
 hipError_t launch_absmax_i8(const int8_t *const *src, const int64_t *n, int nprob,
                             unsigned long long *mx, hipStream_t s) {
-    hipLaunchKernelGGL(k_absmax_i8, dim3(64, (unsigned)nprob), dim3(256), 0, s, src, n, nprob, mx);
+    hipLaunchKernelGGL(k_absmax_i8, dim3(512, (unsigned)nprob), dim3(256), 0, s, src, n, nprob, mx);
     return hipGetLastError();
 }
 
