@@ -213,6 +213,23 @@ ustat_status ustat_plan_autotune(ustat_plan plan, int64_t n, const void *const *
                                  ustat_stream stream, int32_t reps, double *ms);
 
 /*
+ * The same search for a batch of sample sets (arguments as
+ * ustat_eval_batched): every candidate times whole batched evaluations, so
+ * the choice accounts for how the datasets' steps share launches.
+ *
+ * Both autotuning calls keep a per-device cache when the environment
+ * variable USTAT_TUNE_CACHE names a writable file: a result is stored under
+ * a key of the device (architecture and compute-unit count), the plan
+ * (graph, precision, order policy, options) and the shape (log2 buckets of
+ * n, or of the batch's largest and total n, the batch size and d); a later
+ * call with the same key applies the stored tuning and returns its time
+ * without measuring.
+ */
+ustat_status ustat_plan_autotune_batched(ustat_plan plan, int32_t batch, const int64_t *n, int32_t d,
+                                         const double *const *X, double rbf_divisor,
+                                         ustat_stream stream, int32_t reps, double *ms);
+
+/*
  * Partition idx (0 <= idx < num_vstats) in restricted-growth form:
  * block_of (host int32 [m]) gives each vertex's block, blocks numbered in
  * order of first appearance; *mu its Moebius coefficient; *tw the exact

@@ -6,6 +6,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <limits>
@@ -301,6 +303,116 @@ ustat_status ustat_graph_treewidth(int32_t m, int32_t num_edges, const int32_t *
     USTAT_GUARD_END
 }
 
+}  // extern "C"
+
+namespace {
+
+int log2_bucket(int64_t x) {
+    int b = 0;
+    while ((int64_t(1) << b) < x && b < 62) ++b;
+    return b;
+}
+
+// Cache key of an autotuning result: the device (architecture and compute
+// units), the plan (graph, precision, order policy, options) and the shape.
+std::string tune_key(ustat_plan plan, const std::string &shape) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    std::string devs = "unknown";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        devs = std::string(prop.gcnArchName) + "/" + std::to_string(prop.multiProcessorCount);
+    const PlanOptions &o = plan->plan.opts;
+    std::string k = devs + "|m" + std::to_string(plan->plan.m) + "|e";
+    for (const Edge &e : plan->plan.edges) k += std::to_string(e.u) + "-" + std::to_string(e.v) + ",";
+    k += "|p" + std::to_string(o.precision) + "|o" + std::to_string(o.order) + "|s" +
+         std::to_string(o.sparsify) + "|y" + std::to_string((int)o.symmetric) + "|c" +
+         std::to_string((int)o.cse) + "|" + shape;
+    for (char &ch : k)
+        if (ch == ' ' || ch == '\n') ch = '_';
+    return k;
+}
+
+// The per-device tuning cache: a text file named by USTAT_TUNE_CACHE, one
+// line "key gemm_big_min colred_blocks ms" per tuned shape.
+bool tune_cache_lookup(ustat_plan plan, const std::string &key, double *ms) {
+    const char *path = std::getenv("USTAT_TUNE_CACHE");
+    if (!path || !*path) return false;
+    std::FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[4096];
+    bool found = false;
+    while (std::fgets(line, sizeof line, f)) {
+        char k[3900];
+        long long gb = 0, cb = 0;
+        double t = 0;
+        if (std::sscanf(line, "%3899s %lld %lld %lf", k, &gb, &cb, &t) == 4 && key == k && cb >= 1 &&
+            cb <= (1 << 20) && gb >= 0) {
+            plan->plan.tuning.gemm_big_min = gb;
+            plan->plan.tuning.colred_blocks = cb;
+            if (ms) *ms = t;
+            found = true;  // the last matching line wins
+        }
+    }
+    std::fclose(f);
+    if (found) plan->rt.drop_graphs();
+    return found;
+}
+
+void tune_cache_store(ustat_plan plan, const std::string &key, double ms) {
+    const char *path = std::getenv("USTAT_TUNE_CACHE");
+    if (!path || !*path || key.size() >= 3900) return;
+    std::FILE *f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s %lld %lld %.6f\n", key.c_str(), (long long)plan->plan.tuning.gemm_big_min,
+                 (long long)plan->plan.tuning.colred_blocks, ms);
+    std::fclose(f);
+}
+
+// Every candidate tuning (gemm_big_min in {256, 0, never} for fp32 and
+// split-bf16, colred_blocks in {256, 1024, 4096}): one warm-up evaluation
+// (which captures the graph), then the best of reps timed evaluations; the
+// fastest candidate is kept, the previous tuning restored on error.
+ustat_status tune_loop(ustat_plan plan, int32_t reps, const std::function<ustat_status()> &eval,
+                       double *best_ms) {
+    const int prec = plan->plan.opts.precision;
+    std::vector<int64_t> gbs = {256};
+    if (prec == USTAT_F32 || prec == USTAT_BF16X3) gbs = {256, 0, int64_t(1) << 62};
+    const int64_t cbs[3] = {256, 1024, 4096};
+    const Tuning keep = plan->plan.tuning;
+    Tuning best = keep;
+    double best_s = std::numeric_limits<double>::infinity();
+    ustat_status st = USTAT_OK;
+    for (int64_t gb : gbs) {
+        for (int64_t cb : cbs) {
+            plan->plan.tuning.gemm_big_min = gb;
+            plan->plan.tuning.colred_blocks = cb;
+            plan->rt.drop_graphs();
+            st = eval();
+            if (st != USTAT_OK) break;
+            double t = std::numeric_limits<double>::infinity();
+            for (int r = 0; r < reps && st == USTAT_OK; ++r) {
+                auto t0 = std::chrono::steady_clock::now();
+                st = eval();
+                t = std::min(t, std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+            }
+            if (st != USTAT_OK) break;
+            if (t < best_s) {
+                best_s = t;
+                best = plan->plan.tuning;
+            }
+        }
+        if (st != USTAT_OK) break;
+    }
+    plan->plan.tuning = st == USTAT_OK ? best : keep;
+    plan->rt.drop_graphs();
+    if (best_ms) *best_ms = best_s * 1e3;
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
 static ustat_status run(ustat_plan plan, const std::vector<const VProgram *> &progs,
                         std::vector<Dataset> &data, hipStream_t s, std::vector<DatasetResult> &res,
                         std::vector<double> *vout, const std::function<hipError_t(hipStream_t)> &pre,
@@ -368,49 +480,53 @@ ustat_status ustat_plan_autotune(ustat_plan plan, int64_t n, const void *const *
         if (!factors[k]) return fail(USTAT_E_INVALID, "a factor pointer is NULL");
         data[0].factors.push_back(factors[k]);
     }
+    const std::string key = tune_key(plan, "single:n" + std::to_string(log2_bucket(n)));
+    if (tune_cache_lookup(plan, key, ms)) return ok();
     hipStream_t s = (hipStream_t)stream;
     bool own = false;
     if (!s) {
         if (hipStreamCreate(&s) != hipSuccess) return fail(USTAT_E_HIP, "stream creation failed");
         own = true;
     }
-    const int prec = plan->plan.opts.precision;
-    std::vector<int64_t> gbs = {256};
-    if (prec == USTAT_F32 || prec == USTAT_BF16X3) gbs = {256, 0, int64_t(1) << 62};
-    const int64_t cbs[3] = {256, 1024, 4096};
-    const Tuning keep = plan->plan.tuning;
-    Tuning best = keep;
-    double best_s = std::numeric_limits<double>::infinity();
-    ustat_status st = USTAT_OK;
-    // each candidate: one captured (or eager) warm-up evaluation, then the
-    // best of reps timed evaluations, each ending in a stream synchronisation
-    for (int64_t gb : gbs)
-        for (int64_t cb : cbs) {
-            plan->plan.tuning.gemm_big_min = gb;
-            plan->plan.tuning.colred_blocks = cb;
-            plan->rt.drop_graphs();
-            std::string key = "tune:" + std::to_string(n);
-            for (auto f : data[0].factors) key += ":" + std::to_string((uintptr_t)f);
-            std::vector<DatasetResult> res;
-            st = run(plan, plan->all, data, s, res, nullptr, nullptr, key);
-            if (st != USTAT_OK) break;
-            double t = std::numeric_limits<double>::infinity();
-            for (int r = 0; r < reps && st == USTAT_OK; ++r) {
-                auto t0 = std::chrono::steady_clock::now();
-                st = run(plan, plan->all, data, s, res, nullptr, nullptr, key);
-                t = std::min(t, std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
-            }
-            if (st != USTAT_OK) break;
-            if (t < best_s) {
-                best_s = t;
-                best = plan->plan.tuning;
-            }
-        }
-    plan->plan.tuning = st == USTAT_OK ? best : keep;
-    plan->rt.drop_graphs();
+    std::string gkey = "tune:" + std::to_string(n);
+    for (auto f : data[0].factors) gkey += ":" + std::to_string((uintptr_t)f);
+    double best_ms = 0;
+    ustat_status st = tune_loop(plan, reps, [&]() {
+        std::vector<DatasetResult> res;
+        return run(plan, plan->all, data, s, res, nullptr, nullptr, gkey);
+    }, &best_ms);
     if (own) (void)hipStreamDestroy(s);
     if (st != USTAT_OK) return st;
-    if (ms) *ms = best_s * 1e3;
+    tune_cache_store(plan, key, best_ms);
+    if (ms) *ms = best_ms;
+    return ok();
+    USTAT_GUARD_END
+}
+
+ustat_status ustat_plan_autotune_batched(ustat_plan plan, int32_t batch, const int64_t *n, int32_t d,
+                                         const double *const *X, double rbf_divisor,
+                                         ustat_stream stream, int32_t reps, double *ms) {
+    USTAT_GUARD_BEGIN
+    if (!plan) return fail(USTAT_E_INVALID, "plan is NULL");
+    if (batch < 1 || !n || !X || d < 1 || d > 256) return fail(USTAT_E_INVALID, "bad arguments");
+    if (reps < 1 || reps > 100) return fail(USTAT_E_INVALID, "reps must be in 1..100");
+    int64_t nmax = 0, ntot = 0;
+    for (int b = 0; b < batch; ++b) {
+        nmax = std::max(nmax, n[b]);
+        ntot += n[b];
+    }
+    const std::string key = tune_key(plan, "batched:b" + std::to_string(batch) + ":n" +
+                                               std::to_string(log2_bucket(nmax)) + ":t" +
+                                               std::to_string(log2_bucket(ntot)) + ":d" + std::to_string(d));
+    if (tune_cache_lookup(plan, key, ms)) return ok();
+    std::vector<ustat_result> out(batch);
+    double best_ms = 0;
+    ustat_status st = tune_loop(plan, reps, [&]() {
+        return ustat_eval_batched(plan, batch, n, d, X, rbf_divisor, stream, out.data());
+    }, &best_ms);
+    if (st != USTAT_OK) return st;
+    tune_cache_store(plan, key, best_ms);
+    if (ms) *ms = best_ms;
     return ok();
     USTAT_GUARD_END
 }

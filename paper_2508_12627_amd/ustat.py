@@ -76,6 +76,7 @@ EXPORTS = ["ustat_plan_opts_default", "ustat_plan_create", "ustat_plan_destroy",
            "ustat_plan_tuning", "ustat_plan_set_tuning", "ustat_plan_autotune",
            "ustat_eval_noalloc", "ustat_debug_inject", "ustat_plan_create_motifs",
            "ustat_motif_counts", "ustat_eval_lowrank", "ustat_lowrank_info",
+           "ustat_plan_autotune_batched",
            "ustat_status_string", "ustat_last_error"]
 NUM_FEATURES = 18
 
@@ -130,6 +131,7 @@ def load_library(path: str = LIB_PATH):
     L.ustat_plan_tuning.argtypes = [P, pi64, pi64]
     L.ustat_plan_set_tuning.argtypes = [P, i64, i64]
     L.ustat_plan_autotune.argtypes = [P, i64, ctypes.POINTER(P), P, i32, pdbl]
+    L.ustat_plan_autotune_batched.argtypes = [P, i32, pi64, i32, ctypes.POINTER(P), dbl, P, i32, pdbl]
     L.ustat_debug_inject.argtypes = [i32, i64]
     L.ustat_plan_create_motifs.argtypes = [i32, ctypes.POINTER(PlanOpts), ctypes.POINTER(P)]
     L.ustat_motif_counts.argtypes = [P, i64, P, P, pi64]
@@ -255,6 +257,16 @@ def ustat_plan_autotune(h, n: int, factors, stream=None, reps: int = 3) -> float
 
 MOTIFS = {3: ["v-shape", "triangle"],
           4: ["3-star", "path", "tailed-triangle", "square", "diamond", "k4"]}
+
+
+def ustat_plan_autotune_batched(h, Xs, divisor: float, stream=None, reps: int = 2) -> float:
+    ns = (ctypes.c_int64 * len(Xs))(*[int(x.shape[0]) for x in Xs])
+    ptrs = (ctypes.c_void_p * len(Xs))(*[ctypes.c_void_p(x.data_ptr()) for x in Xs])
+    ms = ctypes.c_double()
+    _check(load_library().ustat_plan_autotune_batched(h, len(Xs), ns, int(Xs[0].shape[1]), ptrs,
+                                                      float(divisor), _stream_handle(stream), int(reps),
+                                                      ctypes.byref(ms)))
+    return ms.value
 
 
 def ustat_plan_create_motifs(size: int, order="minfill", cse: bool = True,
@@ -514,6 +526,11 @@ class Plan:
     def autotune(self, factors, stream=None, reps: int = 3) -> float:
         n = self._check_factors(factors)
         return ustat_plan_autotune(self.h, n, factors, stream, reps)
+
+    def autotune_batched(self, Xs, divisor: float, stream=None, reps: int = 2) -> float:
+        for x in Xs:
+            assert x.dtype == torch.float64 and x.is_cuda and x.is_contiguous() and x.dim() == 2
+        return ustat_plan_autotune_batched(self.h, Xs, divisor, stream, reps)
 
     def slice_var(self, idx: int) -> int:
         return ustat_plan_order(self.h, idx, self.m)[1]
