@@ -69,11 +69,14 @@ def measured_lowrank_traffic(kernel, launches_per_step):
     return None
 
 
-def measured_traffic(kind, prec):
+BATCHED_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_batched_c5chord_256.json")
+
+
+def measured_traffic(kind, prec, path=TRAFFIC_FILE):
     """Counter-measured HBM bytes per launch of the kind's kernel, or None
     when no record exists or the kernels changed since it was taken."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             rec = json.load(f)
         from paper_2508_12627_amd.profsum import kernel_source_hash
     except (OSError, ValueError, ImportError):
@@ -102,10 +105,10 @@ def kernel_rooflines(U, plan, X, div, stream, prec, reps=5):
         plan.eval_samples(X, div, stream=stream)
     stats = {k: U.ustat_profile_read(k) for k in KERNELS}
     U.ustat_profile_enable(False)
-    return summarize(stats, reps, prec)
+    return summarize(stats, reps, prec, BATCHED_TRAFFIC_FILE)
 
 
-def summarize(stats, reps, prec):
+def summarize(stats, reps, prec, traffic_path=TRAFFIC_FILE):
     out = {}
     for k, g in stats.items():
         if g["launches"] == 0:
@@ -113,7 +116,8 @@ def summarize(stats, reps, prec):
         sec = g["ms"] * 1e-3
         e = {"kernel": KERNELS[k] + (f"<{prec}>" if k == "gemm" else ""),
              "ms_per_eval": g["ms"] / reps, "launches_per_eval": g["launches"] / reps,
-             "avg_launch_ms": g["ms"] / g["launches"], "traffic": measured_traffic(k, prec)}
+             "avg_launch_ms": g["ms"] / g["launches"],
+             "traffic": measured_traffic(k, prec, traffic_path)}
         if k == "gemm":
             achieved = g["flops"] / sec
             e.update({"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAKS[prec] / 1e12,
@@ -197,9 +201,19 @@ def bench_batched(args):
                                   "5-cycle + chord kernel, 52 restricted V-statistics each",
                       "precision": args.precision}}
     plan = U.Plan(5, W.CYCLE5_CHORD, precision=args.precision, order=args.order)
-    # launch shapes tuned on the whole batch (outside the timed region)
-    out["config"]["tune_ms"] = plan.autotune_batched(Xs, div, stream=stream, reps=2)
+    if args.tuning:
+        gb, cb = (int(v) for v in args.tuning.split(","))
+        plan.set_tuning(gb, cb)
+    else:
+        # launch shapes tuned on the whole batch (outside the timed region)
+        out["config"]["tune_ms"] = plan.autotune_batched(Xs, div, stream=stream, reps=2)
     out["config"]["tuning"] = plan.tuning()
+    if args.profile_steps:
+        for _ in range(args.profile_steps):
+            r = plan.eval_batched(Xs, div, stream=stream)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_steps": args.profile_steps, "value": r[0].value}))
+        return
     steps = max(2, args.steps // 10)
     for _ in range(max(1, args.warmup // 2)):
         r = plan.eval_batched(Xs, div, stream=stream)
@@ -230,7 +244,7 @@ def kernel_rooflines_batched(U, plan, Xs, div, stream, prec, reps=1):
         plan.eval_batched(Xs, div, stream=stream)
     stats = {k: U.ustat_profile_read(k) for k in KERNELS}
     U.ustat_profile_enable(False)
-    return summarize(stats, reps, prec)
+    return summarize(stats, reps, prec, BATCHED_TRAFFIC_FILE)
 
 
 def bench_cycle5_exact(args):

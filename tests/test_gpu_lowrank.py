@@ -159,3 +159,27 @@ def test_errors(U):
     with pytest.raises(U.UstatError) as e:
         U.ustat_eval_lowrank(plan.h, 10, 0, [P, P], [P, P])  # r < 1
     assert e.value.code == 1
+
+
+def test_treewidth4_graph_from_panels(U):
+    """K5: its finest quotient has treewidth 4, which the dense path refuses
+    (n^5 work); from rank-2 panels the low-rank path needs no value with two
+    sample indices and evaluates it at any n."""
+    edges = [(i, j) for i in range(5) for j in range(i + 1, 5)]
+    n, r = 257, 2
+    rng = np.random.default_rng(977)
+    F = [rng.uniform(-1, 1, (n, r)) for _ in edges]
+    G = [rng.uniform(-1, 1, (n, r)) for _ in edges]
+    ref = oracle.ustat_lowrank(edges, F, G)
+    plan = U.Plan(5, edges)
+    assert plan.info()["M"] == 4
+    Fd, Gd = [dev(f) for f in F], [dev(g) for g in G]
+    say(f"lowrank K5 n={n} r={r}")
+    res = plan.eval_lowrank(Fd, Gd)
+    check("k5", res, ref)
+    import torch
+    T = [f @ g.T for f, g in zip(Fd, Gd)]
+    with pytest.raises(U.UstatError) as e:
+        plan.eval([t.contiguous() for t in T])
+    assert e.value.code == 2  # USTAT_E_UNSUPPORTED on the dense path
+    del torch
