@@ -474,7 +474,7 @@ void k_gemm(const GemmDesc *__restrict__ D, int nprob) {
                             unsigned long long a = (unsigned long long)(v < 0 ? -v : v);
                             mloc = a > mloc ? a : mloc;
                         }
-                atomicMax(d.mx_out, mloc);
+                block_atomic_max(d.mx_out, mloc);
             }
         }
         // output fields read once: a reload after each store would wait for

@@ -131,6 +131,7 @@ __global__ __launch_bounds__(256) void k_reduce(const ReduceDesc *__restrict__ D
         __shared__ A cred[4][64];
         const int c = t & 63, g = t >> 6;
         const A *part = static_cast<const A *>(d.part);
+        unsigned long long mxl = 0;  // largest |out[j]| written by this thread
         for (int64_t j0 = (int64_t)blockIdx.y * 64; j0 < d.len; j0 += (int64_t)gridDim.y * 64) {
             const int64_t j = j0 + c;
             A s0 = 0, s1 = 0;
@@ -149,10 +150,14 @@ __global__ __launch_bounds__(256) void k_reduce(const ReduceDesc *__restrict__ D
                 for (int q = 0; q < d.nmul; ++q) s *= load_vec<DOM>(d.mul[q], j);
                 static_cast<A *>(d.out)[j] = s;
                 if constexpr (DOM == DOM_INT) {
-                    if (d.mx_out) atomicMax(d.mx_out, (unsigned long long)(s < 0 ? -s : s));
+                    const unsigned long long a = (unsigned long long)(s < 0 ? -s : s);
+                    mxl = a > mxl ? a : mxl;
                 }
             }
             __syncthreads();
+        }
+        if constexpr (DOM == DOM_INT) {
+            if (d.mx_out) block_atomic_max(d.mx_out, mxl);
         }
         return;
     }

@@ -177,6 +177,29 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t G) {
     return x * per + (x < rem ? x : rem) + idx;
 }
 
+// Running maximum of |entries| kept for the exact path's limb counts: the
+// block's largest value (cross-lane exchange within each wave, then the
+// waves' maxima through LDS) recorded with one device-scope atomic.  Such
+// atomics on a single address execute one after another, so one per lane
+// would cost far more than the kernel's own work.  Every thread of the
+// block calls this once (it synchronises the block); threads without a
+// value pass 0.
+__device__ __forceinline__ void block_atomic_max(unsigned long long *p, unsigned long long v) {
+    __shared__ unsigned long long wmax[16];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long w = __shfl_xor(v, o);
+        v = w > v ? w : v;
+    }
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = (int)((blockDim.x + 63) >> 6);
+        for (int q = 1; q < nw; ++q) v = wmax[q] > v ? wmax[q] : v;
+        atomicMax(p, v);
+    }
+}
+
 // Launchers of the grouped row-mode and column-mode reductions for one
 // (domain, element type) pair, defined in their own translation units.
 template <int DOM, typename T>

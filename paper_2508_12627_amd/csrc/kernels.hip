@@ -172,14 +172,19 @@ __global__ __launch_bounds__(256) void k_rbf(const double *__restrict__ X, int64
 template <int DOM>
 __global__ void k_diag(const DiagDesc *__restrict__ D, int nprob) {
     const DiagDesc &d = D[blockIdx.y];
+    unsigned long long mxl = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < d.n;
          i += (int64_t)gridDim.x * blockDim.x) {
         typedef typename Dom<DOM>::acc A;
         A v = load_elem<DOM>(d.src.p, d.src.dtype, i * d.src.ld + i);
         static_cast<A *>(d.dst)[i] = v;
         if constexpr (DOM == DOM_INT) {
-            if (d.mx_out) atomicMax(d.mx_out, (unsigned long long)(v < 0 ? -v : v));
+            const unsigned long long a = (unsigned long long)(v < 0 ? -v : v);
+            mxl = a > mxl ? a : mxl;
         }
+    }
+    if constexpr (DOM == DOM_INT) {
+        if (d.mx_out) block_atomic_max(d.mx_out, mxl);
     }
 }
 
@@ -559,6 +564,7 @@ __global__ __launch_bounds__(256) void k_slicesrc(const SliceDesc *__restrict__ 
         else tile[r][c] = x;
     }
     __syncthreads();
+    unsigned long long mxl = 0;
     for (int e = t; e < 4096; e += 256) {
         int r = e >> 6, c = e & 63;  // slice i0 + r, entry u0 + c
         int64_t i = i0 + r, u = u0 + c;
@@ -567,8 +573,12 @@ __global__ __launch_bounds__(256) void k_slicesrc(const SliceDesc *__restrict__ 
         for (int q = 0; q < d.nscale; ++q) x *= load_vec<DOM>(d.scale[q], i);
         static_cast<A *>(d.out)[i * n + u] = x;
         if constexpr (DOM == DOM_INT) {
-            if (d.mx_out) atomicMax(d.mx_out, (unsigned long long)(x < 0 ? -x : x));
+            const unsigned long long a = (unsigned long long)(x < 0 ? -x : x);
+            mxl = a > mxl ? a : mxl;
         }
+    }
+    if constexpr (DOM == DOM_INT) {
+        if (d.mx_out) block_atomic_max(d.mx_out, mxl);
     }
 }
 
