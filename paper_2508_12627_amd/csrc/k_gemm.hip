@@ -36,7 +36,7 @@ struct GemmCfg<2> {  // bf16 hi/lo
 template <>
 struct GemmCfg<3> {  // int8 limb (one plane per pass)
     typedef int8_t E;
-    static constexpr int BK = 64, PLANES = 1;
+    static constexpr int BK = 128, PLANES = 1;
 };
 template <>
 struct GemmCfg<kGemmBf16x6> {  // bf16 hi/mid/lo
@@ -87,7 +87,8 @@ struct S256 {
 // chunk ^ (row & 7).  Measured on gfx950 (rocprofv3 SQ_LDS_BANK_CONFLICT),
 // 16-byte fragment reads of 16 rows x 4 chunks conflict whatever the
 // permutation inside 64-byte rows, and not at all over 128-byte rows
-// swizzled this way.
+// swizzled this way.  int8 limbs use the same 128-byte rows with one plane
+// (128 values of k per row, two MFMA k-steps of 64).
 template <int PREC, int R, int NT>
 struct TileIO {
     typedef GemmCfg<PREC> C;
@@ -96,8 +97,9 @@ struct TileIO {
     static constexpr int UNITS = R * UPR * C::PLANES;
     static constexpr int PER = UNITS / NT;
     static_assert(UNITS % NT == 0, "tile units must divide over the threads");
-    static constexpr bool ILV = PREC == 2;  // planes interleaved in 128-byte rows
-    static constexpr int LROW = (PREC == 0) ? ROWB + 16 : ILV ? 2 * ROWB : ROWB;
+    static constexpr bool ILV = PREC == 2 || PREC == 3;  // 128-byte rows, planes interleaved
+    static constexpr int LROW = (PREC == 0) ? ROWB + 16 : ILV ? C::PLANES * ROWB : ROWB;
+    static_assert(!ILV || LROW == 128, "interleaved rows are 128 bytes");
     static constexpr int PLANEB = ILV ? 4 * 16 : R * LROW;  // plane offset: in chunks*16 when ILV
     static constexpr int STAGE = ILV ? R * LROW : PLANEB * C::PLANES;
 
@@ -176,7 +178,7 @@ struct TileIO {
 // One BK step of a wave's FM x FN blocks: A rows from ra0, B rows from rb0
 // (tile-local), fragments read from LDS with the staging layout of R-row
 // tiles (the layout does not depend on R).
-template <int PREC, int FM, int FN, int RA, int RB>
+template <int PREC, int FM, int FN, int RA, int RB, bool OVERLAP = true>
 __device__ __forceinline__ void mma_tile(typename AccT<PREC>::T (&acc)[FM][FN], const char *As,
                                          const char *Bs, int ra0, int rb0, int lane) {
     typedef TileIO<PREC, RA, 64> IOA;
@@ -285,18 +287,45 @@ __device__ __forceinline__ void mma_tile(typename AccT<PREC>::T (&acc)[FM][FN], 
             }
         }
     } else {
-        i32x4 a[FM], b[FN];
+        // two k-steps of 64: 16-byte chunks 0..3 of the row, then 4..7.  With
+        // OVERLAP the second step's fragments are read while the first one's
+        // MFMAs run (16 more live registers: used where the wide sums of
+        // several limb passes are not live, which would spill)
+        i32x4 a[2][FM], b[2][FN];
 #pragma unroll
-        for (int i = 0; i < FM; ++i)
-            a[i] = *reinterpret_cast<const i32x4 *>(As + IOA::off(ra0 + i * 16 + lr, lg));
-#pragma unroll
-        for (int j = 0; j < FN; ++j)
-            b[j] = *reinterpret_cast<const i32x4 *>(Bs + IOB::off(rb0 + j * 16 + lr, lg));
-#pragma unroll
-        for (int i = 0; i < FM; ++i)
+        for (int ks = 0; ks < 2; ++ks) {
 #pragma unroll
             for (int j = 0; j < FN; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[i], b[j], acc[i][j], 0, 0, 0);
+                b[ks][j] = *reinterpret_cast<const i32x4 *>(Bs + IOB::off(rb0 + j * 16 + lr, 4 * ks + lg));
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+                a[ks][i] = *reinterpret_cast<const i32x4 *>(As + IOA::off(ra0 + i * 16 + lr, 4 * ks + lg));
+        }
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[ks][i], b[ks][j], acc[i][j], 0, 0, 0);
+        // scheduling groups: the first step's reads, then its MFMAs two at a
+        // time with one read of the second step between, then the rest
+        if constexpr (OVERLAP) {
+            __builtin_amdgcn_sched_group_barrier(0x100, FM + FN, 0);
+#pragma unroll
+            for (int q = 0; q < FM + FN; ++q) {
+                __builtin_amdgcn_sched_group_barrier(0x008, FM * FN / (FM + FN), 0);
+                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+            }
+            __builtin_amdgcn_sched_group_barrier(0x008, FM * FN, 0);
+        } else {
+            // each step's reads just before its MFMAs
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks) {
+                __builtin_amdgcn_sched_group_barrier(0x100, FM + FN, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, FM * FN, 0);
+            }
+        }
     }
 }
 
@@ -310,7 +339,7 @@ constexpr int gemm_stage_bytes() {
 // global memory straight into the idle LDS buffer (no register staging, no
 // LDS stores), issued at the top of the step; its completion and one
 // barrier end the step.
-template <int PREC, class SH>
+template <int PREC, class SH, bool OVERLAP = true>
 __device__ __forceinline__ void gemm_pass_dma(typename AccT<PREC>::T (&acc)[SH::FM][SH::FN],
                                               const char *Ab, const char *Bb, int64_t ldb,
                                               int64_t planeb, int64_t w0, int64_t x0, int64_t npad,
@@ -337,7 +366,7 @@ __device__ __forceinline__ void gemm_pass_dma(typename AccT<PREC>::T (&acc)[SH::
         IOA::dma(Ab, ldb, planeb, w0, kn * KB, An);
         IOB::dma(Bb, ldb, planeb, x0, kn * KB, An + IOA::STAGE);
         __builtin_amdgcn_sched_barrier(0);
-        mma_tile<PREC, SH::FM, SH::FN, SH::BM, SH::BN>(acc, As, Bs, ra0, rb0, lane);
+        mma_tile<PREC, SH::FM, SH::FN, SH::BM, SH::BN, OVERLAP>(acc, As, Bs, ra0, rb0, lane);
         __builtin_amdgcn_sched_barrier(0);
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
@@ -417,30 +446,38 @@ void k_gemm(const GemmDesc *__restrict__ D, int nprob) {
     long long resi[PREC == 3 ? FM : 1][PREC == 3 ? FN : 1][4];
     (void)resi;
     if constexpr (PREC == 3) {
+        // Limb pair (la, lb) carries weight 2^(7 (la + lb)).  The first pass
+        // (weight 1) initialises the wide sums, so they are not live during
+        // its K loop; only products of multi-limb operands run the others.
+        const int nla = d.la_p ? *d.la_p : d.la, nlb = d.lb_p ? *d.lb_p : d.lb;
+        const char *Ab = static_cast<const char *>(d.A), *Bb = static_cast<const char *>(d.B);
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) acc[i][j] = AT{0, 0, 0, 0};
+        gemm_pass_dma<PREC, SH>(acc, Ab, Bb, ldb, planeb, w0, x0, d.npad, lds);
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
             for (int j = 0; j < FN; ++j)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) resi[i][j][r] = 0;
-        const int nla = d.la_p ? *d.la_p : d.la, nlb = d.lb_p ? *d.lb_p : d.lb;
-        for (int la = 0; la < nla; ++la)
-            for (int lb = 0; lb < nlb; ++lb) {
+                for (int r = 0; r < 4; ++r) resi[i][j][r] = (long long)acc[i][j][r];
+        for (int q = 1; q < nla * nlb; ++q) {
+            const int la = q / nlb, lb = q - (q / nlb) * nlb;
 #pragma unroll
-                for (int i = 0; i < FM; ++i)
+            for (int i = 0; i < FM; ++i)
 #pragma unroll
-                    for (int j = 0; j < FN; ++j) acc[i][j] = AT{0, 0, 0, 0};
-                gemm_pass<PREC, SH>(acc, static_cast<const char *>(d.A) + la * planeb,
-                                    static_cast<const char *>(d.B) + lb * planeb, ldb, planeb, w0,
-                                    x0, d.npad, lds);
-                const long long wgt = 1ll << (7 * (la + lb));
+                for (int j = 0; j < FN; ++j) acc[i][j] = AT{0, 0, 0, 0};
+            gemm_pass_dma<PREC, SH, false>(acc, Ab + la * planeb, Bb + lb * planeb, ldb, planeb,
+                                           w0, x0, d.npad, lds);
+            const long long wgt = 1ll << (7 * (la + lb));
 #pragma unroll
-                for (int i = 0; i < FM; ++i)
+            for (int i = 0; i < FM; ++i)
 #pragma unroll
-                    for (int j = 0; j < FN; ++j)
+                for (int j = 0; j < FN; ++j)
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) resi[i][j][r] += wgt * (long long)acc[i][j][r];
-            }
+                    for (int r = 0; r < 4; ++r) resi[i][j][r] += wgt * (long long)acc[i][j][r];
+        }
     } else {
 #pragma unroll
         for (int i = 0; i < FM; ++i)

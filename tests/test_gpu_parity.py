@@ -188,6 +188,21 @@ def test_int8_signed_factors_exact(U, name):
     assert r.exact == ref
 
 
+@pytest.mark.parametrize("name,n", [("triangle", 300), ("cycle4", 160)])
+def test_int8_signed_multilimb_k_steps(U, name, n):
+    """Multi-limb products over several 128-wide K steps and a ragged tail:
+    full-range signed factors need two limbs each (four limb passes), and the
+    4-cycle's stored product feeds a second GEMM with more limbs."""
+    import torch
+    edges = GRAPHS[name]
+    m = nverts(edges)
+    mats = W.random_int_matrices(len(edges), n, seed=37, lo=-128, hi=127)
+    ref = oracle.ustat_bruteforce_int(edges, mats)
+    say(f"int8 multi-limb {name} n={n}")
+    r = U.Plan(m, edges, precision="i8").eval([dev(M, torch.int8) for M in mats])
+    assert r.exact == ref
+
+
 def test_int8_er_cycle_counts(U):
     import torch
     n, p = 300, 0.08
