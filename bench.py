@@ -84,8 +84,8 @@ def measured_traffic(kind, prec, path=TRAFFIC_FILE):
     if rec.get("source_hash") != kernel_source_hash() or rec.get("precision") != prec:
         return None
     frags = KERNELS[kind].split("/")
-    if kind == "gemm":
-        frags = [f"k_gemm<{PREC_INDEX[prec]}"]
+    if kind == "gemm":  # full products and symmetric ones (P P^T)
+        frags = [f"k_gemm<{PREC_INDEX[prec]}", f"k_gemm_sym<{PREC_INDEX[prec]}"]
     # mean over the matching kernels' launches (a kind may span several
     # kernels, e.g. the row reductions over one and over two matrices)
     tot, cnt = 0.0, 0
@@ -105,7 +105,7 @@ def kernel_rooflines(U, plan, X, div, stream, prec, reps=5):
         plan.eval_samples(X, div, stream=stream)
     stats = {k: U.ustat_profile_read(k) for k in KERNELS}
     U.ustat_profile_enable(False)
-    return summarize(stats, reps, prec, BATCHED_TRAFFIC_FILE)
+    return summarize(stats, reps, prec, TRAFFIC_FILE)
 
 
 def summarize(stats, reps, prec, traffic_path=TRAFFIC_FILE):

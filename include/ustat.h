@@ -94,6 +94,15 @@ typedef enum {
  * symmetric by construction and always read this way.
  */
 #define USTAT_FLAG_SYMMETRIC 2
+/*
+ * USTAT_FLAG_NO_SYM_GEMM: a product P P^T of one prepared operand with
+ * itself (R = K K for a symmetric factor K) is by default computed on the
+ * tiles on and above the diagonal only, their K steps spread evenly over
+ * the compute units, each tile mirrored below (split-bf16 with 256-wide
+ * tiles).  This flag computes every tile instead, for comparisons; results
+ * agree up to the order of fp32 additions.
+ */
+#define USTAT_FLAG_NO_SYM_GEMM 4
 
 typedef struct {
     int32_t precision;          /* ustat_precision                          */
@@ -386,7 +395,8 @@ ustat_status ustat_build_rbf(int64_t n, int32_t d, const double *X, double rbf_d
  * 4 factor build, 5 low-rank summation steps, 6 low-rank chunk sums,
  * 7 low-rank outer-product (GEMM) steps.  ustat_profile_read returns
  * totals since the last reset: milliseconds, number of launches,
- * algorithmic flops (2 n^3 per GEMM, 2 M N n per low-rank GEMM step) and
+ * algorithmic flops (2 n^3 per GEMM, n^2 (n + 1) per symmetric product
+ * P P^T, 2 M N n per low-rank GEMM step) and
  * algorithmic bytes (every operand element read once plus the outputs
  * written, for the column reduction and operand prep kernels).  Any output
  * pointer may be NULL.

@@ -157,6 +157,14 @@ struct LevelWork {
     double gemm_big_flops = 0;
     bool big = false;  // the level's eligible GEMMs take 256-wide tiles
     size_t off_gemm_big = 0;
+    // symmetric products P P^T on 256-wide tiles (stream-K over the tiles on
+    // and above the diagonal, then the fix-up of split tiles)
+    std::vector<GemmDesc> gemm_sym;
+    int64_t gemm_sym_units = 0, gemm_sym_nk = 0, gemm_sym_tiles = 0;
+    double gemm_sym_flops = 0;
+    int sym_blocks = 0;
+    float *sym_part = nullptr;
+    size_t off_gemm_sym = 0;
     // split-bf16 problems on three-plane operands (six products per pair)
     std::vector<GemmDesc> gemm6;
     int64_t gemm6_tiles = 0;
@@ -774,6 +782,19 @@ struct ColPending {
     bool rows = false;  // every matrix symmetric: reduce along rows
 };
 
+// Lays out a level's symmetric products for the stream-K launch: the block
+// count (at most one per compute unit, and few enough that every block
+// covers at least half a tile's K steps, so a tile is split over at most
+// three blocks) and the partial buffer (two slots per block).
+template <class Alloc>
+void layout_symmetric(LevelWork &W, Alloc &&alloc_part) {
+    const int64_t U = W.gemm_sym_units;
+    const int64_t half = std::max<int64_t>(1, (W.gemm_sym_nk + 1) / 2);
+    const int64_t G = std::max<int64_t>(1, std::min<int64_t>(kSymBlocks, U / half));
+    W.sym_blocks = (int)G;
+    W.sym_part = alloc_part((size_t)G * 2 * kSymSlot * sizeof(float));
+}
+
 // Lays out a level's column reductions.  Those reading few distinct
 // matrices are grouped greedily, in node order: a reduction joins the first
 // group of its size n whose matrices together with its own stay within
@@ -1350,10 +1371,26 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
                     if (fmt == PF_BF16X2) S.two_plane[d] = 1;
                     const bool big = W.big && npad % 256 == 0 && !six;
                     g.tiles = (int)(npad / (big ? 256 : 128));
-                    int64_t &tcount = six ? W.gemm6_tiles : big ? W.gemm_big_tiles : W.gemm_tiles;
-                    g.tile_start = tcount;
-                    tcount += (int64_t)g.tiles * g.tiles;
-                    (six ? W.gemm6_flops : big ? W.gemm_big_flops : W.gemm_flops) += 2.0 * (double)n * n * n;
+                    // one prepared operand on both sides: C = P P^T is symmetric
+                    const bool sym = big && plan.opts.sym_gemm && fmt == PF_BF16X2 &&
+                                     nd_.kind == NK::GemmStore && g.A == g.B &&
+                                     cfg.mat_dt == DT_F32;
+                    if (sym) {
+                        const int64_t t = g.tiles, nk = npad / 32;
+                        g.tile_start = W.gemm_sym_units;  // first unit (tile K step)
+                        g.sym_tile0 = W.gemm_sym_tiles;
+                        W.gemm_sym_tiles += t * (t + 1) / 2;
+                        W.gemm_sym_units += t * (t + 1) / 2 * nk;
+                        W.gemm_sym_nk = std::max(W.gemm_sym_nk, nk);
+                        // the products of the entries on and above the diagonal
+                        W.gemm_sym_flops += (double)n * n * (n + 1);
+                    } else {
+                        int64_t &tcount = six ? W.gemm6_tiles : big ? W.gemm_big_tiles : W.gemm_tiles;
+                        g.tile_start = tcount;
+                        tcount += (int64_t)g.tiles * g.tiles;
+                        (six ? W.gemm6_flops : big ? W.gemm_big_flops : W.gemm_flops) +=
+                            2.0 * (double)n * n * n;
+                    }
                     const double cb = n * pA * pS * pB;
                     if (is_int) {
                         if (cb > kOverflow) {
@@ -1397,7 +1434,7 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
                         W.red.push_back(r);
                         nd_.bound = (double)n * n * cb * pZ * paw * pbx;
                     }
-                    (six ? W.gemm6 : big ? W.gemm_big : W.gemm).push_back(g);
+                    (sym ? W.gemm_sym : six ? W.gemm6 : big ? W.gemm_big : W.gemm).push_back(g);
                     break;
                 }
             }
@@ -1406,6 +1443,12 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
                 return "a V-statistic may exceed the 127-bit range";
             }
         }
+        if (!W.gemm_sym.empty())
+            layout_symmetric(W, [&](size_t bytes) {
+                const size_t off = A.alloc(bytes);
+                scratch.push_back({off, bytes});
+                return reinterpret_cast<float *>(P(off));
+            });
         layout_column_reductions(e1recs, W, plan.tuning.colred_blocks, [&](size_t bytes) {
             const size_t off = A.alloc(bytes);
             scratch.push_back({off, bytes});
@@ -1473,6 +1516,7 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
         W.off_prep = S.blob.put(W.prep);
         W.off_gemm = S.blob.put(W.gemm);
         W.off_gemm_big = S.blob.put(W.gemm_big);
+        W.off_gemm_sym = S.blob.put(W.gemm_sym);
         W.off_gemm6 = S.blob.put(W.gemm6);
         W.off_e1 = S.blob.put(W.e1);
         for (int k = 0; k < LevelWork::kColSlots; ++k) W.off_col[k] = S.blob.put(W.col[k]);
@@ -1972,6 +2016,14 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
                 e = launch_gemm(reinterpret_cast<GemmDesc *>(dd + W.off_gemm_big),
                                 (int)W.gemm_big.size(), W.gemm_big_tiles, cfg.prec, 256, stream);
                 if (e != hipSuccess) return fail(e, "gemm");
+            }
+            if (!W.gemm_sym.empty()) {
+                // the product and its fix-up, timed together
+                ProfScope ps(prof, KIND_GEMM, stream, W.gemm_sym_flops);
+                e = launch_gemm_sym(reinterpret_cast<GemmDesc *>(dd + W.off_gemm_sym),
+                                    (int)W.gemm_sym.size(), W.gemm_sym_units, W.sym_blocks,
+                                    W.gemm_sym_tiles, W.sym_part, stream);
+                if (e != hipSuccess) return fail(e, "symmetric gemm");
             }
             if (!W.gemm6.empty()) {
                 ProfScope ps(prof, KIND_GEMM, stream, W.gemm6_flops);

@@ -335,34 +335,33 @@ constexpr int gemm_stage_bytes() {
     return TileIO<PREC, SH::BM, SH::NT>::STAGE + TileIO<PREC, SH::BN, SH::NT>::STAGE;
 }
 
-// K loop of the interleaved split-bf16 layout: the next K tile goes from
-// global memory straight into the idle LDS buffer (no register staging, no
-// LDS stores), issued at the top of the step; its completion and one
-// barrier end the step.
+// K loop of the interleaved layouts over K steps [k0, k1): the next K tile
+// goes from global memory straight into the idle LDS buffer (no register
+// staging, no LDS stores), issued at the top of the step; its completion and
+// one barrier end the step.  Buffer parity counts from k0.
 template <int PREC, class SH, bool OVERLAP = true>
-__device__ __forceinline__ void gemm_pass_dma(typename AccT<PREC>::T (&acc)[SH::FM][SH::FN],
-                                              const char *Ab, const char *Bb, int64_t ldb,
-                                              int64_t planeb, int64_t w0, int64_t x0, int64_t npad,
-                                              char *lds) {
+__device__ __forceinline__ void gemm_range_dma(typename AccT<PREC>::T (&acc)[SH::FM][SH::FN],
+                                               const char *Ab, const char *Bb, int64_t ldb,
+                                               int64_t planeb, int64_t w0, int64_t x0, int64_t k0,
+                                               int64_t k1, char *lds) {
     typedef TileIO<PREC, SH::BM, SH::NT> IOA;
     typedef TileIO<PREC, SH::BN, SH::NT> IOB;
     constexpr int PAIR = IOA::STAGE + IOB::STAGE;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int ra0 = (wv / SH::WN) * SH::FM * 16, rb0 = (wv % SH::WN) * SH::FN * 16;
     constexpr int KB = GemmCfg<PREC>::BK * (int)sizeof(typename GemmCfg<PREC>::E);
-    const int64_t nk = npad / GemmCfg<PREC>::BK;
-    IOA::dma(Ab, ldb, planeb, w0, 0, lds);
-    IOB::dma(Bb, ldb, planeb, x0, 0, lds + IOA::STAGE);
+    IOA::dma(Ab, ldb, planeb, w0, k0 * KB, lds);
+    IOB::dma(Bb, ldb, planeb, x0, k0 * KB, lds + IOA::STAGE);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    for (int64_t kt = 0; kt < nk; ++kt) {
-        const int cur = (int)(kt & 1);
+    for (int64_t kt = k0; kt < k1; ++kt) {
+        const int cur = (int)((kt - k0) & 1);
         char *As = lds + cur * PAIR;
         char *Bs = As + IOA::STAGE;
         char *An = lds + (1 - cur) * PAIR;
         // the last step re-reads its own tile into the idle buffer, which
         // keeps the loop free of branches
-        const int64_t kn = (kt + 1 < nk) ? kt + 1 : kt;
+        const int64_t kn = (kt + 1 < k1) ? kt + 1 : kt;
         IOA::dma(Ab, ldb, planeb, w0, kn * KB, An);
         IOB::dma(Bb, ldb, planeb, x0, kn * KB, An + IOA::STAGE);
         __builtin_amdgcn_sched_barrier(0);
@@ -371,6 +370,15 @@ __device__ __forceinline__ void gemm_pass_dma(typename AccT<PREC>::T (&acc)[SH::
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
     }
+}
+
+template <int PREC, class SH, bool OVERLAP = true>
+__device__ __forceinline__ void gemm_pass_dma(typename AccT<PREC>::T (&acc)[SH::FM][SH::FN],
+                                              const char *Ab, const char *Bb, int64_t ldb,
+                                              int64_t planeb, int64_t w0, int64_t x0, int64_t npad,
+                                              char *lds) {
+    gemm_range_dma<PREC, SH, OVERLAP>(acc, Ab, Bb, ldb, planeb, w0, x0, 0,
+                                      npad / GemmCfg<PREC>::BK, lds);
 }
 
 // K loop of one (A plane set, B plane set) pass with register prefetch and
@@ -584,6 +592,146 @@ void k_gemm(const GemmDesc *__restrict__ D, int nprob) {
     if (threadIdx.x == 0) static_cast<Wd *>(d.part)[local] = red[0];
 }
 
+// ---------------------------------------------------------- symmetric products
+
+// Store a finished tile (I, J), I <= J, of C = P P^T (fp32) and, off the
+// diagonal, its mirror (J, I): lane l holds column x = ... + l % 16 and the
+// four consecutive rows 4 (l / 16) + r, which the mirror writes as one
+// 16-byte store into row x.
+template <int PREC, class SH>
+__device__ __forceinline__ void sym_store(const typename AccT<PREC>::T (&acc)[SH::FM][SH::FN],
+                                          const GemmDesc &d, int64_t I, int64_t J) {
+    static_assert(PREC == 2, "symmetric products: split-bf16 with fp32 output");
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t wr0 = I * SH::BM + (wv / SH::WN) * SH::FM * 16;
+    const int64_t xc0 = J * SH::BN + (wv % SH::WN) * SH::FN * 16;
+    float *const C = static_cast<float *>(d.C);
+    const int64_t ldc = d.ldc, n = d.n;
+    const bool vec = (n % 4) == 0 && (ldc % 4) == 0;
+#pragma unroll
+    for (int i = 0; i < SH::FM; ++i)
+#pragma unroll
+        for (int j = 0; j < SH::FN; ++j) {
+            const int64_t x = xc0 + j * 16 + (lane & 15);
+            const int64_t wb = wr0 + i * 16 + 4 * (lane >> 4);
+            if (x >= n) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (wb + r < n) C[(wb + r) * ldc + x] = acc[i][j][r];
+            if (I == J) continue;
+            if (vec) {
+                if (wb < n) *reinterpret_cast<f32x4 *>(C + x * ldc + wb) = acc[i][j];
+            } else {
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (wb + r < n) C[x * ldc + wb + r] = acc[i][j][r];
+            }
+        }
+}
+
+// Owner (block) of unit u when `units` are cut into G ranges
+// [floor(b units / G), floor((b + 1) units / G)).
+__device__ __forceinline__ int64_t sym_owner(int64_t u, int64_t units, int64_t G) {
+    return ((u + 1) * G - 1) / units;
+}
+
+template <int PREC, class SH>
+__global__ __launch_bounds__(SH::NT) __attribute__((amdgpu_waves_per_eu(2)))
+void k_gemm_sym(const GemmDesc *__restrict__ D, int nprob, int64_t units, float *__restrict__ part) {
+    typedef typename AccT<PREC>::T AT;
+    constexpr int FM = SH::FM, FN = SH::FN, NT = SH::NT;
+    constexpr int ES = (int)sizeof(typename GemmCfg<PREC>::E);
+    extern __shared__ __align__(16) char lds[];
+    const int64_t G = gridDim.x;
+    const int64_t lb = xcd_remap(blockIdx.x, G);  // neighbouring ranges share an XCD
+    const int64_t u0 = lb * units / G, u1 = (lb + 1) * units / G;
+    if (u0 >= u1) return;
+    // first unit of the tile holding unit u
+    auto tile_first = [&](int64_t u) {
+        const GemmDesc &d = D[find_problem(D, nprob, u)];
+        const int64_t nk = d.npad / GemmCfg<PREC>::BK;
+        return d.tile_start + (u - d.tile_start) / nk * nk;
+    };
+    // The range's last piece (the start of a tile, K from 0) goes first and
+    // the rest follow: all blocks then stand at one of two K positions at any
+    // time, which keeps the operand slices being read few (cache reuse).
+    const int64_t ul = tile_first(u1 - 1) > u0 ? tile_first(u1 - 1) : u0;
+    for (int pass = 0; pass < 2; ++pass) {
+        const int64_t ua = pass == 0 ? ul : u0, ub = pass == 0 ? u1 : ul;
+        for (int64_t u = ua; u < ub;) {
+            const int p = __builtin_amdgcn_readfirstlane(find_problem(D, nprob, u));  // uniform
+            const GemmDesc &d = D[p];
+            const int64_t nk = d.npad / GemmCfg<PREC>::BK;
+            const int64_t lu = u - d.tile_start;
+            const int64_t t = lu / nk, k0 = lu - t * nk;
+            const int64_t k1 = (k0 + (ub - u) < nk) ? k0 + (ub - u) : nk;
+            int64_t I, J;
+            sym_tile(t, d.tiles, I, J);
+            AT acc[FM][FN];
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j) acc[i][j] = AT{0, 0, 0, 0};
+            const int64_t ldb = d.ld * ES, planeb = d.plane * ES;
+            gemm_range_dma<PREC, SH>(acc, static_cast<const char *>(d.A),
+                                     static_cast<const char *>(d.B), ldb, planeb, I * SH::BM,
+                                     J * SH::BN, k0, k1, lds);
+            if (k0 == 0 && k1 == nk) {
+                sym_store<PREC, SH>(acc, d, I, J);
+            } else {
+                AT *P = reinterpret_cast<AT *>(part);
+                const int64_t slot = 2 * lb + (u == u0 ? 0 : 1);
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j)
+                        P[slot * (FM * FN * NT) + (i * FN + j) * NT + threadIdx.x] = acc[i][j];
+            }
+            u += k1 - k0;
+        }
+    }
+}
+
+// Fix-up of a symmetric-product launch, one block per tile of the launch:
+// a tile whose units fell to more than one block is the sum of their pieces,
+// added in block order (slot 2 b when the piece holds block b's first unit,
+// else 2 b + 1), then stored with its mirror.
+template <int PREC, class SH>
+__global__ __launch_bounds__(SH::NT) void k_gemm_symfix(const GemmDesc *__restrict__ D, int nprob,
+                                                        int64_t units, int64_t G,
+                                                        const float *__restrict__ part) {
+    typedef typename AccT<PREC>::T AT;
+    constexpr int FM = SH::FM, FN = SH::FN, NT = SH::NT;
+    const int64_t gt = blockIdx.x;
+    int lo = 0, hi = nprob - 1;  // the problem owning tile gt
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (D[mid].sym_tile0 <= gt) lo = mid;
+        else hi = mid - 1;
+    }
+    const GemmDesc &d = D[lo];
+    const int64_t t = gt - d.sym_tile0, nk = d.npad / GemmCfg<PREC>::BK;
+    const int64_t tf = d.tile_start + t * nk;
+    const int64_t bf = sym_owner(tf, units, G), bl = sym_owner(tf + nk - 1, units, G);
+    if (bf == bl) return;  // stored whole by the product kernel
+    const AT *P = reinterpret_cast<const AT *>(part);
+    AT acc[FM][FN];
+    for (int64_t b = bf; b <= bl; ++b) {
+        const int64_t sb = 2 * b + (b * units / G >= tf ? 0 : 1);
+        const AT *Q = P + sb * (FM * FN * NT);
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+                const AT v = Q[(i * FN + j) * NT + threadIdx.x];
+                acc[i][j] = b == bf ? v : acc[i][j] + v;
+            }
+    }
+    int64_t I, J;
+    sym_tile(t, d.tiles, I, J);
+    sym_store<PREC, SH>(acc, d, I, J);
+}
+
 template <int PREC, class SH>
 static hipError_t launch_gemm_t(const GemmDesc *d, int nprob, int64_t total_tiles, hipStream_t s) {
     size_t lds = (size_t)2 * gemm_stage_bytes<PREC, SH>();
@@ -616,6 +764,26 @@ hipError_t launch_gemm(const GemmDesc *d, int nprob, int64_t total_tiles, int pr
         case kGemmBf16x6: return launch_gemm_t<kGemmBf16x6, S128>(d, nprob, total_tiles, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_gemm_sym(const GemmDesc *d, int nprob, int64_t units, int blocks, int64_t tiles,
+                           float *part, hipStream_t s) {
+    static_assert(S256::FM * S256::FN * 4 * S256::NT == kSymSlot, "partial slot size");
+    const size_t lds = (size_t)2 * gemm_stage_bytes<2, S256>();
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_gemm_sym<2, S256>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_gemm_sym<2, S256>), dim3((unsigned)blocks), dim3(S256::NT), lds, s, d,
+                       nprob, units, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_gemm_symfix<2, S256>), dim3((unsigned)tiles), dim3(S256::NT), 0, s, d,
+                       nprob, units, (int64_t)blocks, (const float *)part);
+    return hipGetLastError();
 }
 
 }  // namespace ustat

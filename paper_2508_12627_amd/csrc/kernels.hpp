@@ -159,6 +159,7 @@ struct GemmDesc {
     int64_t tile_start;
     const int32_t *la_p, *lb_p;  // int8 path: limb counts written by prep
     unsigned long long *mx_out;  // int8 path: running max |C|, or null
+    int64_t sym_tile0;           // symmetric products: first tile of the problem in the launch
 };
 
 // Per dataset d, for its programs p in order:
@@ -233,6 +234,47 @@ hipError_t launch_prep(const PrepDesc *d, int nprob, int64_t total_tiles, int do
 constexpr int kGemmBf16x6 = 4;
 hipError_t launch_gemm(const GemmDesc *d, int nprob, int64_t total_tiles, int precision,
                        int tile, hipStream_t s);
+
+// Symmetric products C = P P^T (the same prepared split-bf16 operand on both
+// sides, fp32 output, 256-wide tiles): only the tiles (I, J) with I <= J are
+// computed, in the order of sym_tile, and each one off the diagonal is also
+// stored mirrored at (J, I).  A problem is t (t + 1) / 2 tiles (t =
+// GemmDesc::tiles) of nk = npad / 32 K steps each, "units";
+// GemmDesc::tile_start is its first unit in the launch and sym_tile0 its
+// first tile.  The launch's `units` are cut into `blocks` equal ranges, one
+// per block (stream-K).  A block stores a tile it covers entirely; a piece
+// of a tile goes to partial slot 2 b (the piece holding the block's first
+// unit) or 2 b + 1 (its last), kSymSlot floats each, and a second kernel
+// (one block per tile of the launch, `tiles` in all) adds each split
+// tile's pieces in block order and stores it.
+constexpr int kSymBlocks = 256;                 // compute units of the MI355X
+constexpr int64_t kSymSlot = 256 * 256;         // floats per partial slot
+// Tile t of the order in which symmetric products visit the tiles (I, J),
+// I <= J, of a t_side x t_side grid: 4 x 4 groups of tiles, row by row over
+// the groups on and above the diagonal, column by column inside a group, so
+// that the blocks running at the same time (consecutive ranges of the order)
+// share few operand panels.  Used by the kernel and by the host layout.
+__host__ __device__ inline void sym_tile(int64_t t, int64_t t_side, int64_t &I, int64_t &J) {
+    const int64_t g = (t_side + 3) / 4;
+    I = J = 0;
+    for (int64_t P = 0; P < g; ++P)
+        for (int64_t Q = P; Q < g; ++Q) {
+            const int64_t r0 = 4 * P, r1 = (4 * P + 4 < t_side) ? 4 * P + 4 : t_side;
+            const int64_t c0 = 4 * Q, c1 = (4 * Q + 4 < t_side) ? 4 * Q + 4 : t_side;
+            for (int64_t c = c0; c < c1; ++c) {
+                const int64_t hi = (r1 < c + 1) ? r1 : c + 1;  // rows I <= c of the group
+                const int64_t k = hi > r0 ? hi - r0 : 0;
+                if (t < k) {
+                    I = r0 + t;
+                    J = c;
+                    return;
+                }
+                t -= k;
+            }
+        }
+}
+hipError_t launch_gemm_sym(const GemmDesc *d, int nprob, int64_t units, int blocks, int64_t tiles,
+                           float *part, hipStream_t s);
 // flag[p] = 1 when matrix p (n[p] x n[p], fp32 when f32 else fp64) holds a
 // negative (or NaN) entry, else 0; the flags must be zero on entry.
 hipError_t launch_signscan(const void *const *src, const int64_t *n, int nprob, int f32,
