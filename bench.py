@@ -84,15 +84,19 @@ def measured_traffic(kind, prec, path=TRAFFIC_FILE):
     if rec.get("source_hash") != kernel_source_hash() or rec.get("precision") != prec:
         return None
     frags = KERNELS[kind].split("/")
-    if kind == "gemm":  # full products and symmetric ones (P P^T)
-        frags = [f"k_gemm<{PREC_INDEX[prec]}", f"k_gemm_sym<{PREC_INDEX[prec]}"]
+    if kind == "gemm":  # full products, symmetric ones (P P^T) and their fix-up
+        frags = [f"k_gemm<{PREC_INDEX[prec]}", f"k_gemm_sym<{PREC_INDEX[prec]}",
+                 f"k_gemm_symfix<{PREC_INDEX[prec]}"]
     # mean over the matching kernels' launches (a kind may span several
-    # kernels, e.g. the row reductions over one and over two matrices)
+    # kernels, e.g. the row reductions over one and over two matrices); the
+    # fix-up of a symmetric product belongs to its product's step, so its
+    # bytes count and its launches do not
     tot, cnt = 0.0, 0
     for name, k in rec.get("kernels", {}).items():
         if any(fr in name for fr in frags) and k.get("bytes_per_launch") is not None:
             tot += k["bytes_per_launch"] * k["launches"]
-            cnt += k["launches"]
+            if "k_gemm_symfix" not in name:
+                cnt += k["launches"]
     return tot / cnt if cnt else None
 
 
