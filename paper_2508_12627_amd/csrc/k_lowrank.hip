@@ -233,15 +233,114 @@ __device__ __forceinline__ void kr_tile(const LrKrDesc &st, const double *const 
     }
 }
 
+// Outer-product steps with a short left side (at most 16 indices) and a
+// right side of at most 64: no LDS staging.  For the fp64 MFMA 16x16x4 lane
+// l holds A at (row l % 16, k l / 16) and B at (k l / 16, column l % 16), so
+// each lane forms exactly those products: the left index l % 16 and the
+// right indices 16 cb + l % 16 (cb < 4), at x = xq + l / 16.  The four
+// waves take interleaved groups of four x values of the chunk, and their
+// accumulators are added in wave order through LDS at the end.  Indices
+// past the sides and x past the chunk read clamped addresses and are
+// multiplied by zero.
+template <int NS, int NW>
+__device__ __forceinline__ void kr_small(const LrKrDesc &st, const double *const *__restrict__ tab,
+                                         uint32_t c, double *red) {
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int lr = lane & 15, lg = lane >> 4;
+    constexpr int sb = 0, wb = kLrKrSide;  // short (left) and wide (right) operands
+    const uint32_t MS = (uint32_t)st.M, MW = (uint32_t)st.N;
+    const int nds = st.ndl, ndw = st.ndr;
+    const int32_t *ds = st.dl, *dw = st.dr;
+    const double zs = (uint32_t)lr < MS ? 1.0 : 0.0;
+    const uint32_t isc = min((uint32_t)lr, MS - 1);
+    gptr ps[NS], pw[NW];
+    uint32_t os[NS], ss[NS], sw[NW], ow[4][NW];
+    double zw[4];
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+        ps[u] = (gptr)(tab[st.slot[sb + u]] + st.base[sb + u]);
+        ss[u] = (uint32_t)st.sx[sb + u];
+        os[u] = side_offset(isc, nds, ds, st.st[sb + u]);
+    }
+#pragma unroll
+    for (int u = 0; u < NW; ++u) {
+        pw[u] = (gptr)(tab[st.slot[wb + u]] + st.base[wb + u]);
+        sw[u] = (uint32_t)st.sx[wb + u];
+    }
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+        const uint32_t iw = 16 * cb + lr;
+        zw[cb] = iw < MW ? 1.0 : 0.0;
+#pragma unroll
+        for (int u = 0; u < NW; ++u) ow[cb][u] = side_offset(min(iw, MW - 1), ndw, dw, st.st[wb + u]);
+    }
+    const int ncb = (int)((MW + 15) / 16);  // uniform
+    const uint32_t x0 = c * (uint32_t)st.xchunk;
+    const uint32_t x1 = min((uint32_t)st.nx, x0 + (uint32_t)st.xchunk);
+    f64x4 acc[4];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) acc[cb] = f64x4{0, 0, 0, 0};
+    for (uint32_t xq = x0 + 4 * wv; xq < x1; xq += 16) {
+        const uint32_t x = xq + lg;
+        const uint32_t xc = min(x, x1 - 1);
+        double a = x < x1 ? zs : 0.0;
+#pragma unroll
+        for (int u = 0; u < NS; ++u) a *= ps[u][os[u] + xc * ss[u]];
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+            if (cb >= ncb) break;
+            double b = zw[cb];
+#pragma unroll
+            for (int u = 0; u < NW; ++u) b *= pw[u][ow[cb][u] + xc * sw[u]];
+            acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[cb], 0, 0, 0);
+        }
+    }
+    // red[w][cb][r][lane]
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) red[((wv * 4 + cb) * 4 + r) * 64 + lane] = acc[cb][r];
+    __syncthreads();
+    double *o = const_cast<double *>(tab[0]) + st.out + (int64_t)c * st.nout;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int idx = tid + 256 * q;  // (cb, r, lane)
+        const int cb = idx >> 8, r = (idx >> 6) & 3, l = idx & 63;
+        // item r of lane l: left row l / 16 + 4 r, right column 16 cb + l % 16
+        const uint32_t il = (uint32_t)((l >> 4) + 4 * r), ir = (uint32_t)(16 * cb + (l & 15));
+        if (il >= MS || ir >= MW) continue;
+        double v = red[((0 * 4 + cb) * 4 + r) * 64 + l];
+#pragma unroll
+        for (int w = 1; w < 4; ++w) v += red[((w * 4 + cb) * 4 + r) * 64 + l];
+        o[side_offset(il, st.ndl, st.dl, st.ol) + side_offset(ir, st.ndr, st.dr, st.orr)] = v;
+    }
+}
+
 __global__ __launch_bounds__(kLrThreads) void k_lr_kr(const LrKrDesc *__restrict__ desc,
                                                       int64_t nkr,
                                                       const double *const *__restrict__ tab) {
-    __shared__ double As[kKrBK * kKrPitch], Bs[kKrBK * kKrPitch];
+    // operand tiles of the 64 x 64 path, or the waves' sums of the small one
+    __shared__ double lds[4 * 4 * 4 * 64];
+    static_assert(2 * kKrBK * kKrPitch <= 4 * 4 * 4 * 64, "LDS of the 64 x 64 path");
+    double *As = lds, *Bs = lds + kKrBK * kKrPitch;
     const int64_t b = blockIdx.x;
     const LrKrDesc &st = desc[find_step(desc, nkr, b)];
     const uint32_t bi = (uint32_t)(b - st.block0);
     const uint32_t c = bi / st.tiles, t = bi - c * st.tiles;
     const uint32_t tm = t / st.tiles_n, tn = t - tm * st.tiles_n;
+    if (st.small) {
+        switch (st.nl * 8 + st.nr) {
+#define KS_CASE(S, W) \
+    case S * 8 + W: kr_small<S, W>(st, tab, c, lds); break;
+            KS_CASE(1, 1) KS_CASE(1, 2) KS_CASE(1, 3) KS_CASE(1, 4)
+            KS_CASE(2, 1) KS_CASE(2, 2) KS_CASE(2, 3) KS_CASE(2, 4)
+            KS_CASE(3, 1) KS_CASE(3, 2) KS_CASE(3, 3) KS_CASE(3, 4)
+            KS_CASE(4, 1) KS_CASE(4, 2) KS_CASE(4, 3) KS_CASE(4, 4)
+#undef KS_CASE
+            default: break;
+        }
+        return;
+    }
     switch (st.nl * 8 + st.nr) {
 #define KR_CASE(L, R) \
     case L * 8 + R: kr_tile<L, R>(st, tab, c, tm, tn, As, Bs); break;

@@ -465,8 +465,9 @@ std::string build_lowrank(const Plan &plan, int64_t n, int r, const std::vector<
                 k.nr = cnt[1];
                 k.nx = (int32_t)v.nx;
                 k.nout = (int32_t)v.size;
-                k.tiles_n = (k.N + kLrKrTile - 1) / kLrKrTile;
-                k.tiles = ((k.M + kLrKrTile - 1) / kLrKrTile) * k.tiles_n;
+                if (k.M <= kLrKrSmall && k.N <= kLrKrSmallWide) k.small = 1;
+                k.tiles_n = k.small ? 1 : (k.N + kLrKrTile - 1) / kLrKrTile;
+                k.tiles = k.small ? 1 : ((k.M + kLrKrTile - 1) / kLrKrTile) * k.tiles_n;
                 int64_t nch = std::min<int64_t>(32, std::max<int64_t>(1, (2048 + k.tiles - 1) / k.tiles));
                 nch = std::min<int64_t>(nch, std::max<int64_t>(1, k.nx / 256));
                 nch = std::min<int64_t>(nch, std::max<int64_t>(1, (((int64_t)1 << 31) - 1) / v.size));

@@ -61,7 +61,10 @@ struct LrStepDesc {
 // (right, radix dr); the output element (l, r) is at out + c nout +
 // sum_d digit_d(l) ol[d] + sum_d digit_d(r) orr[d] (c the chunk of x;
 // partials when nchunk > 1).  Offsets within a value fit 31 bits.
+// small = 1 marks a step whose left side has at most 16 indices and right
+// side at most 64: it runs as one "tile" per chunk on a register-only path.
 constexpr int kLrKrTile = 64;
+constexpr int kLrKrSmall = 16, kLrKrSmallWide = 64;
 constexpr int kLrKrSide = 4;
 struct LrKrDesc {
     int32_t ndl, ndr, nl, nr;  // side indices, side operands (1..kLrKrSide)
@@ -72,6 +75,7 @@ struct LrKrDesc {
     int32_t dl[kLrMaxDim], dr[kLrMaxDim];
     int32_t ol[kLrMaxDim], orr[kLrMaxDim];
     int32_t M, N, nx, xchunk, nchunk, tiles_n, tiles, nout;
+    int32_t small, pad;
     int64_t out, block0;
 };
 
