@@ -422,8 +422,7 @@ static ustat_status run(ustat_plan plan, const std::vector<const VProgram *> &pr
     // Launch sequences are captured into a HIP graph and replayed when the
     // stream is not the null stream; profiled runs launch kernel by kernel so
     // that every launch can be timed with events.
-    bool capture = (s != nullptr) && plan->plan.opts.precision != USTAT_I8 && !key.empty() &&
-                   !Profiler::enabled() && !ext;
+    bool capture = (s != nullptr) && !key.empty() && !Profiler::enabled() && !ext;
     std::string err;
     try {
         if (capture) Profiler::suspend(true);

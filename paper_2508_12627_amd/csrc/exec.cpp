@@ -1752,29 +1752,6 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
             for (char c : in_signed) key += c ? '1' : '0';
         }
     }
-    if (capture) {
-        auto git = rt.graphs.find(key);
-        if (git != rt.graphs.end() && git->second.nd == (int)data.size()) {
-            // Replay: the graph reads its own device descriptor blob and
-            // recomputes everything in the workspace from the inputs.
-            HIPCHK(hipGraphLaunch(git->second.exec, stream));
-            HIPCHK(hipStreamSynchronize(stream));
-            const int nd = git->second.nd, nprog = git->second.nprog;
-            out.assign(nd, DatasetResult());
-            size_t vbytes = (size_t)nprog * cfg.wide_es, ubytes = (size_t)nd * cfg.wide_es;
-            const char *h = rt.hres;
-            if (vout) {
-                vout->assign(nprog, 0.0);
-                for (int i = 0; i < nprog; ++i) (*vout)[i] = reinterpret_cast<const double *>(h)[i];
-            }
-            for (int d = 0; d < nd; ++d) {
-                out[d].value = reinterpret_cast<const double *>(h + vbytes)[d];
-                out[d].scale = reinterpret_cast<const double *>(h + vbytes + ubytes)[d];
-                out[d].err_est = git->second.err_est[d];
-            }
-            return "";
-        }
-    }
     std::vector<double> in_bound;
     std::vector<char> in_binary;  // per dataset*edge (INT): all entries 0 or 1
     Profiler *prof = Profiler::active();
@@ -1836,6 +1813,49 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
             const size_t j = slot_of[i];
             in_bound[i] = (double)hm[j];
             in_binary[i] = hm[j] <= 1 && hm[cnt + j] == 0;  // every entry 0 or 1
+        }
+    }
+    if (cfg.domain == DOM_INT) {
+        // the schedule depends on which inputs are 0/1 and on their maxima
+        key += "|int:";
+        for (char c : in_binary) key += c ? '1' : '0';
+        for (double b : in_bound) key += "," + std::to_string((unsigned long long)b);
+    }
+    if (capture) {
+        auto git = rt.graphs.find(key);
+        if (git != rt.graphs.end() && git->second.nd == (int)data.size()) {
+            // Replay: the graph reads its own device descriptor blob and
+            // recomputes everything in the workspace from the inputs (the
+            // exact path's input maxima are staged again where it copies
+            // them from).
+            const Runtime::GraphEntry &ge = git->second;
+            if (!ge.inmx.empty())
+                std::memcpy(rt.hdesc + ge.inmx_off, ge.inmx.data(), ge.inmx.size() * 8);
+            HIPCHK(hipGraphLaunch(ge.exec, stream));
+            HIPCHK(hipStreamSynchronize(stream));
+            const int nd = ge.nd, nprog = ge.nprog;
+            out.assign(nd, DatasetResult());
+            size_t vbytes = (size_t)nprog * cfg.wide_es, ubytes = (size_t)nd * cfg.wide_es;
+            const char *h = rt.hres;
+            if (vout) {
+                vout->assign(nprog, 0.0);
+                for (int i = 0; i < nprog; ++i)
+                    (*vout)[i] = cfg.domain == DOM_FP ? reinterpret_cast<const double *>(h)[i]
+                                                      : (double)reinterpret_cast<const __int128 *>(h)[i];
+            }
+            for (int d = 0; d < nd; ++d) {
+                if (cfg.domain == DOM_FP) {
+                    out[d].value = reinterpret_cast<const double *>(h + vbytes)[d];
+                } else {
+                    const __int128 u = reinterpret_cast<const __int128 *>(h + vbytes)[d];
+                    out[d].value = (double)u;
+                    out[d].exact_hi = (int64_t)(u >> 64);
+                    out[d].exact_lo = (uint64_t)u;
+                }
+                out[d].scale = reinterpret_cast<const double *>(h + vbytes + ubytes)[d];
+                out[d].err_est = ge.err_est[d];
+            }
+            return "";
         }
     }
     // The layout is deterministic: build once against the arena already
@@ -1987,6 +2007,10 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
             e = hipMemcpyAsync(arena + S.off_inmx, hdesc + off, im.size() * 8,
                                hipMemcpyHostToDevice, stream);
             if (e != hipSuccess) return fail(e, "input maxima upload");
+            if (capture) {
+                entry.inmx = im;
+                entry.inmx_off = off;
+            }
         }
         if (!S.diag.empty()) {
             e = launch_diag(reinterpret_cast<DiagDesc *>(dd + S.off_diag), (int)S.diag.size(),

@@ -82,6 +82,10 @@ struct Runtime {
         size_t blob_bytes = 0;
         int nd = 0, nprog = 0;
         std::vector<double> err_est;  // per dataset
+        // exact path: the input maxima the graph copies from the pinned
+        // staging buffer at this offset (rewritten there before a replay)
+        std::vector<unsigned long long> inmx;
+        size_t inmx_off = 0;
     };
     std::map<std::string, GraphEntry> graphs;
     void drop_graphs();

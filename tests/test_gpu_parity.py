@@ -203,6 +203,45 @@ def test_int8_signed_multilimb_k_steps(U, name, n):
     assert r.exact == ref
 
 
+def test_int8_graph_capture_and_replay(U):
+    """Exact plans on a side stream are captured as a graph and replayed:
+    the same 0/1 input twice (capture, then replay), new 0/1 data in the same
+    buffer (replay: the graph reads the inputs again) and entries up to 3 in
+    that buffer (other input maxima: a new schedule and capture), each
+    exact against the oracle's cycle counts or brute force."""
+    import torch
+    n = 120
+    A1 = W.erdos_renyi(n, 0.1, seed=5)
+    A2 = W.erdos_renyi(n, 0.1, seed=6)
+    s = torch.cuda.Stream()
+    P = U.Plan(5, W.CYCLE5, precision="i8")
+    with torch.cuda.stream(s):
+        Ad = dev(A1, torch.int8)
+        for rep in range(2):
+            say(f"int8 capture rep {rep}")
+            r = P.eval([Ad] * 5, stream=s)
+            assert r.exact == 10 * oracle.count_5cycles(A1.astype(np.int64))
+        Ad.copy_(dev(A2, torch.int8))
+        s.synchronize()
+        r = P.eval([Ad] * 5, stream=s)
+        assert r.exact == 10 * oracle.count_5cycles(A2.astype(np.int64))
+        rng = np.random.default_rng(7)
+        A3 = (A2 * rng.integers(1, 4, size=(n, n))).astype(np.int8)
+        Ad.copy_(dev(A3, torch.int8))
+        s.synchronize()
+        ref = oracle.ustat_bruteforce_int(W.CYCLE5, [A3[:40, :40]] * 5)
+        Ad3 = dev(np.ascontiguousarray(A3[:40, :40]), torch.int8)
+        P3 = U.Plan(5, W.CYCLE5, precision="i8")
+        for rep in range(2):
+            r = P3.eval([Ad3] * 5, stream=s)
+            assert r.exact == ref
+        r = P.eval([Ad] * 5, stream=s)
+        r2 = P.eval([Ad] * 5, stream=s)
+        assert r2.exact == r.exact
+    full = U.Plan(5, W.CYCLE5, precision="i8").eval([dev(A3, torch.int8)] * 5)
+    assert r.exact == full.exact
+
+
 def test_int8_er_cycle_counts(U):
     import torch
     n, p = 300, 0.08
