@@ -298,6 +298,33 @@ def bench_cycle5_exact(args):
     print(json.dumps(out))
 
 
+# Published dense peaks of the MI355X (operations/s) for each MFMA kind the
+# kernels use, and its HBM bandwidth (bytes/s).
+SPEC_PEAKS = {"bf16": 2.5e15, "f64": 78.6e12, "i8": 5.0e15, "f32": 157.3e12}
+
+
+def bench_peaks(args):
+    """The rooflines' denominators measured on this device: back-to-back
+    MFMAs of each kind the kernels use, and a streaming copy of 2 x 1 GiB;
+    each next to the published figure."""
+    from paper_2508_12627_amd import ustat as U
+    out = {"metric": "measured peaks (MFMA kinds, streaming copy) against the published MI355X figures",
+           "mfma": {}}
+    for kind, spec in SPEC_PEAKS.items():
+        # a few ms per timed launch (bf16 and int8 issue 16 384 / 32 768
+        # operations per instruction, fp64 and fp32 2 048)
+        iters = 40000 if kind in ("bf16", "i8") else 10000
+        best = max(U.ustat_peak_mfma(kind, iters) for _ in range(3))
+        out["mfma"][kind] = {"measured": best, "published": spec, "frac": best / spec}
+        print(f"peaks: {kind} {best / 1e12:.1f} T/s ({best / spec:.3f} of published)", file=sys.stderr,
+              flush=True)
+    best = max(U.ustat_peak_copy(1 << 30) for _ in range(3))
+    out["hbm_copy"] = {"measured": best, "published": HBM_PEAK, "frac": best / HBM_PEAK,
+                       "unit": "bytes/s (read + write)"}
+    print(f"peaks: copy {best / 1e9:.0f} GB/s", file=sys.stderr, flush=True)
+    print(json.dumps(out))
+
+
 def bench_motifs(args):
     """Induced motif counts of Erdos-Renyi graphs on the exact path at the
     sizes of the paper's motif tables: all 3-vertex motifs of G(20000, p)
@@ -554,7 +581,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--workload", default="cycle4",
-                    choices=["cycle4", "batched", "cycle5-exact", "learned-order", "motifs", "hoif"],
+                    choices=["cycle4", "batched", "cycle5-exact", "learned-order", "motifs", "hoif",
+                             "peaks"],
                     help="cycle4: the headline line; the others print their own line")
     ap.add_argument("--graph-range", default="0:64",
                     help="learned-order workload: graphs lo:hi of the 64")
@@ -595,6 +623,8 @@ def main():
         return bench_motifs(args)
     if args.workload == "hoif":
         return bench_hoif(args)
+    if args.workload == "peaks":
+        return bench_peaks(args)
     m, edges, n, d = WORKLOAD["m"], WORKLOAD["edges"], WORKLOAD["n"], WORKLOAD["d"]
     div = 2.0 * d
     Xh = W.gaussian_samples(n, d, seed=WORKLOAD["seed"])

@@ -389,6 +389,32 @@ ustat_status ustat_build_rbf(int64_t n, int32_t d, const double *X, double rbf_d
                              int32_t precision, void *out, ustat_stream stream);
 
 /*
+ * Peak microbenchmarks: the rates the kernels' rooflines are compared with,
+ * measured on the current device (HIP events around one launch, after one
+ * untimed launch, on `stream`; both calls synchronise with it).
+ *
+ * ustat_peak_mfma: two blocks of four waves per compute unit, each wave
+ * issuing `iters` (1 .. 2^32) rounds of eight independent MFMA instructions
+ * of one kind on register operands: kind 0 bf16 16x16x32 (fp32
+ * accumulation), 1 fp64 16x16x4, 2 int8 16x16x64 (int32 accumulation),
+ * 3 fp32 16x16x4.  *rate receives operations per second (2 per
+ * multiply-add).  sink: device memory of at least 4096 x 32 bytes, owned by
+ * the caller, overwritten with the waves' sums (keeps the work live).
+ *
+ * ustat_peak_copy: a streaming copy of `bytes` (a positive multiple of 16)
+ * from src to dst (device buffers owned by the caller, not overlapping),
+ * eight blocks of 256 threads per compute unit; *rate receives bytes read
+ * plus bytes written per second.
+ *
+ * Errors: USTAT_E_INVALID for bad arguments, USTAT_E_HIP for a failed
+ * launch or event.
+ */
+ustat_status ustat_peak_mfma(int32_t kind, int64_t iters, void *sink, ustat_stream stream,
+                             double *rate);
+ustat_status ustat_peak_copy(const void *src, void *dst, int64_t bytes, ustat_stream stream,
+                             double *rate);
+
+/*
  * Kernel timing (HIP events recorded around every grouped launch on the
  * launch stream; off by default, never active inside graph capture).
  * kind: 0 operand prep, 1 GEMM, 2 column reduction, 3 partial reduction,

@@ -14,7 +14,7 @@ LIB = os.path.join(HERE, "libustat.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["k_rowred_mixed.hip", "k_rowred_int.hip", "k_colred_mixed.hip", "k_colred_int.hip",
            "k_rowred_f64.hip", "k_colred_fp.hip", "k_rowred_f32.hip", "k_gemm.hip", "k_reduce.hip",
-           "kernels.hip", "k_lowrank.hip", "mlp.hip", "exec.cpp", "capi.cpp", "plan.cpp",
+           "kernels.hip", "k_lowrank.hip", "k_peak.hip", "mlp.hip", "exec.cpp", "capi.cpp", "plan.cpp",
            "lowrank.cpp", "costmodel.cpp", "profile.cpp", "inject.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",
@@ -23,10 +23,12 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           "-I" + os.path.join(HERE, "..", "include")]
 
 
-# Per-source code generation options: the low-rank outer-product kernel
-# keeps its fp64 MFMA accumulators in ordinary VGPRs (no copies between
-# accumulation and vector registers around every MFMA group of its loop).
-EXTRA = {"k_lowrank.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
+# Per-source code generation options: the low-rank outer-product kernel and
+# the MFMA peak kernels keep their accumulators in ordinary VGPRs (no copies
+# between accumulation and vector registers around every MFMA group of
+# their loops).
+EXTRA = {"k_lowrank.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
+         "k_peak.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
 
 
 def _compile(src: str) -> str:

@@ -767,6 +767,77 @@ ustat_status ustat_build_rbf(int64_t n, int32_t d, const double *X, double rbf_d
     USTAT_GUARD_END
 }
 
+}  // extern "C"
+
+namespace {
+
+// Times one launch of a peak microbenchmark with HIP events on `s` (after
+// one untimed launch), returning seconds.
+template <class L>
+hipError_t time_launch(hipStream_t s, L &&launch, double *sec) {
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    if (e == hipSuccess) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(a, s);
+    if (e == hipSuccess) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(b, s);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    float ms = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    *sec = ms * 1e-3;
+    return e;
+}
+
+hipError_t compute_units(int *cu) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(cu, hipDeviceAttributeMultiprocessorCount, dev);
+    return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+ustat_status ustat_peak_mfma(int32_t kind, int64_t iters, void *sink, ustat_stream stream,
+                             double *rate) {
+    USTAT_GUARD_BEGIN
+    if (kind < 0 || kind > 3 || iters < 1 || iters > (int64_t)1 << 32 || !sink || !rate)
+        return fail(USTAT_E_INVALID, "bad arguments");
+    int cu = 0;
+    hipError_t e = compute_units(&cu);
+    if (e != hipSuccess) return fail(USTAT_E_HIP, hipGetErrorString(e));
+    double flops = 0, sec = 0;
+    e = time_launch((hipStream_t)stream, [&] {
+        return launch_peak_mfma(kind, 2 * cu, iters, static_cast<char *>(sink), (hipStream_t)stream, &flops);
+    }, &sec);
+    if (e != hipSuccess) return fail(USTAT_E_HIP, hipGetErrorString(e));
+    *rate = sec > 0 ? flops / sec : 0.0;
+    return ok();
+    USTAT_GUARD_END
+}
+
+ustat_status ustat_peak_copy(const void *src, void *dst, int64_t bytes, ustat_stream stream,
+                             double *rate) {
+    USTAT_GUARD_BEGIN
+    if (!src || !dst || !rate || bytes < 16 || bytes % 16 != 0)
+        return fail(USTAT_E_INVALID, "bad arguments");
+    int cu = 0;
+    hipError_t e = compute_units(&cu);
+    if (e != hipSuccess) return fail(USTAT_E_HIP, hipGetErrorString(e));
+    double sec = 0;
+    e = time_launch((hipStream_t)stream, [&] {
+        return launch_peak_copy(src, dst, bytes, 8 * cu, (hipStream_t)stream);
+    }, &sec);
+    if (e != hipSuccess) return fail(USTAT_E_HIP, hipGetErrorString(e));
+    *rate = sec > 0 ? 2.0 * (double)bytes / sec : 0.0;
+    return ok();
+    USTAT_GUARD_END
+}
+
 ustat_status ustat_eval_samples(ustat_plan plan, int64_t n, int32_t d, const double *X,
                                 double rbf_divisor, ustat_stream stream, ustat_result *out) {
     USTAT_GUARD_BEGIN

@@ -275,6 +275,17 @@ __host__ __device__ inline void sym_tile(int64_t t, int64_t t_side, int64_t &I, 
 }
 hipError_t launch_gemm_sym(const GemmDesc *d, int nprob, int64_t units, int blocks, int64_t tiles,
                            float *part, hipStream_t s);
+
+// Peak microbenchmarks (k_peak.hip).  launch_peak_mfma: `blocks` blocks of
+// four waves, each issuing `iters` rounds of eight independent MFMAs of one
+// kind (0 bf16 16x16x32, 1 fp64 16x16x4, 2 int8 16x16x64, 3 fp32 16x16x4);
+// *flops receives the operations launched; sink: kPeakSinkSlots x 32 bytes
+// of device memory.  launch_peak_copy: a streaming copy of `bytes` (a
+// multiple of 16) from src to dst.
+constexpr int kPeakSinkSlots = 4096;
+hipError_t launch_peak_mfma(int kind, int blocks, int64_t iters, char *sink, hipStream_t s,
+                            double *flops);
+hipError_t launch_peak_copy(const void *src, void *dst, int64_t bytes, int blocks, hipStream_t s);
 // flag[p] = 1 when matrix p (n[p] x n[p], fp32 when f32 else fp64) holds a
 // negative (or NaN) entry, else 0; the flags must be zero on entry.
 hipError_t launch_signscan(const void *const *src, const int64_t *n, int nprob, int f32,

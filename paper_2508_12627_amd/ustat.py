@@ -77,7 +77,7 @@ EXPORTS = ["ustat_plan_opts_default", "ustat_plan_create", "ustat_plan_destroy",
            "ustat_plan_tuning", "ustat_plan_set_tuning", "ustat_plan_autotune",
            "ustat_eval_noalloc", "ustat_debug_inject", "ustat_plan_create_motifs",
            "ustat_motif_counts", "ustat_eval_lowrank", "ustat_lowrank_info",
-           "ustat_plan_autotune_batched",
+           "ustat_plan_autotune_batched", "ustat_peak_mfma", "ustat_peak_copy",
            "ustat_status_string", "ustat_last_error"]
 NUM_FEATURES = 18
 
@@ -116,6 +116,8 @@ def load_library(path: str = LIB_PATH):
     L.ustat_eval_batched.argtypes = [P, i32, pi64, i32, ctypes.POINTER(P), dbl, P,
                                      ctypes.POINTER(Result)]
     L.ustat_build_rbf.argtypes = [i64, i32, P, dbl, i32, P, P]
+    L.ustat_peak_mfma.argtypes = [i32, i64, P, P, pdbl]
+    L.ustat_peak_copy.argtypes = [P, P, i64, P, pdbl]
     L.ustat_profile_enable.argtypes = [i32]
     L.ustat_profile_reset.argtypes = []
     L.ustat_profile_read.argtypes = [i32, pdbl, pi64, pdbl, pdbl]
@@ -396,6 +398,29 @@ def ustat_build_rbf(X: torch.Tensor, divisor: float, precision="f64", stream=Non
     _check(load_library().ustat_build_rbf(n, d, ctypes.c_void_p(X.data_ptr()), float(divisor), p,
                                           ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
     return out
+
+
+PEAK_KINDS = {"bf16": 0, "f64": 1, "i8": 2, "f32": 3}
+
+
+def ustat_peak_mfma(kind, iters: int = 20000, stream=None) -> float:
+    """Measured MFMA rate (operations/s) of one instruction kind (see ustat.h)."""
+    k = PEAK_KINDS[kind] if isinstance(kind, str) else int(kind)
+    sink = torch.empty(4096 * 32, dtype=torch.uint8, device="cuda")
+    rate = ctypes.c_double()
+    _check(load_library().ustat_peak_mfma(k, int(iters), ctypes.c_void_p(sink.data_ptr()),
+                                          _stream_handle(stream), ctypes.byref(rate)))
+    return rate.value
+
+
+def ustat_peak_copy(nbytes: int = 1 << 30, stream=None) -> float:
+    """Measured streaming-copy rate (bytes read + written per second)."""
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    rate = ctypes.c_double()
+    _check(load_library().ustat_peak_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                                          int(nbytes), _stream_handle(stream), ctypes.byref(rate)))
+    return rate.value
 
 
 def ustat_profile_enable(on: bool = True):

@@ -46,6 +46,19 @@ def test_invalid_and_unsupported(U):
     assert L.ustat_eval(P.h, 64, ptrs, None, ctypes.byref(r)) == 2  # unsupported, before device work
 
 
+def test_peak_arguments(U):
+    """The peak microbenchmarks check their arguments before any device
+    call."""
+    L = U.load_library()
+    rate = ctypes.c_double()
+    fake = ctypes.c_void_p(4096)
+    assert L.ustat_peak_mfma(4, 10, fake, None, ctypes.byref(rate)) == 1  # unknown kind
+    assert L.ustat_peak_mfma(0, 0, fake, None, ctypes.byref(rate)) == 1   # no rounds
+    assert L.ustat_peak_mfma(0, 10, None, None, ctypes.byref(rate)) == 1  # no sink
+    assert L.ustat_peak_copy(fake, fake, 24, None, ctypes.byref(rate)) == 1  # not a multiple of 16
+    assert L.ustat_peak_copy(fake, None, 32, None, ctypes.byref(rate)) == 1
+
+
 def test_hip_failure_without_device(U):
     import torch
     if torch.cuda.is_available():
