@@ -81,9 +81,41 @@ __global__ __launch_bounds__(kLrThreads) void k_lr_steps(const LrStepDesc *__res
         const int64_t o = bi * kLrThreads + tid;
         if (o >= st.nout) return;
         lr_offsets(st, o, off);
-        double acc = 0.0;
-        for (int64_t x = 0; x < st.nx; ++x) acc += lr_term(p, off, sx, nin, x);
-        ws[st.out + o] = acc;
+        // operand pointers formed once and stepped by their x strides; four
+        // terms at a time in four sums (their loads in flight together),
+        // added in a fixed order
+        const double *q[kLrMaxIn];
+#pragma unroll
+        for (int t = 0; t < kLrMaxIn; ++t) q[t] = p[t] + off[t];
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int64_t x = 0;
+        for (; x + 3 < st.nx; x += 4) {
+            double t0 = q[0][0], t1 = q[0][sx[0]], t2 = q[0][2 * sx[0]], t3 = q[0][3 * sx[0]];
+#pragma unroll
+            for (int t = 1; t < kLrMaxIn; ++t)
+                if (t < nin) {
+                    t0 *= q[t][0];
+                    t1 *= q[t][sx[t]];
+                    t2 *= q[t][2 * sx[t]];
+                    t3 *= q[t][3 * sx[t]];
+                }
+            a0 += t0;
+            a1 += t1;
+            a2 += t2;
+            a3 += t3;
+#pragma unroll
+            for (int t = 0; t < kLrMaxIn; ++t) q[t] += 4 * sx[t];
+        }
+        for (; x < st.nx; ++x) {
+            double t0 = q[0][0];
+#pragma unroll
+            for (int t = 1; t < kLrMaxIn; ++t)
+                if (t < nin) t0 *= q[t][0];
+            a0 += t0;
+#pragma unroll
+            for (int t = 0; t < kLrMaxIn; ++t) q[t] += sx[t];
+        }
+        ws[st.out + o] = (a0 + a1) + (a2 + a3);
         return;
     }
     const int64_t tile = bi / st.nchunk, c = bi - tile * st.nchunk;
