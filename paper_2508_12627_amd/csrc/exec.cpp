@@ -1174,7 +1174,7 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
                 const Node &q = G.nodes[id];
                 if (q.kind != NK::GemmStore && q.kind != NK::GemmFinal) continue;
                 if (gemm_format(q) == PF_BF16X3) continue;
-                const int64_t np_ = up64(q.n, 128);
+                const int64_t np_ = gemm_npad(q.n, gemm_format(q));
                 if (np_ % 256 == 0) t256 += (np_ / 256) * (np_ / 256);
             }
             W.big = (cfg.prec == 1 || cfg.prec == 2) && t256 > 0 && t256 >= plan.tuning.gemm_big_min;
@@ -1186,7 +1186,8 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
             Node &nd_ = G.nodes[id];
             const int d = nd_.d;
             const int64_t n = nd_.n;
-            const int64_t npad = up64(n, 128);
+            const bool is_gemm = nd_.kind == NK::GemmStore || nd_.kind == NK::GemmFinal;
+            const int64_t npad = is_gemm ? gemm_npad(n, gemm_format(nd_)) : up64(n, 128);
             const int tiles64 = (int)((n + 63) / 64);
             if ((int)nd_.A.size() > kMaxMat || (int)nd_.B.size() > kMaxMat ||
                 (int)nd_.Z.size() > kMaxMat || (int)nd_.sv.size() > kMaxVec ||
@@ -1606,7 +1607,7 @@ int factor_operand_format(const Plan &plan, int64_t n, bool nonneg) {
 
 size_t factor_operand_bytes(int format, int64_t n) {
     if (format < 0) return 0;
-    return prep_bytes(format, up64(n, 128), 1);
+    return prep_bytes(format, gemm_npad(n, format), 1);
 }
 
 ScheduleSizes schedule_sizes(const Plan &plan, const std::vector<const VProgram *> &progs,

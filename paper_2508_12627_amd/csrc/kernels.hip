@@ -586,7 +586,7 @@ __global__ __launch_bounds__(256) void k_slicesrc(const SliceDesc *__restrict__ 
 
 hipError_t launch_rbf(const double *X, int64_t n, int32_t d, double divisor, void *out,
                       int32_t dtype, hipStream_t s, void *op, int32_t op_format) {
-    const int64_t npad = (n + 127) / 128 * 128;
+    const int64_t npad = gemm_npad(n, op_format);
     const unsigned T = (unsigned)(op ? npad / 64 : (n + 63) / 64);
     dim3 grid(T, T);
     const double inv = 1.0 / divisor;

@@ -115,6 +115,15 @@ struct Elim0Desc {
 
 enum PrepFormat : int32_t { PF_F64 = 0, PF_F32 = 1, PF_BF16X2 = 2, PF_I8LIMBS = 3, PF_BF16X3 = 4 };
 
+// Padded size of the GEMM operands of an n x n matrix in prep format fmt:
+// fp32 and two-plane split-bf16 operands from n = 1024 on are padded to a
+// multiple of 256 so that their products can take 256-wide tiles; all
+// others to a multiple of 128.
+inline int64_t gemm_npad(int64_t n, int fmt) {
+    const int64_t a = (n >= 1024 && (fmt == PF_F32 || fmt == PF_BF16X2)) ? 256 : 128;
+    return (n + a - 1) / a * a;
+}
+
 // GEMM operand: out[w * ldo + v] = prod_j s_j(v) prod_k A_k(v, w) for
 // w, v < n and 0 in the padding up to npad, every operand stored (w, v)
 // (trans == 1); tiles of 64 rows x 128 columns, (npad/64) * (npad/128) per
