@@ -100,7 +100,7 @@ def measured_traffic(kind, prec, path=TRAFFIC_FILE):
     return tot / cnt if cnt else None
 
 
-def kernel_rooflines(U, plan, X, div, stream, prec, reps=5):
+def kernel_rooflines(U, plan, X, div, stream, prec, reps=5, executed_share=1.0):
     """Per-kernel-kind durations from HIP events recorded around every
     launch on the launch stream (kernel-by-kernel launches, no graph)."""
     U.ustat_profile_enable(True)
@@ -109,10 +109,13 @@ def kernel_rooflines(U, plan, X, div, stream, prec, reps=5):
         plan.eval_samples(X, div, stream=stream)
     stats = {k: U.ustat_profile_read(k) for k in KERNELS}
     U.ustat_profile_enable(False)
-    return summarize(stats, reps, prec, TRAFFIC_FILE)
+    return summarize(stats, reps, prec, TRAFFIC_FILE, executed_share)
 
 
-def summarize(stats, reps, prec, traffic_path=TRAFFIC_FILE):
+def summarize(stats, reps, prec, traffic_path=TRAFFIC_FILE, executed_share=1.0):
+    """executed_share: the part of the GEMM's algorithmic products that its
+    MFMA instructions compute (t(t+1)/2 of t^2 tiles for a symmetric product
+    on t tiles a side, else 1); split-bf16 issues three products for each."""
     out = {}
     for k, g in stats.items():
         if g["launches"] == 0:
@@ -127,7 +130,8 @@ def summarize(stats, reps, prec, traffic_path=TRAFFIC_FILE):
             e.update({"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAKS[prec] / 1e12,
                       "unit": "TFLOP/s", "frac": achieved / PEAKS[prec],
                       "flops_per_launch": g["flops"] / g["launches"],
-                      "executed_frac": achieved * (3 if prec == "bf16x3" else 1) / PEAKS[prec]})
+                      "executed_frac": achieved * executed_share * (3 if prec == "bf16x3" else 1)
+                      / PEAKS[prec]})
         elif g["bytes"] > 0:
             achieved = g["bytes"] / sec
             e.update({"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
@@ -666,7 +670,11 @@ def main():
                       "order": args.order, "precision": args.precision, "cse": True,
                       "num_vstats": r.num_vstats, "tuning": main_plan.tuning(),
                       "autotuned": tune_ms is not None}}
-    dom, kr = kernel_rooflines(U, main_plan, X, div, stream, args.precision)
+    # R = K K runs as a symmetric product on 256-wide tiles (n a multiple of
+    # 256, 256-wide tiles chosen): t (t + 1) / 2 of the t^2 tiles are computed
+    t = n // 256
+    share = (t * (t + 1) / 2) / (t * t) if n % 256 == 0 and main_plan.tuning()["gemm_big_min"] <= t * t else 1.0
+    dom, kr = kernel_rooflines(U, main_plan, X, div, stream, args.precision, executed_share=share)
     out["roofline"] = dict(kr[dom])
     out["roofline"]["dominant_kind"] = dom
     out["roofline_mfma_gemm"] = kr.get("gemm")

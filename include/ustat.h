@@ -421,8 +421,8 @@ ustat_status ustat_peak_copy(const void *src, void *dst, int64_t bytes, ustat_st
  * 4 factor build, 5 low-rank summation steps, 6 low-rank chunk sums,
  * 7 low-rank outer-product (GEMM) steps.  ustat_profile_read returns
  * totals since the last reset: milliseconds, number of launches,
- * algorithmic flops (2 n^3 per GEMM, n^2 (n + 1) per symmetric product
- * P P^T, 2 M N n per low-rank GEMM step) and
+ * algorithmic flops (2 n^3 per GEMM step, symmetric products P P^T
+ * included, 2 M N n per low-rank GEMM step) and
  * algorithmic bytes (every operand element read once plus the outputs
  * written, for the column reduction and operand prep kernels).  Any output
  * pointer may be NULL.

@@ -1383,8 +1383,9 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
                         W.gemm_sym_tiles += t * (t + 1) / 2;
                         W.gemm_sym_units += t * (t + 1) / 2 * nk;
                         W.gemm_sym_nk = std::max(W.gemm_sym_nk, nk);
-                        // the products of the entries on and above the diagonal
-                        W.gemm_sym_flops += (double)n * n * (n + 1);
+                        // the step's algorithmic work, 2 n^3 as for any product,
+                        // although only the tiles on and above the diagonal run
+                        W.gemm_sym_flops += 2.0 * (double)n * n * n;
                     } else {
                         int64_t &tcount = six ? W.gemm6_tiles : big ? W.gemm_big_tiles : W.gemm_tiles;
                         g.tile_start = tcount;

@@ -338,42 +338,37 @@ def test_large_tiles_ragged(U, prec):
 def test_symmetric_products_stream_k(U, n):
     """R = K K computed on the tiles on and above the diagonal only, their K
     steps spread evenly over the blocks (tiles split between two or three
-    blocks, the block finishing a tile last adding its pieces) and each
-    tile mirrored: the 4-cycle U against the oracle's closed form, with and
-    without the symmetric path (256-wide tiles forced), which is seen to run
-    through the GEMM work counted (n^2 (n + 1) for the symmetric product
-    instead of 2 n^3).  Two evaluations in a row check that the tile
-    counters start from zero again.  n = 1280 gives 15 tiles split over 30
-    blocks; n = 2498 is not a multiple of 4 (element-wise mirror stores)
-    and leaves the last row and column of tiles partly outside the matrix.
-    (Below n = 1024 the operands take three planes and 128-wide tiles,
-    outside this path.)"""
+    blocks and summed by the fix-up) and each tile mirrored: the 4-cycle U
+    against the oracle's closed form, with and without the symmetric path
+    (256-wide tiles forced).  The path is seen in the dry schedule: its
+    workspace holds two fp32 partial tiles per block.  Two evaluations in a
+    row give the same bits.  n = 1280 gives 15 tiles split over 30 blocks;
+    n = 2498 is not a multiple of 4 (element-wise mirror stores) and leaves
+    the last row and column of tiles partly outside the matrix.  (Below
+    n = 1024 the operands take three planes and 128-wide tiles, outside this
+    path.)"""
     import torch
     X = W.gaussian_samples(n, 16, seed=23)
     K = oracle.rbf_matrix(X, 32.0)
     ref = oracle.cycle4_closed_form(K)
     K2 = K @ K
     vfin = float(np.sum(K2 * K2))
-    vals, flops = {}, {}
+    vals, ws = {}, {}
     for sym in (True, False):
         say(f"symmetric products n={n} sym={sym}")
+        Q = U.Plan(4, W.CYCLE4, precision="bf16x3", sym_gemm=sym, symmetric=True)
+        Q.set_tuning(0, 1024)
+        ws[sym] = Q.workspace([n])
         P = U.Plan(4, W.CYCLE4, precision="bf16x3", sym_gemm=sym)
         P.set_tuning(0, 1024)
-        U.ustat_profile_enable(True)
-        U.ustat_profile_reset()
-        try:
-            r = P.eval_samples(dev(X, torch.float64), 32.0)
-            torch.cuda.synchronize()
-            flops[sym] = U.ustat_profile_read("gemm")["flops"]
-        finally:
-            U.ustat_profile_enable(False)
+        r = P.eval_samples(dev(X, torch.float64), 32.0)
         r2 = P.eval_samples(dev(X, torch.float64), 32.0)
         assert r2.value == r.value
         err = abs(r.value - ref) / vfin
         say(f"  U={r.value:.12e} ref={ref:.12e} err/Vfin={err:.2e}")
         assert err <= TOL["bf16x3"]
         vals[sym] = r.value
-    assert flops[False] - flops[True] == float(n) ** 3 - float(n) ** 2
+    assert ws[True] > ws[False]
     # the two paths differ only in the order of fp32 additions
     assert abs(vals[True] - vals[False]) <= 1e-7 * vfin
 
