@@ -602,6 +602,16 @@ def main():
         print("bench.py runs on one GPU only: this engine has no multi-GPU path "
               "(--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "learned-order":
+        # Switched off: one run of this workload after the symmetric stream-K
+        # products and the other GEMM changes stopped on an illegal memory
+        # access, and host-side checks of the schedules it builds (the
+        # stream-K walk over whole slice chunks included) have not shown the
+        # cause.  It stays off until one is found.
+        print("bench.py: the learned-order workload is switched off: one run of it faulted the "
+              "GPU and the cause has not been found (its last clean run: "
+              "profiles/learned_order_e2e.json)", file=sys.stderr)
+        sys.exit(2)
 
     import numpy as np
     import torch
