@@ -378,10 +378,11 @@ def test_large_tiles_batched_level(U):
     their GEMMs run in a 256-wide launch, while the two sizes whose padding
     is not a multiple of 256 (1900, 333) share the level in a 128-wide one,
     and a single dataset (64 such tiles) takes 128-wide tiles: all agree to
-    rounding and match the f64 path."""
+    rounding, match the f64 path and, dataset by dataset, the oracle."""
     import torch
     ns = [2048] * 4 + [1900, 333]
-    Xs = [dev(W.gaussian_samples(n, 16, seed=80 + i), torch.float64) for i, n in enumerate(ns)]
+    Xh = [W.gaussian_samples(n, 16, seed=80 + i) for i, n in enumerate(ns)]
+    Xs = [dev(X, torch.float64) for X in Xh]
     P = U.Plan(4, W.CYCLE4, precision="bf16x3")
     say("large tiles batched 4 x 2048 bf16x3")
     rb = P.eval_batched(Xs, 32.0)
@@ -390,6 +391,39 @@ def test_large_tiles_batched_level(U):
         single = P.eval_samples(X, 32.0)
         assert abs(rb[i].value - single.value) <= 1e-6 * single.err_scale
         assert abs(rb[i].value - r64[i].value) <= 1e-6 * r64[i].err_scale
+        ref, S, _ = oracle.ustat_and_scale_einsum(W.CYCLE4, [oracle.rbf_matrix(Xh[i], 32.0)] * 4)
+        say(f"large tiles batched dataset {i} n={ns[i]} vs oracle")
+        assert abs(rb[i].value - ref) <= TOL["bf16x3"] * S
+        assert abs(r64[i].value - ref) <= TOL["f64"] * S
+
+
+def test_batched_workload_full_size_sampled(U):
+    """The whole 256-dataset batch of the batched workload (n ~ U{128..4096},
+    d = 32, Student-t(5) samples, 5-cycle plus chord, RBF divisor 64) in one
+    split-bf16 evaluation with the launch shapes its benchmark uses; three
+    datasets of it (the smallest, and those nearest n = 1024 and 2048) against
+    the oracle, within 1e-6 S each."""
+    import torch
+    ns = [int(x) for x in W.ragged_sizes(256, 128, 4096, seed=4)]
+    d, div = 32, 64.0
+    Xh = [W.student_t_samples(n, d, seed=1000 + i) for i, n in enumerate(ns)]
+    Xs = [dev(X, torch.float64) for X in Xh]
+    P = U.Plan(5, W.CYCLE5_CHORD, precision="bf16x3", order="exhaustive")
+    P.set_tuning(0, 1024)
+    stream = torch.cuda.Stream()
+    say("batched workload: 256 datasets, bf16x3, tuning 0,1024")
+    r = P.eval_batched(Xs, div, stream=stream)
+    torch.cuda.synchronize()
+    picks = sorted({min(range(len(ns)), key=lambda i: ns[i]),
+                    min(range(len(ns)), key=lambda i: abs(ns[i] - 1024)),
+                    min(range(len(ns)), key=lambda i: abs(ns[i] - 2048))})
+    for i in picks:
+        K = oracle.rbf_matrix(Xh[i], div)
+        ref, S, _ = oracle.ustat_and_scale_einsum(W.CYCLE5_CHORD, [K] * 6)
+        err = abs(r[i].value - ref) / S
+        say(f"batched workload dataset {i} n={ns[i]} err/S={err:.3e}")
+        assert err <= TOL["bf16x3"], (i, ns[i], err)
+        check_est(f"batched-{i}", r[i], err, "bf16x3")
 
 
 @pytest.mark.parametrize("name", ["cycle4", "c5chord", "bowtie"])
