@@ -21,56 +21,75 @@ namespace ustat {
 // also written in the GEMM-operand form of that prep format (npad x npad,
 // zero padded: fp64, fp32, or bf16 hi and lo planes), so that no separate
 // operand preparation of the factor is needed.
+// Stores one 64 x 64 tile of the factor (rows r0.., columns c0..) from the
+// LDS tile, transposed when `mirror`.  Every store instruction of a wave
+// writes whole 16-byte pieces of consecutive rows (16 lanes per fp32 row of
+// 64 values, 8 lanes per row of a bf16 plane), so each row segment is
+// written by adjacent lanes of one instruction; the LDS reads of both
+// orientations stay free of bank conflicts (row pitch 65 words).
 template <typename KT, int OPF>
-__device__ __forceinline__ void rbf_store16(KT *__restrict__ K, void *__restrict__ op, int64_t n,
-                                            int64_t npad, int64_t g, int64_t c0, const double (&v)[16]) {
-    if (g < n) {
-        KT *row = K + g * n;
-        if (n % 4 == 0 && c0 + 15 < n) {
-            if constexpr (sizeof(KT) == 4) {
+__device__ __forceinline__ void rbf_store_tile(KT *__restrict__ K, void *__restrict__ op, int64_t n,
+                                               int64_t npad, int64_t r0, int64_t c0,
+                                               const KT (&val)[64][65], bool mirror) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const int t = threadIdx.x;
+    auto at = [&](int r, int c) -> KT { return mirror ? val[c][r] : val[r][c]; };
+    {
+        constexpr int PER = 16 / (int)sizeof(KT), LPR = 64 / PER;
+        const bool vec = n % PER == 0;
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    *reinterpret_cast<f32x4 *>(row + c0 + 4 * q) =
-                        f32x4{(float)v[4 * q], (float)v[4 * q + 1], (float)v[4 * q + 2], (float)v[4 * q + 3]};
+        for (int it = 0; it < 64 * LPR / 256; ++it) {
+            const int idx = it * 256 + t, r = idx / LPR, c = (idx % LPR) * PER;
+            const int64_t g = r0 + r, col = c0 + c;
+            if (g >= n) continue;
+            KT *dst = K + g * n + col;
+            if (vec && col + PER <= n) {
+                if constexpr (sizeof(KT) == 4)
+                    *reinterpret_cast<f32x4 *>(dst) = f32x4{at(r, c), at(r, c + 1), at(r, c + 2), at(r, c + 3)};
+                else
+                    *reinterpret_cast<d2 *>(dst) = d2{at(r, c), at(r, c + 1)};
             } else {
-                typedef double d2 __attribute__((ext_vector_type(2)));
 #pragma unroll
-                for (int q = 0; q < 8; ++q) *reinterpret_cast<d2 *>(row + c0 + 2 * q) = d2{v[2 * q], v[2 * q + 1]};
+                for (int e = 0; e < PER; ++e)
+                    if (col + e < n) dst[e] = at(r, c + e);
             }
-        } else {
-#pragma unroll
-            for (int e = 0; e < 16; ++e)
-                if (c0 + e < n) row[c0 + e] = (KT)v[e];
         }
     }
+    // the operand form covers npad x npad: every row and column of the tile
     if constexpr (OPF == PF_F64) {
-        typedef double d2 __attribute__((ext_vector_type(2)));
-        double *o = static_cast<double *>(op) + g * npad + c0;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) *reinterpret_cast<d2 *>(o + 2 * q) = d2{v[2 * q], v[2 * q + 1]};
+        for (int it = 0; it < 8; ++it) {
+            const int idx = it * 256 + t, r = idx >> 5, c = (idx & 31) * 2;
+            double *o = static_cast<double *>(op) + (r0 + r) * npad + c0 + c;
+            *reinterpret_cast<d2 *>(o) = d2{(double)at(r, c), (double)at(r, c + 1)};
+        }
     } else if constexpr (OPF == PF_F32) {
-        float *o = static_cast<float *>(op) + g * npad + c0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-            *reinterpret_cast<f32x4 *>(o + 4 * q) =
-                f32x4{(float)v[4 * q], (float)v[4 * q + 1], (float)v[4 * q + 2], (float)v[4 * q + 3]};
+        for (int it = 0; it < 4; ++it) {
+            const int idx = it * 256 + t, r = idx >> 4, c = (idx & 15) * 4;
+            float *o = static_cast<float *>(op) + (r0 + r) * npad + c0 + c;
+            *reinterpret_cast<f32x4 *>(o) = f32x4{(float)at(r, c), (float)at(r, c + 1),
+                                                  (float)at(r, c + 2), (float)at(r, c + 3)};
+        }
     } else if constexpr (OPF == PF_BF16X2) {
         // the split of the fp32 factor value, as the operand preparation
         // forms it: hi = bf16(x), lo = bf16(x - hi)
         typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
-        u16x8 hi[2], lo[2];
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const double xd = (double)(float)v[e];
-            const uint16_t h = f32_to_bf16_rne((float)xd);
-            hi[e >> 3][e & 7] = h;
-            lo[e >> 3][e & 7] = f32_to_bf16_rne((float)(xd - (double)bf16_to_f32(h)));
+        for (int it = 0; it < 2; ++it) {
+            const int idx = it * 256 + t, r = idx >> 3, c = (idx & 7) * 8;
+            u16x8 hi, lo;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const double xd = (double)(float)at(r, c + e);
+                const uint16_t h = f32_to_bf16_rne((float)xd);
+                hi[e] = h;
+                lo[e] = f32_to_bf16_rne((float)(xd - (double)bf16_to_f32(h)));
+            }
+            uint16_t *o = static_cast<uint16_t *>(op) + (r0 + r) * npad + c0 + c;
+            *reinterpret_cast<u16x8 *>(o) = hi;
+            *reinterpret_cast<u16x8 *>(o + npad * npad) = lo;
         }
-        uint16_t *o = static_cast<uint16_t *>(op) + g * npad + c0;
-        *reinterpret_cast<u16x8 *>(o) = hi[0];
-        *reinterpret_cast<u16x8 *>(o + 8) = hi[1];
-        *reinterpret_cast<u16x8 *>(o + npad * npad) = lo[0];
-        *reinterpret_cast<u16x8 *>(o + npad * npad + 8) = lo[1];
     }
 }
 
@@ -149,22 +168,9 @@ __global__ __launch_bounds__(256) void k_rbf(const double *__restrict__ X, int64
                 val[row][col] = (KT)((gi < n && gj < n) ? k : 0.0);
             }
     __syncthreads();
-    // direct tile: row r, 16 consecutive columns per thread
-    {
-        const int r = t >> 2, c = (t & 3) * 16;
-        double v[16];
-#pragma unroll
-        for (int e = 0; e < 16; ++e) v[e] = (double)val[r][c + e];
-        rbf_store16<KT, OPF>(K, op, n, npad, i0 + r, j0 + c, v);
-    }
+    rbf_store_tile<KT, OPF>(K, op, n, npad, i0, j0, val, false);
     if (blockIdx.x == blockIdx.y) return;  // the diagonal tile is its own mirror
-    {
-        const int r = t >> 2, c = (t & 3) * 16;
-        double v[16];
-#pragma unroll
-        for (int e = 0; e < 16; ++e) v[e] = (double)val[c + e][r];
-        rbf_store16<KT, OPF>(K, op, n, npad, j0 + r, i0 + c, v);
-    }
+    rbf_store_tile<KT, OPF>(K, op, n, npad, j0, i0, val, true);
 }
 
 // ----------------------------------------------------------------- diag
