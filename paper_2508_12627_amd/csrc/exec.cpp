@@ -28,8 +28,27 @@ void Runtime::drop_graphs() {
     graphs.clear();
 }
 
+hipError_t Runtime::reserve_side(size_t levels) {
+    if (!side) {
+        hipError_t e = hipStreamCreateWithFlags(&side, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            side = nullptr;
+            return e;
+        }
+    }
+    while (level_events.size() < 2 * levels) {
+        hipEvent_t ev;
+        hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e != hipSuccess) return e;
+        level_events.push_back(ev);
+    }
+    return hipSuccess;
+}
+
 Runtime::~Runtime() {
     drop_graphs();
+    for (hipEvent_t ev : level_events) (void)hipEventDestroy(ev);
+    if (side) (void)hipStreamDestroy(side);
     if (arena) (void)hipFree(arena);
     if (ddesc) (void)hipFree(ddesc);
     if (hdesc) (void)hipHostFree(hdesc);
@@ -1970,6 +1989,10 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
                 *blob = nullptr;
             }
         } cguard{stream, &entry.blob};
+        // a level's reductions run on a second stream beside its GEMMs
+        // (created before any capture begins; never for external memory)
+        const bool overlap = plan.opts.overlap && !ext;
+        if (overlap) HIPCHK(rt.reserve_side(S.levels.size()));
         if (capture) {
             HIPCHK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
             cguard.active = true;
@@ -2019,7 +2042,8 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
                             S.diag_maxn, cfg.domain, stream);
             if (e != hipSuccess) return fail(e, "diag");
         }
-        for (auto &W : S.levels) {
+        for (size_t L = 0; L < S.levels.size(); ++L) {
+            auto &W = S.levels[L];
             if (!W.sl.empty()) {
                 e = launch_slicesrc(reinterpret_cast<SliceDesc *>(dd + W.off_sl), (int)W.sl.size(),
                                     W.sl_tiles, cfg.domain, stream);
@@ -2030,6 +2054,21 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
                 e = launch_transpose(reinterpret_cast<TransDesc *>(dd + W.off_tr), (int)W.tr.size(),
                                      W.tr_tiles, stream);
                 if (e != hipSuccess) return fail(e, "transpose");
+            }
+            // The level's reductions read only earlier levels' results, as do
+            // its GEMMs: with both present they run on the second stream,
+            // forked here and joined before the level's partial sums.
+            bool any_red = !W.e1.empty() || !W.e0.empty();
+            for (int k = 0; k < LevelWork::kColSlots; ++k) any_red = any_red || !W.col[k].empty();
+            const bool fork = overlap && any_red &&
+                              (!W.gemm_big.empty() || !W.gemm_sym.empty() || !W.gemm6.empty() ||
+                               !W.gemm.empty());
+            hipStream_t rs = stream;
+            if (fork) {
+                if ((e = hipEventRecord(rt.level_events[2 * L], stream)) != hipSuccess ||
+                    (e = hipStreamWaitEvent(rt.side, rt.level_events[2 * L], 0)) != hipSuccess)
+                    return fail(e, "fork to the second stream");
+                rs = rt.side;
             }
             if (!W.prep.empty()) {
                 ProfScope ps(prof, KIND_PREP, stream, 0, W.prep_bytes);
@@ -2065,22 +2104,27 @@ std::string execute(const Plan &plan, const std::vector<const VProgram *> &progs
             }
             for (int k = 0; k < LevelWork::kColSlots; ++k) {
                 if (W.col[k].empty()) continue;
-                ProfScope ps(prof, KIND_ELIM1, stream, 0, W.col_bytes[k]);
+                ProfScope ps(prof, KIND_ELIM1, rs, 0, W.col_bytes[k]);
                 e = launch_colred(reinterpret_cast<ColDesc *>(dd + W.off_col[k]), (int)W.col[k].size(),
                                   W.col_tiles[k], k % kColMat + 1, W.col_maxout[k], W.col_dtype[k],
-                                  cfg.domain, k >= kColMat, stream);
+                                  cfg.domain, k >= kColMat, rs);
                 if (e != hipSuccess) return fail(e, "column reduction");
             }
             if (!W.e1.empty()) {
-                ProfScope ps(prof, KIND_ELIM1, stream, 0, W.e1_bytes);
+                ProfScope ps(prof, KIND_ELIM1, rs, 0, W.e1_bytes);
                 e = launch_elim1(reinterpret_cast<Elim1Desc *>(dd + W.off_e1), (int)W.e1.size(),
-                                 W.e1_tiles, cfg.domain, stream);
+                                 W.e1_tiles, cfg.domain, rs);
                 if (e != hipSuccess) return fail(e, "elim1");
             }
             if (!W.e0.empty()) {
                 e = launch_elim0(reinterpret_cast<Elim0Desc *>(dd + W.off_e0), (int)W.e0.size(),
-                                 cfg.domain, stream);
+                                 cfg.domain, rs);
                 if (e != hipSuccess) return fail(e, "elim0");
+            }
+            if (fork) {
+                if ((e = hipEventRecord(rt.level_events[2 * L + 1], rt.side)) != hipSuccess ||
+                    (e = hipStreamWaitEvent(stream, rt.level_events[2 * L + 1], 0)) != hipSuccess)
+                    return fail(e, "join of the second stream");
             }
             if (!W.red.empty()) {
                 ProfScope ps(prof, KIND_REDUCE, stream, 0);

@@ -88,6 +88,12 @@ struct Runtime {
         size_t inmx_off = 0;
     };
     std::map<std::string, GraphEntry> graphs;
+    // Second stream (default priority, not blocking on the null stream) for
+    // the reductions that run beside a level's GEMMs, and a fork and a join
+    // event per level; created on first use on the runtime's device.
+    hipStream_t side = nullptr;
+    std::vector<hipEvent_t> level_events;
+    hipError_t reserve_side(size_t levels);
     void drop_graphs();
     ~Runtime();
     hipError_t reserve_arena(size_t bytes);

@@ -26,8 +26,9 @@ __global__ __launch_bounds__(256) void k_rowred(const ColDesc *__restrict__ D, i
     typedef typename Dom<DOM>::acc A;
     typedef typename std::conditional<std::is_void<T>::value, A, T>::type XT;
     constexpr int SEGMAX = 1024, RPW = kRowBlock / 4;
-    __shared__ A svt[NOUT * SEGMAX];  // [output][q][j][lane]
-    __shared__ A res[4][NOUT][RPW];   // reduced sums of each wave's rows
+    // [output][q][j][lane]: with four outputs exactly 32 KB, which lets a
+    // block share a compute unit with a 128 KB GEMM block
+    __shared__ A svt[NOUT * SEGMAX];
     const int64_t b = blockIdx.x;
     const int p = __builtin_amdgcn_readfirstlane(find_problem(D, nprob, b));  // uniform
     const ColDesc &d = D[p];
@@ -116,6 +117,10 @@ __global__ __launch_bounds__(256) void k_rowred(const ColDesc *__restrict__ D, i
                 }
             }
     };
+    // each wave's row sums: lane r holds those of its row r
+    A mine[NOUT];
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o) mine[o] = 0;
     auto run = [&](auto vec_tag) {
         // two register buffers used alternately (row indices are
         // compile-time constants after unrolling, so no copies)
@@ -159,18 +164,17 @@ __global__ __launch_bounds__(256) void k_rowred(const ColDesc *__restrict__ D, i
                     }
                     acc -= term;
                 }
-                if (lane == 0) res[wv][o][r] = acc;
+                if (lane == r) mine[o] = acc;
             }
         }
     };
     if (vecld) run(std::true_type{});
     else run(std::false_type{});
-    __syncthreads();
-    for (int idx = t; idx < 4 * NOUT * RPW; idx += 256) {
-        const int w4 = idx / (NOUT * RPW), o = (idx / RPW) % NOUT, r = idx % RPW;
-        const int64_t w = tr * kRowBlock + w4 * RPW + r;
-        if (o < nout && w < n)
-            ((__attribute__((address_space(1))) A *)(d.o[o].part))[ts * n + w] = res[w4][o][r];
+    const int64_t w = wrow0 + lane;
+    if (lane < RPW && w < n) {
+#pragma unroll
+        for (int o = 0; o < NOUT; ++o)
+            if (o < nout) ((__attribute__((address_space(1))) A *)(d.o[o].part))[ts * n + w] = mine[o];
     }
 }
 

@@ -660,3 +660,34 @@ def test_conditioned_exact_and_chunked(U):
         say(f"conditioned f64 K4 n=150 workspace_limit={lim}")
         b = U.Plan(4, K4, precision="f64", workspace_limit=lim).eval_samples(Xd, 8.0)
         assert abs(a.value - b.value) <= 1e-12 * a.err_scale
+
+
+@pytest.mark.parametrize("case", ["cycle4-samples", "c5chord-batched", "k4-conditioned"])
+def test_second_stream_bitwise(U, case):
+    """A level's reductions on the second stream beside its GEMMs give the
+    results of the serial schedule bit for bit, on first evaluation and on
+    graph replays (the 4-cycle on RBF factors at n = 2048, where the row
+    reductions of K run beside the symmetric product; a ragged batch; a
+    conditioned plan in slice chunks)."""
+    import torch
+    if case == "cycle4-samples":
+        X = dev(W.gaussian_samples(2048, 16, seed=91), torch.float64)
+        run = lambda P: [P.eval_samples(X, 32.0).value for _ in range(3)]
+        mk = lambda ov: U.Plan(4, W.CYCLE4, precision="bf16x3", order="exhaustive", overlap=ov)
+    elif case == "c5chord-batched":
+        ns = [1100, 333, 2048, 700]
+        Xs = [dev(W.gaussian_samples(n, 8, seed=92 + i), torch.float64) for i, n in enumerate(ns)]
+        run = lambda P: [r.value for _ in range(2) for r in P.eval_batched(Xs, 16.0)]
+        mk = lambda ov: U.Plan(5, W.CYCLE5_CHORD, precision="f32", overlap=ov)
+    else:
+        n = 300
+        (M,) = W.random_matrices(1, n, seed=93, lo=0.0, hi=1.0)
+        Kd = dev(0.5 * (M + M.T), torch.float64)
+        run = lambda P: [P.eval([Kd] * 6).value for _ in range(2)]
+        ws1 = U.Plan(4, K4, precision="f64", symmetric=True).workspace([n], shared_factor=False)
+        mk = lambda ov: U.Plan(4, K4, precision="f64", symmetric=True, overlap=ov,
+                               workspace_limit=40 * ws1)
+    say(f"second stream {case}")
+    a = run(mk(True))
+    b = run(mk(False))
+    assert a == b, (a, b)
