@@ -207,9 +207,9 @@ def bench_batched(args):
     out = {"metric": "datasets/s (batched U-statistics)", "unit": "datasets/s",
            "config": {"workload": "256 datasets, n~U{128..4096}, d=32, Student-t(5), "
                                   "5-cycle + chord kernel, 52 restricted V-statistics each",
-                      "precision": args.precision, "second_stream": not args.serial_levels}}
+                      "precision": args.precision, "second_stream": args.overlap_levels}}
     plan = U.Plan(5, W.CYCLE5_CHORD, precision=args.precision, order=args.order,
-                  overlap=not args.serial_levels)
+                  overlap=args.overlap_levels)
     if args.tuning:
         gb, cb = (int(v) for v in args.tuning.split(","))
         plan.set_tuning(gb, cb)
@@ -270,7 +270,7 @@ def bench_cycle5_exact(args):
            "config": {"workload": "G(8192,0.01) seed 3, 5-cycle kernel, int8 MFMA limbs"}}
     for sp in (False, True):
         plan = U.Plan(5, W.CYCLE5, precision="i8", sparsify=sp, symmetric=True,
-                      overlap=not args.serial_levels)
+                      overlap=args.overlap_levels)
         r = plan.eval([Ad] * 5, stream=stream)
         torch.cuda.synchronize()
         steps = max(3, args.steps // 5)
@@ -586,9 +586,8 @@ def main():
     ap.add_argument("--order", default="exhaustive", choices=["minfill", "exhaustive"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
-    ap.add_argument("--serial-levels", action="store_true",
-                    help="run every launch of an evaluation on one stream (no second stream "
-                         "for a level's reductions beside its GEMMs)")
+    ap.add_argument("--overlap-levels", action="store_true",
+                    help="run a level's reductions on a second stream beside its GEMMs")
     ap.add_argument("--workload", default="cycle4",
                     choices=["cycle4", "batched", "cycle5-exact", "learned-order", "motifs", "hoif",
                              "peaks"],
@@ -652,7 +651,7 @@ def main():
     # symmetric: the same DAG as eval_samples builds for its RBF factor, so
     # that tuning on the factor matrix applies to the samples path
     plans = {p: U.Plan(m, edges, precision=p, order=args.order, symmetric=True,
-                       overlap=not args.serial_levels)
+                       overlap=args.overlap_levels)
              for p in ("bf16x3", "f32", "f64")}
     main_plan = plans[args.precision]
     if args.tuning:
@@ -684,7 +683,7 @@ def main():
            "config": {"workload": "4-cycle RBF U-statistic, m=4, n=4096, d=16, divisor 32, "
                                   "15 restricted V-statistics", "n": n, "d": d, "m": m,
                       "order": args.order, "precision": args.precision, "cse": True,
-                      "second_stream": not args.serial_levels,
+                      "second_stream": args.overlap_levels,
                       "num_vstats": r.num_vstats, "tuning": main_plan.tuning(),
                       "autotuned": tune_ms is not None}}
     # R = K K runs as a symmetric product on 256-wide tiles (n a multiple of

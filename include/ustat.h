@@ -104,15 +104,15 @@ typedef enum {
  */
 #define USTAT_FLAG_NO_SYM_GEMM 4
 /*
- * USTAT_FLAG_SERIAL_LEVELS: the reductions of a dependency level (the
+ * USTAT_FLAG_OVERLAP_LEVELS: the reductions of a dependency level (the
  * one-index eliminations and the dot products) read only results of earlier
- * levels, as do the level's GEMMs; by default they run on a second stream of
- * the plan (default priority) beside the GEMMs and are joined by an event
- * before the level's partial sums.  This flag runs every launch on the
- * caller's stream, for comparisons; results are identical bit for bit.  The
- * entry point that allocates nothing always runs serially.
+ * levels, as do the level's GEMMs.  With this flag they run on a second
+ * stream of the plan (default priority) beside the GEMMs, joined by an
+ * event before the level's partial sums; by default every launch runs on
+ * the caller's stream.  Results are identical bit for bit.  The entry point
+ * that allocates nothing always runs serially.
  */
-#define USTAT_FLAG_SERIAL_LEVELS 8
+#define USTAT_FLAG_OVERLAP_LEVELS 8
 
 typedef struct {
     int32_t precision;          /* ustat_precision                          */

@@ -150,7 +150,7 @@ ustat_status ustat_plan_create(int32_t m, int32_t num_edges, const int32_t *edge
     if (o.order < 0 || o.order > 2) return fail(USTAT_E_INVALID, "unknown order policy");
     if (o.sparsify != 0 && o.sparsify != 1) return fail(USTAT_E_INVALID, "sparsify must be 0 or 1");
     if (o.flags & ~(USTAT_FLAG_NO_CSE | USTAT_FLAG_SYMMETRIC | USTAT_FLAG_NO_SYM_GEMM |
-                    USTAT_FLAG_SERIAL_LEVELS))
+                    USTAT_FLAG_OVERLAP_LEVELS))
         return fail(USTAT_E_INVALID, "unknown flag bits");
     try {
         std::unique_ptr<ustat_plan_s> p(new ustat_plan_s());
@@ -166,7 +166,7 @@ ustat_status ustat_plan_create(int32_t m, int32_t num_edges, const int32_t *edge
         po.cse = !(o.flags & USTAT_FLAG_NO_CSE);
         po.symmetric = (o.flags & USTAT_FLAG_SYMMETRIC) != 0;
         po.sym_gemm = !(o.flags & USTAT_FLAG_NO_SYM_GEMM);
-        po.overlap = !(o.flags & USTAT_FLAG_SERIAL_LEVELS);
+        po.overlap = (o.flags & USTAT_FLAG_OVERLAP_LEVELS) != 0;
         if (o.cost_model_path) po.cost_model_path = o.cost_model_path;
         const OrderScorer *scorer = nullptr;
         if (o.order == USTAT_ORDER_LEARNED) {
@@ -1179,7 +1179,7 @@ ustat_status ustat_plan_create_motifs(int32_t size, const ustat_plan_opts *opts,
     if (opts) o = *opts;
     if (o.order < 0 || o.order > 1) return fail(USTAT_E_INVALID, "order policy must be min-fill or exhaustive");
     if (o.flags & ~(USTAT_FLAG_NO_CSE | USTAT_FLAG_SYMMETRIC | USTAT_FLAG_NO_SYM_GEMM |
-                    USTAT_FLAG_SERIAL_LEVELS))
+                    USTAT_FLAG_OVERLAP_LEVELS))
         return fail(USTAT_E_INVALID, "unknown flag bits");
     std::unique_ptr<ustat_plan_s> p(new ustat_plan_s());
     PlanOptions po;
@@ -1192,7 +1192,7 @@ ustat_status ustat_plan_create_motifs(int32_t size, const ustat_plan_opts *opts,
     po.cse = !(o.flags & USTAT_FLAG_NO_CSE);
     po.symmetric = true;      // A and B are symmetric
     po.sym_gemm = !(o.flags & USTAT_FLAG_NO_SYM_GEMM);
-    po.overlap = !(o.flags & USTAT_FLAG_SERIAL_LEVELS);
+    po.overlap = (o.flags & USTAT_FLAG_OVERLAP_LEVELS) != 0;
     for (const MotifKernel &mo : motif_kernels(size)) {
         Plan pl;
         std::string err = make_plan(size, motif_pairs(size), po, nullptr, pl);

@@ -85,7 +85,7 @@ struct PlanOptions {
     bool cse = true;  // merge equal steps across partitions at evaluation
     bool symmetric = false;  // caller's factor matrices are symmetric
     bool sym_gemm = true;    // products P P^T on the tiles on and above the diagonal
-    bool overlap = true;     // a level's reductions on a second stream beside its GEMMs
+    bool overlap = false;    // a level's reductions on a second stream beside its GEMMs
     uint64_t workspace_limit = 0;
     std::string cost_model_path;
     double n_hint = 4096.0;  // sample size orders are ranked for

@@ -32,7 +32,7 @@ STATUS = {0: "ok", 1: "invalid", 2: "unsupported", 3: "nomem", 4: "hip", 5: "ove
 FLAG_NO_CSE = 1
 FLAG_SYMMETRIC = 2
 FLAG_NO_SYM_GEMM = 4
-FLAG_SERIAL_LEVELS = 8
+FLAG_OVERLAP_LEVELS = 8
 FACTOR_DTYPE = {F64: torch.float64, F32: torch.float32, BF16X3: torch.float32, I8: torch.int8}
 PROFILE_KINDS = {"prep": 0, "gemm": 1, "elim1": 2, "reduce": 3, "rbf": 4, "lowrank_step": 5,
                  "lowrank_reduce": 6, "lowrank_outer": 7}
@@ -176,7 +176,7 @@ def _edges_array(edges: Sequence[Tuple[int, int]]):
 def ustat_plan_create(m: int, edges, precision="f64", order="minfill", sparsify=False,
                       workspace_limit: int = 0, cost_model_path: Optional[str] = None,
                       cse: bool = True, n_hint: int = 0, symmetric: bool = False,
-                      sym_gemm: bool = True, overlap: bool = True):
+                      sym_gemm: bool = True, overlap: bool = False):
     L = load_library()
     o = PlanOpts()
     _check(L.ustat_plan_opts_default(ctypes.byref(o)))
@@ -184,7 +184,7 @@ def ustat_plan_create(m: int, edges, precision="f64", order="minfill", sparsify=
     o.order = ORDERS[order] if isinstance(order, str) else int(order)
     o.sparsify = 1 if sparsify else 0
     o.flags = ((0 if cse else FLAG_NO_CSE) | (FLAG_SYMMETRIC if symmetric else 0)
-               | (0 if sym_gemm else FLAG_NO_SYM_GEMM) | (0 if overlap else FLAG_SERIAL_LEVELS))
+               | (0 if sym_gemm else FLAG_NO_SYM_GEMM) | (FLAG_OVERLAP_LEVELS if overlap else 0))
     o.workspace_limit = int(workspace_limit)
     if o.order == ORDER_LEARNED and not cost_model_path:
         cost_model_path = DEFAULT_COST_MODEL
@@ -515,7 +515,7 @@ class Plan:
     def __init__(self, m: int, edges, precision="f64", order="minfill", sparsify=False,
                  workspace_limit: int = 0, cost_model_path: Optional[str] = None,
                  cse: bool = True, n_hint: int = 0, symmetric: bool = False,
-                 sym_gemm: bool = True, overlap: bool = True):
+                 sym_gemm: bool = True, overlap: bool = False):
         self.m = int(m)
         self.edges = [tuple(e) for e in edges]
         self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)

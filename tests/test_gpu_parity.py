@@ -664,8 +664,8 @@ def test_conditioned_exact_and_chunked(U):
 
 @pytest.mark.parametrize("case", ["cycle4-samples", "c5chord-batched", "k4-conditioned"])
 def test_second_stream_bitwise(U, case):
-    """A level's reductions on the second stream beside its GEMMs give the
-    results of the serial schedule bit for bit, on first evaluation and on
+    """A level's reductions on a second stream beside its GEMMs (opt-in)
+    give the results of the serial schedule bit for bit, on first evaluation and on
     graph replays (the 4-cycle on RBF factors at n = 2048, where the row
     reductions of K run beside the symmetric product; a ragged batch; a
     conditioned plan in slice chunks)."""
