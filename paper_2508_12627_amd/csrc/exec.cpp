@@ -974,6 +974,15 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
     S = Schedule();
     Arena A;
     const int nd = (int)data.size();
+    // Symmetric products are not used in evaluations that hold a program
+    // conditioned on a vertex.  One run of such evaluations (split-bf16,
+    // symmetric factors, levels of thousands of products of slice operands)
+    // stopped on an illegal memory access whose cause has not been found;
+    // those evaluations take the full product.
+    bool conditioned_eval = false;
+    for (const VProgram *p : progs) conditioned_eval = conditioned_eval || p->slice_var >= 0;
+    for (const Dataset &d : data)
+        for (const VProgram *p : d.progs) conditioned_eval = conditioned_eval || p->slice_var >= 0;
     const int ne = nd ? (int)data[0].factors.size() : 0;  // factors per dataset (equal for all)
     std::vector<int> poff(nd + 1, 0);
     for (int d = 0; d < nd; ++d) poff[d + 1] = poff[d] + (int)progs_of(progs, data[d]).size();
@@ -1392,9 +1401,11 @@ std::string build_schedule(const Plan &plan, const std::vector<const VProgram *>
                     const bool big = W.big && npad % 256 == 0 && !six;
                     g.tiles = (int)(npad / (big ? 256 : 128));
                     // one prepared operand on both sides: C = P P^T is symmetric
-                    const bool sym = big && plan.opts.sym_gemm && fmt == PF_BF16X2 &&
-                                     nd_.kind == NK::GemmStore && g.A == g.B &&
-                                     cfg.mat_dt == DT_F32;
+                    // (not in evaluations with programs conditioned on a
+                    // vertex: that combination is switched off, see below)
+                    const bool sym = big && plan.opts.sym_gemm && !conditioned_eval &&
+                                     fmt == PF_BF16X2 && nd_.kind == NK::GemmStore &&
+                                     g.A == g.B && cfg.mat_dt == DT_F32;
                     if (sym) {
                         const int64_t t = g.tiles, nk = npad / 32;
                         g.tile_start = W.gemm_sym_units;  // first unit (tile K step)
