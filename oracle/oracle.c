@@ -234,7 +234,7 @@ int oracle_lowrank_dp(int m, int ne, const int *eu, const int *ev, long n, int r
                     phi[eu[k]] *= F[k][i * r + col[k]];
                     phi[ev[k]] *= G[k][i * r + col[k]];
                 }
-                /* descending masks: D[S] is read before any update this round */
+                /* descending masks: D[S] is read before any update of this pass */
                 for (int S = full; S >= 0; --S) {
                     double ds = D[S];
                     if (ds == 0.0) continue;
